@@ -1,0 +1,254 @@
+"""FP64 CPU oracle of the RaDe-GS rasterizer -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product (``paper_2406_01467_amd``)
+never does, and this package never imports the product.
+
+The arithmetic lives in ``rade_oracle.cpp`` (plain C++17, FP64, OpenMP over
+pixels); this module compiles it with g++ on first use and wraps it with
+ctypes on NumPy arrays.
+
+What each function follows (RaDe-GS, arXiv 2406.01467):
+
+* :func:`project` -- Sec. 3.1 Eq. 1-2 (covariance, local affine projection),
+  Sec. 3.2.2 Eq. 8-17 (ray space, q-hat by Eq. 13, p by Eq. 15-17), Sec. 3.3
+  Eq. 21-22 (normal), spherical-harmonic colour (Sec. 3.1 under Eq. 3).
+* :func:`render` -- Eq. 3 (front-to-back alpha blending) applied to colour,
+  the per-pixel depth of Eq. 4, the normal of Eq. 22 and alpha; the median
+  depth of Sec. 1.  Every pixel walks ALL Gaussians in (float32 depth, id)
+  order.
+* :func:`render_bwd`, :func:`project_bwd` -- the hand adjoint (pinned by
+  central finite differences in the tests).
+* :func:`bin_pairs` -- tile lists: (tile, depth) keys ordered by a stable sort.
+
+Parity status: every function is pinned by the CPU tests in
+``tests/test_oracle_*.py`` (closed forms, invariants, library routines, finite
+differences); nothing is "parity unpinned" except the absolute agreement
+with the authors' unpublished CUDA code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rade_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+# Settings vector indices (mirror of the enum in rade_oracle.cpp).
+S_DILATION, S_NEAR, S_ALPHA_MIN, S_ALPHA_MAX, S_T_MIN, S_POWER_CUT = 0, 1, 2, 3, 4, 5
+S_FOV_CLAMP, S_DEGEN, S_BG, S_SH_DEGREE, S_TILE_W, S_TILE_H = 6, 7, 8, 11, 12, 13
+S_FRAG_POWER, S_FRAG_ALPHA, S_FRAG_T, S_FRAG_MED, S_FRAG_CLAMP = 14, 15, 16, 17, 18
+S_COUNT = 19
+
+# Record fields (doubles per (view, Gaussian)).
+R_FIELDS = ["uc", "vc", "z", "tc", "a", "b", "c", "o", "r", "g", "bl", "p0", "p1",
+            "q0", "q1", "n0", "n1", "n2", "tau", "B00", "B01", "B11", "X", "Y"]
+R = {k: i for i, k in enumerate(R_FIELDS)}
+# Gradient fields of the projected quantities.
+G_FIELDS = ["uc", "vc", "a", "b", "c", "o", "r", "g", "bl", "z", "p0", "p1", "n0", "n1", "n2"]
+# Output fields per pixel.
+O_FIELDS = ["r", "g", "b", "dexp", "dmed", "n0", "n1", "n2", "alpha", "tfinal"]
+
+F_CULLED, F_VISIBLE, F_DEGENERATE, F_CLAMP_X, F_CLAMP_Y = 1, 2, 4, 8, 16
+F_RGB_CLAMP = (32, 64, 128)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with g++ (FP64, no FMA contraction)."""
+    with _lock:
+        if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            tmp = _LIB + ".tmp%d" % os.getpid()
+            cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                   "-shared", _SRC, "-o", tmp]
+            subprocess.check_call(cmd)
+            os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_project.argtypes = [P, P, ctypes.c_int, ctypes.c_int64] + [P] * 8
+        lib.oracle_render.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P, P]
+        lib.oracle_render_bwd.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P]
+        lib.oracle_project_bwd.argtypes = [P, P, ctypes.c_int, ctypes.c_int64] + [P] * 11
+        lib.oracle_bin.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                   P, P, P, P, ctypes.c_int64, P]
+        lib.oracle_bin.restype = ctypes.c_int64
+        for f in ("oracle_settings_count", "oracle_view_count", "oracle_record_count",
+                  "oracle_grad_count", "oracle_out_count"):
+            getattr(lib, f).restype = ctypes.c_int
+        assert lib.oracle_settings_count() == S_COUNT
+        assert lib.oracle_record_count() == len(R_FIELDS)
+        assert lib.oracle_grad_count() == len(G_FIELDS)
+        assert lib.oracle_out_count() == len(O_FIELDS)
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def settings(sh_degree=0, dilation=0.3, near=0.2, alpha_min=1.0 / 255.0, alpha_max=0.99,
+             t_min=1e-4, power_cut=4.5, fov_clamp=1.3, degenerate=1e-6, bg=(0.0, 0.0, 0.0),
+             tile=(16, 16), frag_power=2e-5, frag_alpha=1e-5, frag_t=1e-4, frag_med=1e-5,
+             frag_clamp=1e-5) -> np.ndarray:
+    """Settings vector.  Defaults are the readings listed in the design notes:
+    3DGS defaults for the quantities the paper leaves open."""
+    s = np.zeros(S_COUNT, dtype=np.float64)
+    s[S_DILATION], s[S_NEAR], s[S_ALPHA_MIN], s[S_ALPHA_MAX] = dilation, near, alpha_min, alpha_max
+    s[S_T_MIN], s[S_POWER_CUT], s[S_FOV_CLAMP], s[S_DEGEN] = t_min, power_cut, fov_clamp, degenerate
+    s[S_BG:S_BG + 3] = bg
+    s[S_SH_DEGREE] = sh_degree
+    s[S_TILE_W], s[S_TILE_H] = tile
+    s[S_FRAG_POWER], s[S_FRAG_ALPHA], s[S_FRAG_T] = frag_power, frag_alpha, frag_t
+    s[S_FRAG_MED], s[S_FRAG_CLAMP] = frag_med, frag_clamp
+    return s
+
+
+def view_vector(v) -> np.ndarray:
+    """18 doubles: W, H, fx, fy, cx, cy, R (row-major), t."""
+    out = np.zeros(18, dtype=np.float64)
+    out[0], out[1] = v.width, v.height
+    out[2], out[3] = np.float32(v.fx), np.float32(v.fy)
+    out[4], out[5] = np.float32(v.cx), np.float32(v.cy)
+    out[6:15] = np.asarray(v.R, dtype=np.float32).reshape(9)
+    out[15:18] = np.asarray(v.t, dtype=np.float32).reshape(3)
+    return out
+
+
+def _scene_arrays(scene):
+    c = np.ascontiguousarray
+    return (c(scene.means, np.float32), c(scene.scales, np.float32), c(scene.quats, np.float32),
+            c(scene.opacities, np.float32), c(scene.sh, np.float32))
+
+
+def project(s: np.ndarray, views, scene):
+    """Project a scene into views.  Returns (rec [V,N,24] f64, rect [V,N,4]
+    int32, flags [V,N] int32)."""
+    lib = _load()
+    V, N = len(views), scene.n
+    vv = np.ascontiguousarray(np.stack([view_vector(v) for v in views]))
+    rec = np.zeros((V, N, len(R_FIELDS)), np.float64)
+    rect = np.zeros((V, N, 4), np.int32)
+    flags = np.zeros((V, N), np.int32)
+    m, sc, q, o, sh = _scene_arrays(scene)
+    lib.oracle_project(_ptr(s), _ptr(vv), V, N, _ptr(m), _ptr(sc), _ptr(q), _ptr(o), _ptr(sh),
+                       _ptr(rec), _ptr(rect), _ptr(flags))
+    return rec, rect, flags
+
+
+def render(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, pixels=None,
+           want_sig: bool = False):
+    """Render one view from its records (rec [N,24], flags [N]).  ``pixels``:
+    optional int64 pixel indices (py*W + px).  Returns a dict of per-pixel
+    arrays: color (n,3), depth_exp, depth_med, normal (n,3), alpha, t_final,
+    count, last_id, median_id, fragile (bit 0: maps, bit 1: gradients), and
+    optionally sig (discrete signature for finite-difference guards)."""
+    lib = _load()
+    N = rec.shape[0]
+    rec = np.ascontiguousarray(rec, np.float64)
+    flags = np.ascontiguousarray(flags, np.int32)
+    vv = view_vector(view)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = view.width * view.height if pix is None else pix.shape[0]
+    out = np.zeros((npix, len(O_FIELDS)), np.float64)
+    iout = np.zeros((npix, 4), np.int64)
+    sig = np.zeros(npix, np.uint64) if want_sig else None
+    lib.oracle_render(_ptr(s), _ptr(vv), N, _ptr(rec), _ptr(flags), _ptr(pix), npix, _ptr(out),
+                      _ptr(iout), _ptr(sig))
+    res = dict(color=out[:, 0:3], depth_exp=out[:, 3], depth_med=out[:, 4], normal=out[:, 5:8],
+               alpha=out[:, 8], t_final=out[:, 9], count=iout[:, 0], last_id=iout[:, 1],
+               median_id=iout[:, 2], fragile=iout[:, 3])
+    if want_sig:
+        res["sig"] = sig
+    return res
+
+
+def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np.ndarray,
+               pixels=None, gP: np.ndarray | None = None) -> np.ndarray:
+    """Adjoint of :func:`render`.  gout: (npix, 9) upstream gradients of
+    (color 3, depth expected, depth median, normal 3, alpha).  Returns the
+    gradient of the projected quantities, (N, 15) in the order of G_FIELDS."""
+    lib = _load()
+    N = rec.shape[0]
+    vv = view_vector(view)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = view.width * view.height if pix is None else pix.shape[0]
+    gout = np.ascontiguousarray(gout, np.float64).reshape(npix, 9)
+    if gP is None:
+        gP = np.zeros((N, len(G_FIELDS)), np.float64)
+    lib.oracle_render_bwd(_ptr(s), _ptr(vv), N, _ptr(np.ascontiguousarray(rec, np.float64)),
+                          _ptr(np.ascontiguousarray(flags, np.int32)), _ptr(pix), npix,
+                          _ptr(gout), _ptr(gP))
+    return gP
+
+
+def project_bwd(s: np.ndarray, views, scene, gP: np.ndarray) -> dict:
+    """Chain projected-quantity gradients gP [V,N,15] back to the parameters
+    (summed over views)."""
+    lib = _load()
+    V, N = len(views), scene.n
+    vv = np.ascontiguousarray(np.stack([view_vector(v) for v in views]))
+    m, sc, q, o, sh = _scene_arrays(scene)
+    out = dict(means=np.zeros((N, 3)), scales=np.zeros((N, 3)), quats=np.zeros((N, 4)),
+               opacities=np.zeros(N), sh=np.zeros(sh.shape, np.float64))
+    lib.oracle_project_bwd(_ptr(s), _ptr(vv), V, N, _ptr(m), _ptr(sc), _ptr(q), _ptr(o),
+                           _ptr(sh), _ptr(np.ascontiguousarray(gP, np.float64)),
+                           _ptr(out["means"]), _ptr(out["scales"]), _ptr(out["quats"]),
+                           _ptr(out["opacities"]), _ptr(out["sh"]))
+    return out
+
+
+def bin_pairs(views, rect: np.ndarray, z: np.ndarray, tile=(16, 16)):
+    """Binning reference.  rect [V,N,4] int32, z [V,N] float32.  Returns
+    (ids uint32 [M], keys uint64 [M], ranges uint32 [sum tiles, 2])."""
+    lib = _load()
+    V, N = rect.shape[0], rect.shape[1]
+    dims = np.ascontiguousarray([[v.width, v.height] for v in views], np.int32)
+    tiles = sum(((v.width + tile[0] - 1) // tile[0]) * ((v.height + tile[1] - 1) // tile[1])
+                for v in views)
+    rect = np.ascontiguousarray(rect, np.int32)
+    z = np.ascontiguousarray(z, np.float32)
+    M = lib.oracle_bin(_ptr(dims), V, N, tile[0], tile[1], _ptr(rect), _ptr(z), None, None, 0,
+                       None)
+    ids = np.zeros(M, np.uint32)
+    keys = np.zeros(M, np.uint64)
+    ranges = np.zeros((tiles, 2), np.uint32)
+    lib.oracle_bin(_ptr(dims), V, N, tile[0], tile[1], _ptr(rect), _ptr(z), _ptr(ids),
+                   _ptr(keys), M, _ptr(ranges))
+    return ids, keys, ranges
+
+
+# ----------------------------------------------------------------------------
+# Convenience: full forward / backward of a scene in views.
+
+def forward(s: np.ndarray, views, scene, pixels=None, want_sig=False):
+    rec, rect, flags = project(s, views, scene)
+    outs = []
+    for vi, v in enumerate(views):
+        px = None if pixels is None else pixels[vi]
+        outs.append(render(s, v, rec[vi], flags[vi], px, want_sig))
+    return rec, rect, flags, outs
+
+
+def backward(s: np.ndarray, views, scene, gouts, pixels=None, rec=None, flags=None) -> dict:
+    """VJP of the whole path: gouts[v] is (npix_v, 9)."""
+    if rec is None:
+        rec, _, flags = project(s, views, scene)
+    gP = np.zeros((len(views), scene.n, len(G_FIELDS)), np.float64)
+    for vi, v in enumerate(views):
+        px = None if pixels is None else pixels[vi]
+        render_bwd(s, v, rec[vi], flags[vi], gouts[vi], px, gP[vi])
+    return project_bwd(s, views, scene, gP)
