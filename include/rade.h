@@ -1,0 +1,225 @@
+/*
+ * rade.h -- C ABI of the RaDe-GS rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * RaDe-GS (arXiv 2406.01467) renders 3D Gaussians by projecting each one to a
+ * screen-space splat (Sec. 3.1, Eq. 1-2) and alpha-blending front to back
+ * (Eq. 3).  Besides colour it blends a per-pixel depth that is planar over
+ * each splat, d = z_c + p (u_c - u, v_c - v) (Sec. 3.2, Eq. 4, with p from
+ * Eq. 13-17), and the splat's normal n = normalize(J^T n'), n' = -(q, 1)
+ * (Sec. 3.3, Eq. 21-22).  The depth map is the median depth, the depth at
+ * which the accumulated opacity crosses one half (Sec. 1); the normal map is
+ * blended like colour.  This library computes that rasterizer and its
+ * gradient.
+ *
+ * The call sequence of one forward + backward pass over V views:
+ *   rade_views_prepare (host)      fill per-view pixel / tile offsets
+ *   rade_project                   Gaussians -> splats, tiles touched
+ *   rade_bin_sort                  (view, tile) lists of splats in depth order
+ *   rade_render_fwd                colour / depth / normal / alpha maps
+ *   rade_render_bwd                gradients of the Gaussian parameters
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller unless it is
+ *   documented as host memory.  The library never allocates or frees device
+ *   memory; scratch memory comes from a caller-supplied workspace whose size
+ *   the matching *_workspace_bytes function returns.
+ * - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *   default stream) and returns without waiting, except where an argument
+ *   explicitly asks for a host result.  Arguments are validated on the host
+ *   before anything is enqueued; an invalid call enqueues nothing.
+ * - Floating-point data are IEEE FP32, row-major.  Gaussian parameters are
+ *   already activated: scales are standard deviations (> 0), opacities lie
+ *   in (0, 1), quaternions are (w, x, y, z) and need not be normalised (the
+ *   library normalises them and differentiates through the normalisation).
+ * - Spherical harmonics: N x K x 3 floats, K = (degree + 1)^2 (coefficient
+ *   major, RGB minor), real SH with the Condon-Shortley phase in the order
+ *   m = -l..l per degree; colour = max(0, sum_k sh_k Y_k(dir) + 1/2) with
+ *   dir the unit vector from the camera centre to the mean.
+ * - Cameras use OpenCV axes (x right, y down, z forward); pixel (px, py) has
+ *   its centre at (px + 1/2, py + 1/2).
+ * - Maps are planar per view and views are packed back to back: a map with
+ *   C channels holds, for view v, C planes of W_v * H_v floats starting at
+ *   C * views[v].pix_offset.  For one view this is the CHW layout.
+ * - Return value: RADE_OK (0) or a negative error code (rade_strerror).
+ */
+#ifndef RADE_H
+#define RADE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RADE_OK 0
+#define RADE_ERR_INVALID_ARG (-1)  /* bad pointer, size or setting; nothing enqueued */
+#define RADE_ERR_CAPACITY (-2)     /* more (tile, splat) pairs than `capacity` */
+#define RADE_ERR_HIP (-3)          /* a HIP runtime call failed */
+#define RADE_ERR_WORKSPACE (-4)    /* workspace smaller than required */
+
+/* Rasterizer settings.  Quantities the paper leaves open default to the
+ * values of the 3D Gaussian Splatting code base the paper builds on (it
+ * states that it keeps that code base's default parameters, Sec. 4.1). */
+typedef struct rade_settings {
+  int32_t tile_w, tile_h;  /* tile size in pixels: each a multiple of 8, product <= 1024 */
+  int32_t sh_degree;       /* 0..3 */
+  int32_t reserved;
+  double dilation;         /* added to the 2x2 footprint covariance, px^2 (0.3) */
+  double near_plane;       /* Gaussians with camera z <= near are culled (0.2) */
+  double alpha_min;        /* blends with alpha < alpha_min are skipped (1/255) */
+  double alpha_max;        /* alpha is clamped to alpha_max (0.99) */
+  double t_min;            /* a pixel stops before the blend that would leave T < t_min (1e-4) */
+  double power_cut;        /* blends with 1/2 d^T conic d > power_cut are skipped (4.5, 3 sigma) */
+  double fov_clamp;        /* x/z, y/z in the Jacobian clamped to fov_clamp * W/(2 fx) (1.3) */
+  double degenerate;       /* q := 0 when det(B0) <= degenerate * tr(B0)^2 (1e-6) */
+  double bg[3];            /* background colour, blended with the final transmittance */
+} rade_settings;
+
+/* One camera.  The caller fills the first five rows; rade_views_prepare
+ * fills the offsets. */
+typedef struct rade_view {
+  int32_t width, height;   /* pixels, 1..32767 */
+  float fx, fy, cx, cy;    /* pinhole intrinsics in pixels */
+  float R[9];              /* world -> camera rotation, row-major */
+  float t[3];              /* world -> camera translation: x_cam = R x_world + t */
+  int32_t tiles_x, tiles_y;/* tiles per row / column (filled by rade_views_prepare) */
+  int64_t pix_offset;      /* first pixel of this view in the packed maps (filled) */
+  int64_t tile_offset;     /* first global tile index of this view (filled) */
+} rade_view;               /* 96 bytes */
+
+/* Projected splat of one (view, Gaussian), 80 bytes.  The quadratic form of
+ * the splat, power = 1/2 d^T B^-1 d with d = (u_c - u, v_c - v) and B the
+ * dilated 2x2 footprint covariance, is stored in factored form:
+ *   power * log2(e) = (w[0] dx + w[1] dy)^2 + (w[2] dx + w[3] dy)^2,
+ * with (w[0], w[1]) and (w[2], w[3]) the eigenvectors of B scaled by
+ * sqrt(log2(e) / (2 lambda)); it is exact up to FP32 rounding even for
+ * very elongated splats.  rect is the inclusive pixel rectangle that holds
+ * every pixel with alpha >= alpha_min; rect[0] > rect[1] marks a splat that
+ * is culled or off screen (every other field is then unspecified). */
+typedef struct rade_splat {
+  double uc, vc;          /* centre in pixels (projected mean) */
+  float w[4];             /* factored quadratic form, see above */
+  float opacity;
+  float rgb[3];           /* SH colour for this view */
+  float z;                /* camera-space depth of the centre; sort key */
+  float p[2];             /* depth plane: d = z + p . (u_c - u, v_c - v)   (Eq. 4) */
+  float n[3];             /* unit normal in camera space, facing the camera (Eq. 22) */
+  int16_t rect[4];        /* x0, x1, y0, y1 */
+} rade_splat;
+
+/* Host function.  Fills tiles_x, tiles_y, pix_offset and tile_offset of
+ * views[0..V) for the tile size of `s`; returns the totals (either pointer
+ * may be NULL).  The device copy of the views that the other calls read
+ * must be made from the array after this call. */
+int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
+                       int64_t* total_pixels, int64_t* total_tiles);
+
+/* Projection (Sec. 3.1 Eq. 1-2; Sec. 3.2 Eq. 4, 13-17; Sec. 3.3 Eq. 21-22).
+ * For every Gaussian g and view v writes splats[v*N + g] and
+ * tiles_touched[v*N + g] = number of tiles its rect covers (0 if culled).
+ *   views_dev : V rade_view structs in device memory (after views_prepare)
+ *   means N*3, scales N*3, quats N*4, opacities N, sh N*K*3 (see above)
+ * A Gaussian is culled when a parameter is not finite, its camera z <=
+ * near_plane, its quaternion is zero or 255 * opacity <= 1.  The geometry is
+ * evaluated in FP64 and rounded to the FP32 fields once. */
+int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
+                 const float* means, const float* scales, const float* quats,
+                 const float* opacities, const float* sh, rade_splat* splats,
+                 int32_t* tiles_touched, void* stream);
+
+/* Workspace bytes for rade_bin_sort with V views, N Gaussians, `capacity`
+ * pairs and `total_tiles` tiles. */
+size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t total_tiles);
+
+/* Binning and sorting (Sec. 3.1: splats are blended in the order of their
+ * centre depth).  Emits one (tile, splat) pair for every tile a splat's rect
+ * covers and orders the pairs by (global tile, float32 depth, Gaussian id);
+ * equivalently a stable sort by the 64-bit key (tile << 32 | bits(z)).
+ *   views_host/views_dev : the same V prepared views, host and device copies
+ *   splats, tiles_touched: rade_project's outputs
+ *   pair_ids   [capacity] : Gaussian id of each sorted pair
+ *   tile_ranges[2*total_tiles]: [begin, end) into pair_ids per global tile
+ *   keys       [capacity] : optional (may be NULL), the sorted 64-bit keys
+ *   n_pairs_dev           : device int64 receiving the pair count M
+ *   n_pairs_host          : optional host int64; when given the call waits
+ *                           for the pair count, stores it and returns
+ *                           RADE_ERR_CAPACITY at once if M > capacity
+ * When M > capacity, pair_ids and keys are left untouched and every tile
+ * range is empty ([0, 0)); *n_pairs_dev still holds M so the caller can
+ * retry with capacity >= M.  capacity must be < 2^32. */
+int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
+                  const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
+                  const int32_t* tiles_touched, uint32_t* pair_ids, uint32_t* tile_ranges,
+                  uint64_t* keys, int64_t capacity, int64_t* n_pairs_dev,
+                  int64_t* n_pairs_host, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Forward rendering (Eq. 3 applied to colour, the depth of Eq. 4, the normal
+ * of Eq. 22 and alpha; median depth of Sec. 1).  For each pixel, splats of
+ * its tile list are visited in order; a splat is skipped when its power
+ * exceeds power_cut or its alpha = min(alpha_max, opacity * exp(-power)) is
+ * below alpha_min; the pixel stops before a splat that would bring its
+ * transmittance T below t_min.  Blend weights w_i = alpha_i T_i give
+ *   color  (3 planes) = sum w_i rgb_i + T_final bg
+ *   depth  (2 planes) = sum w_i d_i  |  d of the median splat (0 if none)
+ *   normal (3 planes) = sum w_i n_i (not renormalised)
+ *   alpha  (1 plane)  = sum w_i
+ * The median splat is the last one blended while the incoming T > 1/2.
+ * Saved state for rade_render_bwd (1 plane each):
+ *   t_final (float), last (int32: position of the last blended splat within
+ *   its tile's list, -1 if none), median (int32: Gaussian id of the median
+ *   splat, -1 if none); count (int32, optional, may be NULL): splats blended. */
+int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
+                    const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
+                    const uint32_t* pair_ids, const uint32_t* tile_ranges, float* color,
+                    float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
+                    int32_t* median, int32_t* count, void* stream);
+
+/* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
+ * recompute the splats (splats == NULL in rade_render_bwd). */
+size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute);
+
+/* Backward pass: gradients of the Gaussian parameters from the upstream
+ * gradients of the maps of rade_render_fwd.  The blend state of each pixel
+ * is recomputed back to front from the saved final transmittance (no
+ * per-blend state is stored).  d_color (3 planes), d_depth (2 planes:
+ * expected, median), d_normal (3), d_alpha (1) may each be NULL (zero).  No
+ * gradient flows through the choice of the median splat or through the
+ * tile lists.  splats may be NULL, in which case they are recomputed from
+ * the parameters into the workspace.  The outputs d_means (N*3), d_scales
+ * (N*3), d_quats (N*4), d_opacities (N), d_sh (N*K*3) are OVERWRITTEN with
+ * the gradient summed over the V views. */
+int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
+                    const rade_view* views_dev, int32_t V, int64_t N, const float* means,
+                    const float* scales, const float* quats, const float* opacities,
+                    const float* sh, const rade_splat* splats, const uint32_t* pair_ids,
+                    const uint32_t* tile_ranges, const float* t_final, const int32_t* last,
+                    const int32_t* median, const float* d_color, const float* d_depth,
+                    const float* d_normal, const float* d_alpha, float* d_means,
+                    float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Kernel timing without a profiler.  After this call, every launch of the
+ * kernel `kernel` (one of RADE_KERNEL_*) is bracketed by hipEventRecord of
+ * `start_event` and `stop_event` (hipEvent_t passed as void*) on the stream
+ * the kernel is launched on; NULL events switch the recording off.  The
+ * setting is process-wide and not thread-safe: it is meant for benchmarks
+ * that read hipEventElapsedTime after each call. */
+#define RADE_KERNEL_PROJECT 1
+#define RADE_KERNEL_RENDER_FWD 2
+#define RADE_KERNEL_RENDER_BWD 3
+#define RADE_KERNEL_PROJECT_BWD 4
+int rade_set_kernel_events(int kernel, void* start_event, void* stop_event);
+
+/* Static description of an error code (never NULL). */
+const char* rade_strerror(int code);
+
+/* ABI version of this header: 1. */
+int rade_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADE_H */

@@ -1,0 +1,243 @@
+// extern "C" entry points of librade.so: argument checks and launches.
+// Declarations and documentation: include/rade.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace rade {
+hipError_t launch_project(const rade_settings& st, const rade_view* views, int V, int64_t N,
+                          const float* means, const float* scales, const float* quats,
+                          const float* opac, const float* sh, rade_splat* splats,
+                          int32_t* tiles_touched, hipStream_t stream);
+hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, int V, int64_t N,
+                              const float* means, const float* scales, const float* quats,
+                              const float* opac, const float* sh, const float* gsplat,
+                              float* d_means, float* d_scales, float* d_quats, float* d_opac,
+                              float* d_sh, hipStream_t stream);
+size_t bin_sort_workspace(int64_t VN, int64_t capacity);
+hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
+                           const rade_view* views_dev, int V, int64_t N,
+                           const rade_splat* splats, const int32_t* tt, uint32_t* pair_ids,
+                           uint32_t* ranges, uint64_t* keys, int64_t capacity,
+                           int64_t* n_pairs_dev, int64_t* n_pairs_host, void* ws,
+                           hipStream_t st, int* capacity_exceeded);
+bool tile_supported(int tw, int th);
+hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
+                             int64_t tiles, const rade_splat* splats, const uint32_t* ids,
+                             const uint32_t* ranges, float* color, float* depth,
+                             float* normal, float* alpha, float* tf, int32_t* last,
+                             int32_t* med, int32_t* cnt, hipStream_t st);
+hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
+                             int64_t tiles, const rade_splat* splats, const uint32_t* ids,
+                             const uint32_t* ranges, const float* tf, const int32_t* last,
+                             const int32_t* med, const float* dc, const float* dd,
+                             const float* dn, const float* da, float* gsplat,
+                             hipStream_t st);
+}  // namespace rade
+
+namespace {
+
+bool settings_ok(const rade_settings* s) {
+  if (!s) return false;
+  if (!rade::tile_supported(s->tile_w, s->tile_h)) return false;
+  if (s->sh_degree < 0 || s->sh_degree > 3) return false;
+  if (!(s->alpha_min > 0.0) || !(s->alpha_max <= 1.0) || !(s->alpha_min < s->alpha_max))
+    return false;
+  if (!(s->t_min > 0.0 && s->t_min < 1.0) || !(s->power_cut > 0.0)) return false;
+  if (!(s->dilation >= 0.0) || !std::isfinite(s->near_plane) || !(s->fov_clamp > 0.0))
+    return false;
+  if (!(s->degenerate >= 0.0)) return false;
+  return true;
+}
+
+bool views_ok(const rade_view* v, int32_t V) {
+  if (!v || V < 1) return false;
+  for (int i = 0; i < V; ++i) {
+    if (v[i].width < 1 || v[i].height < 1 || v[i].width > 32767 || v[i].height > 32767)
+      return false;
+    if (!(v[i].fx > 0.f) || !(v[i].fy > 0.f)) return false;
+  }
+  return true;
+}
+
+bool counts_ok(int32_t V, int64_t N) {
+  return V >= 1 && N >= 0 && (int64_t)V * N < ((int64_t)1 << 32);
+}
+
+int64_t total_tiles(const rade_view* v, int32_t V) {
+  int64_t t = 0;
+  for (int i = 0; i < V; ++i) t += (int64_t)v[i].tiles_x * v[i].tiles_y;
+  return t;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? RADE_OK : RADE_ERR_HIP; }
+
+}  // namespace
+
+namespace rade {
+KernelEvents& kernel_events(int kernel) {
+  static KernelEvents table[8];
+  return table[(kernel >= 0 && kernel < 8) ? kernel : 0];
+}
+}  // namespace rade
+
+extern "C" {
+
+int rade_abi_version(void) { return 1; }
+
+int rade_set_kernel_events(int kernel, void* start_event, void* stop_event) {
+  if (kernel < RADE_KERNEL_PROJECT || kernel > RADE_KERNEL_PROJECT_BWD) return RADE_ERR_INVALID_ARG;
+  if ((start_event == nullptr) != (stop_event == nullptr)) return RADE_ERR_INVALID_ARG;
+  rade::KernelEvents& e = rade::kernel_events(kernel);
+  e.start = (hipEvent_t)start_event;
+  e.stop = (hipEvent_t)stop_event;
+  return RADE_OK;
+}
+
+const char* rade_strerror(int code) {
+  switch (code) {
+    case RADE_OK: return "ok";
+    case RADE_ERR_INVALID_ARG: return "invalid argument (nothing enqueued)";
+    case RADE_ERR_CAPACITY: return "pair capacity exceeded (n_pairs holds the required count)";
+    case RADE_ERR_HIP: return "HIP runtime error";
+    case RADE_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
+                       int64_t* total_pixels, int64_t* total_tiles_out) {
+  if (!settings_ok(s) || !views_ok(views, V)) return RADE_ERR_INVALID_ARG;
+  int64_t pix = 0, tiles = 0;
+  for (int i = 0; i < V; ++i) {
+    views[i].tiles_x = (views[i].width + s->tile_w - 1) / s->tile_w;
+    views[i].tiles_y = (views[i].height + s->tile_h - 1) / s->tile_h;
+    views[i].pix_offset = pix;
+    views[i].tile_offset = tiles;
+    pix += (int64_t)views[i].width * views[i].height;
+    tiles += (int64_t)views[i].tiles_x * views[i].tiles_y;
+  }
+  if (tiles >= ((int64_t)1 << 31)) return RADE_ERR_INVALID_ARG;
+  if (total_pixels) *total_pixels = pix;
+  if (total_tiles_out) *total_tiles_out = tiles;
+  return RADE_OK;
+}
+
+int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
+                 const float* means, const float* scales, const float* quats,
+                 const float* opacities, const float* sh, rade_splat* splats,
+                 int32_t* tiles_touched, void* stream) {
+  if (!settings_ok(s) || !views_dev || !counts_ok(V, N)) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !splats || !tiles_touched))
+    return RADE_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(quats) & 15) != 0) return RADE_ERR_INVALID_ARG;
+  return hip_status(rade::launch_project(*s, views_dev, V, N, means, scales, quats, opacities,
+                                         sh, splats, tiles_touched, (hipStream_t)stream));
+}
+
+size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t total_tiles) {
+  (void)total_tiles;
+  if (V < 1 || N < 0 || capacity < 0) return 0;
+  return rade::bin_sort_workspace((int64_t)V * N, capacity);
+}
+
+int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
+                  const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
+                  const int32_t* tiles_touched, uint32_t* pair_ids, uint32_t* tile_ranges,
+                  uint64_t* keys, int64_t capacity, int64_t* n_pairs_dev,
+                  int64_t* n_pairs_host, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+  if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
+    return RADE_ERR_INVALID_ARG;
+  if (capacity < 0 || capacity >= ((int64_t)1 << 32)) return RADE_ERR_INVALID_ARG;
+  if (!tile_ranges || !n_pairs_dev || (capacity > 0 && !pair_ids)) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!splats || !tiles_touched)) return RADE_ERR_INVALID_ARG;
+  for (int i = 0; i < V; ++i)
+    if (views_host[i].tiles_x != (views_host[i].width + s->tile_w - 1) / s->tile_w ||
+        views_host[i].tiles_y != (views_host[i].height + s->tile_h - 1) / s->tile_h)
+      return RADE_ERR_INVALID_ARG;  // views not prepared for this tile size
+  if (!workspace || workspace_bytes < rade_bin_sort_workspace(V, N, capacity, 0))
+    return RADE_ERR_WORKSPACE;
+  int exceeded = 0;
+  const hipError_t e = rade::launch_bin_sort(*s, views_host, views_dev, V, N, splats,
+                                             tiles_touched, pair_ids, tile_ranges, keys, capacity,
+                                             n_pairs_dev, n_pairs_host, workspace,
+                                             (hipStream_t)stream, &exceeded);
+  if (e != hipSuccess) return RADE_ERR_HIP;
+  return exceeded ? RADE_ERR_CAPACITY : RADE_OK;
+}
+
+int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
+                    const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
+                    const uint32_t* pair_ids, const uint32_t* tile_ranges, float* color,
+                    float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
+                    int32_t* median, int32_t* count, void* stream) {
+  if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
+    return RADE_ERR_INVALID_ARG;
+  if (!tile_ranges || !color || !depth || !normal || !alpha || !t_final || !last || !median)
+    return RADE_ERR_INVALID_ARG;
+  if (N > 0 && !splats) return RADE_ERR_INVALID_ARG;
+  const int64_t tiles = total_tiles(views_host, V);
+  return hip_status(rade::launch_render_fwd(*s, views_dev, V, N, tiles, splats, pair_ids,
+                                            tile_ranges, color, depth, normal, alpha, t_final,
+                                            last, median, count, (hipStream_t)stream));
+}
+
+size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute) {
+  (void)s;
+  if (V < 1 || N < 0) return 0;
+  const size_t VN = (size_t)V * (size_t)N;
+  size_t bytes = ((VN * 16 * sizeof(float)) + 255) & ~size_t(255);  // per-(view, Gaussian) grads
+  if (recompute)
+    bytes += ((VN * sizeof(rade_splat) + 255) & ~size_t(255)) + ((VN * 4 + 255) & ~size_t(255));
+  return bytes;
+}
+
+int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
+                    const rade_view* views_dev, int32_t V, int64_t N, const float* means,
+                    const float* scales, const float* quats, const float* opacities,
+                    const float* sh, const rade_splat* splats, const uint32_t* pair_ids,
+                    const uint32_t* tile_ranges, const float* t_final, const int32_t* last,
+                    const int32_t* median, const float* d_color, const float* d_depth,
+                    const float* d_normal, const float* d_alpha, float* d_means,
+                    float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
+    return RADE_ERR_INVALID_ARG;
+  if (!tile_ranges || !t_final || !last || !median) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !d_means || !d_scales ||
+                !d_quats || !d_opacities || !d_sh))
+    return RADE_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(quats) & 15) != 0 ||
+      (reinterpret_cast<uintptr_t>(d_quats) & 15) != 0)
+    return RADE_ERR_INVALID_ARG;
+  const int recompute = splats == nullptr ? 1 : 0;
+  if (!workspace || workspace_bytes < rade_render_bwd_workspace(s, V, N, recompute))
+    return RADE_ERR_WORKSPACE;
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t VN = (size_t)V * (size_t)N;
+  char* w = static_cast<char*>(workspace);
+  float* gsplat = reinterpret_cast<float*>(w);
+  if (recompute && N > 0) {
+    const size_t g_bytes = ((VN * 16 * sizeof(float)) + 255) & ~size_t(255);
+    rade_splat* rs = reinterpret_cast<rade_splat*>(w + g_bytes);
+    int32_t* tt = reinterpret_cast<int32_t*>(
+        w + g_bytes + (((VN * sizeof(rade_splat)) + 255) & ~size_t(255)));
+    const hipError_t e = rade::launch_project(*s, views_dev, V, N, means, scales, quats,
+                                              opacities, sh, rs, tt, st);
+    if (e != hipSuccess) return RADE_ERR_HIP;
+    splats = rs;
+  }
+  const int64_t tiles = total_tiles(views_host, V);
+  hipError_t e = rade::launch_render_bwd(*s, views_dev, V, N, tiles, splats, pair_ids,
+                                         tile_ranges, t_final, last, median, d_color, d_depth,
+                                         d_normal, d_alpha, gsplat, st);
+  if (e != hipSuccess) return RADE_ERR_HIP;
+  e = rade::launch_project_bwd(*s, views_dev, V, N, means, scales, quats, opacities, sh, gsplat,
+                               d_means, d_scales, d_quats, d_opacities, d_sh, st);
+  return hip_status(e);
+}
+
+}  // extern "C"

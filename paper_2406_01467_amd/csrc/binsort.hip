@@ -1,0 +1,481 @@
+// Binning of splats into screen tiles and the sort that orders each tile's
+// list by depth (gfx950).
+//
+// RaDe-GS blends splats in the order of their centre depth (Sec. 3.1, the
+// sort before Eq. 3).  Each tile's list must hold every splat whose support
+// rect touches the tile, ordered by (float32 depth, Gaussian id).  Instead of
+// one long radix sort over (tile, depth) 64-bit keys, the visible splats are
+// first sorted by depth (V*N items, 4 passes of 8 bits), then their pairs are
+// emitted in that order and stably sorted by tile (M items, ceil(log2 T)/8
+// passes).  Both sorts are stable, so the result equals the stable sort of
+// the 64-bit keys (tile << 32 | bits(z)) over pairs emitted in Gaussian
+// order, at a fraction of the passes over the (larger) pair array.
+//
+// All item counts that depend on the data live in device memory; every
+// kernel is launched with a grid sized for the capacity and its surplus
+// blocks exit, so the whole sequence can be captured in a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace rade {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;                       // items per thread
+constexpr int kTile = kThreads * kItems;        // items per block (2048)
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of one value per thread (256 threads, 4 waves).
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds_waves, T& total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) lds_waves[wave] = x;
+  __syncthreads();
+  T pre = 0;
+  total = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const T s = lds_waves[w];
+    if (w < wave) pre += s;
+    total += s;
+  }
+  __syncthreads();
+  return pre + x - v;
+}
+
+// Inputs of the scans, as functors over the item index.
+struct FlagInput {  // 1 when the splat touches at least one tile
+  const int32_t* tt;
+  __device__ uint32_t operator()(int64_t i) const { return tt[i] > 0 ? 1u : 0u; }
+};
+struct GatherCount {  // tiles touched by the j-th depth-sorted splat
+  const int32_t* tt;
+  const uint32_t* vals;
+  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)tt[vals[j]]; }
+};
+struct PlainInput {
+  const uint32_t* a;
+  __device__ uint32_t operator()(int64_t i) const { return a[i]; }
+};
+
+// Phase 1: per-block sums.
+template <typename T, typename In>
+__global__ void __launch_bounds__(kThreads)
+k_scan_reduce(In in, int64_t n_max, const uint32_t* n_dev, T* block_sums) {
+  __shared__ T lw[kThreads / 64];
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k)
+    if (base + k < n) s += in(base + k);
+  T total;
+  block_exclusive_scan<T>(s, lw, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Phase 2: exclusive scan of the block sums in one block; writes the total.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_scan_top(T* block_sums, int64_t nb, T* total_out) {
+  __shared__ T lw[kThreads / 64];
+  T carry = 0;
+  for (int64_t base = 0; base < nb; base += kThreads) {
+    const int64_t i = base + threadIdx.x;
+    const T v = i < nb ? block_sums[i] : 0;
+    T tot;
+    const T ex = block_exclusive_scan<T>(v, lw, tot);
+    if (i < nb) block_sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+// Phase 3: per-block exclusive scan plus the block's offset.
+template <typename T, typename In>
+__global__ void __launch_bounds__(kThreads)
+k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, T* out) {
+  __shared__ T lw[kThreads / 64];
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  if ((int64_t)blockIdx.x * kTile >= n) return;  // uniform per block
+  T v[kItems];
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    v[k] = (base + k < n) ? in(base + k) : 0;
+    s += v[k];
+  }
+  T total;
+  T run = block_exclusive_scan<T>(s, lw, total) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compaction of visible splats with their depth keys.
+__global__ void __launch_bounds__(kThreads)
+k_compact(const int32_t* __restrict__ tt, const uint32_t* __restrict__ pos,
+          const rade_splat* __restrict__ splats, int64_t n, uint32_t* __restrict__ keys,
+          uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n || tt[i] <= 0) return;
+  const uint32_t p = pos[i];
+  keys[p] = __float_as_uint(splats[i].z);  // z > near > 0: bits order like values
+  vals[p] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort pass, 8-bit digit at `shift`, stable.
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
+  return (k >> shift) & (kRadix - 1);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+             int shift, int64_t nblocks, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = *n_dev;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[digit_of(keys[i], shift)], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scatter: stable local ranks by wave match masks, local sort in LDS, then
+// digit runs written out contiguously.
+__global__ void __launch_bounds__(kThreads)
+k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                const uint32_t* __restrict__ n_dev, int shift, int64_t nblocks,
+                const uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t cnt[kRadix];                 // running per-digit count in this block
+  __shared__ uint32_t wcnt[kThreads / 64][kRadix]; // per-round per-wave counts
+  __shared__ uint32_t lstart[kRadix];
+  __shared__ uint32_t skey[kTile];
+  __shared__ uint32_t sval[kTile];
+  __shared__ uint32_t lw[kThreads / 64];
+  const int64_t n = *n_dev;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  if (base >= n) return;  // uniform per block
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  cnt[threadIdx.x] = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
+  __syncthreads();
+
+  uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    const bool valid = i < n;
+    key[r] = valid ? kin[i] : 0u;
+    val[r] = valid ? vin[i] : 0u;
+    const uint32_t d = digit_of(key[r], shift);
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const uint32_t lr = (uint32_t)__popcll(peers & lt);
+    if (valid && lr == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    uint32_t pre = cnt[d];
+    for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+    rank[r] = pre + lr;
+    __syncthreads();
+    {
+      uint32_t add = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) {
+        add += wcnt[w][threadIdx.x];
+        wcnt[w][threadIdx.x] = 0;
+      }
+      cnt[threadIdx.x] += add;
+    }
+    __syncthreads();
+  }
+  // local digit starts
+  {
+    uint32_t tot;
+    lstart[threadIdx.x] = block_exclusive_scan<uint32_t>(cnt[threadIdx.x], lw, tot);
+  }
+  __syncthreads();
+  const int64_t nb = (n - base) < kTile ? (n - base) : kTile;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    if (i < n) {
+      const uint32_t lp = lstart[digit_of(key[r], shift)] + rank[r];
+      skey[lp] = key[r];
+      sval[lp] = val[r];
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < nb; i += kThreads) {
+    const uint32_t k = skey[i];
+    const uint32_t d = digit_of(k, shift);
+    const uint64_t dst = (uint64_t)offsets[(int64_t)d * nblocks + blockIdx.x] + (uint64_t)(i - lstart[d]);
+    kout[dst] = k;
+    vout[dst] = sval[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair emission: the j-th depth-sorted splat writes its tiles at offs[j].
+__global__ void __launch_bounds__(kThreads)
+k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
+       const uint32_t* __restrict__ n_dev, const uint64_t* __restrict__ m_dev,
+       int64_t capacity, const int32_t* __restrict__ tt, const rade_splat* __restrict__ splats,
+       const rade_view* __restrict__ views, int64_t N, int tile_w, int tile_h,
+       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= (int64_t)*n_dev || *m_dev > (uint64_t)capacity) return;
+  const uint32_t i = svals[j];
+  const int v = (int)(i / (uint64_t)N);
+  const uint32_t g = (uint32_t)(i - (uint64_t)v * N);
+  const rade_splat& s = splats[i];
+  const int tx0 = s.rect[0] / tile_w, tx1 = s.rect[1] / tile_w;
+  const int ty0 = s.rect[2] / tile_h, ty1 = s.rect[3] / tile_h;
+  const rade_view& vw = views[v];
+  const uint32_t tbase = (uint32_t)vw.tile_offset;
+  uint64_t o = offs[j];
+  // never write past this splat's slot (tiles_touched computed for another
+  // tile size) or past the capacity
+  const uint64_t end = min(o + (uint64_t)max(tt[i], 0), (uint64_t)capacity);
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      if (o >= end) return;
+      tkeys[o] = tbase + (uint32_t)(ty * vw.tiles_x + tx);
+      pids[o] = g;
+      ++o;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_fill_u32(uint32_t* __restrict__ a, int64_t n, uint32_t value) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) a[i] = value;
+}
+
+__global__ void k_finish_counts(const uint64_t* __restrict__ m_dev, int64_t capacity,
+                                uint32_t* __restrict__ m32, int64_t* __restrict__ n_pairs_out) {
+  const uint64_t m = *m_dev;
+  *m32 = m > (uint64_t)capacity ? 0u : (uint32_t)m;  // items the tile sort processes
+  *n_pairs_out = (int64_t)m;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32,
+         uint32_t* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t m = *m32;
+  if (i >= m) return;
+  const uint32_t t = tkeys[i];
+  if (i == 0 || tkeys[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
+  if (i == m - 1 || tkeys[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_keys(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ pids,
+       const uint32_t* __restrict__ m32, const rade_splat* __restrict__ splats,
+       const rade_view* __restrict__ views, int V, int64_t N, uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)*m32) return;
+  const uint32_t t = tkeys[i];
+  const int v = view_of_tile(views, V, t);
+  const float z = splats[(int64_t)v * N + pids[i]].z;
+  keys[i] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(z);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <typename T, typename In>
+hipError_t scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
+                hipStream_t st) {
+  const int64_t nb = n_max > 0 ? (n_max + kTile - 1) / kTile : 1;
+  hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3((unsigned)nb), dim3(kThreads), 0, st, in,
+                     n_max, n_dev, block_sums);
+  hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kThreads), 0, st, block_sums, nb, total);
+  hipLaunchKernelGGL((k_scan_down<T, In>), dim3((unsigned)nb), dim3(kThreads), 0, st, in, n_max,
+                     n_dev, block_sums, out);
+  return hipGetLastError();
+}
+
+// Sorts (keys, vals) of *n_dev items (at most n_max) by the low `bits` bits
+// of the keys; on return the sorted data are in (k0, v0) when the number of
+// passes is even, else in (k1, v1).  Returns the number of passes.
+int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
+               const uint32_t* n_dev, int bits, uint32_t* hist, uint32_t* hist_sums,
+               hipStream_t st) {
+  const int64_t nb = n_max > 0 ? (n_max + kTile - 1) / kTile : 1;
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * kRadixBits;
+    uint32_t* ki = (p & 1) ? k1 : k0;
+    uint32_t* vi = (p & 1) ? v1 : v0;
+    uint32_t* ko = (p & 1) ? k0 : k1;
+    uint32_t* vo = (p & 1) ? v0 : v1;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev, shift,
+                       nb, hist);
+    scan<uint32_t>(PlainInput{hist}, nb * kRadix, nullptr, hist, hist_sums, (uint32_t*)nullptr,
+                   st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                       n_dev, shift, nb, hist);
+  }
+  return passes;
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t vis_pos, dkeys0, dvals0, dkeys1, dvals1, offs, tkeys0, tkeys1, pids1, hist, sums, scal;
+  size_t total;
+};
+
+int ceil_log2(int64_t x) {
+  int b = 0;
+  while (((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+Layout layout(int64_t VN, int64_t capacity) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  const int64_t nmax = VN > capacity ? VN : capacity;
+  const int64_t nb = (nmax + kTile - 1) / kTile + 1;
+  const int64_t hist_n = nb * kRadix;
+  const int64_t scan_n = (hist_n > nmax ? hist_n : nmax);
+  L.vis_pos = take(sizeof(uint32_t) * VN);
+  L.dkeys0 = take(sizeof(uint32_t) * VN);
+  L.dvals0 = take(sizeof(uint32_t) * VN);
+  L.dkeys1 = take(sizeof(uint32_t) * VN);
+  L.dvals1 = take(sizeof(uint32_t) * VN);
+  L.offs = take(sizeof(uint64_t) * VN);
+  L.tkeys0 = take(sizeof(uint32_t) * capacity);
+  L.tkeys1 = take(sizeof(uint32_t) * capacity);
+  L.pids1 = take(sizeof(uint32_t) * capacity);
+  L.hist = take(sizeof(uint32_t) * hist_n);
+  L.sums = take(sizeof(uint64_t) * ((scan_n + kTile - 1) / kTile + 1));
+  L.scal = take(64);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+size_t bin_sort_workspace(int64_t VN, int64_t capacity) { return layout(VN, capacity).total; }
+
+hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
+                           const rade_view* views_dev, int V, int64_t N,
+                           const rade_splat* splats, const int32_t* tt, uint32_t* pair_ids,
+                           uint32_t* ranges, uint64_t* keys, int64_t capacity,
+                           int64_t* n_pairs_dev, int64_t* n_pairs_host, void* ws,
+                           hipStream_t st, int* capacity_exceeded) {
+  *capacity_exceeded = 0;
+  const int64_t VN = (int64_t)V * N;
+  const Layout L = layout(VN, capacity);
+  char* w = static_cast<char*>(ws);
+  uint32_t* vis_pos = (uint32_t*)(w + L.vis_pos);
+  uint32_t* dk0 = (uint32_t*)(w + L.dkeys0);
+  uint32_t* dv0 = (uint32_t*)(w + L.dvals0);
+  uint32_t* dk1 = (uint32_t*)(w + L.dkeys1);
+  uint32_t* dv1 = (uint32_t*)(w + L.dvals1);
+  uint64_t* offs = (uint64_t*)(w + L.offs);
+  uint32_t* tk0 = (uint32_t*)(w + L.tkeys0);
+  uint32_t* tk1 = (uint32_t*)(w + L.tkeys1);
+  uint32_t* pid1 = (uint32_t*)(w + L.pids1);
+  uint32_t* hist = (uint32_t*)(w + L.hist);
+  void* sums = (void*)(w + L.sums);
+  uint32_t* n_vis = (uint32_t*)(w + L.scal);
+  uint64_t* m64 = (uint64_t*)(w + L.scal + 8);
+  uint32_t* m32 = (uint32_t*)(w + L.scal + 16);
+
+  int64_t total_tiles = 0;
+  for (int v = 0; v < V; ++v)
+    total_tiles += (int64_t)views_host[v].tiles_x * views_host[v].tiles_y;
+
+  // 1. visible splats -> compact (depth key, index) list
+  if (VN > 0) {
+    scan<uint32_t>(FlagInput{tt}, VN, nullptr, vis_pos, (uint32_t*)sums, n_vis, st);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(VN, kThreads)), dim3(kThreads), 0, st, tt,
+                       vis_pos, splats, VN, dk0, dv0);
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, n_vis, 1, 0u);
+  }
+  // 2. depth sort
+  const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, hist, (uint32_t*)sums, st);
+  uint32_t* sv = (dpasses & 1) ? dv1 : dv0;
+  // 3. pair offsets in depth order
+  if (VN > 0) {
+    scan<uint64_t>(GatherCount{tt, sv}, VN, n_vis, offs, (uint64_t*)sums, m64, st);
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, (uint32_t*)m64, 2, 0u);
+  }
+  hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(1), 0, st, m64, capacity, m32, n_pairs_dev);
+  if (n_pairs_host) {
+    hipError_t e = hipMemcpyAsync(n_pairs_host, n_pairs_dev, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (*n_pairs_host > capacity) {
+      *capacity_exceeded = 1;
+      hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * total_tiles, kThreads)), dim3(kThreads),
+                         0, st, ranges, 2 * total_tiles, 0u);
+      return hipGetLastError();
+    }
+  }
+  // 4. emit pairs; the tile sort's passes alternate buffers, so emit into
+  // the buffer that makes the last pass land in pair_ids.
+  const int tbits = total_tiles > 1 ? ceil_log2(total_tiles) : 1;
+  const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
+  uint32_t* ek = tk0;
+  uint32_t* ev = (tpasses & 1) ? pid1 : pair_ids;
+  uint32_t* ok_ = tk1;
+  uint32_t* ov = (tpasses & 1) ? pair_ids : pid1;
+  if (VN > 0)
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(VN, kThreads)), dim3(kThreads), 0, st, sv, offs,
+                       n_vis, m64, capacity, tt, splats, views_dev, N, s.tile_w, s.tile_h, ek, ev);
+  // 5. stable sort by tile
+  radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, hist, (uint32_t*)sums, st);
+  uint32_t* sk = (tpasses & 1) ? ok_ : ek;
+  // 6. tile ranges
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * total_tiles, kThreads)), dim3(kThreads), 0,
+                     st, ranges, 2 * total_tiles, 0u);
+  if (capacity > 0)
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(capacity, kThreads)), dim3(kThreads), 0, st, sk,
+                       m32, ranges);
+  // 7. optional 64-bit keys
+  if (keys && capacity > 0)
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(capacity, kThreads)), dim3(kThreads), 0, st, sk,
+                       pair_ids, m32, splats, views_dev, V, N, keys);
+  return hipGetLastError();
+}
+
+}  // namespace rade

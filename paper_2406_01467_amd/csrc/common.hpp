@@ -1,0 +1,93 @@
+// Shared device-side definitions of the RaDe-GS rasterizer library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rade.h"
+
+namespace rade {
+
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kLog2eD = 1.4426950408889634;
+
+static_assert(sizeof(rade_splat) == 80, "splat record must be 80 bytes");
+static_assert(sizeof(rade_view) == 96, "view record must be 96 bytes");
+
+// Render thresholds in the precision the blend loop uses.  Shared by the
+// forward and the backward kernels so both take identical decisions.
+struct BlendParams {
+  float cut2;        // power_cut * log2(e): skip when the factored power exceeds it
+  float alpha_min;
+  float alpha_max;
+  float t_min;
+  float bg[3];
+};
+
+inline BlendParams make_blend_params(const rade_settings& s) {
+  BlendParams b;
+  b.cut2 = (float)(s.power_cut * kLog2eD);
+  b.alpha_min = (float)s.alpha_min;
+  b.alpha_max = (float)s.alpha_max;
+  b.t_min = (float)s.t_min;
+  for (int i = 0; i < 3; ++i) b.bg[i] = (float)s.bg[i];
+  return b;
+}
+
+// Splat as staged in LDS for one tile: centre relative to the tile's first
+// pixel centre, factored quadratic form, opacity, depth, colour, plane,
+// normal.  64 bytes = 4 x 16-byte broadcast reads.
+struct alignas(16) StagedSplat {
+  float ur, vr, w0, w1;
+  float w2, w3, o, z;
+  float r, g, b, p0;
+  float p1, n0, n1, n2;
+};
+
+// alpha of a splat at offset (dx, dy) = (u_c - u, v_c - v).  Returns false
+// when the splat is skipped (outside the cut or below alpha_min).  The
+// forward and backward kernels both call exactly this function, compiled
+// without floating-point contraction, so their decisions match bit for bit.
+__device__ __forceinline__ bool splat_alpha(const StagedSplat& s, float dx, float dy,
+                                            const BlendParams& bp, float& t1, float& t2,
+                                            float& e, float& alpha, bool& clamped) {
+  t1 = fmaf(s.w0, dx, s.w1 * dy);
+  t2 = fmaf(s.w2, dx, s.w3 * dy);
+  const float pw = fmaf(t1, t1, t2 * t2);
+  if (pw > bp.cut2) return false;
+  e = __builtin_amdgcn_exp2f(-pw);
+  const float raw = s.o * e;
+  clamped = raw > bp.alpha_max;
+  alpha = clamped ? bp.alpha_max : raw;
+  return alpha >= bp.alpha_min;
+}
+
+// Tile of a global tile index: linear search over the (few) views.
+__device__ __forceinline__ int view_of_tile(const rade_view* views, int V, int64_t tile) {
+  int v = 0;
+  while (v + 1 < V && views[v + 1].tile_offset <= tile) ++v;
+  return v;
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// Optional events recorded around the launches of one kernel kind (set by
+// rade_set_kernel_events).
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+KernelEvents& kernel_events(int kernel);
+
+struct EventScope {
+  hipStream_t st;
+  KernelEvents& ev;
+  EventScope(int kernel, hipStream_t s) : st(s), ev(kernel_events(kernel)) {
+    if (ev.start) (void)hipEventRecord(ev.start, st);
+  }
+  ~EventScope() {
+    if (ev.stop) (void)hipEventRecord(ev.stop, st);
+  }
+};
+
+}  // namespace rade

@@ -1,0 +1,620 @@
+// Projection of 3D Gaussians to screen-space splats and its adjoint (gfx950).
+//
+// One lane per Gaussian; the lane loops over the views so the parameters
+// (up to 59 floats) are read from HBM once per batch of views.  The geometry
+// is evaluated in FP64: the splat centre must be known to well under 1e-5 px
+// for 1e-5 agreement of the blended maps at 1600 px images, which FP32
+// (ulp(1600) = 1.2e-4) cannot provide.  MI355X runs FP64 FMA at the rate of
+// FP32 non-packed FMA, and this kernel is bound by memory traffic.
+//
+// Math (RaDe-GS, arXiv 2406.01467):
+//   Sigma = R S S^T R^T (Eq. 1); ray-space covariance Sigma' = J W Sigma W^T
+//   J^T (Eq. 2) with the local affine Jacobian J of the map
+//   x -> (fx x/z + cx, fy y/z + cy, |x|) (Sec. 3.2.2).  Written here as
+//   Sigma' = T T^T with T = J (W R_g) diag(s).
+//   Footprint B = Sigma'[0:2,0:2] + dilation I; plane slope
+//   q = -Sigma'[0:2,0:2]^-1 Sigma'[0:2,2], which equals the first two entries
+//   of v'^T Sigma'^-1 / (v'^T Sigma'^-1 v') (Eq. 13) by the Schur complement;
+//   p = (z_c / t_c) q (Eq. 15-17); n = normalize(J^T (-(q, 1))) (Eq. 21-22).
+#include "common.hpp"
+
+namespace rade {
+namespace {
+
+// Real SH basis up to degree 3 (16 values), Condon-Shortley phase, order
+// m = -l..l.  Constants: 1/(2 sqrt(pi)); sqrt(3/(4 pi)); sqrt(15/pi)/2,
+// sqrt(5/pi)/4, sqrt(15/pi)/4; sqrt(35/(2 pi))/4, sqrt(105/pi)/2,
+// sqrt(21/(2 pi))/4, sqrt(7/pi)/4, sqrt(105/pi)/4.
+constexpr double kY0 = 0.28209479177387814;
+constexpr double kY1 = 0.48860251190291992;
+constexpr double kY2a = 1.0925484305920792;
+constexpr double kY2b = 0.31539156525252005;
+constexpr double kY2c = 0.54627421529603959;
+constexpr double kY3a = 0.59004358992664352;
+constexpr double kY3b = 2.8906114426405538;
+constexpr double kY3c = 0.45704579946446572;
+constexpr double kY3d = 0.37317633259011546;
+constexpr double kY3e = 1.4453057213202769;
+
+__device__ __forceinline__ void sh_basis(int deg, double x, double y, double z, double* Y) {
+  Y[0] = kY0;
+  if (deg < 1) return;
+  Y[1] = -kY1 * y;
+  Y[2] = kY1 * z;
+  Y[3] = -kY1 * x;
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double xy = x * y, yz = y * z, xz = x * z;
+  Y[4] = kY2a * xy;
+  Y[5] = -kY2a * yz;
+  Y[6] = kY2b * (2.0 * zz - xx - yy);
+  Y[7] = -kY2a * xz;
+  Y[8] = kY2c * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -kY3a * y * (3.0 * xx - yy);
+  Y[10] = kY3b * xy * z;
+  Y[11] = -kY3c * y * (4.0 * zz - xx - yy);
+  Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -kY3c * x * (4.0 * zz - xx - yy);
+  Y[14] = kY3e * z * (xx - yy);
+  Y[15] = -kY3a * x * (xx - 3.0 * yy);
+}
+
+// Gradient of sum_k c_k Y_k(x, y, z) with respect to (x, y, z) (unit sphere
+// constraint not applied).
+__device__ __forceinline__ void sh_grad(int deg, double x, double y, double z, const double* c,
+                                        double* g) {
+  g[0] = g[1] = g[2] = 0.0;
+  if (deg < 1) return;
+  g[0] += -kY1 * c[3];
+  g[1] += -kY1 * c[1];
+  g[2] += kY1 * c[2];
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  g[0] += kY2a * y * c[4] - kY2a * z * c[7] - 2.0 * kY2b * x * c[6] + 2.0 * kY2c * x * c[8];
+  g[1] += kY2a * x * c[4] - kY2a * z * c[5] - 2.0 * kY2b * y * c[6] - 2.0 * kY2c * y * c[8];
+  g[2] += -kY2a * y * c[5] + 4.0 * kY2b * z * c[6] - kY2a * x * c[7];
+  if (deg < 3) return;
+  // Y9 = -a y (3xx - yy)
+  g[0] += -kY3a * 6.0 * x * y * c[9];
+  g[1] += -kY3a * (3.0 * xx - 3.0 * yy) * c[9];
+  // Y10 = b x y z
+  g[0] += kY3b * y * z * c[10];
+  g[1] += kY3b * x * z * c[10];
+  g[2] += kY3b * x * y * c[10];
+  // Y11 = -c y (4zz - xx - yy)
+  g[0] += kY3c * 2.0 * x * y * c[11];
+  g[1] += -kY3c * (4.0 * zz - xx - 3.0 * yy) * c[11];
+  g[2] += -kY3c * 8.0 * y * z * c[11];
+  // Y12 = d z (2zz - 3xx - 3yy)
+  g[0] += -kY3d * 6.0 * x * z * c[12];
+  g[1] += -kY3d * 6.0 * y * z * c[12];
+  g[2] += kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * c[12];
+  // Y13 = -c x (4zz - xx - yy)
+  g[0] += -kY3c * (4.0 * zz - 3.0 * xx - yy) * c[13];
+  g[1] += kY3c * 2.0 * x * y * c[13];
+  g[2] += -kY3c * 8.0 * x * z * c[13];
+  // Y14 = e z (xx - yy)
+  g[0] += kY3e * 2.0 * x * z * c[14];
+  g[1] += -kY3e * 2.0 * y * z * c[14];
+  g[2] += kY3e * (xx - yy) * c[14];
+  // Y15 = -a x (xx - 3yy)
+  g[0] += -kY3a * (3.0 * xx - 3.0 * yy) * c[15];
+  g[1] += kY3a * 6.0 * x * y * c[15];
+}
+
+struct ViewD {
+  double R[9], t[3], fx, fy, cx, cy, limx, limy, C[3];
+  int W, H, tiles_x;
+};
+
+__device__ __forceinline__ ViewD load_view(const rade_view& v, double fov_clamp) {
+  ViewD o;
+  for (int i = 0; i < 9; ++i) o.R[i] = (double)v.R[i];
+  for (int i = 0; i < 3; ++i) o.t[i] = (double)v.t[i];
+  o.fx = v.fx; o.fy = v.fy; o.cx = v.cx; o.cy = v.cy;
+  o.W = v.width; o.H = v.height; o.tiles_x = v.tiles_x;
+  o.limx = fov_clamp * (double)v.width / (2.0 * o.fx);
+  o.limy = fov_clamp * (double)v.height / (2.0 * o.fy);
+  // camera centre in world coordinates: C = -R^T t
+  for (int i = 0; i < 3; ++i)
+    o.C[i] = -(o.R[i] * o.t[0] + o.R[3 + i] * o.t[1] + o.R[6 + i] * o.t[2]);
+  return o;
+}
+
+// Everything the forward computes for one (view, Gaussian) and the backward
+// needs again.
+struct Geo {
+  double X, Y, Z, tc;
+  double J0[3], J1[3], J2[3];   // rows of J
+  bool clx, cly;
+  double xi, eta;
+  double Wm[9];                 // W R_g diag(s): column k = (W R_g)[:,k] * s_k
+  double T[9];                  // J Wm
+  double B00, B01, B11, b0, b1; // Sigma' entries (undilated footprint and coupling)
+  double D00, D11;              // dilated diagonal (D01 = B01)
+  double detD;
+  bool degenerate;
+  double q0, q1;
+  double nr[3], nlen;
+};
+
+struct Params {
+  double mu[3], s[3], qn[4], qinv, Rg[9];
+  float o;
+};
+
+__device__ __forceinline__ bool finitef(float x) { return isfinite(x); }
+
+// Quaternion (w,x,y,z), unit -> rotation matrix (row-major).
+__device__ __forceinline__ void quat_to_mat(const double* q, double* Rm) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+  Rm[0] = 1.0 - 2.0 * (yy + zz); Rm[1] = 2.0 * (xy - wz);        Rm[2] = 2.0 * (xz + wy);
+  Rm[3] = 2.0 * (xy + wz);        Rm[4] = 1.0 - 2.0 * (xx + zz); Rm[5] = 2.0 * (yz - wx);
+  Rm[6] = 2.0 * (xz - wy);        Rm[7] = 2.0 * (yz + wx);        Rm[8] = 1.0 - 2.0 * (xx + yy);
+}
+
+// Camera-space centre; products of two FP32 numbers are exact in FP64, so the
+// left-to-right summation fixes the result bit for bit.
+__device__ __forceinline__ void cam_centre(const ViewD& v, const double* mu, double* x) {
+  for (int i = 0; i < 3; ++i) {
+    double a = __dmul_rn(v.R[3 * i + 0], mu[0]);
+    a = __dadd_rn(a, __dmul_rn(v.R[3 * i + 1], mu[1]));
+    a = __dadd_rn(a, __dmul_rn(v.R[3 * i + 2], mu[2]));
+    x[i] = __dadd_rn(a, v.t[i]);
+  }
+}
+
+// Forward geometry of one (view, Gaussian); false when culled by depth.
+__device__ bool geometry(const ViewD& v, const Params& P, const rade_settings& st, Geo& G) {
+  double x[3];
+  cam_centre(v, P.mu, x);
+  G.X = x[0]; G.Y = x[1]; G.Z = x[2];
+  if (!(G.Z > st.near_plane)) return false;
+  G.tc = sqrt(G.X * G.X + G.Y * G.Y + G.Z * G.Z);
+  const double iz = 1.0 / G.Z;
+  double xi = G.X * iz, eta = G.Y * iz;
+  G.clx = xi < -v.limx || xi > v.limx;
+  G.cly = eta < -v.limy || eta > v.limy;
+  xi = fmin(v.limx, fmax(-v.limx, xi));
+  eta = fmin(v.limy, fmax(-v.limy, eta));
+  G.xi = xi; G.eta = eta;
+  G.J0[0] = v.fx * iz; G.J0[1] = 0.0; G.J0[2] = -v.fx * xi * iz;
+  G.J1[0] = 0.0; G.J1[1] = v.fy * iz; G.J1[2] = -v.fy * eta * iz;
+  const double it = 1.0 / G.tc;
+  G.J2[0] = G.X * it; G.J2[1] = G.Y * it; G.J2[2] = G.Z * it;
+  // Wm = (R_world * R_g) diag(s)
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      const double a = v.R[3 * i + 0] * P.Rg[0 + k] + v.R[3 * i + 1] * P.Rg[3 + k] +
+                       v.R[3 * i + 2] * P.Rg[6 + k];
+      G.Wm[3 * i + k] = a * P.s[k];
+    }
+  // T = J Wm
+  const double* Jr[3] = {G.J0, G.J1, G.J2};
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k)
+      G.T[3 * j + k] = Jr[j][0] * G.Wm[k] + Jr[j][1] * G.Wm[3 + k] + Jr[j][2] * G.Wm[6 + k];
+  const double* T0 = G.T;
+  const double* T1 = G.T + 3;
+  const double* T2 = G.T + 6;
+  G.B00 = T0[0] * T0[0] + T0[1] * T0[1] + T0[2] * T0[2];
+  G.B01 = T0[0] * T1[0] + T0[1] * T1[1] + T0[2] * T1[2];
+  G.B11 = T1[0] * T1[0] + T1[1] * T1[1] + T1[2] * T1[2];
+  G.b0 = T0[0] * T2[0] + T0[1] * T2[1] + T0[2] * T2[2];
+  G.b1 = T1[0] * T2[0] + T1[1] * T2[1] + T1[2] * T2[2];
+  G.D00 = G.B00 + st.dilation;
+  G.D11 = G.B11 + st.dilation;
+  G.detD = G.D00 * G.D11 - G.B01 * G.B01;
+  // plane slope q (Schur form of Eq. 13)
+  const double det0 = G.B00 * G.B11 - G.B01 * G.B01;
+  const double tr0 = G.B00 + G.B11;
+  G.degenerate = !(det0 > st.degenerate * tr0 * tr0);
+  if (G.degenerate) {
+    G.q0 = 0.0; G.q1 = 0.0;
+  } else {
+    const double id = 1.0 / det0;
+    G.q0 = -(G.B11 * G.b0 - G.B01 * G.b1) * id;
+    G.q1 = -(G.B00 * G.b1 - G.B01 * G.b0) * id;
+  }
+  for (int k = 0; k < 3; ++k) G.nr[k] = -(G.q0 * G.J0[k] + G.q1 * G.J1[k] + G.J2[k]);
+  G.nlen = sqrt(G.nr[0] * G.nr[0] + G.nr[1] * G.nr[1] + G.nr[2] * G.nr[2]);
+  return true;
+}
+
+__device__ __forceinline__ bool load_params(int64_t g, const float* means, const float* scales,
+                                            const float* quats, const float* opac, Params& P) {
+  const float m0 = means[3 * g], m1 = means[3 * g + 1], m2 = means[3 * g + 2];
+  const float s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
+  const float4 q = *reinterpret_cast<const float4*>(quats + 4 * g);
+  const float o = opac[g];
+  bool ok = finitef(m0) && finitef(m1) && finitef(m2) && finitef(s0) && finitef(s1) &&
+            finitef(s2) && finitef(q.x) && finitef(q.y) && finitef(q.z) && finitef(q.w) &&
+            finitef(o);
+  P.mu[0] = m0; P.mu[1] = m1; P.mu[2] = m2;
+  P.s[0] = s0; P.s[1] = s1; P.s[2] = s2;
+  P.o = o;
+  const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
+  const double qq = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  ok = ok && qq > 0.0 && (255.0 * (double)o > 1.0);
+  P.qinv = ok ? 1.0 / qq : 0.0;
+  P.qn[0] = qw * P.qinv; P.qn[1] = qx * P.qinv; P.qn[2] = qy * P.qinv; P.qn[3] = qz * P.qinv;
+  quat_to_mat(P.qn, P.Rg);
+  return ok;
+}
+
+__device__ __forceinline__ void store_invisible(rade_splat* out) {
+  rade_splat s = {};
+  s.rect[0] = 0; s.rect[1] = -1; s.rect[2] = 0; s.rect[3] = -1;
+  *out = s;
+}
+
+template <int KMAX>
+__global__ void __launch_bounds__(256)
+k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
+          const float* __restrict__ means, const float* __restrict__ scales,
+          const float* __restrict__ quats, const float* __restrict__ opac,
+          const float* __restrict__ sh, rade_splat* __restrict__ splats,
+          int32_t* __restrict__ tiles_touched) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int deg = st.sh_degree;
+  const int K = (deg + 1) * (deg + 1);
+  Params P;
+  bool ok = load_params(g, means, scales, quats, opac, P);
+  float coef[3 * KMAX];
+#pragma unroll
+  for (int i = 0; i < 3 * KMAX; ++i) {
+    coef[i] = (i < 3 * K) ? sh[3 * K * g + i] : 0.0f;
+    ok = ok && finitef(coef[i]);
+  }
+  for (int vi = 0; vi < V; ++vi) {
+    const int64_t o = (int64_t)vi * N + g;
+    const ViewD v = load_view(views[vi], st.fov_clamp);
+    Geo G;
+    if (!ok || !geometry(v, P, st, G) || !(G.detD > 0.0)) {
+      store_invisible(splats + o);
+      tiles_touched[o] = 0;
+      continue;
+    }
+    rade_splat out;
+    out.uc = v.fx * G.X / G.Z + v.cx;
+    out.vc = v.fy * G.Y / G.Z + v.cy;
+    // Eigen-factored quadratic form of the dilated footprint.
+    {
+      const double m = 0.5 * (G.D00 + G.D11);
+      const double h = 0.5 * (G.D00 - G.D11);
+      const double r = sqrt(h * h + G.B01 * G.B01);
+      const double l1 = m + r;
+      const double l2 = G.detD / l1;
+      double ex, ey;
+      if (r == 0.0) {
+        ex = 1.0; ey = 0.0;
+      } else if (h >= 0.0) {
+        // (l1 - D11, B01) is well conditioned when D00 >= D11
+        ex = l1 - G.D11; ey = G.B01;
+      } else {
+        ex = G.B01; ey = l1 - G.D00;
+      }
+      const double en = 1.0 / sqrt(ex * ex + ey * ey);
+      ex *= en; ey *= en;
+      const double k1 = sqrt(kLog2eD / (2.0 * l1));
+      const double k2 = sqrt(kLog2eD / (2.0 * l2));
+      out.w[0] = (float)(ex * k1); out.w[1] = (float)(ey * k1);
+      out.w[2] = (float)(-ey * k2); out.w[3] = (float)(ex * k2);
+    }
+    out.opacity = P.o;
+    out.z = (float)G.Z;
+    const double zt = G.Z / G.tc;
+    out.p[0] = (float)(zt * G.q0);
+    out.p[1] = (float)(zt * G.q1);
+    const double inl = 1.0 / G.nlen;
+    out.n[0] = (float)(G.nr[0] * inl);
+    out.n[1] = (float)(G.nr[1] * inl);
+    out.n[2] = (float)(G.nr[2] * inl);
+    // colour
+    {
+      double d[3] = {P.mu[0] - v.C[0], P.mu[1] - v.C[1], P.mu[2] - v.C[2]};
+      const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double Y[16];
+      sh_basis(deg, d[0] * idn, d[1] * idn, d[2] * idn, Y);
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K) acc += (double)coef[3 * k + c] * Y[k];
+        out.rgb[c] = (float)fmax(acc + 0.5, 0.0);
+      }
+    }
+    // support rect: alpha >= alpha_min inside power <= tau
+    const double tau = fmin(st.power_cut, log(255.0 * (double)P.o));
+    const double rx = sqrt(2.0 * tau * G.D00) * (1.0 + 1e-6) + 1e-3;
+    const double ry = sqrt(2.0 * tau * G.D11) * (1.0 + 1e-6) + 1e-3;
+    const double xlo = (out.uc - rx) - 0.5, xhi = (out.uc + rx) - 0.5;
+    const double ylo = (out.vc - ry) - 0.5, yhi = (out.vc + ry) - 0.5;
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    if (isfinite(xlo) && isfinite(xhi) && isfinite(ylo) && isfinite(yhi) && xhi >= 0.0 &&
+        yhi >= 0.0 && xlo <= v.W - 1.0 && ylo <= v.H - 1.0) {
+      x0 = max(0, (int)ceil(fmax(xlo, -1.0)));
+      x1 = min(v.W - 1, (int)floor(fmin(xhi, (double)v.W)));
+      y0 = max(0, (int)ceil(fmax(ylo, -1.0)));
+      y1 = min(v.H - 1, (int)floor(fmin(yhi, (double)v.H)));
+    }
+    int32_t nt = 0;
+    if (x0 <= x1 && y0 <= y1) {
+      const int tx0 = x0 / st.tile_w, tx1 = x1 / st.tile_w;
+      const int ty0 = y0 / st.tile_h, ty1 = y1 / st.tile_h;
+      nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    } else {
+      x0 = 0; x1 = -1; y0 = 0; y1 = -1;
+    }
+    out.rect[0] = (int16_t)x0; out.rect[1] = (int16_t)x1;
+    out.rect[2] = (int16_t)y0; out.rect[3] = (int16_t)y1;
+    splats[o] = out;
+    tiles_touched[o] = nt;
+  }
+}
+
+// Gradient record of one (view, Gaussian) from the render backward:
+// du, dv, da, db, dc (conic), do, drgb[3], dz, dp[2], dn[3], pad.
+constexpr int kGradStride = 16;
+
+template <int KMAX>
+__global__ void __launch_bounds__(256)
+k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
+              const float* __restrict__ means, const float* __restrict__ scales,
+              const float* __restrict__ quats, const float* __restrict__ opac,
+              const float* __restrict__ sh, const float* __restrict__ gsplat,
+              float* __restrict__ d_means, float* __restrict__ d_scales,
+              float* __restrict__ d_quats, float* __restrict__ d_opac,
+              float* __restrict__ d_sh) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int deg = st.sh_degree;
+  const int K = (deg + 1) * (deg + 1);
+  Params P;
+  bool ok = load_params(g, means, scales, quats, opac, P);
+  double coef[3 * KMAX];
+  double gcoef[3 * KMAX];
+#pragma unroll
+  for (int i = 0; i < 3 * KMAX; ++i) {
+    coef[i] = (i < 3 * K) ? (double)sh[3 * K * g + i] : 0.0;
+    gcoef[i] = 0.0;
+    ok = ok && isfinite(coef[i]);
+  }
+  double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gqn[4] = {0, 0, 0, 0}, go = 0.0;
+  for (int vi = 0; ok && vi < V; ++vi) {
+    const float* gr = gsplat + ((int64_t)vi * N + g) * kGradStride;
+    const float4 ga = *reinterpret_cast<const float4*>(gr);
+    const float4 gb = *reinterpret_cast<const float4*>(gr + 4);
+    const float4 gc = *reinterpret_cast<const float4*>(gr + 8);
+    const float4 gd = *reinterpret_cast<const float4*>(gr + 12);
+    const double guc = ga.x, gvc = ga.y, gA = ga.z, gB = ga.w;
+    const double gC = gb.x, gO = gb.y, gR0 = gb.z, gR1 = gb.w;
+    const double gR2 = gc.x, gZd = gc.y, gp0 = gc.z, gp1 = gc.w;
+    const double gn0 = gd.x, gn1 = gd.y, gn2 = gd.z;
+    if (guc == 0.0 && gvc == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && gO == 0.0 &&
+        gR0 == 0.0 && gR1 == 0.0 && gR2 == 0.0 && gZd == 0.0 && gp0 == 0.0 && gp1 == 0.0 &&
+        gn0 == 0.0 && gn1 == 0.0 && gn2 == 0.0)
+      continue;
+    const ViewD v = load_view(views[vi], st.fov_clamp);
+    Geo G;
+    if (!geometry(v, P, st, G) || !(G.detD > 0.0)) continue;
+    go += gO;
+
+    // --- colour -> SH coefficients and the viewing direction
+    {
+      double d[3] = {P.mu[0] - v.C[0], P.mu[1] - v.C[1], P.mu[2] - v.C[2]};
+      const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double idn = 1.0 / dn;
+      const double u[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
+      double Y[16];
+      sh_basis(deg, u[0], u[1], u[2], Y);
+      double grgb[3] = {gR0, gR1, gR2};
+      double cw[16];
+      for (int k = 0; k < 16; ++k) cw[k] = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K) acc += coef[3 * k + c] * Y[k];
+        if (acc + 0.5 < 0.0) grgb[c] = 0.0;  // clamped channel
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K) {
+            gcoef[3 * k + c] += grgb[c] * Y[k];
+            cw[k] += grgb[c] * coef[3 * k + c];
+          }
+      }
+      double gu[3];
+      sh_grad(deg, u[0], u[1], u[2], cw, gu);
+      const double ud = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
+      for (int i = 0; i < 3; ++i) gmu[i] += (gu[i] - u[i] * ud) * idn;
+    }
+
+    const double X = G.X, Yc = G.Y, Z = G.Z, tc = G.tc;
+    const double iz = 1.0 / Z, iz2 = iz * iz;
+    double gx[3];
+    gx[0] = guc * v.fx * iz;
+    gx[1] = gvc * v.fy * iz;
+    gx[2] = -(guc * v.fx * X + gvc * v.fy * Yc) * iz2 + gZd;
+    // p = (Z / tc) q
+    double gq0 = Z / tc * gp0, gq1 = Z / tc * gp1;
+    const double pq = gp0 * G.q0 + gp1 * G.q1;
+    gx[2] += pq / tc;
+    double gtc = -Z * pq / (tc * tc);
+    // n = nr / |nr|, nr = -(q0 J0 + q1 J1 + J2)
+    double gJ0[3], gJ1[3], gJ2[3];
+    {
+      const double il = 1.0 / G.nlen;
+      const double n[3] = {G.nr[0] * il, G.nr[1] * il, G.nr[2] * il};
+      const double nd = n[0] * gn0 + n[1] * gn1 + n[2] * gn2;
+      const double gr[3] = {(gn0 - n[0] * nd) * il, (gn1 - n[1] * nd) * il,
+                            (gn2 - n[2] * nd) * il};
+      gq0 -= G.J0[0] * gr[0] + G.J0[1] * gr[1] + G.J0[2] * gr[2];
+      gq1 -= G.J1[0] * gr[0] + G.J1[1] * gr[1] + G.J1[2] * gr[2];
+      for (int k = 0; k < 3; ++k) {
+        gJ0[k] = -G.q0 * gr[k];
+        gJ1[k] = -G.q1 * gr[k];
+        gJ2[k] = -gr[k];
+      }
+    }
+    // Gradients of the symmetric Sigma' entries: g00, g11, g01 (the sum over
+    // both off-diagonal positions), gb0, gb1.
+    double g00 = 0.0, g11 = 0.0, g01 = 0.0, gb0 = 0.0, gb1 = 0.0;
+    if (!G.degenerate) {
+      const double det0 = G.B00 * G.B11 - G.B01 * G.B01;
+      const double id = 1.0 / det0;
+      // h = B0^-1 gq
+      const double h0 = (G.B11 * gq0 - G.B01 * gq1) * id;
+      const double h1 = (G.B00 * gq1 - G.B01 * gq0) * id;
+      g00 += -h0 * G.q0;
+      g11 += -h1 * G.q1;
+      g01 += -(h0 * G.q1 + h1 * G.q0);
+      gb0 = -h0;
+      gb1 = -h1;
+    }
+    // conic = D^-1 with D the dilated footprint: gD = -C Gc C.
+    {
+      const double idt = 1.0 / G.detD;
+      const double ca = G.D11 * idt, cb = -G.B01 * idt, cc = G.D00 * idt;
+      const double G00 = gA, G01 = 0.5 * gB, G11 = gC;
+      const double m00 = ca * G00 + cb * G01, m01 = ca * G01 + cb * G11;
+      const double m10 = cb * G00 + cc * G01, m11 = cb * G01 + cc * G11;
+      g00 += -(m00 * ca + m01 * cb);
+      g11 += -(m10 * cb + m11 * cc);
+      g01 += -((m00 * cb + m01 * cc) + (m10 * ca + m11 * cb));
+    }
+    // Sigma' entries as dot products of rows of T.
+    double gT[9];
+    for (int k = 0; k < 3; ++k) {
+      const double t0 = G.T[k], t1 = G.T[3 + k], t2 = G.T[6 + k];
+      gT[k] = 2.0 * g00 * t0 + g01 * t1 + gb0 * t2;
+      gT[3 + k] = 2.0 * g11 * t1 + g01 * t0 + gb1 * t2;
+      gT[6 + k] = gb0 * t0 + gb1 * t1;
+    }
+    // T = J Wm: gJ_j += gT_j Wm^T, gWm = J^T gT
+    double* gJr[3] = {gJ0, gJ1, gJ2};
+    const double* Jr[3] = {G.J0, G.J1, G.J2};
+    double gW[9];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) gW[3 * i + k] = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          acc += gT[3 * j + k] * G.Wm[3 * i + k];
+          gW[3 * i + k] += Jr[j][i] * gT[3 * j + k];
+        }
+        gJr[j][i] += acc;
+      }
+    // Wm = (R Rg) diag(s): gs_k, g(R Rg)
+    double gV[9];
+    for (int i = 0; i < 9; ++i) gV[i] = gW[i] * P.s[i % 3];
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        const double vik = v.R[3 * i] * P.Rg[k] + v.R[3 * i + 1] * P.Rg[3 + k] +
+                           v.R[3 * i + 2] * P.Rg[6 + k];
+        acc += gW[3 * i + k] * vik;
+      }
+      gs[k] += acc;
+    }
+    // gRg = R^T gV
+    double gRg[9];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 3; ++k)
+        gRg[3 * a + k] = v.R[a] * gV[k] + v.R[3 + a] * gV[3 + k] + v.R[6 + a] * gV[6 + k];
+    // rotation matrix -> unit quaternion
+    {
+      const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+      const double* r = gRg;
+      gqn[0] += 2.0 * (-z * r[1] + y * r[2] + z * r[3] - x * r[5] - y * r[6] + x * r[7]);
+      gqn[1] += 2.0 * (y * r[1] + z * r[2] + y * r[3] - 2.0 * x * r[4] - w * r[5] + z * r[6] +
+                       w * r[7] - 2.0 * x * r[8]);
+      gqn[2] += 2.0 * (-2.0 * y * r[0] + x * r[1] + w * r[2] + x * r[3] + z * r[5] - w * r[6] +
+                       z * r[7] - 2.0 * y * r[8]);
+      gqn[3] += 2.0 * (-2.0 * z * r[0] - w * r[1] + x * r[2] + w * r[3] - 2.0 * z * r[4] +
+                       y * r[5] + x * r[6] + y * r[7]);
+    }
+    // J(x): rows 0,1 (with the x/z, y/z clamps), row 2 = x / tc
+    gx[2] += -(gJ0[0] * v.fx + gJ1[1] * v.fy) * iz2;
+    if (G.clx) {
+      gx[2] += gJ0[2] * v.fx * G.xi * iz2;
+    } else {
+      gx[0] += -gJ0[2] * v.fx * iz2;
+      gx[2] += gJ0[2] * 2.0 * v.fx * X * iz2 * iz;
+    }
+    if (G.cly) {
+      gx[2] += gJ1[2] * v.fy * G.eta * iz2;
+    } else {
+      gx[1] += -gJ1[2] * v.fy * iz2;
+      gx[2] += gJ1[2] * 2.0 * v.fy * Yc * iz2 * iz;
+    }
+    {
+      const double it = 1.0 / tc;
+      const double xs[3] = {X * it, Yc * it, Z * it};
+      const double dd = gJ2[0] * xs[0] + gJ2[1] * xs[1] + gJ2[2] * xs[2];
+      for (int j = 0; j < 3; ++j) gx[j] += (gJ2[j] - xs[j] * dd) * it + gtc * xs[j];
+    }
+    // x = R mu + t
+    for (int i = 0; i < 3; ++i)
+      gmu[i] += v.R[i] * gx[0] + v.R[3 + i] * gx[1] + v.R[6 + i] * gx[2];
+  }
+  // unit quaternion -> raw quaternion
+  const double qd = P.qn[0] * gqn[0] + P.qn[1] * gqn[1] + P.qn[2] * gqn[2] + P.qn[3] * gqn[3];
+  float4 dq;
+  dq.x = (float)((gqn[0] - P.qn[0] * qd) * P.qinv);
+  dq.y = (float)((gqn[1] - P.qn[1] * qd) * P.qinv);
+  dq.z = (float)((gqn[2] - P.qn[2] * qd) * P.qinv);
+  dq.w = (float)((gqn[3] - P.qn[3] * qd) * P.qinv);
+  if (!ok) dq = make_float4(0.f, 0.f, 0.f, 0.f);
+  *reinterpret_cast<float4*>(d_quats + 4 * g) = dq;
+  for (int i = 0; i < 3; ++i) {
+    d_means[3 * g + i] = ok ? (float)gmu[i] : 0.0f;
+    d_scales[3 * g + i] = ok ? (float)gs[i] : 0.0f;
+  }
+  d_opac[g] = ok ? (float)go : 0.0f;
+  for (int i = 0; i < 3 * K; ++i) d_sh[3 * K * g + i] = ok ? (float)gcoef[i] : 0.0f;
+}
+
+}  // namespace
+
+hipError_t launch_project(const rade_settings& st, const rade_view* views, int V, int64_t N,
+                          const float* means, const float* scales, const float* quats,
+                          const float* opac, const float* sh, rade_splat* splats,
+                          int32_t* tiles_touched, hipStream_t stream) {
+  if (N == 0) return hipSuccess;
+  const dim3 block(256);
+  const dim3 grid((unsigned)((N + 255) / 256));
+  EventScope timing(RADE_KERNEL_PROJECT, stream);
+  switch (st.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<1>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
+    case 1: hipLaunchKernelGGL(k_project<4>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
+    case 2: hipLaunchKernelGGL(k_project<9>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
+    default: hipLaunchKernelGGL(k_project<16>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, int V, int64_t N,
+                              const float* means, const float* scales, const float* quats,
+                              const float* opac, const float* sh, const float* gsplat,
+                              float* d_means, float* d_scales, float* d_quats, float* d_opac,
+                              float* d_sh, hipStream_t stream) {
+  if (N == 0) return hipSuccess;
+  const dim3 block(256);
+  const dim3 grid((unsigned)((N + 255) / 256));
+  EventScope timing(RADE_KERNEL_PROJECT_BWD, stream);
+  switch (st.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<4>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<9>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
+    default: hipLaunchKernelGGL(k_project_bwd<16>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rade

@@ -1,0 +1,130 @@
+"""Helpers of the GPU parity tests: run the HIP path through the C ABI and the
+oracle on the same seeded inputs, and compare."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_01467_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        raise RuntimeError("librade.so missing: build before running GPU tests")
+    return torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_settings(s):
+    return oracle.settings(sh_degree=s.sh_degree, dilation=s.dilation, near=s.near_plane,
+                           alpha_min=s.alpha_min, alpha_max=s.alpha_max, t_min=s.t_min,
+                           power_cut=s.power_cut, fov_clamp=s.fov_clamp,
+                           degenerate=s.degenerate, bg=s.bg, tile=(s.tile_w, s.tile_h))
+
+
+def to_dev(scene, dev):
+    import torch
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    return (t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacities),
+            t(scene.sh.reshape(scene.n, scene.sh.shape[1] * 3)))
+
+
+def gpu_forward(scene, views, settings, dev, keep=True):
+    """Returns (rasterizer, maps, per-view numpy dicts)."""
+    import torch
+    from paper_2406_01467_amd.raster import Rasterizer
+    rast = Rasterizer(views, settings, dev)
+    params = to_dev(scene, dev)
+    maps = rast.forward(*params, want_count=True, keep_splats=keep)
+    torch.cuda.synchronize()
+    per_view = []
+    pair_ids = maps.state.pair_ids.cpu().numpy().astype(np.int64)
+    ranges = maps.state.ranges.cpu().numpy().astype(np.int64).reshape(-1, 2)
+    for vi, v in enumerate(views):
+        d = {k: t.cpu().numpy() for k, t in maps.view_planes(rast, vi).items()}
+        vc = rast.views_c[vi]
+        H, W = v.height, v.width
+        py, px = np.mgrid[0:H, 0:W]
+        tile = vc.tile_offset + (py // settings.tile_h) * vc.tiles_x + px // settings.tile_w
+        last = d["last"][0]
+        lid = np.where(last >= 0, pair_ids[np.clip(ranges[tile, 0] + last, 0,
+                                                    max(0, len(pair_ids) - 1))], -1)
+        d["last_id"] = lid
+        per_view.append(d)
+    return rast, maps, per_view, params
+
+
+def flat(a):
+    return np.asarray(a).reshape(a.shape[0], -1) if a.ndim == 3 else a.reshape(-1)
+
+
+def compare_maps(g, o, pixels=None, tol=1e-5, check_int=True, label=""):
+    """g: GPU per-view dict (C,H,W); o: oracle dict for the pixel list (or all
+    pixels).  Non-fragile pixels only.  Element-wise bound
+    |x - x_ref| <= tol (|x_ref| + 1e-3 max|x_ref|), and for the normal
+    components, whose terms cancel, tol (|x_ref| + 1e-3 max|x_ref| + alpha_ref).
+    Integer maps exact.  Returns the number of fragile pixels."""
+    frag = (o["fragile"] & 1) != 0
+    keep = ~frag
+
+    def gp(name, c=None):
+        a = g[name]
+        a = a.reshape(a.shape[0], -1)
+        a = a if pixels is None else a[:, pixels]
+        return a if c is None else a[c]
+
+    alpha_ref = np.asarray(o["alpha"], np.float64)[keep]
+    failures = []
+
+    def check(got, ref, what, cancelling=False):
+        got = np.asarray(got, np.float64)[keep]
+        ref = np.asarray(ref, np.float64)[keep]
+        if ref.size == 0:
+            return
+        floor = 1e-3 * np.abs(ref).max()
+        if cancelling:
+            # Sum of terms of both signs bounded by the blend weights: FP32
+            # round-off scales with sum |w_i f_i| <= sum w_i = alpha.
+            floor = floor + alpha_ref
+        err = np.abs(got - ref)
+        bound = tol * (np.abs(ref) + floor)
+        bad = err > bound
+        rel = err / (np.abs(ref) + floor + 1e-30)
+        i = int(np.argmax(rel))
+        if bad.any():
+            failures.append(f"{label}{what}: {bad.sum()} of {bad.size} pixels beyond "
+                            f"{tol}; worst rel {rel[i]:.3g} (ref {ref[i]:.6g} got {got[i]:.6g} "
+                            f"alpha {alpha_ref[i]:.4g} err/alpha "
+                            f"{err[i] / max(alpha_ref[i], 1e-30):.3g})")
+
+    for c in range(3):
+        check(gp("color", c), o["color"][:, c], f"color[{c}]")
+        check(gp("normal", c), o["normal"][:, c], f"normal[{c}]", cancelling=True)
+    check(gp("depth", 0), o["depth_exp"], "depth_exp")
+    check(gp("depth", 1), o["depth_med"], "depth_med")
+    check(gp("alpha", 0), o["alpha"], "alpha")
+    check(gp("t_final", 0), o["t_final"], "t_final")
+    if check_int:
+        for name, ref in (("count", o["count"]), ("median", o["median_id"])):
+            got = gp(name, 0)
+            mism = (got != ref) & keep
+            if mism.any():
+                failures.append(f"{label}{name}: {mism.sum()} mismatching pixels")
+        lid = g["last_id"].reshape(-1)
+        lid = lid if pixels is None else lid[pixels]
+        mism = (lid != o["last_id"]) & keep
+        if mism.any():
+            failures.append(f"{label}last_id: {mism.sum()} mismatching pixels")
+    for f in failures:
+        print(f, flush=True)
+    assert not failures, failures
+    return int(frag.sum())
