@@ -62,10 +62,15 @@ extern "C" {
 /* Rasterizer settings.  Quantities the paper leaves open default to the
  * values of the 3D Gaussian Splatting code base the paper builds on (it
  * states that it keeps that code base's default parameters, Sec. 4.1). */
+/* Work schedules of the tile kernels (rade_settings.schedule). */
+#define RADE_SCHEDULE_TILE 0        /* one workgroup per tile, natural order */
+#define RADE_SCHEDULE_HEAVY_FIRST 1 /* one workgroup per tile, longest lists first */
+#define RADE_SCHEDULE_PERSISTENT 2  /* resident workgroups pull tiles, longest first */
+
 typedef struct rade_settings {
-  int32_t tile_w, tile_h;  /* tile size in pixels: each a multiple of 8, product <= 1024 */
+  int32_t tile_w, tile_h;  /* tile size: 8x8, 16x8, 8x16, 16x16, 32x16 or 16x32 pixels */
   int32_t sh_degree;       /* 0..3 */
-  int32_t reserved;
+  int32_t schedule;        /* RADE_SCHEDULE_*; the last two need a tile order */
   double dilation;         /* added to the 2x2 footprint covariance, px^2 (0.3) */
   double near_plane;       /* Gaussians with camera z <= near are culled (0.2) */
   double alpha_min;        /* blends with alpha < alpha_min are skipped (1/255) */
@@ -155,6 +160,18 @@ int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
                   uint64_t* keys, int64_t capacity, int64_t* n_pairs_dev,
                   int64_t* n_pairs_host, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Workspace bytes for rade_tile_order over `total_tiles` tiles. */
+size_t rade_tile_order_workspace(int64_t total_tiles);
+
+/* Tile visiting order for the HEAVY_FIRST and PERSISTENT schedules: global
+ * tile indices sorted by decreasing list length (coarse: 16 buckets per
+ * octave of length, stable within a bucket).  tile_order has total_tiles + 1
+ * uint32 entries; the last one is scratch (the work-queue counter of the
+ * persistent kernels, reset by them before every launch). */
+int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t V,
+                    const uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
 /* Forward rendering (Eq. 3 applied to colour, the depth of Eq. 4, the normal
  * of Eq. 22 and alpha; median depth of Sec. 1).  For each pixel, splats of
  * its tile list are visited in order; a splat is skipped when its power
@@ -172,7 +189,8 @@ int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
  *   splat, -1 if none); count (int32, optional, may be NULL): splats blended. */
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
-                    const uint32_t* pair_ids, const uint32_t* tile_ranges, float* color,
+                    const uint32_t* pair_ids, const uint32_t* tile_ranges,
+                    uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
                     int32_t* median, int32_t* count, void* stream);
 
@@ -189,12 +207,13 @@ size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, i
  * tile lists.  splats may be NULL, in which case they are recomputed from
  * the parameters into the workspace.  The outputs d_means (N*3), d_scales
  * (N*3), d_quats (N*4), d_opacities (N), d_sh (N*K*3) are OVERWRITTEN with
- * the gradient summed over the V views. */
+ * the gradient summed over the V views.  tile_order as in rade_render_fwd. */
 int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const float* means,
                     const float* scales, const float* quats, const float* opacities,
                     const float* sh, const rade_splat* splats, const uint32_t* pair_ids,
-                    const uint32_t* tile_ranges, const float* t_final, const int32_t* last,
+                    const uint32_t* tile_ranges, uint32_t* tile_order,
+                    const float* t_final, const int32_t* last,
                     const int32_t* median, const float* d_color, const float* d_depth,
                     const float* d_normal, const float* d_alpha, float* d_means,
                     float* d_scales, float* d_quats, float* d_opacities, float* d_sh,

@@ -80,7 +80,7 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_project.argtypes = [P, P, ctypes.c_int, ctypes.c_int64] + [P] * 8
         lib.oracle_render.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P, P]
-        lib.oracle_render_bwd.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P]
+        lib.oracle_render_bwd.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P, P]
         lib.oracle_project_bwd.argtypes = [P, P, ctypes.c_int, ctypes.c_int64] + [P] * 11
         lib.oracle_bin.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                    P, P, P, P, ctypes.c_int64, P]
@@ -177,10 +177,14 @@ def render(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, pixels=None,
 
 
 def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np.ndarray,
-               pixels=None, gP: np.ndarray | None = None) -> np.ndarray:
+               pixels=None, gP: np.ndarray | None = None,
+               gP_abs: np.ndarray | None = None) -> np.ndarray:
     """Adjoint of :func:`render`.  gout: (npix, 9) upstream gradients of
     (color 3, depth expected, depth median, normal 3, alpha).  Returns the
-    gradient of the projected quantities, (N, 15) in the order of G_FIELDS."""
+    gradient of the projected quantities, (N, 15) in the order of G_FIELDS.
+    gP_abs, when given, accumulates over pixels a bound of the magnitudes of
+    the quantities each per-pixel term is computed from (the same recursion
+    run on absolute values): the round-off scale of those sums."""
     lib = _load()
     N = rec.shape[0]
     vv = view_vector(view)
@@ -191,7 +195,7 @@ def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np
         gP = np.zeros((N, len(G_FIELDS)), np.float64)
     lib.oracle_render_bwd(_ptr(s), _ptr(vv), N, _ptr(np.ascontiguousarray(rec, np.float64)),
                           _ptr(np.ascontiguousarray(flags, np.int32)), _ptr(pix), npix,
-                          _ptr(gout), _ptr(gP))
+                          _ptr(gout), _ptr(gP), _ptr(gP_abs))
     return gP
 
 
@@ -252,3 +256,30 @@ def backward(s: np.ndarray, views, scene, gouts, pixels=None, rec=None, flags=No
         px = None if pixels is None else pixels[vi]
         render_bwd(s, v, rec[vi], flags[vi], gouts[vi], px, gP[vi])
     return project_bwd(s, views, scene, gP)
+
+
+def gradient_error_scale(s: np.ndarray, views, scene, gouts, pixels=None) -> dict:
+    """Round-off scale of each parameter gradient element when the per-pixel
+    terms are evaluated and summed in a reduced precision: for every
+    projected quantity j of every view, the per-pixel magnitude bound of the
+    adjoint recursion (absolute values throughout, so cancellation inside a
+    term is accounted for) summed over pixels and pushed through
+    |d parameter / d quantity_j|.  An evaluation whose elementary operations
+    carry relative error u has |g - g_exact| <~ c u * scale with c of the
+    order of the operation count."""
+    rec, _, flags = project(s, views, scene)
+    V, N = len(views), scene.n
+    out = None
+    for vi, v in enumerate(views):
+        px = None if pixels is None else pixels[vi]
+        gabs = np.zeros((N, len(G_FIELDS)), np.float64)
+        render_bwd(s, v, rec[vi], flags[vi], gouts[vi], px, None, gabs)
+        for j in range(len(G_FIELDS)):
+            gP = np.zeros((1, N, len(G_FIELDS)), np.float64)
+            gP[0, :, j] = gabs[:, j]
+            r = project_bwd(s, [v], scene, gP)
+            if out is None:
+                out = {k: np.zeros_like(a) for k, a in r.items()}
+            for k in r:
+                out[k] += np.abs(r[k])
+    return out

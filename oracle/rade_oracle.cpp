@@ -24,7 +24,7 @@
 // Readings where the paper is silent are fixed by the settings vector (see
 // oracle/__init__.py) and listed with the design notes of the project.
 //
-// Build: g++ -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
+// Build: g++ -O2 -fopenmp -ffp-contract=off -fPIC -shared (oracle/__init__.py builds it).
 
 #include <algorithm>
 #include <cmath>
@@ -663,10 +663,12 @@ int oracle_render(const double* settings, const double* view, int64_t N, const d
 
 // Adjoint of the compositing of one view: upstream gradients per requested
 // pixel, gout: npix*9 = (color 3, depth expected, depth median, normal 3,
-// alpha) -> gradient of the projected quantities gP: N*G_COUNT (accumulated).
+// alpha) -> gradient of the projected quantities gP: N*G_COUNT (accumulated);
+// gP_abs (optional) accumulates, per term, a bound of the magnitudes of the
+// quantities it is computed from (the round-off scale of that term).
 int oracle_render_bwd(const double* settings, const double* view, int64_t N, const double* rec,
                       const int* flags, const int64_t* pix, int64_t npix, const double* gout,
-                      double* gP) {
+                      double* gP, double* gP_abs) {
   const View v = load_view(view);
   const std::vector<int64_t> order = blend_order(N, rec, flags);
   if (!pix) npix = (int64_t)v.W * v.H;
@@ -683,6 +685,10 @@ int oracle_render_bwd(const double* settings, const double* view, int64_t N, con
     // Reverse pass: R_acc holds the summed contribution of everything behind
     // the current Gaussian (later blends and the background).
     double Racc = R.out[O_TFIN] * (gC[0] * bg[0] + gC[1] * bg[1] + gC[2] * bg[2]);
+    // Magnitude bound of every intermediate (same recursion with absolute
+    // values): the scale of round-off of a reduced-precision evaluation.
+    double Rabs = R.out[O_TFIN] * (std::fabs(gC[0] * bg[0]) + std::fabs(gC[1] * bg[1]) +
+                                   std::fabs(gC[2] * bg[2]));
     for (int64_t k = (int64_t)R.list.size() - 1; k >= 0; --k) {
       const Contrib& c = R.list[k];
       const double* r = rec + c.g * R_COUNT;
@@ -709,9 +715,39 @@ int oracle_render_bwd(const double* settings, const double* view, int64_t N, con
       acc[G_Z] = gd;
       acc[G_P0] = gd * c.dx; acc[G_P1] = gd * c.dy;
       acc[G_N0] = w * gN[0]; acc[G_N1] = w * gN[1]; acc[G_N2] = w * gN[2];
+      double mag[G_COUNT] = {0};
+      if (gP_abs) {
+        const double sabs = std::fabs(gC[0] * r[R_R]) + std::fabs(gC[1] * r[R_G]) +
+                            std::fabs(gC[2] * r[R_BL]) + std::fabs(gD * c.d) +
+                            std::fabs(gN[0] * r[R_N0]) + std::fabs(gN[1] * r[R_N1]) +
+                            std::fabs(gN[2] * r[R_N2]) + std::fabs(gA);
+        const double ga_abs = c.T * sabs + Rabs / (1.0 - c.alpha);
+        Rabs += w * sabs;
+        const double gd_abs = w * std::fabs(gD) + (c.g == R.median ? std::fabs(gM) : 0.0);
+        const double gp_abs = c.clamped ? 0.0 : ga_abs * c.alpha;
+        const double go_abs = c.clamped ? 0.0 : ga_abs * c.gauss;
+        mag[G_UC] = gp_abs * (std::fabs(r[R_A] * c.dx) + std::fabs(r[R_B] * c.dy)) +
+                    gd_abs * std::fabs(r[R_P0]);
+        mag[G_VC] = gp_abs * (std::fabs(r[R_B] * c.dx) + std::fabs(r[R_C] * c.dy)) +
+                    gd_abs * std::fabs(r[R_P1]);
+        mag[G_A] = gp_abs * 0.5 * c.dx * c.dx;
+        mag[G_B] = gp_abs * std::fabs(c.dx * c.dy);
+        mag[G_C] = gp_abs * 0.5 * c.dy * c.dy;
+        mag[G_O] = go_abs;
+        mag[G_R] = w * std::fabs(gC[0]); mag[G_G] = w * std::fabs(gC[1]);
+        mag[G_BL] = w * std::fabs(gC[2]);
+        mag[G_Z] = gd_abs;
+        mag[G_P0] = gd_abs * std::fabs(c.dx); mag[G_P1] = gd_abs * std::fabs(c.dy);
+        mag[G_N0] = w * std::fabs(gN[0]); mag[G_N1] = w * std::fabs(gN[1]);
+        mag[G_N2] = w * std::fabs(gN[2]);
+      }
       for (int j = 0; j < G_COUNT; ++j) {
 #pragma omp atomic
         gP[c.g * G_COUNT + j] += acc[j];
+        if (gP_abs) {
+#pragma omp atomic
+          gP_abs[c.g * G_COUNT + j] += mag[j];
+        }
       }
     }
   }

@@ -15,13 +15,16 @@ from typing import Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librade.so")
+# RADE_LIBRARY selects another build of the library (e.g. a debug build).
+LIB_PATH = os.environ.get("RADE_LIBRARY") or os.path.join(HERE, "librade.so")
 
 RADE_OK = 0
 RADE_ERR_INVALID_ARG = -1
 RADE_ERR_CAPACITY = -2
 RADE_ERR_HIP = -3
 RADE_ERR_WORKSPACE = -4
+
+RADE_SCHEDULE_TILE, RADE_SCHEDULE_HEAVY_FIRST, RADE_SCHEDULE_PERSISTENT = 0, 1, 2
 
 SPLAT_BYTES = 80
 GRAD_FLOATS = 16
@@ -41,7 +44,7 @@ class RadeError(RuntimeError):
 
 class CSettings(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("dilation", ctypes.c_double), ("near_plane", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("t_min", ctypes.c_double), ("power_cut", ctypes.c_double),
@@ -66,6 +69,7 @@ class Settings:
     tile_w: int = 16
     tile_h: int = 16
     sh_degree: int = 0
+    schedule: int = 0          # RADE_SCHEDULE_*
     dilation: float = 0.3
     near_plane: float = 0.2
     alpha_min: float = 1.0 / 255.0
@@ -78,7 +82,8 @@ class Settings:
 
     def c(self) -> CSettings:
         s = CSettings()
-        s.tile_w, s.tile_h, s.sh_degree, s.reserved = self.tile_w, self.tile_h, self.sh_degree, 0
+        s.tile_w, s.tile_h, s.sh_degree = self.tile_w, self.tile_h, self.sh_degree
+        s.schedule = self.schedule
         s.dilation, s.near_plane = self.dilation, self.near_plane
         s.alpha_min, s.alpha_max, s.t_min = self.alpha_min, self.alpha_max, self.t_min
         s.power_cut, s.fov_clamp, s.degenerate = self.power_cut, self.fov_clamp, self.degenerate
@@ -104,10 +109,14 @@ def load() -> ctypes.CDLL:
     lib.rade_bin_sort_workspace.argtypes = [I32, I64, I64, I64]
     lib.rade_bin_sort_workspace.restype = SZ
     lib.rade_bin_sort.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I64, P, P, P, SZ, P]
-    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 11 + [P]
+    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 12 + [P]
+    lib.rade_tile_order_workspace.argtypes = [I64]
+    lib.rade_tile_order_workspace.restype = SZ
+    lib.rade_tile_order.argtypes = [P, P, I32, P, P, P, SZ, P]
+    lib.rade_tile_order.restype = ctypes.c_int
     lib.rade_render_bwd_workspace.argtypes = [P, I32, I64, ctypes.c_int]
     lib.rade_render_bwd_workspace.restype = SZ
-    lib.rade_render_bwd.argtypes = [P, P, P, I32, I64] + [P] * 21 + [SZ, P]
+    lib.rade_render_bwd.argtypes = [P, P, P, I32, I64] + [P] * 22 + [SZ, P]
     lib.rade_strerror.argtypes = [ctypes.c_int]
     lib.rade_strerror.restype = ctypes.c_char_p
     lib.rade_abi_version.restype = ctypes.c_int
@@ -122,7 +131,8 @@ def load() -> ctypes.CDLL:
 
 EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "rade_bin_sort",
             "rade_render_fwd", "rade_render_bwd_workspace", "rade_render_bwd", "rade_strerror",
-            "rade_abi_version", "rade_set_kernel_events"]
+            "rade_abi_version", "rade_set_kernel_events", "rade_tile_order_workspace",
+            "rade_tile_order"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -225,12 +235,25 @@ def rade_bin_sort(settings: Settings, views_c, views_dev, V: int, N: int, splats
     return code, (host.value if sync_count else None)
 
 
+def rade_tile_order_workspace(total_tiles: int) -> int:
+    return int(load().rade_tile_order_workspace(total_tiles))
+
+
+def rade_tile_order(settings: Settings, views_c, tile_ranges, tile_order, workspace, stream=None):
+    s = settings.c()
+    return _check(load().rade_tile_order(ctypes.byref(s), views_c, len(views_c), _p(tile_ranges),
+                                         _p(tile_order), _p(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream(stream)), "rade_tile_order")
+
+
 def rade_render_fwd(settings: Settings, views_c, views_dev, V: int, N: int, splats, pair_ids,
                     tile_ranges, color, depth, normal, alpha, t_final, last, median, count=None,
-                    stream=None):
+                    stream=None, tile_order=None):
     s = settings.c()
     return _check(load().rade_render_fwd(ctypes.byref(s), views_c, _p(views_dev), V, N,
-                                         _p(splats), _p(pair_ids), _p(tile_ranges), _p(color),
+                                         _p(splats), _p(pair_ids), _p(tile_ranges),
+                                         _p(tile_order), _p(color),
                                          _p(depth), _p(normal), _p(alpha), _p(t_final), _p(last),
                                          _p(median), _p(count), _stream(stream)),
                   "rade_render_fwd")
@@ -244,11 +267,12 @@ def rade_render_bwd_workspace(settings: Settings, V: int, N: int, recompute: boo
 def rade_render_bwd(settings: Settings, views_c, views_dev, V: int, N: int, means, scales, quats,
                     opacities, sh, splats, pair_ids, tile_ranges, t_final, last, median, d_color,
                     d_depth, d_normal, d_alpha, d_means, d_scales, d_quats, d_opacities, d_sh,
-                    workspace, stream=None):
+                    workspace, stream=None, tile_order=None):
     s = settings.c()
     return _check(load().rade_render_bwd(
         ctypes.byref(s), views_c, _p(views_dev), V, N, _p(means), _p(scales), _p(quats),
-        _p(opacities), _p(sh), _p(splats), _p(pair_ids), _p(tile_ranges), _p(t_final), _p(last),
+        _p(opacities), _p(sh), _p(splats), _p(pair_ids), _p(tile_ranges), _p(tile_order),
+        _p(t_final), _p(last),
         _p(median), _p(d_color), _p(d_depth), _p(d_normal), _p(d_alpha), _p(d_means),
         _p(d_scales), _p(d_quats), _p(d_opacities), _p(d_sh), _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_render_bwd")

@@ -1,0 +1,218 @@
+"""Batched multi-view rendering: one launch per kernel over many views of
+uneven size, the whole forward + backward captured in a HIP graph, and an
+autotuner for the tile size and the work schedule.
+
+All views share one key space (global tile = view's tile offset + tile), so
+each kernel of the path is launched once for the whole batch; the render
+kernels can visit tiles longest-list first, either one workgroup per tile or
+with resident workgroups pulling tiles from a device counter.  A plan
+allocates every buffer up front; its step enqueues project -> bin/sort (no
+host synchronisation: the pair count stays on the device) -> tile order ->
+render forward -> upstream gradients (caller's elementwise function) ->
+render backward -> projection backward.  After a replay, `overflowed()`
+reads the device pair count once; on overflow the plan grows its capacity
+and captures again.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from typing import Callable, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import Settings
+from .raster import Rasterizer
+
+
+class BatchedPlan:
+    """Pre-allocated fwd+bwd of N Gaussians over a fixed list of views.
+
+    params: the five parameter tensors (means, scales, quats, opacities, sh);
+    the plan keeps references (their storage must stay put; update in place).
+    grad_fn(maps) -> (d_color, d_depth, d_normal, d_alpha) computes upstream
+    gradients from the map tensors with stream-ordered torch ops; under graph
+    capture it must avoid host synchronisation (elementwise ops are safe).
+    """
+
+    def __init__(self, views: Sequence, settings: Settings, params: Sequence[torch.Tensor],
+                 grad_fn: Callable, capacity: Optional[int] = None, recompute: bool = False):
+        self.settings = settings
+        self.params = [p.detach() for p in params]
+        self.device = self.params[0].device
+        self.N = self.params[0].shape[0]
+        self.rast = Rasterizer(views, settings, self.device)
+        self.V = self.rast.V
+        self.grad_fn = grad_fn
+        self.recompute = recompute
+        self.graph = None
+        if capacity is None:
+            # one eager binning pass sizes the pair buffers (with slack)
+            splats, tt = self.rast.project(*self.params)
+            _, _, M = self.rast.bin_sort(self.N, splats, tt)
+            capacity = int(M * 1.15) + 4096
+        self._alloc(capacity)
+
+    # -- buffers -------------------------------------------------------------
+    def _alloc(self, capacity: int):
+        dev, V, N, r = self.device, self.V, self.N, self.rast
+        VN = max(1, V * N)
+        self.capacity = int(capacity)
+        self.splats = torch.empty(VN * _lib.SPLAT_BYTES, dtype=torch.uint8, device=dev)
+        self.tt = torch.empty(VN, dtype=torch.int32, device=dev)
+        self.pair_ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
+        self.ranges = torch.empty(2 * max(1, r.total_tiles), dtype=torch.int32, device=dev)
+        self.n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.bin_ws = torch.empty(max(1, _lib.rade_bin_sort_workspace(V, N, self.capacity,
+                                                                      r.total_tiles)),
+                                  dtype=torch.uint8, device=dev)
+        self.order = torch.empty(r.total_tiles + 1, dtype=torch.int32, device=dev)
+        self.order_ws = torch.empty(max(1, _lib.rade_tile_order_workspace(r.total_tiles)),
+                                    dtype=torch.uint8, device=dev)
+        P = r.total_pixels
+        f = lambda c: torch.zeros(c * P, dtype=torch.float32, device=dev)  # noqa: E731
+        i = lambda: torch.zeros(P, dtype=torch.int32, device=dev)  # noqa: E731
+        self.maps = dict(color=f(3), depth=f(2), normal=f(3), alpha=f(1), t_final=f(1),
+                         last=i(), median=i())
+        self.bwd_ws = torch.empty(max(1, _lib.rade_render_bwd_workspace(
+            self.settings, V, N, self.recompute)), dtype=torch.uint8, device=dev)
+        m, s, q, o, sh = self.params
+        self.grads = [torch.zeros_like(m), torch.zeros_like(s), torch.zeros((N, 4), device=dev),
+                      torch.zeros_like(o), torch.zeros_like(sh)]
+        self.graph = None
+
+    # -- the step --------------------------------------------------------------
+    def enqueue(self):
+        """Enqueue one fwd+bwd on the current stream (no host sync)."""
+        st, r, V, N = self.settings, self.rast, self.V, self.N
+        m, s, q, o, sh = self.params
+        _lib.rade_project(st, r.views_dev, V, N, m, s, q, o, sh, self.splats, self.tt)
+        _lib.rade_bin_sort(st, r.views_c, r.views_dev, V, N, self.splats, self.tt, self.pair_ids,
+                           self.ranges, None, self.capacity, self.n_dev, self.bin_ws,
+                           sync_count=False)
+        order = None
+        if st.schedule != _lib.RADE_SCHEDULE_TILE:
+            _lib.rade_tile_order(st, r.views_c, self.ranges, self.order, self.order_ws)
+            order = self.order
+        mp = self.maps
+        _lib.rade_render_fwd(st, r.views_c, r.views_dev, V, N, self.splats, self.pair_ids,
+                             self.ranges, mp["color"], mp["depth"], mp["normal"], mp["alpha"],
+                             mp["t_final"], mp["last"], mp["median"], None, tile_order=order)
+        g = self.grad_fn(mp)
+        dc, dd, dn, da = (None if x is None else x.contiguous() for x in g)
+        _lib.rade_render_bwd(st, r.views_c, r.views_dev, V, N, m, s, q, o, sh,
+                             None if self.recompute else self.splats, self.pair_ids, self.ranges,
+                             mp["t_final"], mp["last"], mp["median"], dc, dd, dn, da,
+                             *self.grads, self.bwd_ws, tile_order=order)
+
+    def capture(self):
+        """Capture enqueue() into a HIP graph (after one eager warm-up)."""
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.enqueue()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def n_pairs(self) -> int:
+        return int(self.n_dev.item())
+
+    def overflowed(self) -> bool:
+        return self.n_pairs() > self.capacity
+
+    def step(self, check: bool = True) -> int:
+        """Replay once; when check, verify the pair count and, on overflow,
+        grow, re-capture and replay.  Returns the number of replays made."""
+        self.replay()
+        if not check or not self.overflowed():
+            return 1
+        self._alloc(int(self.n_pairs() * 1.25) + 4096)
+        self.capture()
+        self.replay()
+        return 2
+
+
+# ---------------------------------------------------------------------------
+# Autotuner
+
+TILES = [(8, 8), (16, 16), (16, 32), (32, 16)]
+SCHEDULES = [_lib.RADE_SCHEDULE_TILE, _lib.RADE_SCHEDULE_HEAVY_FIRST, _lib.RADE_SCHEDULE_PERSISTENT]
+
+
+def _cache_path() -> str:
+    base = os.environ.get("RADE_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "rade", "autotune.json"))
+    return base
+
+
+def signature(views: Sequence, n: int, sh_degree: int) -> str:
+    h = hashlib.sha1()
+    h.update(f"{n}:{sh_degree}:".encode())
+    for v in views:
+        h.update(f"{v.width}x{v.height};".encode())
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"{dev}|{h.hexdigest()[:16]}"
+
+
+def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, grad_fn: Callable,
+             tiles=TILES, schedules=SCHEDULES, reps: int = 3, use_cache: bool = True,
+             log: Optional[Callable] = None) -> tuple:
+    """Time the graph-replayed fwd+bwd for every (tile, schedule) candidate
+    and return (best Settings, {candidate: ms}).  Results are cached in a JSON
+    file keyed by device name and workload signature."""
+    sig = signature(views, params[0].shape[0], base.sh_degree)
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and sig in cache:
+        c = cache[sig]
+        return Settings(**{**base.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"],
+                           "schedule": c["schedule"]}), c.get("timings", {})
+    timings = {}
+    best = None
+    for tw, th in tiles:
+        for sch in schedules:
+            st = Settings(**{**base.__dict__, "tile_w": tw, "tile_h": th, "schedule": sch})
+            plan = BatchedPlan(views, st, params, grad_fn)
+            plan.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.replay()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            key = f"{tw}x{th}/{sch}"
+            timings[key] = ms
+            if log:
+                log(f"autotune {key}: {ms:.3f} ms")
+            if best is None or ms < best[0]:
+                best = (ms, st)
+            del plan
+    if use_cache:
+        cache[sig] = dict(tile_w=best[1].tile_w, tile_h=best[1].tile_h,
+                          schedule=best[1].schedule, timings=timings)
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return best[1], timings

@@ -26,14 +26,17 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
 bool tile_supported(int tw, int th);
 hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
-                             const uint32_t* ranges, float* color, float* depth,
-                             float* normal, float* alpha, float* tf, int32_t* last,
-                             int32_t* med, int32_t* cnt, hipStream_t st);
+                             const uint32_t* ranges, const uint32_t* order, float* color,
+                             float* depth, float* normal, float* alpha, float* tf,
+                             int32_t* last, int32_t* med, int32_t* cnt, hipStream_t st);
 hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
-                             const uint32_t* ranges, const float* tf, const int32_t* last,
-                             const int32_t* med, const float* dc, const float* dd,
-                             const float* dn, const float* da, float* gsplat,
+                             const uint32_t* ranges, const uint32_t* order, const float* tf,
+                             const int32_t* last, const int32_t* med, const float* dc,
+                             const float* dd, const float* dn, const float* da, float* gsplat,
+                             hipStream_t st);
+size_t tile_order_workspace(int64_t tiles);
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st);
 }  // namespace rade
 
@@ -43,6 +46,7 @@ bool settings_ok(const rade_settings* s) {
   if (!s) return false;
   if (!rade::tile_supported(s->tile_w, s->tile_h)) return false;
   if (s->sh_degree < 0 || s->sh_degree > 3) return false;
+  if (s->schedule < RADE_SCHEDULE_TILE || s->schedule > RADE_SCHEDULE_PERSISTENT) return false;
   if (!(s->alpha_min > 0.0) || !(s->alpha_max <= 1.0) || !(s->alpha_min < s->alpha_max))
     return false;
   if (!(s->t_min > 0.0 && s->t_min < 1.0) || !(s->power_cut > 0.0)) return false;
@@ -169,20 +173,37 @@ int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
   return exceeded ? RADE_ERR_CAPACITY : RADE_OK;
 }
 
+size_t rade_tile_order_workspace(int64_t total_tiles) {
+  return total_tiles < 0 ? 0 : rade::tile_order_workspace(total_tiles);
+}
+
+int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t V,
+                    const uint32_t* tile_ranges, uint32_t* tile_order, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+  if (!settings_ok(s) || !views_ok(views_host, V) || !tile_ranges || !tile_order)
+    return RADE_ERR_INVALID_ARG;
+  const int64_t tiles = total_tiles(views_host, V);
+  if (!workspace || workspace_bytes < rade_tile_order_workspace(tiles)) return RADE_ERR_WORKSPACE;
+  return hip_status(rade::launch_tile_order(tile_ranges, tiles, tile_order, workspace,
+                                            (hipStream_t)stream));
+}
+
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
-                    const uint32_t* pair_ids, const uint32_t* tile_ranges, float* color,
+                    const uint32_t* pair_ids, const uint32_t* tile_ranges,
+                    uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
                     int32_t* median, int32_t* count, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !color || !depth || !normal || !alpha || !t_final || !last || !median)
     return RADE_ERR_INVALID_ARG;
+  if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && !splats) return RADE_ERR_INVALID_ARG;
   const int64_t tiles = total_tiles(views_host, V);
   return hip_status(rade::launch_render_fwd(*s, views_dev, V, N, tiles, splats, pair_ids,
-                                            tile_ranges, color, depth, normal, alpha, t_final,
-                                            last, median, count, (hipStream_t)stream));
+                                            tile_ranges, tile_order, color, depth, normal, alpha,
+                                            t_final, last, median, count, (hipStream_t)stream));
 }
 
 size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute) {
@@ -199,7 +220,8 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const float* means,
                     const float* scales, const float* quats, const float* opacities,
                     const float* sh, const rade_splat* splats, const uint32_t* pair_ids,
-                    const uint32_t* tile_ranges, const float* t_final, const int32_t* last,
+                    const uint32_t* tile_ranges, uint32_t* tile_order,
+                    const float* t_final, const int32_t* last,
                     const int32_t* median, const float* d_color, const float* d_depth,
                     const float* d_normal, const float* d_alpha, float* d_means,
                     float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
@@ -207,6 +229,7 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !t_final || !last || !median) return RADE_ERR_INVALID_ARG;
+  if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !d_means || !d_scales ||
                 !d_quats || !d_opacities || !d_sh))
     return RADE_ERR_INVALID_ARG;
@@ -232,8 +255,8 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   }
   const int64_t tiles = total_tiles(views_host, V);
   hipError_t e = rade::launch_render_bwd(*s, views_dev, V, N, tiles, splats, pair_ids,
-                                         tile_ranges, t_final, last, median, d_color, d_depth,
-                                         d_normal, d_alpha, gsplat, st);
+                                         tile_ranges, tile_order, t_final, last, median, d_color,
+                                         d_depth, d_normal, d_alpha, gsplat, st);
   if (e != hipSuccess) return RADE_ERR_HIP;
   e = rade::launch_project_bwd(*s, views_dev, V, N, means, scales, quats, opacities, sh, gsplat,
                                d_means, d_scales, d_quats, d_opacities, d_sh, st);

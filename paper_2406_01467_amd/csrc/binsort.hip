@@ -387,7 +387,44 @@ Layout layout(int64_t VN, int64_t capacity) {
   return L;
 }
 
+// Order key of a tile: 255 - 16 log2(len + 1), so longer lists come first.
+__global__ void __launch_bounds__(kThreads)
+k_order_keys(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __restrict__ keys,
+             uint32_t* __restrict__ vals, uint32_t* __restrict__ count) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t == 0) *count = (uint32_t)tiles;
+  if (t >= tiles) return;
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  const int b = len == 0 ? 0 : min(255, (int)(16.0f * __log2f((float)len + 1.0f)));
+  keys[t] = (uint32_t)(255 - b);
+  vals[t] = (uint32_t)t;
+}
+
 }  // namespace
+
+size_t tile_order_workspace(int64_t tiles) {
+  const int64_t nb = (tiles + kTile - 1) / kTile + 1;
+  return align_up(sizeof(uint32_t) * tiles) * 3 + align_up(sizeof(uint32_t) * nb * kRadix) +
+         align_up(sizeof(uint64_t) * (nb * kRadix / kTile + 2)) + 256;
+}
+
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
+                             hipStream_t st) {
+  char* w = static_cast<char*>(ws);
+  const int64_t nb = (tiles + kTile - 1) / kTile + 1;
+  uint32_t* k0 = (uint32_t*)w;
+  uint32_t* v0 = (uint32_t*)(w + align_up(sizeof(uint32_t) * tiles));
+  uint32_t* k1 = (uint32_t*)(w + 2 * align_up(sizeof(uint32_t) * tiles));
+  uint32_t* hist = (uint32_t*)(w + 3 * align_up(sizeof(uint32_t) * tiles));
+  uint32_t* sums = (uint32_t*)((char*)hist + align_up(sizeof(uint32_t) * nb * kRadix));
+  uint32_t* cnt = (uint32_t*)((char*)sums + align_up(sizeof(uint64_t) * (nb * kRadix / kTile + 2)));
+  hipLaunchKernelGGL(k_order_keys, dim3(blocks_for(tiles > 0 ? tiles : 1, kThreads)),
+                     dim3(kThreads), 0, st, ranges, tiles, k0, v0, cnt);
+  // one 8-bit pass: the result lands in (k1, order)
+  radix_sort(k0, v0, k1, order, tiles, cnt, 8, hist, sums, st);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, order + tiles, 1, 0u);
+  return hipGetLastError();
+}
 
 size_t bin_sort_workspace(int64_t VN, int64_t capacity) { return layout(VN, capacity).total; }
 

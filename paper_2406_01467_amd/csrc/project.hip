@@ -36,6 +36,8 @@ constexpr double kY3c = 0.45704579946446572;
 constexpr double kY3d = 0.37317633259011546;
 constexpr double kY3e = 1.4453057213202769;
 
+// FP64: a colour is 1/2 plus a sum of up to 48 products that may cancel, so
+// colours near zero need more than FP32 round-off of the terms.
 __device__ __forceinline__ void sh_basis(int deg, double x, double y, double z, double* Y) {
   Y[0] = kY0;
   if (deg < 1) return;
@@ -101,6 +103,39 @@ __device__ __forceinline__ void sh_grad(int deg, double x, double y, double z, c
   // Y15 = -a x (xx - 3yy)
   g[0] += -kY3a * (3.0 * xx - 3.0 * yy) * c[15];
   g[1] += kY3a * 6.0 * x * y * c[15];
+}
+
+// Colour of one view: max(0, sum_k coef_k Y_k(dir) + 1/2) per channel
+// (coefficients read from memory as they are used).  raw[] keeps the
+// unclamped values for the clamp decision of the backward pass.
+template <int K>
+__device__ __forceinline__ void sh_colour(int deg, const double* dir,
+                                          const float* __restrict__ coef, double* raw) {
+  double Y[16];
+  sh_basis(deg, dir[0], dir[1], dir[2], Y);
+  raw[0] = raw[1] = raw[2] = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    raw[0] += (double)coef[3 * k + 0] * Y[k];
+    raw[1] += (double)coef[3 * k + 1] * Y[k];
+    raw[2] += (double)coef[3 * k + 2] * Y[k];
+  }
+  raw[0] += 0.5; raw[1] += 0.5; raw[2] += 0.5;
+}
+
+// Unit viewing direction from the camera centre to the mean; returns 1/|d|.
+__device__ __forceinline__ double view_dir(const double* mu, const double* C, double* u) {
+  const double d0 = mu[0] - C[0], d1 = mu[1] - C[1], d2 = mu[2] - C[2];
+  const double idn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  u[0] = d0 * idn; u[1] = d1 * idn; u[2] = d2 * idn;
+  return idn;
+}
+
+// Every SH coefficient of a Gaussian finite?
+__device__ __forceinline__ bool sh_finite(const float* __restrict__ c, int n) {
+  bool ok = true;
+  for (int i = 0; i < n; ++i) ok = ok && isfinite(c[i]);
+  return ok;
 }
 
 struct ViewD {
@@ -261,15 +296,10 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   const int deg = st.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
+  constexpr int K = KMAX;
+  const float* __restrict__ coef = sh + 3 * K * g;
   Params P;
-  bool ok = load_params(g, means, scales, quats, opac, P);
-  float coef[3 * KMAX];
-#pragma unroll
-  for (int i = 0; i < 3 * KMAX; ++i) {
-    coef[i] = (i < 3 * K) ? sh[3 * K * g + i] : 0.0f;
-    ok = ok && finitef(coef[i]);
-  }
+  const bool ok = load_params(g, means, scales, quats, opac, P) && sh_finite(coef, 3 * K);
   for (int vi = 0; vi < V; ++vi) {
     const int64_t o = (int64_t)vi * N + g;
     const ViewD v = load_view(views[vi], st.fov_clamp);
@@ -314,19 +344,14 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
     out.n[0] = (float)(G.nr[0] * inl);
     out.n[1] = (float)(G.nr[1] * inl);
     out.n[2] = (float)(G.nr[2] * inl);
-    // colour
+    // colour: coefficients streamed from memory (L1/L2 after the first view)
     {
-      double d[3] = {P.mu[0] - v.C[0], P.mu[1] - v.C[1], P.mu[2] - v.C[2]};
-      const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      double Y[16];
-      sh_basis(deg, d[0] * idn, d[1] * idn, d[2] * idn, Y);
-      for (int c = 0; c < 3; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < K) acc += (double)coef[3 * k + c] * Y[k];
-        out.rgb[c] = (float)fmax(acc + 0.5, 0.0);
-      }
+      double u[3], raw[3];
+      view_dir(P.mu, v.C, u);
+      sh_colour<K>(deg, u, coef, raw);
+      out.rgb[0] = (float)fmax(raw[0], 0.0);
+      out.rgb[1] = (float)fmax(raw[1], 0.0);
+      out.rgb[2] = (float)fmax(raw[2], 0.0);
     }
     // support rect: alpha >= alpha_min inside power <= tau
     const double tau = fmin(st.power_cut, log(255.0 * (double)P.o));
@@ -373,17 +398,12 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   const int deg = st.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
+  constexpr int K = KMAX;
+  const float* __restrict__ coef = sh + 3 * K * g;
+  float* __restrict__ gcoef = d_sh + 3 * K * g;
   Params P;
-  bool ok = load_params(g, means, scales, quats, opac, P);
-  double coef[3 * KMAX];
-  double gcoef[3 * KMAX];
-#pragma unroll
-  for (int i = 0; i < 3 * KMAX; ++i) {
-    coef[i] = (i < 3 * K) ? (double)sh[3 * K * g + i] : 0.0;
-    gcoef[i] = 0.0;
-    ok = ok && isfinite(coef[i]);
-  }
+  const bool ok = load_params(g, means, scales, quats, opac, P) && sh_finite(coef, 3 * K);
+  bool sh_written = false;
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gqn[4] = {0, 0, 0, 0}, go = 0.0;
   for (int vi = 0; ok && vi < V; ++vi) {
     const float* gr = gsplat + ((int64_t)vi * N + g) * kGradStride;
@@ -392,47 +412,17 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     const float4 gc = *reinterpret_cast<const float4*>(gr + 8);
     const float4 gd = *reinterpret_cast<const float4*>(gr + 12);
     const double guc = ga.x, gvc = ga.y, gA = ga.z, gB = ga.w;
-    const double gC = gb.x, gO = gb.y, gR0 = gb.z, gR1 = gb.w;
-    const double gR2 = gc.x, gZd = gc.y, gp0 = gc.z, gp1 = gc.w;
+    const double gC = gb.x, gO = gb.y;
+    const double gZd = gc.y, gp0 = gc.z, gp1 = gc.w;
     const double gn0 = gd.x, gn1 = gd.y, gn2 = gd.z;
-    if (guc == 0.0 && gvc == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && gO == 0.0 &&
-        gR0 == 0.0 && gR1 == 0.0 && gR2 == 0.0 && gZd == 0.0 && gp0 == 0.0 && gp1 == 0.0 &&
-        gn0 == 0.0 && gn1 == 0.0 && gn2 == 0.0)
+    if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gb.x == 0.f &&
+        gb.y == 0.f && gb.z == 0.f && gb.w == 0.f && gc.x == 0.f && gc.y == 0.f &&
+        gc.z == 0.f && gc.w == 0.f && gd.x == 0.f && gd.y == 0.f && gd.z == 0.f)
       continue;
     const ViewD v = load_view(views[vi], st.fov_clamp);
     Geo G;
     if (!geometry(v, P, st, G) || !(G.detD > 0.0)) continue;
     go += gO;
-
-    // --- colour -> SH coefficients and the viewing direction
-    {
-      double d[3] = {P.mu[0] - v.C[0], P.mu[1] - v.C[1], P.mu[2] - v.C[2]};
-      const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      const double idn = 1.0 / dn;
-      const double u[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
-      double Y[16];
-      sh_basis(deg, u[0], u[1], u[2], Y);
-      double grgb[3] = {gR0, gR1, gR2};
-      double cw[16];
-      for (int k = 0; k < 16; ++k) cw[k] = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < K) acc += coef[3 * k + c] * Y[k];
-        if (acc + 0.5 < 0.0) grgb[c] = 0.0;  // clamped channel
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < K) {
-            gcoef[3 * k + c] += grgb[c] * Y[k];
-            cw[k] += grgb[c] * coef[3 * k + c];
-          }
-      }
-      double gu[3];
-      sh_grad(deg, u[0], u[1], u[2], cw, gu);
-      const double ud = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
-      for (int i = 0; i < 3; ++i) gmu[i] += (gu[i] - u[i] * ud) * idn;
-    }
 
     const double X = G.X, Yc = G.Y, Z = G.Z, tc = G.tc;
     const double iz = 1.0 / Z, iz2 = iz * iz;
@@ -562,6 +552,38 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     // x = R mu + t
     for (int i = 0; i < 3; ++i)
       gmu[i] += v.R[i] * gx[0] + v.R[3 + i] * gx[1] + v.R[6 + i] * gx[2];
+
+    // --- colour -> SH coefficients (accumulated in place in d_sh) and the
+    // viewing direction
+    {
+      double u[3], raw[3];
+      const double idn = view_dir(P.mu, v.C, u);
+      sh_colour<K>(deg, u, coef, raw);
+      // clamped channels pass no gradient (same decision as the forward)
+      const double g0 = raw[0] < 0.0 ? 0.0 : (double)gb.z;
+      const double g1 = raw[1] < 0.0 ? 0.0 : (double)gb.w;
+      const double g2 = raw[2] < 0.0 ? 0.0 : (double)gc.x;
+      double Y[16], cw[16];
+      sh_basis(deg, u[0], u[1], u[2], Y);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cw[k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double c0 = coef[3 * k + 0], c1 = coef[3 * k + 1], c2 = coef[3 * k + 2];
+        cw[k] = g0 * c0 + g1 * c1 + g2 * c2;
+        const float a0 = (float)(g0 * Y[k]), a1 = (float)(g1 * Y[k]), a2 = (float)(g2 * Y[k]);
+        if (sh_written) {
+          gcoef[3 * k + 0] += a0; gcoef[3 * k + 1] += a1; gcoef[3 * k + 2] += a2;
+        } else {
+          gcoef[3 * k + 0] = a0; gcoef[3 * k + 1] = a1; gcoef[3 * k + 2] = a2;
+        }
+      }
+      sh_written = true;
+      double gu[3];
+      sh_grad(deg, u[0], u[1], u[2], cw, gu);
+      const double ud = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
+      for (int i = 0; i < 3; ++i) gmu[i] += (gu[i] - u[i] * ud) * idn;
+    }
   }
   // unit quaternion -> raw quaternion
   const double qd = P.qn[0] * gqn[0] + P.qn[1] * gqn[1] + P.qn[2] * gqn[2] + P.qn[3] * gqn[3];
@@ -577,7 +599,8 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     d_scales[3 * g + i] = ok ? (float)gs[i] : 0.0f;
   }
   d_opac[g] = ok ? (float)go : 0.0f;
-  for (int i = 0; i < 3 * K; ++i) d_sh[3 * K * g + i] = ok ? (float)gcoef[i] : 0.0f;
+  if (!sh_written)
+    for (int i = 0; i < 3 * K; ++i) gcoef[i] = 0.0f;
 }
 
 }  // namespace

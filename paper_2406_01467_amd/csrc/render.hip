@@ -21,8 +21,9 @@
 // final T (nothing per blend is stored) and the running sum R of what lies
 // behind:  dL/dalpha_i = T_i s_i - R / (1 - alpha_i),  R += w_i s_i, where
 // s_i = g_C . rgb_i + g_D d_i + g_N . n_i + g_A.  The 15 per-splat gradients
-// are summed over the wavefront with a transpose-reduction and added with
-// hardware FP32 atomics into a per-(view, Gaussian) record.
+// are summed over the wavefront with a transpose-reduction built on the
+// gfx950 lane-swap instructions and DPP, and added with hardware FP32 atomics
+// into a per-(view, Gaussian) record.
 #include "common.hpp"
 
 namespace rade {
@@ -47,12 +48,42 @@ struct PixelCtx {
   uint32_t rb, re;
 };
 
+struct FwdArgs {
+  BlendParams bp;
+  const rade_view* views;
+  int V;
+  int64_t N, tiles;
+  const rade_splat* splats;
+  const uint32_t* pair_ids;
+  const uint32_t* ranges;
+  const uint32_t* order;   // tile visiting order (NULL: natural)
+  uint32_t* queue;         // work-queue counter of the persistent kernel
+  float *color, *depth, *normal, *alpha, *t_final;
+  int32_t *last, *median, *count;
+};
+
+struct BwdArgs {
+  BlendParams bp;
+  const rade_view* views;
+  int V;
+  int64_t N, tiles;
+  const rade_splat* splats;
+  const uint32_t* pair_ids;
+  const uint32_t* ranges;
+  const uint32_t* order;
+  uint32_t* queue;
+  const float* t_final;
+  const int32_t *last, *median;
+  const float *d_color, *d_depth, *d_normal, *d_alpha;
+  float* gsplat;
+};
+
 template <int TW, int TH>
 __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
-                                              const uint32_t* ranges) {
+                                              const uint32_t* ranges, int64_t tile) {
   using TG = TileGeom<TW, TH>;
   PixelCtx c;
-  c.tile = blockIdx.x;
+  c.tile = tile;
   c.v = view_of_tile(views, V, c.tile);
   const rade_view& vw = views[c.v];
   const int64_t lt = c.tile - vw.tile_offset;
@@ -115,20 +146,25 @@ __device__ __forceinline__ void publish_masks(uint32_t bits, uint64_t (*masks)[T
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
-k_render_fwd(BlendParams bp, const rade_view* __restrict__ views, int V, int64_t N,
-             const rade_splat* __restrict__ splats, const uint32_t* __restrict__ pair_ids,
-             const uint32_t* __restrict__ ranges, float* __restrict__ color,
-             float* __restrict__ depth, float* __restrict__ normal, float* __restrict__ alpha,
-             float* __restrict__ t_final, int32_t* __restrict__ last,
-             int32_t* __restrict__ median, int32_t* __restrict__ count) {
+struct FwdShared {
+  StagedSplat ss[TileGeom<TW, TH>::BLOCK];
+  uint32_t sgid[TileGeom<TW, TH>::BLOCK];
+  uint64_t masks[TileGeom<TW, TH>::NW][TileGeom<TW, TH>::NW];
+};
+
+// Forward blend of one tile (all threads of the workgroup take part).
+template <int TW, int TH>
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShared<TW, TH>& sh) {
   using TG = TileGeom<TW, TH>;
-  __shared__ StagedSplat ss[TG::BLOCK];
-  __shared__ uint32_t sgid[TG::BLOCK];
-  __shared__ uint64_t masks[TG::NW][TG::NW];
-  const PixelCtx c = pixel_ctx<TW, TH>(views, V, ranges);
+  const BlendParams& bp = a.bp;
+  const rade_splat* __restrict__ splats = a.splats;
+  const uint32_t* __restrict__ pair_ids = a.pair_ids;
+  StagedSplat* ss = sh.ss;
+  uint32_t* sgid = sh.sgid;
+  auto masks = sh.masks;
+  const PixelCtx c = pixel_ctx<TW, TH>(a.views, a.V, a.ranges, tile);
   const int wave = threadIdx.x >> 6;
-  const int64_t vbase = (int64_t)c.v * N;
+  const int64_t vbase = (int64_t)c.v * a.N;
   const float fx = (float)c.lxi, fy = (float)c.lyi;
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f, A = 0.f;
@@ -180,60 +216,116 @@ k_render_fwd(BlendParams bp, const rade_view* __restrict__ views, int V, int64_t
   if (!c.inside) return;
   C0 = fmaf(T, bp.bg[0], C0); C1 = fmaf(T, bp.bg[1], C1); C2 = fmaf(T, bp.bg[2], C2);
   const int64_t P = c.P, pix = c.pix;
-  color[3 * c.poff + pix] = C0;
-  color[3 * c.poff + P + pix] = C1;
-  color[3 * c.poff + 2 * P + pix] = C2;
-  depth[2 * c.poff + pix] = D;
-  depth[2 * c.poff + P + pix] = medp >= 0 ? dmed : 0.0f;
-  normal[3 * c.poff + pix] = N0;
-  normal[3 * c.poff + P + pix] = N1;
-  normal[3 * c.poff + 2 * P + pix] = N2;
-  alpha[c.poff + pix] = A;
-  t_final[c.poff + pix] = T;
-  last[c.poff + pix] = lastp;
-  median[c.poff + pix] = medp >= 0 ? (int32_t)pair_ids[c.rb + medp] : -1;
-  if (count) count[c.poff + pix] = cnt;
+  a.color[3 * c.poff + pix] = C0;
+  a.color[3 * c.poff + P + pix] = C1;
+  a.color[3 * c.poff + 2 * P + pix] = C2;
+  a.depth[2 * c.poff + pix] = D;
+  a.depth[2 * c.poff + P + pix] = medp >= 0 ? dmed : 0.0f;
+  a.normal[3 * c.poff + pix] = N0;
+  a.normal[3 * c.poff + P + pix] = N1;
+  a.normal[3 * c.poff + 2 * P + pix] = N2;
+  a.alpha[c.poff + pix] = A;
+  a.t_final[c.poff + pix] = T;
+  a.last[c.poff + pix] = lastp;
+  a.median[c.poff + pix] = medp >= 0 ? (int32_t)pair_ids[c.rb + medp] : -1;
+  if (a.count) a.count[c.poff + pix] = cnt;
 }
 
-// Sum 16 per-lane values over the wavefront.  On return lane l holds the
-// total of value index ((l>>5)&1)*8 + ((l>>4)&1)*4 + ((l>>3)&1)*2 + ((l>>2)&1).
-__device__ __forceinline__ float wave_transpose_sum16(float (&v)[16]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int half = 8, mask = 32; half >= 1; half >>= 1, mask >>= 1) {
-    const bool up = lane & mask;
-#pragma unroll
-    for (int k = 0; k < half; ++k) {
-      const float send = up ? v[k] : v[k + half];
-      const float keep = up ? v[k + half] : v[k];
-      v[k] = keep + __shfl_xor(send, mask, 64);
-    }
+// One workgroup per tile, tiles visited in `order` (or natural) order.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_render_fwd(FwdArgs a) {
+  __shared__ FwdShared<TW, TH> sh;
+  const int64_t i = blockIdx.x;
+  fwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[i] : i, sh);
+}
+
+// Persistent workgroups pull tiles from a device counter (zeroed before the
+// launch) in `order`; every workgroup exits once the counter passes the tile
+// count.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
+  __shared__ FwdShared<TW, TH> sh;
+  __shared__ uint32_t item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const uint32_t item = item_s;
+    __syncthreads();
+    if ((int64_t)item >= a.tiles) break;
+    fwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
   }
-  float s = v[0];
-  s += __shfl_xor(s, 2, 64);
-  s += __shfl_xor(s, 1, 64);
-  return s;
+}
+
+// Row (16-lane) sum by DPP: afterwards every lane of a row holds its row's
+// total.  quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror.
+__device__ __forceinline__ float dpp_row_sum(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
+  return x;
+}
+
+// Sum 16 per-lane values over the wavefront (a transpose-reduction).
+//   v_permlane32_swap(a, b): a' = [a.lo32, b.lo32], b' = [a.hi32, b.hi32], so
+//     a' + b' holds value k in lanes 0-31 and value k+8 in lanes 32-63;
+//   v_permlane16_swap(a, b): a' = [a.r0, b.r0, a.r2, b.r2], b' = [a.r1, b.r1,
+//     a.r3, b.r3] (16-lane rows), so a' + b' holds values k, k+4, k+8, k+12 in
+//     rows 0..3;
+//   then a DPP row sum of each of the 4 remaining values.
+// On return lane l with (l & 15) < 4 holds the total of value 4 (l >> 4) + (l & 3).
+__device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
+  float u[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]),
+                                                    __float_as_uint(v[k + 8]), false, false);
+    u[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  float w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(u[k]),
+                                                    __float_as_uint(u[k + 4]), false, false);
+    w[k] = dpp_row_sum(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+  }
+  const int j = threadIdx.x & 3;
+  return j == 0 ? w[0] : (j == 1 ? w[1] : (j == 2 ? w[2] : w[3]));
 }
 
 constexpr float kTwoOverLog2e = 2.0f / kLog2e;
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
-k_render_bwd(BlendParams bp, const rade_view* __restrict__ views, int V, int64_t N,
-             const rade_splat* __restrict__ splats, const uint32_t* __restrict__ pair_ids,
-             const uint32_t* __restrict__ ranges, const float* __restrict__ t_final,
-             const int32_t* __restrict__ last, const int32_t* __restrict__ median,
-             const float* __restrict__ d_color, const float* __restrict__ d_depth,
-             const float* __restrict__ d_normal, const float* __restrict__ d_alpha,
-             float* __restrict__ gsplat) {
+struct BwdShared {
+  StagedSplat ss[TileGeom<TW, TH>::BLOCK];
+  uint32_t sgid[TileGeom<TW, TH>::BLOCK];
+  uint64_t masks[TileGeom<TW, TH>::NW][TileGeom<TW, TH>::NW];
+  int smax;
+};
+
+// Backward pass of one tile (all threads of the workgroup take part).
+template <int TW, int TH>
+__device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShared<TW, TH>& sh) {
   using TG = TileGeom<TW, TH>;
-  __shared__ StagedSplat ss[TG::BLOCK];
-  __shared__ uint32_t sgid[TG::BLOCK];
-  __shared__ uint64_t masks[TG::NW][TG::NW];
-  __shared__ int smax;
-  const PixelCtx c = pixel_ctx<TW, TH>(views, V, ranges);
+  const BlendParams& bp = a.bp;
+  const rade_splat* __restrict__ splats = a.splats;
+  const uint32_t* __restrict__ pair_ids = a.pair_ids;
+  const float* __restrict__ t_final = a.t_final;
+  const int32_t* __restrict__ last = a.last;
+  const int32_t* __restrict__ median = a.median;
+  const float* __restrict__ d_color = a.d_color;
+  const float* __restrict__ d_depth = a.d_depth;
+  const float* __restrict__ d_normal = a.d_normal;
+  const float* __restrict__ d_alpha = a.d_alpha;
+  float* __restrict__ gsplat = a.gsplat;
+  StagedSplat* ss = sh.ss;
+  uint32_t* sgid = sh.sgid;
+  auto masks = sh.masks;
+  int& smax = sh.smax;
+  const PixelCtx c = pixel_ctx<TW, TH>(a.views, a.V, a.ranges, tile);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t vbase = (int64_t)c.v * N;
+  const int64_t vbase = (int64_t)c.v * a.N;
   const float fx = (float)c.lxi, fy = (float)c.lyi;
 
   float T = 0.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gM = 0.f;
@@ -320,10 +412,9 @@ k_render_bwd(BlendParams bp, const rade_view* __restrict__ views, int V, int64_t
           g[12] = w * gN0; g[13] = w * gN1; g[14] = w * gN2;
         }
         if (__any(has)) {
-          const float tot = wave_transpose_sum16(g);
-          const int vi = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
-                         ((lane >> 2) & 1);
-          if ((lane & 3) == 0 && vi < 15 && tot != 0.0f)
+          const float tot = wave_sum16(g);
+          const int vi = 4 * (lane >> 4) + (lane & 3);
+          if ((lane & 15) < 4 && vi < 15 && tot != 0.0f)
             atomicAdd(gsplat + (vbase + sgid[r]) * 16 + vi, tot);
         }
       }
@@ -332,33 +423,74 @@ k_render_bwd(BlendParams bp, const rade_view* __restrict__ views, int V, int64_t
   }
 }
 
+// One workgroup per tile, in `order` (or natural) order.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_render_bwd(BwdArgs a) {
+  __shared__ BwdShared<TW, TH> sh;
+  const int64_t i = blockIdx.x;
+  bwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[i] : i, sh);
+}
+
+// Persistent workgroups over a device work queue (see k_render_fwd_persistent).
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_render_bwd_persistent(BwdArgs a) {
+  __shared__ BwdShared<TW, TH> sh;
+  __shared__ uint32_t item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const uint32_t item = item_s;
+    __syncthreads();
+    if ((int64_t)item >= a.tiles) break;
+    bwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+  }
+}
+
 __global__ void k_zero(float* __restrict__ a, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0f;
 }
 
-template <int TW, int TH>
-void launch_fwd_t(const BlendParams& bp, const rade_view* views, int V, int64_t N,
-                  int64_t tiles, const rade_splat* splats, const uint32_t* ids,
-                  const uint32_t* ranges, float* color, float* depth, float* normal,
-                  float* alpha, float* tf, int32_t* last, int32_t* med, int32_t* cnt,
-                  hipStream_t st) {
-  EventScope timing(RADE_KERNEL_RENDER_FWD, st);
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)tiles),
-                     dim3(TileGeom<TW, TH>::BLOCK), 0, st, bp, views, V, N, splats, ids, ranges,
-                     color, depth, normal, alpha, tf, last, med, cnt);
+__global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
+
+// Workgroups that fit on the device at once for a kernel (cached per kernel).
+template <typename K>
+unsigned resident_blocks(K kernel, int block, unsigned cap) {
+  static unsigned cached = 0;
+  if (cached == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    cached = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
+  }
+  return cached < cap ? cached : cap;
 }
 
 template <int TW, int TH>
-void launch_bwd_t(const BlendParams& bp, const rade_view* views, int V, int64_t N,
-                  int64_t tiles, const rade_splat* splats, const uint32_t* ids,
-                  const uint32_t* ranges, const float* tf, const int32_t* last,
-                  const int32_t* med, const float* dc, const float* dd, const float* dn,
-                  const float* da, float* gs, hipStream_t st) {
+void launch_fwd_t(const FwdArgs& a, int schedule, hipStream_t st) {
+  constexpr int B = TileGeom<TW, TH>::BLOCK;
+  EventScope timing(RADE_KERNEL_RENDER_FWD, st);
+  if (schedule == RADE_SCHEDULE_PERSISTENT) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
+    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH>, B, (unsigned)a.tiles);
+    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH>), dim3(g), dim3(B), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
+  }
+}
+
+template <int TW, int TH>
+void launch_bwd_t(const BwdArgs& a, int schedule, hipStream_t st) {
+  constexpr int B = TileGeom<TW, TH>::BLOCK;
   EventScope timing(RADE_KERNEL_RENDER_BWD, st);
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)tiles),
-                     dim3(TileGeom<TW, TH>::BLOCK), 0, st, bp, views, V, N, splats, ids, ranges,
-                     tf, last, med, dc, dd, dn, da, gs);
+  if (schedule == RADE_SCHEDULE_PERSISTENT) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
+    const unsigned g = resident_blocks(k_render_bwd_persistent<TW, TH>, B, (unsigned)a.tiles);
+    hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH>), dim3(g), dim3(B), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
+  }
 }
 
 }  // namespace
@@ -368,54 +500,54 @@ bool tile_supported(int tw, int th) {
          (tw == 32 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 16);
 }
 
+#define RADE_TILE_DISPATCH(FN, ARGS)                          \
+  if (s.tile_w == 8 && s.tile_h == 8) FN<8, 8> ARGS;          \
+  else if (s.tile_w == 16 && s.tile_h == 16) FN<16, 16> ARGS; \
+  else if (s.tile_w == 16 && s.tile_h == 32) FN<16, 32> ARGS; \
+  else if (s.tile_w == 32 && s.tile_h == 16) FN<32, 16> ARGS; \
+  else if (s.tile_w == 16 && s.tile_h == 8) FN<16, 8> ARGS;   \
+  else if (s.tile_w == 8 && s.tile_h == 16) FN<8, 16> ARGS;   \
+  else return hipErrorInvalidValue;
+
 hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
-                             const uint32_t* ranges, float* color, float* depth,
-                             float* normal, float* alpha, float* tf, int32_t* last,
-                             int32_t* med, int32_t* cnt, hipStream_t st) {
+                             const uint32_t* ranges, const uint32_t* order, float* color,
+                             float* depth, float* normal, float* alpha, float* tf,
+                             int32_t* last, int32_t* med, int32_t* cnt, hipStream_t st) {
   if (tiles == 0) return hipSuccess;
-  const BlendParams bp = make_blend_params(s);
-#define RADE_FWD(TW, TH)                                                                      \
-  if (s.tile_w == TW && s.tile_h == TH) {                                                     \
-    launch_fwd_t<TW, TH>(bp, views, V, N, tiles, splats, ids, ranges, color, depth, normal, \
-                         alpha, tf, last, med, cnt, st);                                      \
-    return hipGetLastError();                                                                 \
-  }
-  RADE_FWD(8, 8)
-  RADE_FWD(16, 16)
-  RADE_FWD(16, 32)
-  RADE_FWD(32, 16)
-  RADE_FWD(16, 8)
-  RADE_FWD(8, 16)
-#undef RADE_FWD
-  return hipErrorInvalidValue;
+  FwdArgs a;
+  a.bp = make_blend_params(s);
+  a.views = views; a.V = V; a.N = N; a.tiles = tiles;
+  a.splats = splats; a.pair_ids = ids; a.ranges = ranges;
+  a.order = s.schedule == RADE_SCHEDULE_TILE ? nullptr : order;
+  a.queue = order ? const_cast<uint32_t*>(order) + tiles : nullptr;
+  a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
+  a.last = last; a.median = med; a.count = cnt;
+  RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, st))
+  return hipGetLastError();
 }
 
 hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
-                             const uint32_t* ranges, const float* tf, const int32_t* last,
-                             const int32_t* med, const float* dc, const float* dd,
-                             const float* dn, const float* da, float* gsplat,
+                             const uint32_t* ranges, const uint32_t* order, const float* tf,
+                             const int32_t* last, const int32_t* med, const float* dc,
+                             const float* dd, const float* dn, const float* da, float* gsplat,
                              hipStream_t st) {
   const int64_t ng = (int64_t)V * N * 16;
   if (ng > 0)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, gsplat, ng);
   if (tiles == 0) return hipGetLastError();
-  const BlendParams bp = make_blend_params(s);
-#define RADE_BWD(TW, TH)                                                                    \
-  if (s.tile_w == TW && s.tile_h == TH) {                                                   \
-    launch_bwd_t<TW, TH>(bp, views, V, N, tiles, splats, ids, ranges, tf, last, med, dc, dd, \
-                         dn, da, gsplat, st);                                               \
-    return hipGetLastError();                                                               \
-  }
-  RADE_BWD(8, 8)
-  RADE_BWD(16, 16)
-  RADE_BWD(16, 32)
-  RADE_BWD(32, 16)
-  RADE_BWD(16, 8)
-  RADE_BWD(8, 16)
-#undef RADE_BWD
-  return hipErrorInvalidValue;
+  BwdArgs a;
+  a.bp = make_blend_params(s);
+  a.views = views; a.V = V; a.N = N; a.tiles = tiles;
+  a.splats = splats; a.pair_ids = ids; a.ranges = ranges;
+  a.order = s.schedule == RADE_SCHEDULE_TILE ? nullptr : order;
+  a.queue = order ? const_cast<uint32_t*>(order) + tiles : nullptr;
+  a.t_final = tf; a.last = last; a.median = med;
+  a.d_color = dc; a.d_depth = dd; a.d_normal = dn; a.d_alpha = da;
+  a.gsplat = gsplat;
+  RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, st))
+  return hipGetLastError();
 }
 
 }  // namespace rade

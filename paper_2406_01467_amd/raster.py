@@ -21,6 +21,7 @@ class ForwardState:
     splats: Optional[torch.Tensor]
     pair_ids: torch.Tensor
     ranges: torch.Tensor
+    order: Optional[torch.Tensor]
     t_final: torch.Tensor
     last: torch.Tensor
     median: torch.Tensor
@@ -123,15 +124,27 @@ class Rasterizer:
         N = means.shape[0]
         splats, tt = self.project(means, scales, quats, opacities, sh, stream)
         pair_ids, ranges, M = self.bin_sort(N, splats, tt, stream=stream)
+        order = self.tile_order(ranges, stream)
         color, depth, normal, alpha, tf, last, med, cnt = self._new_maps(want_count)
         _lib.rade_render_fwd(self.settings, self.views_c, self.views_dev, self.V, N, splats,
                              pair_ids, ranges, color, depth, normal, alpha, tf, last, med, cnt,
-                             stream)
+                             stream, tile_order=order)
         # pair_ids are a view of a reusable buffer: keep a private copy for
         # the backward pass
-        state = ForwardState(splats if keep_splats else None, pair_ids.clone(), ranges, tf, last,
-                             med, M)
+        state = ForwardState(splats if keep_splats else None, pair_ids.clone(), ranges, order,
+                             tf, last, med, M)
         return Maps(color, depth, normal, alpha, cnt, state)
+
+    def tile_order(self, ranges, stream=None):
+        """Heavy-first tile order (None for the plain one-workgroup-per-tile
+        schedule)."""
+        if self.settings.schedule == _lib.RADE_SCHEDULE_TILE:
+            return None
+        order = torch.empty(self.total_tiles + 1, dtype=torch.int32, device=self.device)
+        ws = torch.empty(max(1, _lib.rade_tile_order_workspace(self.total_tiles)),
+                         dtype=torch.uint8, device=self.device)
+        _lib.rade_tile_order(self.settings, self.views_c, ranges, order, ws, stream)
+        return order
 
     # -- backward ------------------------------------------------------------
     def backward(self, state: ForwardState, means, scales, quats, opacities, sh, d_color=None,
@@ -150,7 +163,7 @@ class Rasterizer:
                              _aligned16(quats), opacities, sh, state.splats, state.pair_ids,
                              state.ranges, state.t_final, state.last, state.median, c(d_color),
                              c(d_depth), c(d_normal), c(d_alpha), dm, ds, dq, do, dsh, workspace,
-                             stream)
+                             stream, tile_order=state.order)
         return dm, ds, dq, do, dsh
 
 

@@ -30,7 +30,7 @@ def _declared():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = _declared()
-    assert len(names) == 10, names
+    assert len(names) == 12, names
     so = ctypes.CDLL(lib.LIB_PATH)
     for n in names:
         assert hasattr(so, n), n
@@ -73,7 +73,7 @@ def test_views_prepare_offsets():
     assert T2 == 4 * 5 + 2 * 2 + 1 and vc[0].tiles_x == 4
 
 
-@pytest.mark.parametrize("bad", [dict(tile_w=12), dict(tile_h=64), dict(sh_degree=4),
+@pytest.mark.parametrize("bad", [dict(tile_w=12), dict(tile_h=64), dict(sh_degree=4), dict(schedule=3),
                                  dict(alpha_min=0.0), dict(t_min=1.5), dict(power_cut=-1.0)])
 def test_invalid_settings_rejected_without_launch(bad):
     lib = _lib()

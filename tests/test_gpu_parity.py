@@ -305,27 +305,27 @@ def test_degenerate_inputs():
 # ---------------------------------------------------------------------------
 # backward
 
-def _grad_check(got, ref, label, tol=1e-4, normwise_tol=1e-5):
+def _grad_check(got, ref, scale, label, tol=1e-4, normwise_tol=1e-5):
     """Per parameter group: norm-wise ||g - g_ref|| / ||g_ref|| <= 1e-5, and
-    element-wise |g - g_ref| <= 1e-4 (|g_ref| + 0.1 rms(g_ref) + 1e-3
-    max|g_ref|).  A per-Gaussian gradient is a sum over pixels (and views) of
-    FP32 terms of both signs; its absolute round-off is a few units of FP32
-    round-off times the sum of the magnitudes of those terms (measured: about
-    2e-7 of the group's largest gradient), not of their possibly cancelling
-    sum, hence the floor."""
+    element-wise |g - g_ref| <= 1e-4 (|g_ref| + 0.1 S), where S is the
+    oracle's round-off scale of that element (sum over pixels of |term|,
+    pushed through |d param / d splat quantity|).  A gradient element is a
+    sum of per-pixel FP32 terms of both signs; its attainable accuracy is set
+    by the size of the terms, not by their (possibly cancelling) sum: the
+    bound allows 1e-5 S, about 170 units of FP32 round-off."""
     worst = {}
     for k in ref:
         r = np.asarray(ref[k], np.float64).reshape(ref[k].shape[0], -1)
         g = np.asarray(got[k], np.float64).reshape(r.shape)
+        S = np.asarray(scale[k], np.float64).reshape(r.shape)
         if r.size == 0:
             continue
-        rms = np.sqrt(np.mean(r * r)) + 1e-30
-        err = np.abs(g - r) / (np.abs(r) + 0.1 * rms + 1e-3 * np.abs(r).max())
+        err = np.abs(g - r) / (np.abs(r) + 0.1 * S + 1e-30)
         nrm = np.linalg.norm(g - r) / (np.linalg.norm(r) + 1e-30)
         i = np.unravel_index(np.argmax(err), err.shape)
         worst[k] = (float(err.max()), float(nrm))
         say(f"  grad {k}: normwise {nrm:.3g}; worst elem {err[i]:.3g} (ref {r[i]:.4g} got "
-            f"{g[i]:.4g}, rms {rms:.4g})")
+            f"{g[i]:.4g}, scale {S[i]:.4g}); max |err|/S {np.max(np.abs(g - r) / (S + 1e-30)):.3g}")
     say(label, "gradient errors (element, normwise)", worst)
     for k, (w, n) in worst.items():
         assert w <= tol and n <= normwise_tol, (label, k, w, n)
@@ -364,10 +364,12 @@ def _bwd_parity(scene, views, s, seed, label, pixels=None, recompute=False):
             gouts.append(g[pl])
         else:
             gouts.append(g)
-    ref = oracle.backward(st, views, scene, gouts, pixels=pix_lists if pixels is not None else None)
+    pl = pix_lists if pixels is not None else None
+    ref = oracle.backward(st, views, scene, gouts, pixels=pl)
+    scale = oracle.gradient_error_scale(st, views, scene, gouts, pixels=pl)
     got = dict(means=dm.cpu().numpy(), scales=ds.cpu().numpy(), quats=dq.cpu().numpy(),
                opacities=do.cpu().numpy(), sh=dsh.cpu().numpy())
-    _grad_check(got, ref, label)
+    _grad_check(got, ref, scale, label)
 
 
 def test_render_bwd_64x64_full():
@@ -393,3 +395,35 @@ def test_render_bwd_800x800_200k_sampled_pixels():
     rng = np.random.default_rng(34)
     pix = np.sort(rng.choice(views[0].pixels, 400, replace=False)).astype(np.int64)
     _bwd_parity(scene, views, _settings(sh_degree=3), 35, "bwd 800x800 sampled", pixels=pix)
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_schedules_match_one_workgroup_per_tile(schedule):
+    # Heavy-first order and the persistent work queue change only which
+    # workgroup processes a tile: maps are bitwise identical, gradients equal
+    # up to the order of the FP32 atomic additions.
+    import torch
+    dev = device()
+    from paper_2406_01467_amd.raster import Rasterizer
+    scene = synth.make_scene_clusters(20000, seed=14, width=200, height=150, dist_range=(2, 8))
+    views = [synth.identity_view(200, 150)] + synth.make_views_orbit(
+        scene.means.mean(0), 8.0, 2, seed=15, sizes=[(170, 96), (64, 200)])
+    params = to_dev(scene, dev)
+    outs = {}
+    for sch in (0, schedule):
+        rast = Rasterizer(views, _settings(sh_degree=3, schedule=sch), dev)
+        maps = rast.forward(*params, want_count=True)
+        rng = np.random.default_rng(3)
+        P = rast.total_pixels
+        g = [torch.from_numpy(rng.normal(size=k * P).astype(np.float32)).to(dev) for k in (3, 2, 3, 1)]
+        grads = rast.backward(maps.state, *params, *g)
+        torch.cuda.synchronize()
+        outs[sch] = (maps, [x.cpu().numpy() for x in grads])
+    m0, g0 = outs[0]
+    m1, g1 = outs[schedule]
+    for k in ("color", "depth", "normal", "alpha", "count"):
+        assert torch.equal(getattr(m0, k), getattr(m1, k)), k
+    for k in ("t_final", "last", "median"):
+        assert torch.equal(getattr(m0.state, k), getattr(m1.state, k)), k
+    for a, b in zip(g0, g1):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
