@@ -283,3 +283,77 @@ def gradient_error_scale(s: np.ndarray, views, scene, gouts, pixels=None) -> dic
             for k in r:
                 out[k] += np.abs(r[k])
     return out
+
+
+# ----------------------------------------------------------------------------
+# Normal-consistency regulariser (Sec. 3.4, Eq. 24), FP64 NumPy.
+
+def _abs_cross(a, b):
+    """Componentwise bound |a x b| <= (|a_y b_z| + |a_z b_y|, ...)."""
+    return np.stack([np.abs(a[1] * b[2]) + np.abs(a[2] * b[1]),
+                     np.abs(a[2] * b[0]) + np.abs(a[0] * b[2]),
+                     np.abs(a[0] * b[1]) + np.abs(a[1] * b[0])])
+
+
+def normal_consistency(view, depth_med, normal, alpha, weight, magnitude=False):
+    """Eq. 24 on the blended maps of one view: sum_i w_i (1 - n_i . n~) =
+    alpha - N . n~ per pixel, averaged over interior pixels and scaled by
+    ``weight``.  n~ is the unit normal of the back-projected median-depth map
+    from central differences, oriented towards the camera (zero where the
+    cross product vanishes).  depth_med (H,W), normal (3,H,W), alpha (H,W).
+    Returns (loss, dL/d depth_med, dL/d normal, dL/d alpha); n~ is not
+    detached."""
+    D = np.asarray(depth_med, np.float64)
+    Nm = np.asarray(normal, np.float64)
+    A = np.asarray(alpha, np.float64)
+    H, W = D.shape
+    gD = np.zeros((H, W))
+    gN = np.zeros((3, H, W))
+    gA = np.zeros((H, W))
+    if H < 3 or W < 3:
+        return 0.0, gD, gN, gA
+    fx, fy = float(np.float32(view.fx)), float(np.float32(view.fy))
+    cx, cy = float(np.float32(view.cx)), float(np.float32(view.cy))
+    xs = (np.arange(W) + 0.5 - cx) / fx
+    ys = (np.arange(H) + 0.5 - cy) / fy
+    r = np.stack([np.broadcast_to(xs[None, :], (H, W)), np.broadcast_to(ys[:, None], (H, W)),
+                  np.ones((H, W))])
+    P = D[None] * r                                   # back-projected points
+    du = P[:, 1:-1, 2:] - P[:, 1:-1, :-2]             # central differences
+    dv = P[:, 2:, 1:-1] - P[:, :-2, 1:-1]
+    c = np.cross(du, dv, axis=0)
+    nc = np.sqrt((c * c).sum(0))
+    ok = nc > 0
+    chat = np.where(ok, c / np.where(ok, nc, 1.0), 0.0)
+    s = np.where((c * P[:, 1:-1, 1:-1]).sum(0) > 0, -1.0, 1.0)
+    nt = s * chat
+    Ni, Ai = Nm[:, 1:-1, 1:-1], A[1:-1, 1:-1]
+    w = weight / ((H - 2) * (W - 2))
+    loss = w * float((Ai - (Ni * nt).sum(0)).sum())
+    gA[1:-1, 1:-1] = w
+    gN[:, 1:-1, 1:-1] = -w * nt
+    nd = (Ni * chat).sum(0)
+    gc = np.where(ok, -w * s * (Ni - nd * chat) / np.where(ok, nc, 1.0), 0.0)
+    g_du = np.cross(dv, gc, axis=0)
+    g_dv = np.cross(gc, du, axis=0)
+    gP = np.zeros((3, H, W))
+    gP[:, 1:-1, 2:] += g_du
+    gP[:, 1:-1, :-2] -= g_du
+    gP[:, 2:, 1:-1] += g_dv
+    gP[:, :-2, 1:-1] -= g_dv
+    gD = (gP * r).sum(0)
+    if not magnitude:
+        return loss, gD, gN, gA
+    # Round-off scale of dL/dD: the same recursion on magnitudes (the depth
+    # gradient is a discrete divergence whose terms cancel on smooth maps).
+    gc_m = np.where(ok, abs(w) * (np.abs(Ni) + np.abs(nd) * np.abs(chat)) /
+                    np.where(ok, nc, 1.0), 0.0)
+    gdu_m = _abs_cross(dv, gc_m)
+    gdv_m = _abs_cross(gc_m, du)
+    gP_m = np.zeros((3, H, W))
+    gP_m[:, 1:-1, 2:] += gdu_m
+    gP_m[:, 1:-1, :-2] += gdu_m
+    gP_m[:, 2:, 1:-1] += gdv_m
+    gP_m[:, :-2, 1:-1] += gdv_m
+    gD_mag = (gP_m * np.abs(r)).sum(0)
+    return loss, gD, gN, gA, gD_mag
