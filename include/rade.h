@@ -219,6 +219,27 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
                     void* workspace, size_t workspace_bytes, void* stream);
 
+/* Workspace bytes for rade_normal_consistency over `total_pixels` pixels. */
+size_t rade_normal_consistency_workspace(int64_t total_pixels);
+
+/* Normal-consistency regulariser (Sec. 3.4, Eq. 24) of rendered maps and its
+ * gradient.  Per view, over the interior pixels p (not on the border), with
+ * P(q) the back-projection of the median depth D (depth plane 1) through
+ * pixel q's centre:
+ *   c(p)  = (P(p + x) - P(p - x)) x (P(p + y) - P(p - y)),
+ *   n~(p) = c / |c| oriented towards the camera (0 where c = 0),
+ *   loss[v] = weight / n_interior * sum_p (alpha(p) - N(p) . n~(p)),
+ * which equals Eq. 24's sum_i w_i (1 - n_i . n~) because alpha and N are the
+ * blended weights and normals.  loss (V floats, device) is overwritten; the
+ * gradient is ADDED to d_depth (plane 1 only), d_normal and d_alpha (same
+ * planar layouts as the maps), so other loss terms can be accumulated there
+ * first.  n~ is not detached: the gradient reaches the median depth. */
+int rade_normal_consistency(const rade_view* views_host, const rade_view* views_dev, int32_t V,
+                            const float* depth, const float* normal, const float* alpha,
+                            float weight, float* loss, float* d_depth, float* d_normal,
+                            float* d_alpha, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
 /* Kernel timing without a profiler.  After this call, every launch of the
  * kernel `kernel` (one of RADE_KERNEL_*) is bracketed by hipEventRecord of
  * `start_event` and `stop_event` (hipEvent_t passed as void*) on the stream

@@ -121,6 +121,10 @@ def load() -> ctypes.CDLL:
     lib.rade_strerror.restype = ctypes.c_char_p
     lib.rade_abi_version.restype = ctypes.c_int
     lib.rade_set_kernel_events.argtypes = [ctypes.c_int, P, P]
+    lib.rade_normal_consistency_workspace.argtypes = [I64]
+    lib.rade_normal_consistency_workspace.restype = SZ
+    lib.rade_normal_consistency.argtypes = [P, P, I32] + [P] * 3 + [ctypes.c_float] + [P] * 5 + [SZ, P]
+    lib.rade_normal_consistency.restype = ctypes.c_int
     lib.rade_set_kernel_events.restype = ctypes.c_int
     for f in ("rade_views_prepare", "rade_project", "rade_bin_sort", "rade_render_fwd",
               "rade_render_bwd"):
@@ -132,7 +136,7 @@ def load() -> ctypes.CDLL:
 EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "rade_bin_sort",
             "rade_render_fwd", "rade_render_bwd_workspace", "rade_render_bwd", "rade_strerror",
             "rade_abi_version", "rade_set_kernel_events", "rade_tile_order_workspace",
-            "rade_tile_order"]
+            "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -276,3 +280,15 @@ def rade_render_bwd(settings: Settings, views_c, views_dev, V: int, N: int, mean
         _p(median), _p(d_color), _p(d_depth), _p(d_normal), _p(d_alpha), _p(d_means),
         _p(d_scales), _p(d_quats), _p(d_opacities), _p(d_sh), _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_render_bwd")
+
+
+def rade_normal_consistency_workspace(total_pixels: int) -> int:
+    return int(load().rade_normal_consistency_workspace(total_pixels))
+
+
+def rade_normal_consistency(views_c, views_dev, depth, normal, alpha, weight: float, loss, d_depth,
+                            d_normal, d_alpha, workspace, stream=None):
+    return _check(load().rade_normal_consistency(
+        views_c, _p(views_dev), len(views_c), _p(depth), _p(normal), _p(alpha), float(weight),
+        _p(loss), _p(d_depth), _p(d_normal), _p(d_alpha), _p(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)), "rade_normal_consistency")

@@ -36,6 +36,12 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
                              const float* dd, const float* dn, const float* da, float* gsplat,
                              hipStream_t st);
 size_t tile_order_workspace(int64_t tiles);
+size_t normal_consistency_workspace(int64_t total_pixels);
+hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
+                                     const float* depth, const float* normal,
+                                     const float* alpha, float weight, float* loss,
+                                     float* d_depth, float* d_normal, float* d_alpha, void* ws,
+                                     hipStream_t st);
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st);
 }  // namespace rade
@@ -186,6 +192,30 @@ int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t
   if (!workspace || workspace_bytes < rade_tile_order_workspace(tiles)) return RADE_ERR_WORKSPACE;
   return hip_status(rade::launch_tile_order(tile_ranges, tiles, tile_order, workspace,
                                             (hipStream_t)stream));
+}
+
+size_t rade_normal_consistency_workspace(int64_t total_pixels) {
+  return total_pixels < 0 ? 0 : rade::normal_consistency_workspace(total_pixels);
+}
+
+int rade_normal_consistency(const rade_view* views_host, const rade_view* views_dev, int32_t V,
+                            const float* depth, const float* normal, const float* alpha,
+                            float weight, float* loss, float* d_depth, float* d_normal,
+                            float* d_alpha, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  if (!views_ok(views_host, V) || !views_dev || !depth || !normal || !alpha || !loss ||
+      !d_depth || !d_normal || !d_alpha || !std::isfinite(weight))
+    return RADE_ERR_INVALID_ARG;
+  int64_t total = 0;
+  for (int i = 0; i < V; ++i) {
+    if (views_host[i].pix_offset != total) return RADE_ERR_INVALID_ARG;  // not prepared
+    total += (int64_t)views_host[i].width * views_host[i].height;
+  }
+  if (!workspace || workspace_bytes < rade_normal_consistency_workspace(total))
+    return RADE_ERR_WORKSPACE;
+  return hip_status(rade::launch_normal_consistency(views_dev, V, total, depth, normal, alpha,
+                                                    weight, loss, d_depth, d_normal, d_alpha,
+                                                    workspace, (hipStream_t)stream));
 }
 
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,

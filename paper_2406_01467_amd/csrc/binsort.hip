@@ -246,34 +246,68 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 }
 
 // ---------------------------------------------------------------------------
-// Pair emission: the j-th depth-sorted splat writes its tiles at offs[j].
+// Pair emission, one thread per pair: pair p belongs to the depth-sorted splat
+// j with offs[j] <= p < offs[j + 1] and is its (p - offs[j])-th tile in
+// row-major order of its tile rect.  A block covers kEmitPairs consecutive
+// pairs, hence at most kEmitPairs consecutive splats (each has >= 1 pair):
+// their offsets are staged in LDS and each thread finds its splat by binary
+// search there.  Writes are coalesced and the work is balanced whatever the
+// splat sizes.
+constexpr int kEmitPairs = 1024;
+
 __global__ void __launch_bounds__(kThreads)
 k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
        const uint32_t* __restrict__ n_dev, const uint64_t* __restrict__ m_dev,
-       int64_t capacity, const int32_t* __restrict__ tt, const rade_splat* __restrict__ splats,
+       int64_t capacity, const rade_splat* __restrict__ splats,
        const rade_view* __restrict__ views, int64_t N, int tile_w, int tile_h,
        uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids) {
-  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (j >= (int64_t)*n_dev || *m_dev > (uint64_t)capacity) return;
-  const uint32_t i = svals[j];
-  const int v = (int)(i / (uint64_t)N);
-  const uint32_t g = (uint32_t)(i - (uint64_t)v * N);
-  const rade_splat& s = splats[i];
-  const int tx0 = s.rect[0] / tile_w, tx1 = s.rect[1] / tile_w;
-  const int ty0 = s.rect[2] / tile_h, ty1 = s.rect[3] / tile_h;
-  const rade_view& vw = views[v];
-  const uint32_t tbase = (uint32_t)vw.tile_offset;
-  uint64_t o = offs[j];
-  // never write past this splat's slot (tiles_touched computed for another
-  // tile size) or past the capacity
-  const uint64_t end = min(o + (uint64_t)max(tt[i], 0), (uint64_t)capacity);
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      if (o >= end) return;
-      tkeys[o] = tbase + (uint32_t)(ty * vw.tiles_x + tx);
-      pids[o] = g;
-      ++o;
+  __shared__ uint64_t win[kEmitPairs + 1];
+  __shared__ int64_t j0_s;
+  const uint64_t M = *m_dev;
+  const int64_t nvis = *n_dev;
+  const uint64_t P0 = (uint64_t)blockIdx.x * kEmitPairs;
+  if (P0 >= M || M > (uint64_t)capacity) return;  // uniform per block
+  if (threadIdx.x == 0) {
+    // last j with offs[j] <= P0
+    int64_t lo = 0, hi = nvis - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= P0) lo = mid; else hi = mid - 1;
     }
+    j0_s = lo;
+  }
+  __syncthreads();
+  const int64_t j0 = j0_s;
+  for (int w = threadIdx.x; w <= kEmitPairs; w += kThreads) {
+    const int64_t j = j0 + w;
+    win[w] = j < nvis ? offs[j] : M;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kEmitPairs / kThreads; ++r) {
+    const uint64_t p = P0 + (uint64_t)r * kThreads + threadIdx.x;
+    if (p >= M) break;
+    int lo = 0, hi = kEmitPairs;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (win[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    const int64_t j = j0 + lo;
+    const uint64_t k = p - win[lo];
+    const uint32_t i = svals[j];
+    const int v = (int)(i / (uint64_t)N);
+    const uint32_t g = (uint32_t)(i - (uint64_t)v * N);
+    const rade_splat& sp = splats[i];
+    const int tx0 = sp.rect[0] / tile_w, tx1 = sp.rect[1] / tile_w;
+    const int ty0 = sp.rect[2] / tile_h, ty1 = sp.rect[3] / tile_h;
+    const int nx = tx1 - tx0 + 1;
+    // stay inside the rect even if tiles_touched disagrees with it
+    const int ty = min(ty0 + (int)(k / (uint64_t)nx), ty1);
+    const int tx = tx0 + (int)(k % (uint64_t)nx);
+    const rade_view& vw = views[v];
+    tkeys[p] = (uint32_t)vw.tile_offset + (uint32_t)(ty * vw.tiles_x + tx);
+    pids[p] = g;
+  }
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -314,8 +348,9 @@ k_keys(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ pids,
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Launch errors are left pending for the caller's final hipGetLastError.
 template <typename T, typename In>
-hipError_t scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
+void scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
                 hipStream_t st) {
   const int64_t nb = n_max > 0 ? (n_max + kTile - 1) / kTile : 1;
   hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3((unsigned)nb), dim3(kThreads), 0, st, in,
@@ -323,7 +358,6 @@ hipError_t scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_su
   hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kThreads), 0, st, block_sums, nb, total);
   hipLaunchKernelGGL((k_scan_down<T, In>), dim3((unsigned)nb), dim3(kThreads), 0, st, in, n_max,
                      n_dev, block_sums, out);
-  return hipGetLastError();
 }
 
 // Sorts (keys, vals) of *n_dev items (at most n_max) by the low `bits` bits
@@ -496,9 +530,10 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* ev = (tpasses & 1) ? pid1 : pair_ids;
   uint32_t* ok_ = tk1;
   uint32_t* ov = (tpasses & 1) ? pair_ids : pid1;
-  if (VN > 0)
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(VN, kThreads)), dim3(kThreads), 0, st, sv, offs,
-                       n_vis, m64, capacity, tt, splats, views_dev, N, s.tile_w, s.tile_h, ek, ev);
+  if (VN > 0 && capacity > 0)
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(capacity, kEmitPairs)), dim3(kThreads), 0, st, sv,
+                       offs, n_vis, m64, capacity, splats, views_dev, N, s.tile_w, s.tile_h, ek,
+                       ev);
   // 5. stable sort by tile
   radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, hist, (uint32_t*)sums, st);
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;

@@ -1,0 +1,184 @@
+// Normal-consistency regulariser on the rendered maps (Sec. 3.4, Eq. 24) and
+// its gradient, fused into two pixel-parallel kernels (gfx950).
+//
+// Per view, over interior pixels p (one pixel away from every border):
+//   P(q)  = D_med(q) * ((x_q + 1/2 - cx)/fx, (y_q + 1/2 - cy)/fy, 1)
+//           (back-projected median depth)
+//   c(p)  = (P(p+x) - P(p-x)) x (P(p+y) - P(p-y))   (central differences)
+//   n~(p) = s c / |c|, s = +-1 so that n~ faces the camera (n~ . P(p) <= 0)
+//   L_n   = weight / n_int * sum_p (A(p) - N(p) . n~(p))
+// Eq. 24 writes sum_i w_i (1 - n_i . n~) per pixel; with A = sum_i w_i and
+// N = sum_i w_i n_i that is A - N . n~, exactly, from the blended maps.
+// The gradient flows into A, N and (through n~, not detached) D_med.
+#include "common.hpp"
+
+namespace rade {
+namespace {
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ int view_of_pixel(const rade_view* views, int V, int64_t pix) {
+  int v = 0;
+  while (v + 1 < V && views[v + 1].pix_offset <= pix) ++v;
+  return v;
+}
+
+// Pass 1: per interior pixel, the loss term, dL/dA, dL/dN and the gradients
+// of the two difference vectors (6 floats, kept for pass 2).
+__global__ void __launch_bounds__(kT)
+k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const float* __restrict__ depth,
+           const float* __restrict__ normal, const float* __restrict__ alpha, float weight,
+           float* __restrict__ loss, float* __restrict__ d_normal, float* __restrict__ d_alpha,
+           float* __restrict__ gdiff, float* __restrict__ partial) {
+  const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+  float term = 0.0f;
+  int v = 0;
+  if (q < total) {
+    v = view_of_pixel(views, V, q);
+    const rade_view& vw = views[v];
+    const int64_t o = vw.pix_offset, P = (int64_t)vw.width * vw.height;
+    const int64_t pix = q - o;
+    const int px = (int)(pix % vw.width), py = (int)(pix / vw.width);
+    float* gd = gdiff + 6 * q;
+    const bool interior = px >= 1 && py >= 1 && px <= vw.width - 2 && py <= vw.height - 2;
+    if (!interior) {
+      for (int k = 0; k < 6; ++k) gd[k] = 0.0f;
+    } else {
+      const float wn = weight / (float)((vw.width - 2) * (vw.height - 2));
+      const float* Dm = depth + 2 * o + P;  // median plane
+      // Central differences of the back-projected points, written through
+      // depth differences so FP32 does not cancel |P| ~ D against |dP| ~ D/f:
+      // P(p +- x) = D(p +- x) (r(p) +- (1/fx, 0, 0)), r(p) = (rx, ry, 1).
+      const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
+      const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
+      const float Dl = Dm[pix - 1], Dr = Dm[pix + 1];
+      const float Du = Dm[pix - vw.width], Dd = Dm[pix + vw.width];
+      const float dx_ = Dr - Dl, sx = Dr + Dl;
+      const float dy_ = Dd - Du, sy = Dd + Du;
+      const float du[3] = {dx_ * rx + sx / vw.fx, dx_ * ry, dx_};
+      const float dv[3] = {dy_ * rx, dy_ * ry + sy / vw.fy, dy_};
+      const float Pc[3] = {Dm[pix] * rx, Dm[pix] * ry, Dm[pix]};
+      const float c[3] = {du[1] * dv[2] - du[2] * dv[1], du[2] * dv[0] - du[0] * dv[2],
+                          du[0] * dv[1] - du[1] * dv[0]};
+      const float cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+      const float N0 = normal[3 * o + pix], N1 = normal[3 * o + P + pix],
+                  N2 = normal[3 * o + 2 * P + pix];
+      const float A = alpha[o + pix];
+      float nt[3] = {0.f, 0.f, 0.f};
+      float gc[3] = {0.f, 0.f, 0.f};
+      if (cc > 1e-30f) {
+        const float inv = rsqrtf(cc);
+        const float s = (c[0] * Pc[0] + c[1] * Pc[1] + c[2] * Pc[2]) > 0.0f ? -1.0f : 1.0f;
+        const float ch[3] = {c[0] * inv, c[1] * inv, c[2] * inv};
+        for (int k = 0; k < 3; ++k) nt[k] = s * ch[k];
+        // dL/dc = -wn d(N . n~)/dc = -wn s (N - (N . c^) c^) / |c|
+        const float nd = N0 * ch[0] + N1 * ch[1] + N2 * ch[2];
+        const float Nv[3] = {N0, N1, N2};
+        for (int k = 0; k < 3; ++k) gc[k] = -wn * s * (Nv[k] - nd * ch[k]) * inv;
+      }
+      term = A - (N0 * nt[0] + N1 * nt[1] + N2 * nt[2]);
+      // d/d(du) = dv x gc, d/d(dv) = gc x du
+      gd[0] = dv[1] * gc[2] - dv[2] * gc[1];
+      gd[1] = dv[2] * gc[0] - dv[0] * gc[2];
+      gd[2] = dv[0] * gc[1] - dv[1] * gc[0];
+      gd[3] = gc[1] * du[2] - gc[2] * du[1];
+      gd[4] = gc[2] * du[0] - gc[0] * du[2];
+      gd[5] = gc[0] * du[1] - gc[1] * du[0];
+      d_alpha[o + pix] += wn;
+      d_normal[3 * o + pix] -= wn * nt[0];
+      d_normal[3 * o + P + pix] -= wn * nt[1];
+      d_normal[3 * o + 2 * P + pix] -= wn * nt[2];
+      term *= wn;
+    }
+  }
+  // loss value: a wave inside one view writes its sum to partial[wave] (the
+  // per-view sums are finished by k_nc_sum); a wave that straddles two views
+  // (rare) adds its terms atomically.
+  const int lane = threadIdx.x & 63;
+  const int v0 = __shfl(v, 0, 64);
+  const bool one_view = __all(v == v0);
+  const int64_t gw = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+  if (one_view) {
+    float x = term;
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    if (lane == 0) partial[gw] = x;
+  } else {
+    if (lane == 0) partial[gw] = 0.0f;
+    if (term != 0.0f) atomicAdd(loss + v, term);
+  }
+}
+
+// Per view (one workgroup each): sum of the wave partials over the view's
+// pixel range, added to loss[v].
+__global__ void __launch_bounds__(kT)
+k_nc_sum(const rade_view* __restrict__ views, int64_t n_waves, const float* __restrict__ partial,
+         float* __restrict__ loss) {
+  __shared__ float red[kT / 64];
+  const rade_view& vw = views[blockIdx.x];
+  const int64_t w0 = vw.pix_offset >> 6;
+  const int64_t w1 = min(n_waves, (vw.pix_offset + (int64_t)vw.width * vw.height + 63) >> 6);
+  float x = 0.0f;
+  for (int64_t w = w0 + threadIdx.x; w < w1; w += kT) x += partial[w];
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int i = 0; i < kT / 64; ++i) t += red[i];
+    atomicAdd(loss + blockIdx.x, t);
+  }
+}
+
+// Pass 2: dL/dD_med(q) = r(q) . (g_du(q-x) - g_du(q+x) + g_dv(q-y) - g_dv(q+y)).
+__global__ void __launch_bounds__(kT)
+k_nc_pass2(const rade_view* __restrict__ views, int V, int64_t total,
+           const float* __restrict__ gdiff, float* __restrict__ d_depth) {
+  const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (q >= total) return;
+  const int v = view_of_pixel(views, V, q);
+  const rade_view& vw = views[v];
+  const int64_t o = vw.pix_offset, P = (int64_t)vw.width * vw.height;
+  const int64_t pix = q - o;
+  const int px = (int)(pix % vw.width), py = (int)(pix / vw.width);
+  float g[3] = {0.f, 0.f, 0.f};
+  // each neighbour's entry is zero when that neighbour is not interior
+  if (px >= 1) for (int k = 0; k < 3; ++k) g[k] += gdiff[6 * (q - 1) + k];
+  if (px + 1 < vw.width) for (int k = 0; k < 3; ++k) g[k] -= gdiff[6 * (q + 1) + k];
+  if (py >= 1) for (int k = 0; k < 3; ++k) g[k] += gdiff[6 * (q - vw.width) + 3 + k];
+  if (py + 1 < vw.height) for (int k = 0; k < 3; ++k) g[k] -= gdiff[6 * (q + vw.width) + 3 + k];
+  const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
+  const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
+  d_depth[2 * o + P + pix] += g[0] * rx + g[1] * ry + g[2];
+}
+
+__global__ void k_zero_f(float* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0f;
+}
+
+}  // namespace
+
+size_t normal_consistency_workspace(int64_t total_pixels) {
+  const int64_t waves = (total_pixels + kT - 1) / kT * (kT / 64);
+  return (size_t)total_pixels * 6 * sizeof(float) + (size_t)waves * sizeof(float) + 256;
+}
+
+hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
+                                     const float* depth, const float* normal,
+                                     const float* alpha, float weight, float* loss,
+                                     float* d_depth, float* d_normal, float* d_alpha, void* ws,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f, dim3((V + 255) / 256), dim3(256), 0, st, loss, V);
+  if (total == 0) return hipGetLastError();
+  float* gdiff = static_cast<float*>(ws);
+  const unsigned blocks = (unsigned)((total + kT - 1) / kT);
+  const int64_t n_waves = (int64_t)blocks * (kT / 64);
+  float* partial = gdiff + 6 * total;
+  hipLaunchKernelGGL(k_nc_pass1, dim3(blocks), dim3(kT), 0, st, views, V, total, depth, normal,
+                     alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
+  hipLaunchKernelGGL(k_nc_sum, dim3(V), dim3(kT), 0, st, views, n_waves, partial, loss);
+  hipLaunchKernelGGL(k_nc_pass2, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff, d_depth);
+  return hipGetLastError();
+}
+
+}  // namespace rade

@@ -105,12 +105,59 @@ __device__ __forceinline__ void sh_grad(int deg, double x, double y, double z, c
   g[1] += kY3a * 6.0 * x * y * c[15];
 }
 
-// Colour of one view: max(0, sum_k coef_k Y_k(dir) + 1/2) per channel
-// (coefficients read from memory as they are used).  raw[] keeps the
-// unclamped values for the clamp decision of the backward pass.
+// One Gaussian's 3K SH coefficients (row g of the N x K x 3 array) in
+// registers.  VEC: the row is a whole number of 16-byte words and aligned,
+// so it moves in dwordx4 loads/stores (a wave's 64 rows are 64 separate
+// cache lines per instruction; 4x fewer instructions than dword access).
+template <int K, bool VEC>
+__device__ __forceinline__ void load_row(const float* __restrict__ p, float (&c)[3 * K]) {
+  if constexpr (VEC) {
+    const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 3 * K / 4; ++i) {
+      const float4 t = p4[i];
+      c[4 * i] = t.x; c[4 * i + 1] = t.y; c[4 * i + 2] = t.z; c[4 * i + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) c[i] = p[i];
+  }
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void store_row(float* __restrict__ p, const float (&c)[3 * K],
+                                          bool accumulate) {
+  if constexpr (VEC) {
+    float4* p4 = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 3 * K / 4; ++i) {
+      float4 t = make_float4(c[4 * i], c[4 * i + 1], c[4 * i + 2], c[4 * i + 3]);
+      if (accumulate) {
+        const float4 o = p4[i];
+        t.x += o.x; t.y += o.y; t.z += o.z; t.w += o.w;
+      }
+      p4[i] = t;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) p[i] = accumulate ? p[i] + c[i] : c[i];
+  }
+}
+
 template <int K>
-__device__ __forceinline__ void sh_colour(int deg, const double* dir,
-                                          const float* __restrict__ coef, double* raw) {
+__device__ __forceinline__ bool row_finite(const float (&c)[3 * K]) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) ok = ok && isfinite(c[i]);
+  return ok;
+}
+
+// Colour of one view: max(0, sum_k coef_k Y_k(dir) + 1/2) per channel.
+// raw[] keeps the unclamped values for the clamp decision of the backward
+// pass.
+template <int K>
+__device__ __forceinline__ void sh_colour(int deg, const double* dir, const float (&coef)[3 * K],
+                                          double* raw) {
   double Y[16];
   sh_basis(deg, dir[0], dir[1], dir[2], Y);
   raw[0] = raw[1] = raw[2] = 0.0;
@@ -129,13 +176,6 @@ __device__ __forceinline__ double view_dir(const double* mu, const double* C, do
   const double idn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   u[0] = d0 * idn; u[1] = d1 * idn; u[2] = d2 * idn;
   return idn;
-}
-
-// Every SH coefficient of a Gaussian finite?
-__device__ __forceinline__ bool sh_finite(const float* __restrict__ c, int n) {
-  bool ok = true;
-  for (int i = 0; i < n; ++i) ok = ok && isfinite(c[i]);
-  return ok;
 }
 
 struct ViewD {
@@ -286,7 +326,7 @@ __device__ __forceinline__ void store_invisible(rade_splat* out) {
   *out = s;
 }
 
-template <int KMAX>
+template <int KMAX, bool VEC>
 __global__ void __launch_bounds__(256)
 k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
           const float* __restrict__ means, const float* __restrict__ scales,
@@ -297,14 +337,22 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   if (g >= N) return;
   const int deg = st.sh_degree;
   constexpr int K = KMAX;
-  const float* __restrict__ coef = sh + 3 * K * g;
+  const float* __restrict__ coef_g = sh + 3 * K * g;
   Params P;
-  const bool ok = load_params(g, means, scales, quats, opac, P) && sh_finite(coef, 3 * K);
+  const bool ok = load_params(g, means, scales, quats, opac, P);
   for (int vi = 0; vi < V; ++vi) {
     const int64_t o = (int64_t)vi * N + g;
     const ViewD v = load_view(views[vi], st.fov_clamp);
     Geo G;
-    if (!ok || !geometry(v, P, st, G) || !(G.detD > 0.0)) {
+    // coefficients loaded per view, after the geometry (L1/L2 after the
+    // first view), so they are not live across it
+    float coef[3 * K];
+    bool vis = ok && geometry(v, P, st, G) && G.detD > 0.0;
+    if (vis) {
+      load_row<K, VEC>(coef_g, coef);
+      vis = row_finite<K>(coef);
+    }
+    if (!vis) {
       store_invisible(splats + o);
       tiles_touched[o] = 0;
       continue;
@@ -344,7 +392,6 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
     out.n[0] = (float)(G.nr[0] * inl);
     out.n[1] = (float)(G.nr[1] * inl);
     out.n[2] = (float)(G.nr[2] * inl);
-    // colour: coefficients streamed from memory (L1/L2 after the first view)
     {
       double u[3], raw[3];
       view_dir(P.mu, v.C, u);
@@ -386,7 +433,7 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
 // du, dv, da, db, dc (conic), do, drgb[3], dz, dp[2], dn[3], pad.
 constexpr int kGradStride = 16;
 
-template <int KMAX>
+template <int KMAX, bool VEC>
 __global__ void __launch_bounds__(256)
 k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
               const float* __restrict__ means, const float* __restrict__ scales,
@@ -399,10 +446,15 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
   if (g >= N) return;
   const int deg = st.sh_degree;
   constexpr int K = KMAX;
-  const float* __restrict__ coef = sh + 3 * K * g;
+  const float* __restrict__ coef_g = sh + 3 * K * g;
   float* __restrict__ gcoef = d_sh + 3 * K * g;
   Params P;
-  const bool ok = load_params(g, means, scales, quats, opac, P) && sh_finite(coef, 3 * K);
+  bool ok = load_params(g, means, scales, quats, opac, P);
+  {
+    float coef[3 * K];
+    load_row<K, VEC>(coef_g, coef);
+    ok = ok && row_finite<K>(coef);
+  }
   bool sh_written = false;
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gqn[4] = {0, 0, 0, 0}, go = 0.0;
   for (int vi = 0; ok && vi < V; ++vi) {
@@ -556,6 +608,8 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     // --- colour -> SH coefficients (accumulated in place in d_sh) and the
     // viewing direction
     {
+      float coef[3 * K], gc_row[3 * K];
+      load_row<K, VEC>(coef_g, coef);
       double u[3], raw[3];
       const double idn = view_dir(P.mu, v.C, u);
       sh_colour<K>(deg, u, coef, raw);
@@ -571,13 +625,11 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
       for (int k = 0; k < K; ++k) {
         const double c0 = coef[3 * k + 0], c1 = coef[3 * k + 1], c2 = coef[3 * k + 2];
         cw[k] = g0 * c0 + g1 * c1 + g2 * c2;
-        const float a0 = (float)(g0 * Y[k]), a1 = (float)(g1 * Y[k]), a2 = (float)(g2 * Y[k]);
-        if (sh_written) {
-          gcoef[3 * k + 0] += a0; gcoef[3 * k + 1] += a1; gcoef[3 * k + 2] += a2;
-        } else {
-          gcoef[3 * k + 0] = a0; gcoef[3 * k + 1] = a1; gcoef[3 * k + 2] = a2;
-        }
+        gc_row[3 * k + 0] = (float)(g0 * Y[k]);
+        gc_row[3 * k + 1] = (float)(g1 * Y[k]);
+        gc_row[3 * k + 2] = (float)(g2 * Y[k]);
       }
+      store_row<K, VEC>(gcoef, gc_row, sh_written);
       sh_written = true;
       double gu[3];
       sh_grad(deg, u[0], u[1], u[2], cw, gu);
@@ -599,8 +651,12 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     d_scales[3 * g + i] = ok ? (float)gs[i] : 0.0f;
   }
   d_opac[g] = ok ? (float)go : 0.0f;
-  if (!sh_written)
-    for (int i = 0; i < 3 * K; ++i) gcoef[i] = 0.0f;
+  if (!sh_written) {
+    float zero[3 * K];
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) zero[i] = 0.0f;
+    store_row<K, VEC>(gcoef, zero, false);
+  }
 }
 
 }  // namespace
@@ -613,12 +669,17 @@ hipError_t launch_project(const rade_settings& st, const rade_view* views, int V
   const dim3 block(256);
   const dim3 grid((unsigned)((N + 255) / 256));
   EventScope timing(RADE_KERNEL_PROJECT, stream);
+  const bool vec = (reinterpret_cast<uintptr_t>(sh) & 15) == 0;
+#define RADE_PROJECT(K, V4)                                                                 \
+  hipLaunchKernelGGL((k_project<K, V4>), grid, block, 0, stream, st, views, V, N, means,    \
+                     scales, quats, opac, sh, splats, tiles_touched)
   switch (st.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<1>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
-    case 1: hipLaunchKernelGGL(k_project<4>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
-    case 2: hipLaunchKernelGGL(k_project<9>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
-    default: hipLaunchKernelGGL(k_project<16>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, splats, tiles_touched); break;
+    case 0: RADE_PROJECT(1, false); break;
+    case 1: if (vec) RADE_PROJECT(4, true); else RADE_PROJECT(4, false); break;
+    case 2: RADE_PROJECT(9, false); break;
+    default: if (vec) RADE_PROJECT(16, true); else RADE_PROJECT(16, false); break;
   }
+#undef RADE_PROJECT
   return hipGetLastError();
 }
 
@@ -631,12 +692,17 @@ hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, i
   const dim3 block(256);
   const dim3 grid((unsigned)((N + 255) / 256));
   EventScope timing(RADE_KERNEL_PROJECT_BWD, stream);
+  const bool vec = ((reinterpret_cast<uintptr_t>(sh) | reinterpret_cast<uintptr_t>(d_sh)) & 15) == 0;
+#define RADE_PROJECT_BWD(K, V4)                                                             \
+  hipLaunchKernelGGL((k_project_bwd<K, V4>), grid, block, 0, stream, st, views, V, N, means, \
+                     scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh)
   switch (st.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<4>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<9>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
-    default: hipLaunchKernelGGL(k_project_bwd<16>, grid, block, 0, stream, st, views, V, N, means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh); break;
+    case 0: RADE_PROJECT_BWD(1, false); break;
+    case 1: if (vec) RADE_PROJECT_BWD(4, true); else RADE_PROJECT_BWD(4, false); break;
+    case 2: RADE_PROJECT_BWD(9, false); break;
+    default: if (vec) RADE_PROJECT_BWD(16, true); else RADE_PROJECT_BWD(16, false); break;
   }
+#undef RADE_PROJECT_BWD
   return hipGetLastError();
 }
 

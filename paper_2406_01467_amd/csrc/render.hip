@@ -104,12 +104,44 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
   return c;
 }
 
+// Does the splat's support reach the 8x8 block of pixel offsets [bx, bx+7] x
+// [by, by+7] (relative to the tile's first pixel centre)?  The factored
+// power Q = (w0 dx + w1 dy)^2 + (w2 dx + w3 dy)^2, dx = ur - x, dy = vr - y,
+// is convex, so its minimum over the block's rectangle is 0 when the centre
+// lies inside and is otherwise reached on an edge, where it is a 1-D
+// quadratic minimised in closed form.  The block is kept when that minimum
+// is within the support bound tau2 (with a margin far above FP32 round-off:
+// skipping a block must never drop a blend the pixel loop would take).
+__device__ __forceinline__ bool block_reached(float ur, float vr, float w0, float w1, float w2,
+                                              float w3, float A, float B, float C, float invA,
+                                              float invC, float tau2, int bx, int by) {
+  const float xlo = ur - (float)(bx + 7), xhi = ur - (float)bx;
+  const float ylo = vr - (float)(by + 7), yhi = vr - (float)by;
+  if (xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f) return true;
+  auto q = [&](float dx, float dy) {
+    const float t1 = fmaf(w0, dx, w1 * dy), t2 = fmaf(w2, dx, w3 * dy);
+    return fmaf(t1, t1, t2 * t2);
+  };
+  auto on_x_edge = [&](float X) {  // dx = X, dy free in [ylo, yhi]
+    const float dy = fminf(fmaxf(-B * X * invC, ylo), yhi);
+    return q(X, dy);
+  };
+  auto on_y_edge = [&](float Y) {  // dy = Y, dx free in [xlo, xhi]
+    const float dx = fminf(fmaxf(-B * Y * invA, xlo), xhi);
+    return q(dx, Y);
+  };
+  const float m = fminf(fminf(on_x_edge(xlo), on_x_edge(xhi)), fminf(on_y_edge(ylo), on_y_edge(yhi)));
+  return m <= tau2;
+}
+
 // Stage splat `idx` of the tile list into LDS slot threadIdx.x and return
-// the bit set of 8x8 blocks its support rect touches.
+// the bit set of 8x8 blocks its support reaches (support rect first, then
+// the exact ellipse-against-block test).
 template <int TW, int TH>
 __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats, int64_t vbase,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
-                                          const PixelCtx& c, StagedSplat* ss, uint32_t* sgid) {
+                                          const PixelCtx& c, const BlendParams& bp,
+                                          StagedSplat* ss, uint32_t* sgid) {
   using TG = TileGeom<TW, TH>;
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
@@ -130,6 +162,22 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
   for (int k = 0; k < TG::NW; ++k) {
     const int bx = 8 * (k % TG::NWX), by = 8 * (k / TG::NWX);
     if (rx0 <= bx + 7 && rx1 >= bx && ry0 <= by + 7 && ry1 >= by) bits |= 1u << k;
+  }
+  if (bits & (bits - 1)) {
+    // more than one block inside the rect: drop those the ellipse misses.
+    // Support: power <= cut and opacity 2^-power >= alpha_min.
+    const float A = fmaf(s.w0, s.w0, s.w2 * s.w2), B = fmaf(s.w0, s.w1, s.w2 * s.w3);
+    const float C = fmaf(s.w1, s.w1, s.w3 * s.w3);
+    const float invA = A > 0.0f ? 1.0f / A : 0.0f, invC = C > 0.0f ? 1.0f / C : 0.0f;
+    const float lo = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
+    const float tau2 = fminf(bp.cut2, lo) * 1.001f + 0.01f;
+#pragma unroll
+    for (int k = 0; k < TG::NW; ++k) {
+      const int bx = 8 * (k % TG::NWX), by = 8 * (k / TG::NWX);
+      if (((bits >> k) & 1u) &&
+          !block_reached(s.ur, s.vr, s.w0, s.w1, s.w2, s.w3, A, B, C, invA, invC, tau2, bx, by))
+        bits &= ~(1u << k);
+    }
   }
   return bits;
 }
@@ -176,7 +224,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
     if (__syncthreads_and(done ? 1 : 0)) break;
     const uint32_t idx = b0 + threadIdx.x;
     uint32_t bits = 0;
-    if (idx < c.re) bits = stage<TW, TH>(splats, vbase, pair_ids, idx, c, ss, sgid);
+    if (idx < c.re) bits = stage<TW, TH>(splats, vbase, pair_ids, idx, c, bp, ss, sgid);
     publish_masks<TW, TH>(bits, masks);
     __syncthreads();
     bool wave_live = !__all(done);
@@ -366,7 +414,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
     const int bstart = bend > TG::BLOCK ? bend - TG::BLOCK : 0;
     const int li = bstart + (int)threadIdx.x;
     uint32_t bits = 0;
-    if (li < bend) bits = stage<TW, TH>(splats, vbase, pair_ids, c.rb + (uint32_t)li, c, ss, sgid);
+    if (li < bend) bits = stage<TW, TH>(splats, vbase, pair_ids, c.rb + (uint32_t)li, c, bp, ss, sgid);
     publish_masks<TW, TH>(bits, masks);
     __syncthreads();
     for (int cw = TG::NW - 1; cw >= 0; --cw) {
