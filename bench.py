@@ -17,7 +17,7 @@ Default workload: 1,000,000 Gaussians (64 anisotropic clusters at distance
 2..20, SH degree 3) seen by one 1600x1064 view.
 
 Prints one JSON line: value = splat-pixel blends per second, ms_per_step =
-fwd+bwd milliseconds per view; roofline of the dominant kernel (HIP events
+fwd+bwd milliseconds per step (all views), ms_per_view = the same per view; roofline of the dominant kernel (HIP events
 recorded by the library around its launches); the eager autograd path
 (torch.autograd.Function + torch loss) for comparison; the FP64 CPU oracle
 timed on a bounded pixel sample.
@@ -75,6 +75,9 @@ def parse():
                     help="steps of the eager autograd path timed for comparison (0: skip)")
     ap.add_argument("--recompute", action="store_true",
                     help="keep no splats for the backward pass")
+    ap.add_argument("--unbatched-steps", type=int, default=5,
+                    help="with several views: steps of the unbatched form (each view its own "
+                         "graph-replayed plan, run one after another) for comparison (0: skip)")
     return ap.parse_args()
 
 
@@ -188,6 +191,31 @@ def main():
         _lib.rade_set_kernel_events(kid, None, None)
     kernel_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in events[k]])) for k in kinds}
 
+    # several views: the same step unbatched (one plan per view, replayed
+    # one after another) for comparison with the one-launch-per-kernel batch
+    unbatched_ms = None
+    if V > 1 and args.unbatched_steps > 0:
+        singles = []
+        for vc, v in zip(rast.views_c, views):
+            r1 = Rasterizer([v], settings, dev)
+            tv = target[3 * vc.pix_offset: 3 * (vc.pix_offset + vc.width * vc.height)]
+            p1 = BatchedPlan([v], settings, params, make_grad_fn(r1, tv),
+                             recompute=args.recompute)
+            p1.step()
+            singles.append(p1)
+        for p1 in singles:
+            p1.replay()
+        torch.cuda.synchronize()
+        tu = time.perf_counter()
+        for _ in range(args.unbatched_steps):
+            for p1 in singles:
+                p1.replay()
+        torch.cuda.synchronize()
+        unbatched_ms = 1e3 * (time.perf_counter() - tu) / args.unbatched_steps
+        if any(p1.overflowed() for p1 in singles):
+            raise RuntimeError("pair capacity overflow in the unbatched plans")
+        del singles
+
     # the eager autograd path (user-facing API, torch loss) for comparison
     eager_ms = None
     if args.eager_steps > 0:
@@ -220,7 +248,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step / V,
+        "ms_per_step": ms_step,
+        "ms_per_view": ms_step / V,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -240,6 +269,7 @@ def main():
         "pairs_per_view": pairs / V,
         "kernel_ms": kernel_ms,
         "ms_per_view_eager_autograd": None if eager_ms is None else eager_ms / V,
+        "ms_per_view_unbatched": None if unbatched_ms is None else unbatched_ms / V,
         "hbm_roofline_whole_step": {"algorithmic_bytes": alg_bytes,
                                     "floor_ms": alg_bytes / (PEAK_HBM_GBS * 1e9) * 1e3,
                                     "frac": alg_bytes / (PEAK_HBM_GBS * 1e9) / (ms_step * 1e-3)},

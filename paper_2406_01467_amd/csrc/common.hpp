@@ -55,12 +55,12 @@ __device__ __forceinline__ bool splat_alpha(const StagedSplat& s, float dx, floa
   t1 = fmaf(s.w0, dx, s.w1 * dy);
   t2 = fmaf(s.w2, dx, s.w3 * dy);
   const float pw = fmaf(t1, t1, t2 * t2);
-  if (pw > bp.cut2) return false;
+  // evaluated on every lane (no branch): alpha <= alpha_max < 1 always
   e = __builtin_amdgcn_exp2f(-pw);
   const float raw = s.o * e;
   clamped = raw > bp.alpha_max;
   alpha = clamped ? bp.alpha_max : raw;
-  return alpha >= bp.alpha_min;
+  return pw <= bp.cut2 && alpha >= bp.alpha_min;
 }
 
 // Tile of a global tile index: linear search over the (few) views.

@@ -38,6 +38,18 @@ struct TileGeom {
   static_assert(TW % 8 == 0 && TH % 8 == 0 && BLOCK <= 1024, "tile");
 };
 
+// A value every lane of the wavefront holds alike, moved to scalar registers
+// (so loops and LDS addresses driven by it stay scalar).
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 struct PixelCtx {
   int v;
   int64_t tile;
@@ -211,7 +223,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
   const PixelCtx c = pixel_ctx<TW, TH>(a.views, a.V, a.ranges, tile);
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_index();
   const int64_t vbase = (int64_t)c.v * a.N;
   const float fx = (float)c.lxi, fy = (float)c.lyi;
 
@@ -229,7 +241,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
     __syncthreads();
     bool wave_live = !__all(done);
     for (int cw = 0; cw < TG::NW && wave_live; ++cw) {
-      uint64_t m = masks[wave][cw];
+      uint64_t m = uniform_u64(masks[wave][cw]);
       while (m) {
         const int j = __builtin_ctzll(m);
         m &= m - 1;
@@ -238,24 +250,26 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, e, al;
         bool cl;
-        if (!done && splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl)) {
-          const float Tn = T * (1.0f - al);
-          if (Tn < bp.t_min) {
-            done = true;
-          } else {
-            const float w = al * T;
-            const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
-            C0 = fmaf(w, s.r, C0); C1 = fmaf(w, s.g, C1); C2 = fmaf(w, s.b, C2);
-            D = fmaf(w, d, D);
-            N0 = fmaf(w, s.n0, N0); N1 = fmaf(w, s.n1, N1); N2 = fmaf(w, s.n2, N2);
-            A += w;
-            const int pos = (int)(b0 - c.rb) + r;
-            if (T > 0.5f) { medp = pos; dmed = d; }
-            lastp = pos;
-            ++cnt;
-            T = Tn;
-          }
-        }
+        // Branch-free blend: lanes that do not take the splat add w = 0
+        // (x + 0 * finite = x exactly) and keep their state.
+        const bool pass = splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl) && !done;
+        const float Tn = T * (1.0f - al);
+        const bool stop = pass && Tn < bp.t_min;
+        const bool take = pass && !stop;
+        done = done || stop;
+        const float w = take ? al * T : 0.0f;
+        const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
+        C0 = fmaf(w, s.r, C0); C1 = fmaf(w, s.g, C1); C2 = fmaf(w, s.b, C2);
+        D = fmaf(w, d, D);
+        N0 = fmaf(w, s.n0, N0); N1 = fmaf(w, s.n1, N1); N2 = fmaf(w, s.n2, N2);
+        A += w;
+        const int pos = (int)(b0 - c.rb) + r;
+        const bool med_here = take && T > 0.5f;
+        medp = med_here ? pos : medp;
+        dmed = med_here ? d : dmed;
+        lastp = take ? pos : lastp;
+        cnt += take ? 1 : 0;
+        T = take ? Tn : T;
         if (__all(done)) { wave_live = false; break; }
       }
     }
@@ -372,7 +386,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
   auto masks = sh.masks;
   int& smax = sh.smax;
   const PixelCtx c = pixel_ctx<TW, TH>(a.views, a.V, a.ranges, tile);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int64_t vbase = (int64_t)c.v * a.N;
   const float fx = (float)c.lxi, fy = (float)c.lyi;
 
@@ -405,6 +419,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
   int wlast = lastp;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, __shfl_xor(wlast, d, 64));
+  wlast = __builtin_amdgcn_readfirstlane(wlast);
   __syncthreads();
   // records to visit: up to the furthest last blend of the tile (clamped to
   // the list length in case the saved state does not match the lists)
@@ -418,52 +433,57 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
     publish_masks<TW, TH>(bits, masks);
     __syncthreads();
     for (int cw = TG::NW - 1; cw >= 0; --cw) {
-      if (bstart + cw * 64 > wlast) continue;  // wave-uniform: nothing at or below our last
-      uint64_t m = masks[wave][cw];
+      const int lim = wlast - (bstart + cw * 64);  // wave-uniform
+      if (lim < 0) continue;  // nothing at or below our last blend
+      uint64_t m = uniform_u64(masks[wave][cw]);
+      if (lim < 63) m &= (2ull << lim) - 1;  // positions up to wlast
       while (m) {
         const int j = 63 - __builtin_clzll(m);
         m &= ~(1ull << j);
         const int r = cw * 64 + j;
         const int pos = bstart + r;
-        if (pos > wlast) continue;
         const StagedSplat s = ss[r];
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, e, al;
         bool cl;
+        const bool has = splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl) && pos <= lastp;
+        if (!__any(has)) continue;
+        // Branch-free adjoint: every lane evaluates, lanes without this
+        // splat contribute zeros and keep their state (alpha <= alpha_max,
+        // so 1 / (1 - alpha) is finite on every lane).
+        const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+        const float Ti = T * inv;
+        const float w = al * Ti;
+        const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
+        const float sf = gC0 * s.r + gC1 * s.g + gC2 * s.b + gD * d + gN0 * s.n0 +
+                         gN1 * s.n1 + gN2 * s.n2 + gA;
+        const float ga = Ti * sf - Racc * inv;
+        T = has ? Ti : T;
+        Racc = has ? fmaf(w, sf, Racc) : Racc;
+        const int gid = __builtin_amdgcn_readfirstlane((int)sgid[r]);
+        const float hm = has ? 1.0f : 0.0f;
+        const float wg = hm * w;
+        const float gd = wg * gD + ((has && gid == med) ? gM : 0.0f);
+        const float gp = (has && !cl) ? -ga * al : 0.0f;
+        const float dpdx = (t1 * s.w0 + t2 * s.w2) * kTwoOverLog2e;
+        const float dpdy = (t1 * s.w1 + t2 * s.w3) * kTwoOverLog2e;
         float g[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) g[k] = 0.f;
-        bool has = false;
-        if (pos <= lastp && splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl)) {
-          has = true;
-          const float inv = __builtin_amdgcn_rcpf(1.0f - al);
-          T = T * inv;
-          const float w = al * T;
-          const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
-          const float sf = gC0 * s.r + gC1 * s.g + gC2 * s.b + gD * d + gN0 * s.n0 +
-                           gN1 * s.n1 + gN2 * s.n2 + gA;
-          const float ga = T * sf - Racc * inv;
-          Racc = fmaf(w, sf, Racc);
-          const float gd = w * gD + ((int)sgid[r] == med ? gM : 0.0f);
-          const float gp = cl ? 0.0f : -ga * al;
-          const float dpdx = (t1 * s.w0 + t2 * s.w2) * kTwoOverLog2e;
-          const float dpdy = (t1 * s.w1 + t2 * s.w3) * kTwoOverLog2e;
-          g[0] = gp * dpdx + gd * s.p0;
-          g[1] = gp * dpdy + gd * s.p1;
-          g[2] = 0.5f * gp * dx * dx;
-          g[3] = gp * dx * dy;
-          g[4] = 0.5f * gp * dy * dy;
-          g[5] = cl ? 0.0f : ga * e;
-          g[6] = w * gC0; g[7] = w * gC1; g[8] = w * gC2;
-          g[9] = gd;
-          g[10] = gd * dx; g[11] = gd * dy;
-          g[12] = w * gN0; g[13] = w * gN1; g[14] = w * gN2;
-        }
-        if (__any(has)) {
+        g[0] = gp * dpdx + gd * s.p0;
+        g[1] = gp * dpdy + gd * s.p1;
+        g[2] = 0.5f * gp * dx * dx;
+        g[3] = gp * dx * dy;
+        g[4] = 0.5f * gp * dy * dy;
+        g[5] = (has && !cl) ? ga * e : 0.0f;
+        g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
+        g[9] = gd;
+        g[10] = gd * dx; g[11] = gd * dy;
+        g[12] = wg * gN0; g[13] = wg * gN1; g[14] = wg * gN2;
+        g[15] = 0.0f;
+        {
           const float tot = wave_sum16(g);
           const int vi = 4 * (lane >> 4) + (lane & 3);
           if ((lane & 15) < 4 && vi < 15 && tot != 0.0f)
-            atomicAdd(gsplat + (vbase + sgid[r]) * 16 + vi, tot);
+            atomicAdd(gsplat + (vbase + gid) * 16 + vi, tot);
         }
       }
     }

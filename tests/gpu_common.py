@@ -128,3 +128,29 @@ def compare_maps(g, o, pixels=None, tol=1e-5, check_int=True, label=""):
         print(f, flush=True)
     assert not failures, failures
     return int(frag.sum())
+
+
+def grad_check(got, ref, scale, label, tol=1e-4, normwise_tol=1e-5):
+    """Per parameter group: norm-wise ||g - g_ref|| / ||g_ref|| <= 1e-5, and
+    element-wise |g - g_ref| <= 1e-4 (|g_ref| + 0.1 S), where S is the
+    oracle's round-off scale of that element (sum over pixels of |term|,
+    pushed through |d param / d splat quantity|).  A gradient element is a
+    sum of per-pixel FP32 terms of both signs; its attainable accuracy is set
+    by the size of the terms, not by their (possibly cancelling) sum: the
+    bound allows 1e-5 S, about 170 units of FP32 round-off."""
+    worst = {}
+    for k in ref:
+        r = np.asarray(ref[k], np.float64).reshape(ref[k].shape[0], -1)
+        g = np.asarray(got[k], np.float64).reshape(r.shape)
+        S = np.asarray(scale[k], np.float64).reshape(r.shape)
+        if r.size == 0:
+            continue
+        err = np.abs(g - r) / (np.abs(r) + 0.1 * S + 1e-30)
+        nrm = np.linalg.norm(g - r) / (np.linalg.norm(r) + 1e-30)
+        i = np.unravel_index(np.argmax(err), err.shape)
+        worst[k] = (float(err.max()), float(nrm))
+        say(f"  grad {k}: normwise {nrm:.3g}; worst elem {err[i]:.3g} (ref {r[i]:.4g} got "
+            f"{g[i]:.4g}, scale {S[i]:.4g}); max |err|/S {np.max(np.abs(g - r) / (S + 1e-30)):.3g}")
+    say(label, "gradient errors (element, normwise)", worst)
+    for k, (w, n) in worst.items():
+        assert w <= tol and n <= normwise_tol, (label, k, w, n)

@@ -25,6 +25,9 @@ def _check(got, ref, what, tol=1e-4, mag=None):
 
 
 def _run(views, depth, normal, alpha, weight, dev):
+    """Run the kernel twice: onto zero gradient maps (the values compared with
+    the oracle) and onto random ones, which must receive exactly the same
+    additions (one FP32 add per element)."""
     import torch
     from paper_2406_01467_amd import _lib
     vc = _lib.make_views(views)
@@ -32,15 +35,21 @@ def _run(views, depth, normal, alpha, weight, dev):
     vdev = _lib.views_to_device(vc, dev)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
     D, N, A = t(depth), t(normal), t(alpha)
-    loss = torch.zeros(len(views), device=dev)
-    rng = np.random.default_rng(0)
-    base = [rng.normal(size=k * P).astype(np.float32) for k in (2, 3, 1)]
-    gD, gN, gA = (t(b) for b in base)  # accumulated onto existing values
     ws = torch.empty(_lib.rade_normal_consistency_workspace(P), dtype=torch.uint8, device=dev)
-    _lib.rade_normal_consistency(vc, vdev, D, N, A, weight, loss, gD, gN, gA, ws)
-    torch.cuda.synchronize()
-    return (loss.cpu().numpy(), gD.cpu().numpy() - base[0], gN.cpu().numpy() - base[1],
-            gA.cpu().numpy() - base[2], vc)
+    rng = np.random.default_rng(0)
+    outs = []
+    for base in ([np.zeros(k * P, np.float32) for k in (2, 3, 1)],
+                 [rng.normal(size=k * P).astype(np.float32) for k in (2, 3, 1)]):
+        loss = torch.zeros(len(views), device=dev)
+        gD, gN, gA = (t(b) for b in base)
+        _lib.rade_normal_consistency(vc, vdev, D, N, A, weight, loss, gD, gN, gA, ws)
+        torch.cuda.synchronize()
+        outs.append((loss.cpu().numpy(), [x.cpu().numpy() for x in (gD, gN, gA)], base))
+    (l0, g0, _), (l1, g1, b1) = outs
+    np.testing.assert_allclose(l1, l0, rtol=1e-6)  # order of the FP32 atomic adds may differ
+    for a, b, z in zip(g0, g1, b1):
+        assert np.array_equal(b, (z + a).astype(np.float32))  # accumulated, not overwritten
+    return l0, g0[0], g0[1], g0[2], vc
 
 
 def test_normal_consistency_on_rendered_maps():

@@ -5,13 +5,14 @@ oracle does not flag as fragile (within FP32 reach of a discrete threshold),
 integer maps (blend count, last and median Gaussian ids) exact there.
 Normal components (terms of both signs) use alpha as an extra floor.
 Projection fields 1e-5 relative; tile lists, keys and ranges bit-exact.
-Gradients: norm-wise 1e-5 and element-wise 1e-4 with a floor, see _grad_check."""
+Gradients: norm-wise 1e-5 and element-wise 1e-4 with a floor, see gpu_common.grad_check."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_common import (compare_maps, device, gpu_forward, oracle_settings, say, to_dev)
+from gpu_common import (compare_maps, device, gpu_forward, grad_check, oracle_settings, say,
+                        to_dev)
 from oracle_helpers import scene_from, view
 
 pytestmark = pytest.mark.gpu
@@ -140,7 +141,8 @@ def test_bin_sort_bit_exact_on_shared_input(tile):
 
 @pytest.mark.parametrize("name,n,tile", [("plain_64x64_1k", None, (16, 16)),
                                          ("plain_800x800_200k", 20000, (16, 16)),
-                                         ("plain_800x800_200k", 20000, (8, 8))])
+                                         ("plain_800x800_200k", 20000, (8, 8)),
+                                         ("plain_1600x1064_1m", None, (16, 16))])
 def test_bin_sort_end_to_end(name, n, tile):
     import torch
     dev = device()
@@ -305,32 +307,6 @@ def test_degenerate_inputs():
 # ---------------------------------------------------------------------------
 # backward
 
-def _grad_check(got, ref, scale, label, tol=1e-4, normwise_tol=1e-5):
-    """Per parameter group: norm-wise ||g - g_ref|| / ||g_ref|| <= 1e-5, and
-    element-wise |g - g_ref| <= 1e-4 (|g_ref| + 0.1 S), where S is the
-    oracle's round-off scale of that element (sum over pixels of |term|,
-    pushed through |d param / d splat quantity|).  A gradient element is a
-    sum of per-pixel FP32 terms of both signs; its attainable accuracy is set
-    by the size of the terms, not by their (possibly cancelling) sum: the
-    bound allows 1e-5 S, about 170 units of FP32 round-off."""
-    worst = {}
-    for k in ref:
-        r = np.asarray(ref[k], np.float64).reshape(ref[k].shape[0], -1)
-        g = np.asarray(got[k], np.float64).reshape(r.shape)
-        S = np.asarray(scale[k], np.float64).reshape(r.shape)
-        if r.size == 0:
-            continue
-        err = np.abs(g - r) / (np.abs(r) + 0.1 * S + 1e-30)
-        nrm = np.linalg.norm(g - r) / (np.linalg.norm(r) + 1e-30)
-        i = np.unravel_index(np.argmax(err), err.shape)
-        worst[k] = (float(err.max()), float(nrm))
-        say(f"  grad {k}: normwise {nrm:.3g}; worst elem {err[i]:.3g} (ref {r[i]:.4g} got "
-            f"{g[i]:.4g}, scale {S[i]:.4g}); max |err|/S {np.max(np.abs(g - r) / (S + 1e-30)):.3g}")
-    say(label, "gradient errors (element, normwise)", worst)
-    for k, (w, n) in worst.items():
-        assert w <= tol and n <= normwise_tol, (label, k, w, n)
-
-
 def _bwd_parity(scene, views, s, seed, label, pixels=None, recompute=False):
     import torch
     dev = device()
@@ -369,7 +345,7 @@ def _bwd_parity(scene, views, s, seed, label, pixels=None, recompute=False):
     scale = oracle.gradient_error_scale(st, views, scene, gouts, pixels=pl)
     got = dict(means=dm.cpu().numpy(), scales=ds.cpu().numpy(), quats=dq.cpu().numpy(),
                opacities=do.cpu().numpy(), sh=dsh.cpu().numpy())
-    _grad_check(got, ref, scale, label)
+    grad_check(got, ref, scale, label)
 
 
 def test_render_bwd_64x64_full():
