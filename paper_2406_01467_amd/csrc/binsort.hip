@@ -161,32 +161,33 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter: stable local ranks by wave match masks, local sort in LDS, then
-// digit runs written out contiguously.
-__global__ void __launch_bounds__(kThreads)
-k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                const uint32_t* __restrict__ n_dev, int shift, int64_t nblocks,
-                const uint32_t* __restrict__ offsets) {
-  __shared__ uint32_t cnt[kRadix];                 // running per-digit count in this block
-  __shared__ uint32_t wcnt[kThreads / 64][kRadix]; // per-round per-wave counts
-  __shared__ uint32_t lstart[kRadix];
-  __shared__ uint32_t skey[kTile];
-  __shared__ uint32_t sval[kTile];
-  __shared__ uint32_t lw[kThreads / 64];
-  const int64_t n = *n_dev;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  if (base >= n) return;  // uniform per block
+// Shared memory of one sorting workgroup.
+struct RankShared {
+  uint32_t cnt[kRadix];                  // per-digit count of the tile
+  uint32_t wcnt[kThreads / 64][kRadix];  // per-round per-wave counts
+  uint32_t lstart[kRadix];               // first local position of each digit
+  uint32_t dbase[kRadix];                // global position of each digit's run
+  uint32_t skey[kTile];
+  uint32_t sval[kTile];
+  uint32_t lw[kThreads / 64];
+};
+
+// Stable ranks of the tile's items [base, min(base + kTile, n)) among equal
+// digits (wave match masks: 8 ballots per item), the per-digit counts in
+// sh.cnt and the local digit starts in sh.lstart.  On return the items sit
+// in key/val with their local sorted positions in pos.
+__device__ __forceinline__ void rank_tile(const uint32_t* __restrict__ kin,
+                                          const uint32_t* __restrict__ vin, int64_t base,
+                                          int64_t n, int shift, RankShared& sh,
+                                          uint32_t (&key)[kItems], uint32_t (&val)[kItems],
+                                          uint32_t (&pos)[kItems]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-
-  cnt[threadIdx.x] = 0;
+  sh.cnt[threadIdx.x] = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
+  for (int w = 0; w < kThreads / 64; ++w) sh.wcnt[w][threadIdx.x] = 0;
   __syncthreads();
-
-  uint32_t key[kItems], val[kItems], rank[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
@@ -202,47 +203,75 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
     const uint32_t lr = (uint32_t)__popcll(peers & lt);
-    if (valid && lr == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    if (valid && lr == 0) sh.wcnt[wave][d] = (uint32_t)__popcll(peers);
     __syncthreads();
-    uint32_t pre = cnt[d];
-    for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
-    rank[r] = pre + lr;
+    uint32_t pre = sh.cnt[d];
+    for (int w = 0; w < wave; ++w) pre += sh.wcnt[w][d];
+    pos[r] = pre + lr;
     __syncthreads();
     {
       uint32_t add = 0;
 #pragma unroll
       for (int w = 0; w < kThreads / 64; ++w) {
-        add += wcnt[w][threadIdx.x];
-        wcnt[w][threadIdx.x] = 0;
+        add += sh.wcnt[w][threadIdx.x];
+        sh.wcnt[w][threadIdx.x] = 0;
       }
-      cnt[threadIdx.x] += add;
+      sh.cnt[threadIdx.x] += add;
     }
     __syncthreads();
   }
-  // local digit starts
   {
     uint32_t tot;
-    lstart[threadIdx.x] = block_exclusive_scan<uint32_t>(cnt[threadIdx.x], lw, tot);
+    sh.lstart[threadIdx.x] = block_exclusive_scan<uint32_t>(sh.cnt[threadIdx.x], sh.lw, tot);
   }
   __syncthreads();
-  const int64_t nb = (n - base) < kTile ? (n - base) : kTile;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) pos[r] += sh.lstart[digit_of(key[r], shift)];
+}
+
+// Local sort in LDS, then each digit's run written out contiguously at
+// sh.dbase[digit].
+__device__ __forceinline__ void scatter_tile(int64_t base, int64_t n, int shift,
+                                             RankShared& sh, const uint32_t (&key)[kItems],
+                                             const uint32_t (&val)[kItems],
+                                             const uint32_t (&pos)[kItems],
+                                             uint32_t* __restrict__ kout,
+                                             uint32_t* __restrict__ vout) {
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
     if (i < n) {
-      const uint32_t lp = lstart[digit_of(key[r], shift)] + rank[r];
-      skey[lp] = key[r];
-      sval[lp] = val[r];
+      sh.skey[pos[r]] = key[r];
+      sh.sval[pos[r]] = val[r];
     }
   }
   __syncthreads();
+  const int64_t nb = (n - base) < kTile ? (n - base) : kTile;
   for (int64_t i = threadIdx.x; i < nb; i += kThreads) {
-    const uint32_t k = skey[i];
+    const uint32_t k = sh.skey[i];
     const uint32_t d = digit_of(k, shift);
-    const uint64_t dst = (uint64_t)offsets[(int64_t)d * nblocks + blockIdx.x] + (uint64_t)(i - lstart[d]);
+    const uint64_t dst = (uint64_t)sh.dbase[d] + (uint64_t)(i - sh.lstart[d]);
     kout[dst] = k;
-    vout[dst] = sval[i];
+    vout[dst] = sh.sval[i];
   }
+}
+
+// Scatter of the multi-kernel pass: digit offsets per (digit, block) from
+// the scanned histogram.
+__global__ void __launch_bounds__(kThreads)
+k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                const uint32_t* __restrict__ n_dev, int shift, int64_t nblocks,
+                const uint32_t* __restrict__ offsets) {
+  __shared__ RankShared sh;
+  const int64_t n = *n_dev;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  if (base >= n) return;  // uniform per block
+  uint32_t key[kItems], val[kItems], pos[kItems];
+  rank_tile(kin, vin, base, n, shift, sh, key, val, pos);
+  sh.dbase[threadIdx.x] = offsets[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  __syncthreads();
+  scatter_tile(base, n, shift, sh, key, val, pos, kout, vout);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,17 +322,20 @@ k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
       if (win[mid] <= p) lo = mid; else hi = mid - 1;
     }
     const int64_t j = j0 + lo;
-    const uint64_t k = p - win[lo];
+    // a splat covers fewer than 2^31 tiles and V*N < 2^32 (32-bit ids), so
+    // the divisions below are 32-bit
+    const uint32_t k = (uint32_t)(p - win[lo]);
     const uint32_t i = svals[j];
-    const int v = (int)(i / (uint64_t)N);
-    const uint32_t g = (uint32_t)(i - (uint64_t)v * N);
+    const uint32_t v = i / (uint32_t)N;
+    const uint32_t g = i - v * (uint32_t)N;
     const rade_splat& sp = splats[i];
     const int tx0 = sp.rect[0] / tile_w, tx1 = sp.rect[1] / tile_w;
     const int ty0 = sp.rect[2] / tile_h, ty1 = sp.rect[3] / tile_h;
-    const int nx = tx1 - tx0 + 1;
+    const uint32_t nx = (uint32_t)(tx1 - tx0 + 1);
+    const uint32_t row = k / nx;
     // stay inside the rect even if tiles_touched disagrees with it
-    const int ty = min(ty0 + (int)(k / (uint64_t)nx), ty1);
-    const int tx = tx0 + (int)(k % (uint64_t)nx);
+    const int ty = min(ty0 + (int)row, ty1);
+    const int tx = tx0 + (int)(k - row * nx);
     const rade_view& vw = views[v];
     tkeys[p] = (uint32_t)vw.tile_offset + (uint32_t)(ty * vw.tiles_x + tx);
     pids[p] = g;
@@ -348,10 +380,12 @@ k_keys(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ pids,
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// Launch errors are left pending for the caller's final hipGetLastError.
+// Exclusive scan of in(0..n) into out (n = *n_dev, or n_max when n_dev is
+// NULL), total into *total.  Launch errors are left pending for the
+// caller's final hipGetLastError.
 template <typename T, typename In>
 void scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
-                hipStream_t st) {
+          hipStream_t st) {
   const int64_t nb = n_max > 0 ? (n_max + kTile - 1) / kTile : 1;
   hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3((unsigned)nb), dim3(kThreads), 0, st, in,
                      n_max, n_dev, block_sums);

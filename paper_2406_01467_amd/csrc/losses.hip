@@ -91,41 +91,51 @@ k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const floa
       term *= wn;
     }
   }
-  // loss value: a wave inside one view writes its sum to partial[wave] (the
-  // per-view sums are finished by k_nc_sum); a wave that straddles two views
-  // (rare) adds its terms atomically.
-  const int lane = threadIdx.x & 63;
-  const int v0 = __shfl(v, 0, 64);
-  const bool one_view = __all(v == v0);
-  const int64_t gw = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
-  if (one_view) {
+  // loss value: a workgroup inside one view writes its sum to partial[block]
+  // (added up per view by k_nc_sum); a workgroup that straddles two views
+  // (rare) writes 0 there and adds its terms per lane.
+  __shared__ float red[kT / 64];
+  const int64_t q0 = (int64_t)blockIdx.x * kT;
+  const int64_t q1 = min(total, q0 + kT) - 1;
+  const int v0 = view_of_pixel(views, V, q0), v1 = view_of_pixel(views, V, q1);
+  if (v0 == v1) {
     float x = term;
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    if (lane == 0) partial[gw] = x;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.0f;
+      for (int i = 0; i < kT / 64; ++i) t += red[i];
+      partial[blockIdx.x] = t;
+    }
   } else {
-    if (lane == 0) partial[gw] = 0.0f;
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0.0f;
     if (term != 0.0f) atomicAdd(loss + v, term);
   }
 }
 
-// Per view (one workgroup each): sum of the wave partials over the view's
-// pixel range, added to loss[v].
+// Loss per view: workgroup (v, c) sums chunk c of view v's pass-1 partials
+// and adds it to loss[v] (kSumChunks atomics per view).
+constexpr int kSumChunks = 32;
+
 __global__ void __launch_bounds__(kT)
-k_nc_sum(const rade_view* __restrict__ views, int64_t n_waves, const float* __restrict__ partial,
+k_nc_sum(const rade_view* __restrict__ views, const float* __restrict__ partial,
          float* __restrict__ loss) {
   __shared__ float red[kT / 64];
   const rade_view& vw = views[blockIdx.x];
-  const int64_t w0 = vw.pix_offset >> 6;
-  const int64_t w1 = min(n_waves, (vw.pix_offset + (int64_t)vw.width * vw.height + 63) >> 6);
+  const int64_t b0 = vw.pix_offset / kT;
+  const int64_t b1 = (vw.pix_offset + (int64_t)vw.width * vw.height + kT - 1) / kT;
+  const int64_t per = (b1 - b0 + kSumChunks - 1) / kSumChunks;
+  const int64_t c0 = b0 + (int64_t)blockIdx.y * per, c1 = min(b1, c0 + per);
   float x = 0.0f;
-  for (int64_t w = w0 + threadIdx.x; w < w1; w += kT) x += partial[w];
+  for (int64_t b = c0 + threadIdx.x; b < c1; b += kT) x += partial[b];
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
     float t = 0.0f;
     for (int i = 0; i < kT / 64; ++i) t += red[i];
-    atomicAdd(loss + blockIdx.x, t);
+    if (c0 < c1) atomicAdd(loss + blockIdx.x, t);
   }
 }
 
@@ -159,8 +169,8 @@ __global__ void k_zero_f(float* __restrict__ a, int n) {
 }  // namespace
 
 size_t normal_consistency_workspace(int64_t total_pixels) {
-  const int64_t waves = (total_pixels + kT - 1) / kT * (kT / 64);
-  return (size_t)total_pixels * 6 * sizeof(float) + (size_t)waves * sizeof(float) + 256;
+  const int64_t blocks = (total_pixels + kT - 1) / kT;
+  return (size_t)total_pixels * 6 * sizeof(float) + (size_t)blocks * sizeof(float) + 256;
 }
 
 hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
@@ -172,11 +182,10 @@ hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t tota
   if (total == 0) return hipGetLastError();
   float* gdiff = static_cast<float*>(ws);
   const unsigned blocks = (unsigned)((total + kT - 1) / kT);
-  const int64_t n_waves = (int64_t)blocks * (kT / 64);
   float* partial = gdiff + 6 * total;
   hipLaunchKernelGGL(k_nc_pass1, dim3(blocks), dim3(kT), 0, st, views, V, total, depth, normal,
                      alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
-  hipLaunchKernelGGL(k_nc_sum, dim3(V), dim3(kT), 0, st, views, n_waves, partial, loss);
+  hipLaunchKernelGGL(k_nc_sum, dim3(V, kSumChunks), dim3(kT), 0, st, views, partial, loss);
   hipLaunchKernelGGL(k_nc_pass2, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff, d_depth);
   return hipGetLastError();
 }
