@@ -54,7 +54,10 @@ R = {k: i for i, k in enumerate(R_FIELDS)}
 # Gradient fields of the projected quantities.
 G_FIELDS = ["uc", "vc", "a", "b", "c", "o", "r", "g", "bl", "z", "p0", "p1", "n0", "n1", "n2"]
 # Output fields per pixel.
-O_FIELDS = ["r", "g", "b", "dexp", "dmed", "n0", "n1", "n2", "alpha", "tfinal"]
+O_FIELDS = ["r", "g", "b", "dexp", "dmed", "n0", "n1", "n2", "alpha", "tfinal", "dist"]
+# Upstream-gradient columns of render_bwd: colour 3, expected depth, median
+# depth, normal 3, alpha, depth distortion (Eq. 23).
+GOUT = 10
 
 F_CULLED, F_VISIBLE, F_DEGENERATE, F_CLAMP_X, F_CLAMP_Y = 1, 2, 4, 8, 16
 F_RGB_CLAMP = (32, 64, 128)
@@ -169,7 +172,8 @@ def render(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, pixels=None,
     lib.oracle_render(_ptr(s), _ptr(vv), N, _ptr(rec), _ptr(flags), _ptr(pix), npix, _ptr(out),
                       _ptr(iout), _ptr(sig))
     res = dict(color=out[:, 0:3], depth_exp=out[:, 3], depth_med=out[:, 4], normal=out[:, 5:8],
-               alpha=out[:, 8], t_final=out[:, 9], count=iout[:, 0], last_id=iout[:, 1],
+               alpha=out[:, 8], t_final=out[:, 9], distortion=out[:, 10], count=iout[:, 0],
+               last_id=iout[:, 1],
                median_id=iout[:, 2], fragile=iout[:, 3])
     if want_sig:
         res["sig"] = sig
@@ -180,7 +184,9 @@ def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np
                pixels=None, gP: np.ndarray | None = None,
                gP_abs: np.ndarray | None = None) -> np.ndarray:
     """Adjoint of :func:`render`.  gout: (npix, 9) upstream gradients of
-    (color 3, depth expected, depth median, normal 3, alpha).  Returns the
+    (color 3, depth expected, depth median, normal 3, alpha), or (npix, 10)
+    with the depth distortion of Eq. 23 last (its adjoint holds the blend
+    weights constant, as the training loss detaches them).  Returns the
     gradient of the projected quantities, (N, 15) in the order of G_FIELDS.
     gP_abs, when given, accumulates over pixels a bound of the magnitudes of
     the quantities each per-pixel term is computed from (the same recursion
@@ -190,7 +196,10 @@ def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np
     vv = view_vector(view)
     pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
     npix = view.width * view.height if pix is None else pix.shape[0]
-    gout = np.ascontiguousarray(gout, np.float64).reshape(npix, 9)
+    gout = np.asarray(gout, np.float64).reshape(npix, -1)
+    if gout.shape[1] == 9:
+        gout = np.concatenate([gout, np.zeros((npix, 1))], axis=1)
+    gout = np.ascontiguousarray(gout).reshape(npix, GOUT)
     if gP is None:
         gP = np.zeros((N, len(G_FIELDS)), np.float64)
     lib.oracle_render_bwd(_ptr(s), _ptr(vv), N, _ptr(np.ascontiguousarray(rec, np.float64)),
@@ -248,7 +257,7 @@ def forward(s: np.ndarray, views, scene, pixels=None, want_sig=False):
 
 
 def backward(s: np.ndarray, views, scene, gouts, pixels=None, rec=None, flags=None) -> dict:
-    """VJP of the whole path: gouts[v] is (npix_v, 9)."""
+    """VJP of the whole path: gouts[v] is (npix_v, 9) or (npix_v, 10)."""
     if rec is None:
         rec, _, flags = project(s, views, scene)
     gP = np.zeros((len(views), scene.n, len(G_FIELDS)), np.float64)

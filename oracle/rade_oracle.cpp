@@ -18,6 +18,10 @@
 //     normal and alpha for every requested pixel over ALL Gaussians in
 //     ascending (float32(z_c), id) order -- no tiles -- plus the median depth
 //     (Sec. 1: depth at which accumulated opacity crosses one half);
+//   * the depth-distortion term of Sec. 3.4 (Eq. 23) per pixel,
+//     sum_{i,j} w_i w_j (d_i - d_j)^2 over the blended splats, as the plain
+//     double sum (the training loss detaches the weights: its adjoint flows
+//     through the per-pixel depths d_i only);
 //   * the hand-written adjoint of all of the above (FP64);
 //   * a binning reference (std::stable_sort of (tile, depth) keys).
 //
@@ -82,7 +86,12 @@ enum {
 };
 
 // Per-pixel outputs (doubles).
-enum { O_R = 0, O_G, O_B, O_DEXP, O_DMED, O_N0, O_N1, O_N2, O_ALPHA, O_TFIN, O_COUNT = 10 };
+enum {
+  O_R = 0, O_G, O_B, O_DEXP, O_DMED, O_N0, O_N1, O_N2, O_ALPHA, O_TFIN, O_DIST, O_COUNT = 11
+};
+// Upstream gradients per pixel (doubles): colour 3, expected depth, median
+// depth, normal 3, alpha, depth distortion.
+constexpr int GOUT = 10;
 
 struct M3 {
   double m[9];
@@ -424,6 +433,7 @@ void render_pixel(const double* s, const double* rec, const std::vector<int64_t>
   R.list.clear();
   const double pcx = px + 0.5, pcy = py + 0.5;
   int64_t stop_g = -1;
+  std::vector<double> ws, ds;  // weight and depth of every blended splat
   for (int64_t g : order) {
     const double* r = rec + g * R_COUNT;
     const double dx = r[R_UC] - pcx, dy = r[R_VC] - pcy;
@@ -452,8 +462,16 @@ void render_pixel(const double* s, const double* rec, const std::vector<int64_t>
     R.last = g;
     R.sig = mix64(R.sig, (uint64_t)g * 2 + (clamped ? 1 : 0));
     if (keep_list) R.list.push_back({g, alpha, T, dx, dy, d, gauss, clamped});
+    ws.push_back(w);
+    ds.push_back(d);
     T = Tn;
   }
+  // Eq. 23: sum over all ordered pairs of blended splats.
+  double dist = 0.0;
+  for (size_t i = 0; i < ws.size(); ++i)
+    for (size_t j = 0; j < ws.size(); ++j)
+      dist += ws[i] * ws[j] * (ds[i] - ds[j]) * (ds[i] - ds[j]);
+  R.out[O_DIST] = dist;
   R.out[O_R] += T * s[S_BG0]; R.out[O_G] += T * s[S_BG1]; R.out[O_B] += T * s[S_BG2];
   R.out[O_TFIN] = T;
   R.sig = mix64(R.sig, (uint64_t)(R.median + 7));
@@ -662,8 +680,10 @@ int oracle_render(const double* settings, const double* view, int64_t N, const d
 }
 
 // Adjoint of the compositing of one view: upstream gradients per requested
-// pixel, gout: npix*9 = (color 3, depth expected, depth median, normal 3,
-// alpha) -> gradient of the projected quantities gP: N*G_COUNT (accumulated);
+// pixel, gout: npix*GOUT = (color 3, depth expected, depth median, normal 3,
+// alpha, depth distortion) -> gradient of the projected quantities gP:
+// N*G_COUNT (accumulated); the distortion term treats the blend weights as
+// constants (they are detached in the training loss, Sec. 4.1);
 // gP_abs (optional) accumulates, per term, a bound of the magnitudes of the
 // quantities it is computed from (the round-off scale of that term).
 int oracle_render_bwd(const double* settings, const double* view, int64_t N, const double* rec,
@@ -679,9 +699,9 @@ int oracle_render_bwd(const double* settings, const double* view, int64_t N, con
     const int px = (int)(idx % v.W), py = (int)(idx / v.W);
     PixelResult R;
     render_pixel(settings, rec, order, px, py, true, R);
-    const double* g = gout + i * 9;
+    const double* g = gout + i * GOUT;
     const double gC[3] = {g[0], g[1], g[2]}, gD = g[3], gM = g[4];
-    const double gN[3] = {g[5], g[6], g[7]}, gA = g[8];
+    const double gN[3] = {g[5], g[6], g[7]}, gA = g[8], gL = g[9];
     // Reverse pass: R_acc holds the summed contribution of everything behind
     // the current Gaussian (later blends and the background).
     double Racc = R.out[O_TFIN] * (gC[0] * bg[0] + gC[1] * bg[1] + gC[2] * bg[2]);
@@ -698,6 +718,15 @@ int oracle_render_bwd(const double* settings, const double* view, int64_t N, con
       const double galpha = c.T * sfeat - Racc / (1.0 - c.alpha);
       Racc += w * sfeat;
       double gd = w * gD + (c.g == R.median ? gM : 0.0);
+      // d/dd_k of sum_{i,j} w_i w_j (d_i - d_j)^2 = 4 w_k sum_j w_j (d_k - d_j)
+      double sdist = 0.0, sdist_abs = 0.0;
+      if (gL != 0.0) {
+        for (const Contrib& o : R.list) {
+          sdist += o.alpha * o.T * (c.d - o.d);
+          sdist_abs += o.alpha * o.T * (std::fabs(c.d) + std::fabs(o.d));
+        }
+        gd += gL * 4.0 * w * sdist;
+      }
       double gpow = 0.0, go = 0.0;
       if (!c.clamped) {
         gpow = -galpha * c.alpha;  // d alpha / d power = -alpha
@@ -723,7 +752,8 @@ int oracle_render_bwd(const double* settings, const double* view, int64_t N, con
                             std::fabs(gN[2] * r[R_N2]) + std::fabs(gA);
         const double ga_abs = c.T * sabs + Rabs / (1.0 - c.alpha);
         Rabs += w * sabs;
-        const double gd_abs = w * std::fabs(gD) + (c.g == R.median ? std::fabs(gM) : 0.0);
+        const double gd_abs = w * std::fabs(gD) + (c.g == R.median ? std::fabs(gM) : 0.0) +
+                              std::fabs(gL) * 4.0 * w * sdist_abs;
         const double gp_abs = c.clamped ? 0.0 : ga_abs * c.alpha;
         const double go_abs = c.clamped ? 0.0 : ga_abs * c.gauss;
         mag[G_UC] = gp_abs * (std::fabs(r[R_A] * c.dx) + std::fabs(r[R_B] * c.dy)) +
