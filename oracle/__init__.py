@@ -54,7 +54,8 @@ R = {k: i for i, k in enumerate(R_FIELDS)}
 # Gradient fields of the projected quantities.
 G_FIELDS = ["uc", "vc", "a", "b", "c", "o", "r", "g", "bl", "z", "p0", "p1", "n0", "n1", "n2"]
 # Output fields per pixel.
-O_FIELDS = ["r", "g", "b", "dexp", "dmed", "n0", "n1", "n2", "alpha", "tfinal", "dist"]
+O_FIELDS = ["r", "g", "b", "dexp", "dmed", "n0", "n1", "n2", "alpha", "tfinal", "dist",
+            "dist_mag"]
 # Upstream-gradient columns of render_bwd: colour 3, expected depth, median
 # depth, normal 3, alpha, depth distortion (Eq. 23).
 GOUT = 10
@@ -172,8 +173,8 @@ def render(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, pixels=None,
     lib.oracle_render(_ptr(s), _ptr(vv), N, _ptr(rec), _ptr(flags), _ptr(pix), npix, _ptr(out),
                       _ptr(iout), _ptr(sig))
     res = dict(color=out[:, 0:3], depth_exp=out[:, 3], depth_med=out[:, 4], normal=out[:, 5:8],
-               alpha=out[:, 8], t_final=out[:, 9], distortion=out[:, 10], count=iout[:, 0],
-               last_id=iout[:, 1],
+               alpha=out[:, 8], t_final=out[:, 9], distortion=out[:, 10],
+               distortion_mag=out[:, 11], count=iout[:, 0], last_id=iout[:, 1],
                median_id=iout[:, 2], fragile=iout[:, 3])
     if want_sig:
         res["sig"] = sig

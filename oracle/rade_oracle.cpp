@@ -87,7 +87,8 @@ enum {
 
 // Per-pixel outputs (doubles).
 enum {
-  O_R = 0, O_G, O_B, O_DEXP, O_DMED, O_N0, O_N1, O_N2, O_ALPHA, O_TFIN, O_DIST, O_COUNT = 11
+  O_R = 0, O_G, O_B, O_DEXP, O_DMED, O_N0, O_N1, O_N2, O_ALPHA, O_TFIN, O_DIST, O_DIST_MAG,
+  O_COUNT = 12
 };
 // Upstream gradients per pixel (doubles): colour 3, expected depth, median
 // depth, normal 3, alpha, depth distortion.
@@ -466,12 +467,18 @@ void render_pixel(const double* s, const double* rec, const std::vector<int64_t>
     ds.push_back(d);
     T = Tn;
   }
-  // Eq. 23: sum over all ordered pairs of blended splats.
-  double dist = 0.0;
+  // Eq. 23: sum over all ordered pairs of blended splats.  dist_mag =
+  // sum w_i w_j |d_i - d_j| (|d_i| + |d_j|) bounds the first-order change of
+  // the sum per unit relative perturbation of the depths: the round-off scale
+  // of an evaluation from depths rounded to a lower precision.
+  double dist = 0.0, mag = 0.0;
   for (size_t i = 0; i < ws.size(); ++i)
-    for (size_t j = 0; j < ws.size(); ++j)
+    for (size_t j = 0; j < ws.size(); ++j) {
       dist += ws[i] * ws[j] * (ds[i] - ds[j]) * (ds[i] - ds[j]);
+      mag += ws[i] * ws[j] * std::fabs(ds[i] - ds[j]) * (std::fabs(ds[i]) + std::fabs(ds[j]));
+    }
   R.out[O_DIST] = dist;
+  R.out[O_DIST_MAG] = mag;
   R.out[O_R] += T * s[S_BG0]; R.out[O_G] += T * s[S_BG1]; R.out[O_B] += T * s[S_BG2];
   R.out[O_TFIN] = T;
   R.sig = mix64(R.sig, (uint64_t)(R.median + 7));
