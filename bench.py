@@ -59,6 +59,35 @@ BYTES_PER_GAUSSIAN = 236 * 2 + 80 * 2 + 8 + 128 + 236
 BYTES_PER_PAIR = 8 + 32 + 4 + 84 + 84
 BYTES_PER_PIXEL = 52 + 52 + 36
 
+# HBM traffic of one launch of the dominant kernel, from two rocprofv3 --pmc
+# runs of paper_2406_01467_amd/profile_step.py (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch), each scaled by what the counter reads for a copy kernel
+# of known size (FETCH_SIZE reads half of the bytes a plain copy moves,
+# WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
+# on (SHA-1 of render.hip + common.hpp) and for the 1600x1064 / 1M workload
+# at 16x16 tiles; reported as null otherwise.
+MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
+                    "sources_sha1": "df2f5269e69176d149154446c5c00f0ab2de50bf",
+                    "fetch_bytes": 363075335, "write_bytes": 154785088,
+                    "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
+
+
+def _render_sources_sha1() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("render.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2406_01467_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str, tile: str):
+    t = MEASURED_TRAFFIC
+    if (t is None or t["kernel"] != kernel or t["workload"] != workload or t["tile"] != tile
+            or t["sources_sha1"] != _render_sources_sha1()):
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -75,6 +104,8 @@ def parse():
                     help="steps of the eager autograd path timed for comparison (0: skip)")
     ap.add_argument("--recompute", action="store_true",
                     help="keep no splats for the backward pass")
+    ap.add_argument("--distortion", action="store_true",
+                    help="add w_d = 100 x the depth distortion of Eq. 23 to the loss")
     ap.add_argument("--unbatched-steps", type=int, default=5,
                     help="with several views: steps of the unbatched form (each view its own "
                          "graph-replayed plan, run one after another) for comparison (0: skip)")
@@ -127,7 +158,7 @@ def main():
     import synth
     from paper_2406_01467_amd import Settings, _lib
     from paper_2406_01467_amd.batched import BatchedPlan, autotune
-    from paper_2406_01467_amd.loss import make_grad_fn, torch_loss
+    from paper_2406_01467_amd.loss import W_DIST, make_grad_fn, torch_loss
     from paper_2406_01467_amd.raster import Rasterizer, render
 
     dev = torch.device("cuda:0")
@@ -140,10 +171,13 @@ def main():
     target = torch.from_numpy(synth.random_targets(views, seed=7)["color"]).to(dev)
     V = len(views)
 
+    w_dist = W_DIST if args.distortion else 0.0
     timings = {}
     if args.tile == "auto":
         probe = Rasterizer(views, settings, dev)
-        settings, timings = autotune(views, params, settings, make_grad_fn(probe, target))
+        settings, timings = autotune(views, params, settings,
+                                     make_grad_fn(probe, target, w_dist=w_dist),
+                                     distortion=args.distortion)
     rast = Rasterizer(views, settings, dev)
 
     # blends and pairs per step (deterministic for fixed inputs)
@@ -154,8 +188,9 @@ def main():
         pairs = int(maps.state.n_pairs)
         del maps
 
-    grad_fn = make_grad_fn(rast, target)
-    plan = BatchedPlan(views, settings, params, grad_fn, recompute=args.recompute)
+    grad_fn = make_grad_fn(rast, target, w_dist=w_dist)
+    plan = BatchedPlan(views, settings, params, grad_fn, recompute=args.recompute,
+                       distortion=args.distortion)
     plan.step()  # capture, replay, grow on overflow
     for _ in range(args.warmup):
         plan.replay()
@@ -199,8 +234,8 @@ def main():
         for vc, v in zip(rast.views_c, views):
             r1 = Rasterizer([v], settings, dev)
             tv = target[3 * vc.pix_offset: 3 * (vc.pix_offset + vc.width * vc.height)]
-            p1 = BatchedPlan([v], settings, params, make_grad_fn(r1, tv),
-                             recompute=args.recompute)
+            p1 = BatchedPlan([v], settings, params, make_grad_fn(r1, tv, w_dist=w_dist),
+                             recompute=args.recompute, distortion=args.distortion)
             p1.step()
             singles.append(p1)
         for p1 in singles:
@@ -224,8 +259,10 @@ def main():
         def eager_step():
             for p in leaves:
                 p.grad = None
-            c, d, n, a = render(rast, *leaves, recompute=args.recompute)
-            torch_loss(c, d, n, a, target, rast.views_c).backward()
+            outs = render(rast, *leaves, recompute=args.recompute, distortion=args.distortion)
+            torch_loss(*outs[:4], target, rast.views_c,
+                       distortion=outs[4] if args.distortion else None,
+                       w_dist=w_dist).backward()
 
         for _ in range(2):
             eager_step()
@@ -259,12 +296,15 @@ def main():
                    "pixels": rast.total_pixels, "sh_degree": scene.sh_degree,
                    "tile": f"{settings.tile_w}x{settings.tile_h}",
                    "schedule": settings.schedule,
-                   "loss": "L1 colour + 5 x normal consistency (Eq. 24, median depth)",
+                   "loss": "L1 colour + 5 x normal consistency (Eq. 24, median depth)" +
+                           (" + 100 x depth distortion (Eq. 23)" if args.distortion else ""),
                    "mode": "whole fwd+bwd step replayed as one HIP graph",
                    "recompute_splats": bool(args.recompute)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(dom, args.workload,
+                                                 f"{settings.tile_w}x{settings.tile_h}")},
         "blends_per_view": blends / V,
         "pairs_per_view": pairs / V,
         "kernel_ms": kernel_ms,

@@ -186,13 +186,16 @@ int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t
  * Saved state for rade_render_bwd (1 plane each):
  *   t_final (float), last (int32: position of the last blended splat within
  *   its tile's list, -1 if none), median (int32: Gaussian id of the median
- *   splat, -1 if none); count (int32, optional, may be NULL): splats blended. */
+ *   splat, -1 if none); count (int32, optional, may be NULL): splats blended.
+ * distortion (1 plane, optional, may be NULL): the depth distortion of
+ * Sec. 3.4 Eq. 23 per pixel, sum_{i,j} w_i w_j (d_i - d_j)^2 over the blended
+ * splats (d_i the depth of Eq. 4 at the pixel). */
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
-                    int32_t* median, int32_t* count, void* stream);
+                    int32_t* median, int32_t* count, float* distortion, void* stream);
 
 /* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
  * recompute the splats (splats == NULL in rade_render_bwd). */
@@ -207,7 +210,14 @@ size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, i
  * tile lists.  splats may be NULL, in which case they are recomputed from
  * the parameters into the workspace.  The outputs d_means (N*3), d_scales
  * (N*3), d_quats (N*4), d_opacities (N), d_sh (N*K*3) are OVERWRITTEN with
- * the gradient summed over the V views.  tile_order as in rade_render_fwd. */
+ * the gradient summed over the V views.  tile_order as in rade_render_fwd.
+ * d_distortion (1 plane, optional, may be NULL): upstream gradient of the
+ * distortion map; its adjoint holds the blend weights constant (they are
+ * detached in the training loss of Sec. 4.1), so it reaches each splat
+ * through its depth only: 4 g A w_i (d_i - D/A) with A and D the alpha and
+ * expected-depth maps of the forward, which must then be passed as `alpha`
+ * (1 plane) and `depth` (the 2-plane depth map); both are ignored when
+ * d_distortion is NULL. */
 int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const float* means,
                     const float* scales, const float* quats, const float* opacities,
@@ -215,7 +225,8 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const uint32_t* tile_ranges, uint32_t* tile_order,
                     const float* t_final, const int32_t* last,
                     const int32_t* median, const float* d_color, const float* d_depth,
-                    const float* d_normal, const float* d_alpha, float* d_means,
+                    const float* d_normal, const float* d_alpha, const float* d_distortion,
+                    const float* depth, const float* alpha, float* d_means,
                     float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
                     void* workspace, size_t workspace_bytes, void* stream);
 
@@ -255,7 +266,7 @@ int rade_set_kernel_events(int kernel, void* start_event, void* stop_event);
 /* Static description of an error code (never NULL). */
 const char* rade_strerror(int code);
 
-/* ABI version of this header: 1. */
+/* ABI version of this header: 2. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

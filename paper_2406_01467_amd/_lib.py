@@ -93,6 +93,7 @@ class Settings:
 
 
 _lib = None
+ABI_VERSION = 2
 
 
 def load() -> ctypes.CDLL:
@@ -109,17 +110,20 @@ def load() -> ctypes.CDLL:
     lib.rade_bin_sort_workspace.argtypes = [I32, I64, I64, I64]
     lib.rade_bin_sort_workspace.restype = SZ
     lib.rade_bin_sort.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I64, P, P, P, SZ, P]
-    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 12 + [P]
+    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 13 + [P]
     lib.rade_tile_order_workspace.argtypes = [I64]
     lib.rade_tile_order_workspace.restype = SZ
     lib.rade_tile_order.argtypes = [P, P, I32, P, P, P, SZ, P]
     lib.rade_tile_order.restype = ctypes.c_int
     lib.rade_render_bwd_workspace.argtypes = [P, I32, I64, ctypes.c_int]
     lib.rade_render_bwd_workspace.restype = SZ
-    lib.rade_render_bwd.argtypes = [P, P, P, I32, I64] + [P] * 22 + [SZ, P]
+    lib.rade_render_bwd.argtypes = [P, P, P, I32, I64] + [P] * 25 + [SZ, P]
     lib.rade_strerror.argtypes = [ctypes.c_int]
     lib.rade_strerror.restype = ctypes.c_char_p
     lib.rade_abi_version.restype = ctypes.c_int
+    if lib.rade_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} implements ABI {lib.rade_abi_version()}, this binding "
+                           f"needs {ABI_VERSION}: rebuild with `python -m paper_2406_01467_amd.build`")
     lib.rade_set_kernel_events.argtypes = [ctypes.c_int, P, P]
     lib.rade_normal_consistency_workspace.argtypes = [I64]
     lib.rade_normal_consistency_workspace.restype = SZ
@@ -253,13 +257,13 @@ def rade_tile_order(settings: Settings, views_c, tile_ranges, tile_order, worksp
 
 def rade_render_fwd(settings: Settings, views_c, views_dev, V: int, N: int, splats, pair_ids,
                     tile_ranges, color, depth, normal, alpha, t_final, last, median, count=None,
-                    stream=None, tile_order=None):
+                    stream=None, tile_order=None, distortion=None):
     s = settings.c()
     return _check(load().rade_render_fwd(ctypes.byref(s), views_c, _p(views_dev), V, N,
                                          _p(splats), _p(pair_ids), _p(tile_ranges),
                                          _p(tile_order), _p(color),
                                          _p(depth), _p(normal), _p(alpha), _p(t_final), _p(last),
-                                         _p(median), _p(count), _stream(stream)),
+                                         _p(median), _p(count), _p(distortion), _stream(stream)),
                   "rade_render_fwd")
 
 
@@ -271,13 +275,16 @@ def rade_render_bwd_workspace(settings: Settings, V: int, N: int, recompute: boo
 def rade_render_bwd(settings: Settings, views_c, views_dev, V: int, N: int, means, scales, quats,
                     opacities, sh, splats, pair_ids, tile_ranges, t_final, last, median, d_color,
                     d_depth, d_normal, d_alpha, d_means, d_scales, d_quats, d_opacities, d_sh,
-                    workspace, stream=None, tile_order=None):
+                    workspace, stream=None, tile_order=None, d_distortion=None, depth=None,
+                    alpha=None):
+    """d_distortion (optional) needs the forward's depth (2 planes) and alpha maps."""
     s = settings.c()
     return _check(load().rade_render_bwd(
         ctypes.byref(s), views_c, _p(views_dev), V, N, _p(means), _p(scales), _p(quats),
         _p(opacities), _p(sh), _p(splats), _p(pair_ids), _p(tile_ranges), _p(tile_order),
         _p(t_final), _p(last),
-        _p(median), _p(d_color), _p(d_depth), _p(d_normal), _p(d_alpha), _p(d_means),
+        _p(median), _p(d_color), _p(d_depth), _p(d_normal), _p(d_alpha), _p(d_distortion),
+        _p(depth), _p(alpha), _p(d_means),
         _p(d_scales), _p(d_quats), _p(d_opacities), _p(d_sh), _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_render_bwd")
 

@@ -36,10 +36,13 @@ class BatchedPlan:
     grad_fn(maps) -> (d_color, d_depth, d_normal, d_alpha) computes upstream
     gradients from the map tensors with stream-ordered torch ops; under graph
     capture it must avoid host synchronisation (elementwise ops are safe).
+    With distortion=True the forward also writes maps["distortion"] (Eq. 23)
+    and grad_fn returns a fifth gradient, that of the distortion map.
     """
 
     def __init__(self, views: Sequence, settings: Settings, params: Sequence[torch.Tensor],
-                 grad_fn: Callable, capacity: Optional[int] = None, recompute: bool = False):
+                 grad_fn: Callable, capacity: Optional[int] = None, recompute: bool = False,
+                 distortion: bool = False):
         self.settings = settings
         self.params = [p.detach() for p in params]
         self.device = self.params[0].device
@@ -48,6 +51,7 @@ class BatchedPlan:
         self.V = self.rast.V
         self.grad_fn = grad_fn
         self.recompute = recompute
+        self.distortion = distortion
         self.graph = None
         if capacity is None:
             # one eager binning pass sizes the pair buffers (with slack)
@@ -77,6 +81,8 @@ class BatchedPlan:
         i = lambda: torch.zeros(P, dtype=torch.int32, device=dev)  # noqa: E731
         self.maps = dict(color=f(3), depth=f(2), normal=f(3), alpha=f(1), t_final=f(1),
                          last=i(), median=i())
+        if self.distortion:
+            self.maps["distortion"] = f(1)
         self.bwd_ws = torch.empty(max(1, _lib.rade_render_bwd_workspace(
             self.settings, V, N, self.recompute)), dtype=torch.uint8, device=dev)
         m, s, q, o, sh = self.params
@@ -100,13 +106,17 @@ class BatchedPlan:
         mp = self.maps
         _lib.rade_render_fwd(st, r.views_c, r.views_dev, V, N, self.splats, self.pair_ids,
                              self.ranges, mp["color"], mp["depth"], mp["normal"], mp["alpha"],
-                             mp["t_final"], mp["last"], mp["median"], None, tile_order=order)
+                             mp["t_final"], mp["last"], mp["median"], None, tile_order=order,
+                             distortion=mp.get("distortion"))
         g = self.grad_fn(mp)
-        dc, dd, dn, da = (None if x is None else x.contiguous() for x in g)
+        g = [None if x is None else x.contiguous() for x in g]
+        dc, dd, dn, da = g[:4]
+        ddist = g[4] if self.distortion and len(g) > 4 else None
         _lib.rade_render_bwd(st, r.views_c, r.views_dev, V, N, m, s, q, o, sh,
                              None if self.recompute else self.splats, self.pair_ids, self.ranges,
                              mp["t_final"], mp["last"], mp["median"], dc, dd, dn, da,
-                             *self.grads, self.bwd_ws, tile_order=order)
+                             *self.grads, self.bwd_ws, tile_order=order, d_distortion=ddist,
+                             depth=mp["depth"], alpha=mp["alpha"])
 
     def capture(self):
         """Capture enqueue() into a HIP graph (after one eager warm-up)."""
@@ -169,11 +179,11 @@ def signature(views: Sequence, n: int, sh_degree: int) -> str:
 
 def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, grad_fn: Callable,
              tiles=TILES, schedules=SCHEDULES, reps: int = 3, use_cache: bool = True,
-             log: Optional[Callable] = None) -> tuple:
+             log: Optional[Callable] = None, distortion: bool = False) -> tuple:
     """Time the graph-replayed fwd+bwd for every (tile, schedule) candidate
     and return (best Settings, {candidate: ms}).  Results are cached in a JSON
     file keyed by device name and workload signature."""
-    sig = signature(views, params[0].shape[0], base.sh_degree)
+    sig = signature(views, params[0].shape[0], base.sh_degree) + ("|dist" if distortion else "")
     path = _cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -191,7 +201,7 @@ def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, gr
     for tw, th in tiles:
         for sch in schedules:
             st = Settings(**{**base.__dict__, "tile_w": tw, "tile_h": th, "schedule": sch})
-            plan = BatchedPlan(views, st, params, grad_fn)
+            plan = BatchedPlan(views, st, params, grad_fn, distortion=distortion)
             plan.step()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

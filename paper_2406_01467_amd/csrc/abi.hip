@@ -28,13 +28,15 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
-                             int32_t* last, int32_t* med, int32_t* cnt, hipStream_t st);
+                             int32_t* last, int32_t* med, int32_t* cnt, float* distortion,
+                             hipStream_t st);
 hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, const float* tf,
                              const int32_t* last, const int32_t* med, const float* dc,
-                             const float* dd, const float* dn, const float* da, float* gsplat,
-                             hipStream_t st);
+                             const float* dd, const float* dn, const float* da,
+                             const float* ddist, const float* fwd_depth, const float* fwd_alpha,
+                             float* gsplat, hipStream_t st);
 size_t tile_order_workspace(int64_t tiles);
 size_t normal_consistency_workspace(int64_t total_pixels);
 hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
@@ -95,7 +97,7 @@ KernelEvents& kernel_events(int kernel) {
 
 extern "C" {
 
-int rade_abi_version(void) { return 1; }
+int rade_abi_version(void) { return 2; }
 
 int rade_set_kernel_events(int kernel, void* start_event, void* stop_event) {
   if (kernel < RADE_KERNEL_PROJECT || kernel > RADE_KERNEL_PROJECT_BWD) return RADE_ERR_INVALID_ARG;
@@ -223,7 +225,7 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
-                    int32_t* median, int32_t* count, void* stream) {
+                    int32_t* median, int32_t* count, float* distortion, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !color || !depth || !normal || !alpha || !t_final || !last || !median)
@@ -233,7 +235,8 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
   const int64_t tiles = total_tiles(views_host, V);
   return hip_status(rade::launch_render_fwd(*s, views_dev, V, N, tiles, splats, pair_ids,
                                             tile_ranges, tile_order, color, depth, normal, alpha,
-                                            t_final, last, median, count, (hipStream_t)stream));
+                                            t_final, last, median, count, distortion,
+                                            (hipStream_t)stream));
 }
 
 size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute) {
@@ -253,12 +256,14 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const uint32_t* tile_ranges, uint32_t* tile_order,
                     const float* t_final, const int32_t* last,
                     const int32_t* median, const float* d_color, const float* d_depth,
-                    const float* d_normal, const float* d_alpha, float* d_means,
+                    const float* d_normal, const float* d_alpha, const float* d_distortion,
+                    const float* depth, const float* alpha, float* d_means,
                     float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
                     void* workspace, size_t workspace_bytes, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !t_final || !last || !median) return RADE_ERR_INVALID_ARG;
+  if (d_distortion && (!depth || !alpha)) return RADE_ERR_INVALID_ARG;
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !d_means || !d_scales ||
                 !d_quats || !d_opacities || !d_sh))
@@ -286,7 +291,8 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   const int64_t tiles = total_tiles(views_host, V);
   hipError_t e = rade::launch_render_bwd(*s, views_dev, V, N, tiles, splats, pair_ids,
                                          tile_ranges, tile_order, t_final, last, median, d_color,
-                                         d_depth, d_normal, d_alpha, gsplat, st);
+                                         d_depth, d_normal, d_alpha, d_distortion, depth, alpha,
+                                         gsplat, st);
   if (e != hipSuccess) return RADE_ERR_HIP;
   e = rade::launch_project_bwd(*s, views_dev, V, N, means, scales, quats, opacities, sh, gsplat,
                                d_means, d_scales, d_quats, d_opacities, d_sh, st);

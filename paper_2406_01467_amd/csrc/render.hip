@@ -16,6 +16,16 @@
 // w = alpha T times (rgb, d, n, 1), record the median splat while T > 1/2,
 // and set T = T (1 - alpha).
 //
+// Optionally (template flag DIST) the forward also returns the depth
+// distortion of Sec. 3.4 Eq. 23 per pixel, sum_{i,j} w_i w_j (d_i - d_j)^2 =
+// 2 A S with A = sum_i w_i and S = sum_i w_i (d_i - m)^2 about the weighted
+// mean m, both updated per blend in the weighted incremental form
+// S += A w / (A + w) (d - m)^2, m += w / (A + w) (d - m), whose terms are
+// all non-negative, unlike A sum w d^2 - (sum w d)^2 which cancels in FP32.
+// Its adjoint with the weights held constant (they are detached in the
+// training loss, Sec. 4.1) adds 4 g A w_i (d_i - m) to each splat's depth
+// gradient, with A and m = D_exp / A read from the forward's maps.
+//
 // Backward, per pixel, back to front from the last blended splat, with the
 // transmittance recovered as T_i = T_{i+1} / (1 - alpha_i) from the saved
 // final T (nothing per blend is stored) and the running sum R of what lies
@@ -70,7 +80,7 @@ struct FwdArgs {
   const uint32_t* ranges;
   const uint32_t* order;   // tile visiting order (NULL: natural)
   uint32_t* queue;         // work-queue counter of the persistent kernel
-  float *color, *depth, *normal, *alpha, *t_final;
+  float *color, *depth, *normal, *alpha, *t_final, *distortion;
   int32_t *last, *median, *count;
 };
 
@@ -87,6 +97,7 @@ struct BwdArgs {
   const float* t_final;
   const int32_t *last, *median;
   const float *d_color, *d_depth, *d_normal, *d_alpha;
+  const float *d_distortion, *fwd_depth, *fwd_alpha;  // DIST only
   float* gsplat;
 };
 
@@ -213,7 +224,7 @@ struct FwdShared {
 };
 
 // Forward blend of one tile (all threads of the workgroup take part).
-template <int TW, int TH>
+template <int TW, int TH, bool DIST>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShared<TW, TH>& sh) {
   using TG = TileGeom<TW, TH>;
   const BlendParams& bp = a.bp;
@@ -229,6 +240,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f, A = 0.f;
   float dmed = 0.f;
+  float dmean = 0.f, dvar = 0.f;  // DIST: weighted mean depth and sum w (d - mean)^2
   int cnt = 0, lastp = -1, medp = -1;
   bool done = !c.inside;
 
@@ -262,6 +274,16 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
         C0 = fmaf(w, s.r, C0); C1 = fmaf(w, s.g, C1); C2 = fmaf(w, s.b, C2);
         D = fmaf(w, d, D);
         N0 = fmaf(w, s.n0, N0); N1 = fmaf(w, s.n1, N1); N2 = fmaf(w, s.n2, N2);
+        if constexpr (DIST) {
+          // m += w/(A+w) delta, S += A w/(A+w) delta^2 (A before this
+          // blend): every term of S is a product of non-negative factors, so
+          // nothing cancels (the first splat adds exactly 0)
+          const float r = take ? __builtin_amdgcn_rcpf(A + w) : 0.0f;
+          const float delta = d - dmean;
+          const float wr = w * r;
+          dmean = fmaf(wr, delta, dmean);
+          dvar = fmaf(A * wr, delta * delta, dvar);
+        }
         A += w;
         const int pos = (int)(b0 - c.rb) + r;
         const bool med_here = take && T > 0.5f;
@@ -291,20 +313,21 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
   a.last[c.poff + pix] = lastp;
   a.median[c.poff + pix] = medp >= 0 ? (int32_t)pair_ids[c.rb + medp] : -1;
   if (a.count) a.count[c.poff + pix] = cnt;
+  if constexpr (DIST) a.distortion[c.poff + pix] = 2.0f * A * dvar;
 }
 
 // One workgroup per tile, tiles visited in `order` (or natural) order.
-template <int TW, int TH>
+template <int TW, int TH, bool DIST>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd(FwdArgs a) {
   __shared__ FwdShared<TW, TH> sh;
   const int64_t i = blockIdx.x;
-  fwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[i] : i, sh);
+  fwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[i] : i, sh);
 }
 
 // Persistent workgroups pull tiles from a device counter (zeroed before the
 // launch) in `order`; every workgroup exits once the counter passes the tile
 // count.
-template <int TW, int TH>
+template <int TW, int TH, bool DIST>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
   __shared__ FwdShared<TW, TH> sh;
   __shared__ uint32_t item_s;
@@ -314,29 +337,30 @@ __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
     const uint32_t item = item_s;
     __syncthreads();
     if ((int64_t)item >= a.tiles) break;
-    fwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+    fwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
   }
 }
 
-// Row (16-lane) sum by DPP: afterwards every lane of a row holds its row's
-// total.  quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
-// row_mirror.
-__device__ __forceinline__ float dpp_row_sum(float x) {
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
-  return x;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-// Sum 16 per-lane values over the wavefront (a transpose-reduction).
-//   v_permlane32_swap(a, b): a' = [a.lo32, b.lo32], b' = [a.hi32, b.hi32], so
-//     a' + b' holds value k in lanes 0-31 and value k+8 in lanes 32-63;
-//   v_permlane16_swap(a, b): a' = [a.r0, b.r0, a.r2, b.r2], b' = [a.r1, b.r1,
-//     a.r3, b.r3] (16-lane rows), so a' + b' holds values k, k+4, k+8, k+12 in
-//     rows 0..3;
-//   then a DPP row sum of each of the 4 remaining values.
-// On return lane l with (l & 15) < 4 holds the total of value 4 (l >> 4) + (l & 3).
+// Sum 16 per-lane values over the wavefront by transpose-reduction: every
+// level pairs each lane with a partner across one more lane direction, keeps
+// half of its values and adds the partner's copy of them, so the number of
+// values per lane halves while the set of lanes each value covers doubles.
+//   1. v_permlane32_swap(a, b) gives a' = [a.lo32, b.lo32], b' = [a.hi32,
+//      b.hi32]: a' + b' is value k in lanes 0-31, value k+8 in lanes 32-63;
+//   2. v_permlane16_swap(a, b) gives a' = [a.r0, b.r0, a.r2, b.r2], b' =
+//      [a.r1, b.r1, a.r3, b.r3] (16-lane rows): +4 where lane bit 4 is set;
+//   3. DPP row_ror:8 (partner = lane ^ 8): +2 where bit 3 is set;
+//   4. DPP row_half_mirror (partner = lane ^ 7 within each 8 lanes): +1
+//      where bit 2 is set;
+//   5. DPP quad_perm xor 1 and xor 2 sum the 4 lanes of each quad.
+// The partner directions 32, 16, 8, 7, 1, 2 span all 6 lane bits, so every
+// lane is counted once.  On return every lane l holds the total of value
+// l >> 2.
 __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
   float u[8];
 #pragma unroll
@@ -350,10 +374,15 @@ __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
   for (int k = 0; k < 4; ++k) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(u[k]),
                                                     __float_as_uint(u[k + 4]), false, false);
-    w[k] = dpp_row_sum(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+    w[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  const int j = threadIdx.x & 3;
-  return j == 0 ? w[0] : (j == 1 ? w[1] : (j == 2 ? w[2] : w[3]));
+  const bool b3 = (threadIdx.x & 8) != 0, b2 = (threadIdx.x & 4) != 0;
+  const float x0 = (b3 ? w[2] : w[0]) + dpp<0x128>(b3 ? w[0] : w[2]);
+  const float x1 = (b3 ? w[3] : w[1]) + dpp<0x128>(b3 ? w[1] : w[3]);
+  float y = (b2 ? x1 : x0) + dpp<0x141>(b2 ? x0 : x1);
+  y += dpp<0xB1>(y);
+  y += dpp<0x4E>(y);
+  return y;
 }
 
 constexpr float kTwoOverLog2e = 2.0f / kLog2e;
@@ -367,7 +396,7 @@ struct BwdShared {
 };
 
 // Backward pass of one tile (all threads of the workgroup take part).
-template <int TW, int TH>
+template <int TW, int TH, bool DIST>
 __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShared<TW, TH>& sh) {
   using TG = TileGeom<TW, TH>;
   const BlendParams& bp = a.bp;
@@ -392,6 +421,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
 
   float T = 0.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gM = 0.f;
   float gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gA = 0.f;
+  float kdist = 0.f, mdist = 0.f;  // DIST: 4 g A and the weighted mean depth
   int lastp = -1, med = -1;
   if (c.inside) {
     const int64_t P = c.P, pix = c.pix;
@@ -410,6 +440,11 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
       gN2 = d_normal[3 * c.poff + 2 * P + pix];
     }
     if (d_alpha) gA = d_alpha[c.poff + pix];
+    if constexpr (DIST) {
+      const float Am = a.fwd_alpha[c.poff + pix];
+      kdist = 4.0f * a.d_distortion[c.poff + pix] * Am;
+      mdist = Am > 0.0f ? a.fwd_depth[2 * c.poff + pix] / Am : 0.0f;
+    }
   }
   float Racc = T * (gC0 * bp.bg[0] + gC1 * bp.bg[1] + gC2 * bp.bg[2]);
 
@@ -455,24 +490,34 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
         const float Ti = T * inv;
         const float w = al * Ti;
         const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
-        const float sf = gC0 * s.r + gC1 * s.g + gC2 * s.b + gD * d + gN0 * s.n0 +
-                         gN1 * s.n1 + gN2 * s.n2 + gA;
-        const float ga = Ti * sf - Racc * inv;
+        // explicit FMAs (the file compiles without contraction so that the
+        // alpha decisions above match the forward bit for bit)
+        float sf = fmaf(gC0, s.r, gA);
+        sf = fmaf(gC1, s.g, sf);
+        sf = fmaf(gC2, s.b, sf);
+        sf = fmaf(gD, d, sf);
+        sf = fmaf(gN0, s.n0, sf);
+        sf = fmaf(gN1, s.n1, sf);
+        sf = fmaf(gN2, s.n2, sf);
+        const float ga = fmaf(Ti, sf, -(Racc * inv));
         T = has ? Ti : T;
         Racc = has ? fmaf(w, sf, Racc) : Racc;
         const int gid = __builtin_amdgcn_readfirstlane((int)sgid[r]);
         const float hm = has ? 1.0f : 0.0f;
         const float wg = hm * w;
-        const float gd = wg * gD + ((has && gid == med) ? gM : 0.0f);
+        float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
+        if constexpr (DIST) gd = fmaf(kdist * wg, d - mdist, gd);
+        // d power / d(dx, dy) = (t1 w0 + t2 w2, t1 w1 + t2 w3) 2 / log2(e)
         const float gp = (has && !cl) ? -ga * al : 0.0f;
-        const float dpdx = (t1 * s.w0 + t2 * s.w2) * kTwoOverLog2e;
-        const float dpdy = (t1 * s.w1 + t2 * s.w3) * kTwoOverLog2e;
+        const float gpk = gp * kTwoOverLog2e;
+        const float hg = 0.5f * gp;
         float g[16];
-        g[0] = gp * dpdx + gd * s.p0;
-        g[1] = gp * dpdy + gd * s.p1;
-        g[2] = 0.5f * gp * dx * dx;
-        g[3] = gp * dx * dy;
-        g[4] = 0.5f * gp * dy * dy;
+        g[0] = fmaf(gpk, fmaf(t1, s.w0, t2 * s.w2), gd * s.p0);
+        g[1] = fmaf(gpk, fmaf(t1, s.w1, t2 * s.w3), gd * s.p1);
+        const float hdx = hg * dx;
+        g[2] = hdx * dx;
+        g[3] = (gp * dx) * dy;
+        g[4] = (hg * dy) * dy;
         g[5] = (has && !cl) ? ga * e : 0.0f;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;
@@ -481,8 +526,8 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
         g[15] = 0.0f;
         {
           const float tot = wave_sum16(g);
-          const int vi = 4 * (lane >> 4) + (lane & 3);
-          if ((lane & 15) < 4 && vi < 15 && tot != 0.0f)
+          const int vi = lane >> 2;
+          if ((lane & 3) == 0 && vi < 15 && tot != 0.0f)
             atomicAdd(gsplat + (vbase + gid) * 16 + vi, tot);
         }
       }
@@ -492,15 +537,15 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
 }
 
 // One workgroup per tile, in `order` (or natural) order.
-template <int TW, int TH>
+template <int TW, int TH, bool DIST>
 __global__ void __launch_bounds__(TW * TH) k_render_bwd(BwdArgs a) {
   __shared__ BwdShared<TW, TH> sh;
   const int64_t i = blockIdx.x;
-  bwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[i] : i, sh);
+  bwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[i] : i, sh);
 }
 
 // Persistent workgroups over a device work queue (see k_render_fwd_persistent).
-template <int TW, int TH>
+template <int TW, int TH, bool DIST>
 __global__ void __launch_bounds__(TW * TH) k_render_bwd_persistent(BwdArgs a) {
   __shared__ BwdShared<TW, TH> sh;
   __shared__ uint32_t item_s;
@@ -510,7 +555,7 @@ __global__ void __launch_bounds__(TW * TH) k_render_bwd_persistent(BwdArgs a) {
     const uint32_t item = item_s;
     __syncthreads();
     if ((int64_t)item >= a.tiles) break;
-    bwd_tile<TW, TH>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+    bwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
   }
 }
 
@@ -521,10 +566,10 @@ __global__ void k_zero(float* __restrict__ a, int64_t n) {
 
 __global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
 
-// Workgroups that fit on the device at once for a kernel (cached per kernel).
+// Workgroups that fit on the device at once for a kernel; `cached` is the
+// caller's per-kernel cache (0 until first computed).
 template <typename K>
-unsigned resident_blocks(K kernel, int block, unsigned cap) {
-  static unsigned cached = 0;
+unsigned resident_blocks(K kernel, int block, unsigned cap, unsigned& cached) {
   if (cached == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
@@ -535,30 +580,46 @@ unsigned resident_blocks(K kernel, int block, unsigned cap) {
   return cached < cap ? cached : cap;
 }
 
+template <int TW, int TH, bool DIST>
+void launch_fwd_d(const FwdArgs& a, int schedule, hipStream_t st) {
+  constexpr int B = TileGeom<TW, TH>::BLOCK;
+  if (schedule == RADE_SCHEDULE_PERSISTENT) {
+    static unsigned cached = 0;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
+    const unsigned g =
+        resident_blocks(k_render_fwd_persistent<TW, TH, DIST>, B, (unsigned)a.tiles, cached);
+    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST>), dim3(g), dim3(B), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
+  }
+}
+
 template <int TW, int TH>
 void launch_fwd_t(const FwdArgs& a, int schedule, hipStream_t st) {
-  constexpr int B = TileGeom<TW, TH>::BLOCK;
   EventScope timing(RADE_KERNEL_RENDER_FWD, st);
+  if (a.distortion) launch_fwd_d<TW, TH, true>(a, schedule, st);
+  else launch_fwd_d<TW, TH, false>(a, schedule, st);
+}
+
+template <int TW, int TH, bool DIST>
+void launch_bwd_d(const BwdArgs& a, int schedule, hipStream_t st) {
+  constexpr int B = TileGeom<TW, TH>::BLOCK;
   if (schedule == RADE_SCHEDULE_PERSISTENT) {
+    static unsigned cached = 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
-    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH>, B, (unsigned)a.tiles);
-    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH>), dim3(g), dim3(B), 0, st, a);
+    const unsigned g =
+        resident_blocks(k_render_bwd_persistent<TW, TH, DIST>, B, (unsigned)a.tiles, cached);
+    hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH, DIST>), dim3(g), dim3(B), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, DIST>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
   }
 }
 
 template <int TW, int TH>
 void launch_bwd_t(const BwdArgs& a, int schedule, hipStream_t st) {
-  constexpr int B = TileGeom<TW, TH>::BLOCK;
   EventScope timing(RADE_KERNEL_RENDER_BWD, st);
-  if (schedule == RADE_SCHEDULE_PERSISTENT) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
-    const unsigned g = resident_blocks(k_render_bwd_persistent<TW, TH>, B, (unsigned)a.tiles);
-    hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH>), dim3(g), dim3(B), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
-  }
+  if (a.d_distortion) launch_bwd_d<TW, TH, true>(a, schedule, st);
+  else launch_bwd_d<TW, TH, false>(a, schedule, st);
 }
 
 }  // namespace
@@ -581,7 +642,8 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
-                             int32_t* last, int32_t* med, int32_t* cnt, hipStream_t st) {
+                             int32_t* last, int32_t* med, int32_t* cnt, float* distortion,
+                             hipStream_t st) {
   if (tiles == 0) return hipSuccess;
   FwdArgs a;
   a.bp = make_blend_params(s);
@@ -590,7 +652,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
   a.order = s.schedule == RADE_SCHEDULE_TILE ? nullptr : order;
   a.queue = order ? const_cast<uint32_t*>(order) + tiles : nullptr;
   a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
-  a.last = last; a.median = med; a.count = cnt;
+  a.last = last; a.median = med; a.count = cnt; a.distortion = distortion;
   RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, st))
   return hipGetLastError();
 }
@@ -599,8 +661,9 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, const float* tf,
                              const int32_t* last, const int32_t* med, const float* dc,
-                             const float* dd, const float* dn, const float* da, float* gsplat,
-                             hipStream_t st) {
+                             const float* dd, const float* dn, const float* da,
+                             const float* ddist, const float* fwd_depth, const float* fwd_alpha,
+                             float* gsplat, hipStream_t st) {
   const int64_t ng = (int64_t)V * N * 16;
   if (ng > 0)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, gsplat, ng);
@@ -613,6 +676,7 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
   a.queue = order ? const_cast<uint32_t*>(order) + tiles : nullptr;
   a.t_final = tf; a.last = last; a.median = med;
   a.d_color = dc; a.d_depth = dd; a.d_normal = dn; a.d_alpha = da;
+  a.d_distortion = ddist; a.fwd_depth = fwd_depth; a.fwd_alpha = fwd_alpha;
   a.gsplat = gsplat;
   RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, st))
   return hipGetLastError();

@@ -1,7 +1,9 @@
 """The training loss used to exercise the rasterizer: L1 on colour plus
 w_n x the normal-consistency term of Sec. 3.4, Eq. 24 (w_n = 5, Sec. 4.1),
 with the normal n~ taken from the median-depth map by central differences of
-back-projected points and not detached.
+back-projected points and not detached; optionally plus w_d x the mean over
+pixels of the depth distortion of Eq. 23 (w_d = 100 in Sec. 4.1; its
+gradient holds the blend weights constant).
 
 `make_grad_fn` returns the upstream gradients into pre-allocated buffers
 (torch elementwise ops for L1, the library's fused kernel for Eq. 24), safe
@@ -16,12 +18,15 @@ import torch.nn.functional as F
 from . import _lib
 
 W_NORMAL = 5.0
+W_DIST = 100.0
 
 
-def make_grad_fn(rast, target, w_normal: float = W_NORMAL):
+def make_grad_fn(rast, target, w_normal: float = W_NORMAL, w_dist: float = 0.0):
     """Upstream gradients of the benchmark loss into pre-allocated buffers:
     L1 colour (torch elementwise, mean per view) + w_normal x Eq. 24 (fused
-    library kernel).  Safe inside a HIP graph: no allocation, no host sync."""
+    library kernel) [+ w_dist x mean distortion (Eq. 23): a constant
+    gradient map, returned fifth].  Safe inside a HIP graph: no allocation,
+    no host sync."""
     dev, P = rast.device, rast.total_pixels
     wvec = torch.empty(3 * P, dtype=torch.float32, device=dev)
     for vc in rast.views_c:
@@ -29,10 +34,17 @@ def make_grad_fn(rast, target, w_normal: float = W_NORMAL):
         wvec[3 * vc.pix_offset: 3 * vc.pix_offset + 3 * n] = 1.0 / (3 * n)
     tmp = torch.empty(3 * P, dtype=torch.float32, device=dev)
     dC = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    dD = torch.empty(2 * P, dtype=torch.float32, device=dev)
-    dN = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    dA = torch.empty(P, dtype=torch.float32, device=dev)
+    # dD, dN, dA share one buffer so one fill clears them before the Eq. 24
+    # kernel adds into them
+    dDNA = torch.empty(6 * P, dtype=torch.float32, device=dev)
+    dD, dN, dA = dDNA[:2 * P], dDNA[2 * P:5 * P], dDNA[5 * P:]
     loss = torch.empty(rast.V, dtype=torch.float32, device=dev)
+    dL = None
+    if w_dist > 0.0:
+        dL = torch.empty(P, dtype=torch.float32, device=dev)
+        for vc in rast.views_c:
+            n = vc.width * vc.height
+            dL[vc.pix_offset: vc.pix_offset + n] = w_dist / n
     ws = torch.empty(max(1, _lib.rade_normal_consistency_workspace(P)), dtype=torch.uint8,
                      device=dev)
 
@@ -40,18 +52,19 @@ def make_grad_fn(rast, target, w_normal: float = W_NORMAL):
         torch.sub(maps["color"], target, out=tmp)
         torch.sign(tmp, out=tmp)
         torch.mul(tmp, wvec, out=dC)
-        dD.zero_()
-        dN.zero_()
-        dA.zero_()
+        dDNA.zero_()
         _lib.rade_normal_consistency(rast.views_c, rast.views_dev, maps["depth"], maps["normal"],
                                      maps["alpha"], w_normal, loss, dD, dN, dA, ws)
+        if dL is not None:
+            return dC, dD, dN, dA, dL
         return dC, dD, dN, dA
 
     grad_fn.loss = loss
     return grad_fn
 
 
-def torch_loss(color, depth, normal, alpha, target, views_c, w_normal: float = W_NORMAL):
+def torch_loss(color, depth, normal, alpha, target, views_c, w_normal: float = W_NORMAL,
+               distortion=None, w_dist: float = 0.0):
     """The same loss written with torch ops (eager autograd path)."""
     total = color.new_zeros(())
     for vc in views_c:
@@ -71,4 +84,6 @@ def torch_loss(color, depth, normal, alpha, target, views_c, w_normal: float = W
         facing = torch.where((n * X[:, 1:-1, 1:-1]).sum(0) > 0, -1.0, 1.0)
         l_n = (A[1:-1, 1:-1] - (Nm[:, 1:-1, 1:-1] * n * facing).sum(0)).mean()
         total = total + (C - T).abs().mean() + w_normal * l_n
+        if distortion is not None and w_dist > 0.0:
+            total = total + w_dist * distortion[o: o + P].mean()
     return total

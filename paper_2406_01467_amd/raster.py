@@ -26,6 +26,9 @@ class ForwardState:
     last: torch.Tensor
     median: torch.Tensor
     n_pairs: int
+    # the forward's depth and alpha maps (read by the distortion adjoint)
+    depth: Optional[torch.Tensor] = None
+    alpha: Optional[torch.Tensor] = None
 
 
 @dataclasses.dataclass
@@ -36,6 +39,7 @@ class Maps:
     alpha: torch.Tensor    # 1 plane per view
     count: Optional[torch.Tensor]
     state: ForwardState
+    distortion: Optional[torch.Tensor] = None  # 1 plane per view (Eq. 23), if asked for
 
     def view_planes(self, rast: "Rasterizer", v: int) -> dict:
         """Per-view (C, H, W) tensors of view v."""
@@ -49,6 +53,8 @@ class Maps:
                    last=cut(self.state.last, 1), median=cut(self.state.median, 1))
         if self.count is not None:
             out["count"] = cut(self.count, 1)
+        if self.distortion is not None:
+            out["distortion"] = cut(self.distortion, 1)
         return out
 
 
@@ -120,20 +126,22 @@ class Rasterizer:
         return pair_ids, ranges, M
 
     def forward(self, means, scales, quats, opacities, sh, want_count: bool = False,
-                keep_splats: bool = True, stream=None) -> Maps:
+                keep_splats: bool = True, stream=None, want_distortion: bool = False) -> Maps:
         N = means.shape[0]
         splats, tt = self.project(means, scales, quats, opacities, sh, stream)
         pair_ids, ranges, M = self.bin_sort(N, splats, tt, stream=stream)
         order = self.tile_order(ranges, stream)
         color, depth, normal, alpha, tf, last, med, cnt = self._new_maps(want_count)
+        dist = (torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
+                if want_distortion else None)
         _lib.rade_render_fwd(self.settings, self.views_c, self.views_dev, self.V, N, splats,
                              pair_ids, ranges, color, depth, normal, alpha, tf, last, med, cnt,
-                             stream, tile_order=order)
+                             stream, tile_order=order, distortion=dist)
         # pair_ids are a view of a reusable buffer: keep a private copy for
         # the backward pass
         state = ForwardState(splats if keep_splats else None, pair_ids.clone(), ranges, order,
-                             tf, last, med, M)
-        return Maps(color, depth, normal, alpha, cnt, state)
+                             tf, last, med, M, depth, alpha)
+        return Maps(color, depth, normal, alpha, cnt, state, dist)
 
     def tile_order(self, ranges, stream=None):
         """Heavy-first tile order (None for the plain one-workgroup-per-tile
@@ -148,7 +156,7 @@ class Rasterizer:
 
     # -- backward ------------------------------------------------------------
     def backward(self, state: ForwardState, means, scales, quats, opacities, sh, d_color=None,
-                 d_depth=None, d_normal=None, d_alpha=None, stream=None):
+                 d_depth=None, d_normal=None, d_alpha=None, stream=None, d_distortion=None):
         N = means.shape[0]
         recompute = state.splats is None
         ws = _lib.rade_render_bwd_workspace(self.settings, self.V, N, recompute)
@@ -163,32 +171,42 @@ class Rasterizer:
                              _aligned16(quats), opacities, sh, state.splats, state.pair_ids,
                              state.ranges, state.t_final, state.last, state.median, c(d_color),
                              c(d_depth), c(d_normal), c(d_alpha), dm, ds, dq, do, dsh, workspace,
-                             stream, tile_order=state.order)
+                             stream, tile_order=state.order, d_distortion=c(d_distortion),
+                             depth=state.depth, alpha=state.alpha)
         return dm, ds, dq, do, dsh
 
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rast: Rasterizer, recompute: bool, means, scales, quats, opacities, sh):
-        maps = rast.forward(means, scales, quats, opacities, sh, keep_splats=not recompute)
+    def forward(ctx, rast: Rasterizer, recompute: bool, distortion: bool, means, scales, quats,
+                opacities, sh):
+        maps = rast.forward(means, scales, quats, opacities, sh, keep_splats=not recompute,
+                            want_distortion=distortion)
         ctx.rast = rast
         ctx.state = maps.state
+        ctx.distortion = distortion
         ctx.save_for_backward(means, scales, quats, opacities, sh)
+        if distortion:
+            return maps.color, maps.depth, maps.normal, maps.alpha, maps.distortion
         return maps.color, maps.depth, maps.normal, maps.alpha
 
     @staticmethod
-    def backward(ctx, g_color, g_depth, g_normal, g_alpha):
+    def backward(ctx, g_color, g_depth, g_normal, g_alpha, g_dist=None):
         means, scales, quats, opacities, sh = ctx.saved_tensors
         dm, ds, dq, do, dsh = ctx.rast.backward(ctx.state, means, scales, quats, opacities, sh,
-                                                g_color, g_depth, g_normal, g_alpha)
+                                                g_color, g_depth, g_normal, g_alpha,
+                                                d_distortion=g_dist if ctx.distortion else None)
         ctx.state = None
-        return None, None, dm, ds, dq, do, dsh
+        return None, None, None, dm, ds, dq, do, dsh
 
 
-def render(rast: Rasterizer, means, scales, quats, opacities, sh, recompute: bool = False):
+def render(rast: Rasterizer, means, scales, quats, opacities, sh, recompute: bool = False,
+           distortion: bool = False):
     """Differentiable render of all views of `rast`.  Returns packed planar
     (color [3P], depth [2P], normal [3P], alpha [P]) with P the total pixel
-    count.  recompute=True keeps no splats for the backward pass (they are
-    recomputed from the parameters); the per-pixel blend state is always
-    recomputed from the saved final transmittance."""
-    return _RenderFn.apply(rast, recompute, means, scales, quats, opacities, sh)
+    count, and with distortion=True also the depth-distortion map [P] of
+    Eq. 23 (its gradient holds the blend weights constant, as the training
+    loss detaches them).  recompute=True keeps no splats for the backward
+    pass (they are recomputed from the parameters); the per-pixel blend
+    state is always recomputed from the saved final transmittance."""
+    return _RenderFn.apply(rast, recompute, distortion, means, scales, quats, opacities, sh)
