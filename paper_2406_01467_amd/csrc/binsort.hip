@@ -275,21 +275,22 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 }
 
 // ---------------------------------------------------------------------------
-// Pair emission, one thread per pair: pair p belongs to the depth-sorted splat
-// j with offs[j] <= p < offs[j + 1] and is its (p - offs[j])-th tile in
-// row-major order of its tile rect.  A block covers kEmitPairs consecutive
-// pairs, hence at most kEmitPairs consecutive splats (each has >= 1 pair):
-// their offsets are staged in LDS and each thread finds its splat by binary
-// search there.  Writes are coalesced and the work is balanced whatever the
-// splat sizes.
+// Pair emission, four consecutive pairs per thread: pair p belongs to the
+// depth-sorted splat j with offs[j] <= p < offs[j + 1] and is its
+// (p - offs[j])-th tile in row-major order of its tile rect.  A block covers
+// kEmitPairs consecutive pairs, hence at most kEmitPairs consecutive splats
+// (each has >= 1 pair): their offsets are staged in LDS.  Writes are
+// coalesced and the work is balanced whatever the splat sizes.
 constexpr int kEmitPairs = 1024;
+constexpr int kEmitPerThread = kEmitPairs / kThreads;  // 4 consecutive pairs
+static_assert(kEmitPerThread == 4, "emit stores four pairs as one 16-byte word");
 
 __global__ void __launch_bounds__(kThreads)
 k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
        const uint32_t* __restrict__ n_dev, const uint64_t* __restrict__ m_dev,
        int64_t capacity, const rade_splat* __restrict__ splats,
        const rade_view* __restrict__ views, int64_t N, int tile_w, int tile_h,
-       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids) {
+       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids, int vec_stores) {
   __shared__ uint64_t win[kEmitPairs + 1];
   __shared__ int64_t j0_s;
   const uint64_t M = *m_dev;
@@ -312,33 +313,63 @@ k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
     win[w] = j < nvis ? offs[j] : M;
   }
   __syncthreads();
+  // Four consecutive pairs per thread: the first one's splat by binary
+  // search in the window, the next ones by stepping forward (every listed
+  // splat has at least one pair, so this is at most one step per pair); one
+  // 16-byte store per output array when all four exist.
+  const uint64_t pb = P0 + (uint64_t)kEmitPerThread * threadIdx.x;
+  if (pb >= M) return;
+  int lo = 0, hi = kEmitPairs;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (win[mid] <= pb) lo = mid; else hi = mid - 1;
+  }
+  uint32_t tk[kEmitPerThread], pg[kEmitPerThread];
+  int cur = -1;
+  int tx0 = 0, ty0 = 0, ty1 = 0;
+  uint32_t nx = 1, g = 0, toff = 0, tiles_x = 0;
 #pragma unroll
-  for (int r = 0; r < kEmitPairs / kThreads; ++r) {
-    const uint64_t p = P0 + (uint64_t)r * kThreads + threadIdx.x;
-    if (p >= M) break;
-    int lo = 0, hi = kEmitPairs;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (win[mid] <= p) lo = mid; else hi = mid - 1;
+  for (int r = 0; r < kEmitPerThread; ++r) {
+    const uint64_t p = pb + r;
+    tk[r] = 0u;
+    pg[r] = 0u;
+    if (p >= M) continue;
+    while (lo < kEmitPairs && win[lo + 1] <= p) ++lo;
+    if (lo != cur) {
+      cur = lo;
+      // V*N < 2^32 (32-bit ids): 32-bit divisions
+      const uint32_t i = svals[j0 + lo];
+      const uint32_t v = i / (uint32_t)N;
+      g = i - v * (uint32_t)N;
+      const rade_splat& sp = splats[i];
+      tx0 = sp.rect[0] / tile_w;
+      const int tx1 = sp.rect[1] / tile_w;
+      ty0 = sp.rect[2] / tile_h;
+      ty1 = sp.rect[3] / tile_h;
+      nx = (uint32_t)(tx1 - tx0 + 1);
+      toff = (uint32_t)views[v].tile_offset;
+      tiles_x = (uint32_t)views[v].tiles_x;
     }
-    const int64_t j = j0 + lo;
-    // a splat covers fewer than 2^31 tiles and V*N < 2^32 (32-bit ids), so
-    // the divisions below are 32-bit
+    // pair k of the splat is its k-th tile in row-major order of its rect (a
+    // splat covers fewer than 2^31 tiles); stay inside the rect even if
+    // tiles_touched disagrees with it
     const uint32_t k = (uint32_t)(p - win[lo]);
-    const uint32_t i = svals[j];
-    const uint32_t v = i / (uint32_t)N;
-    const uint32_t g = i - v * (uint32_t)N;
-    const rade_splat& sp = splats[i];
-    const int tx0 = sp.rect[0] / tile_w, tx1 = sp.rect[1] / tile_w;
-    const int ty0 = sp.rect[2] / tile_h, ty1 = sp.rect[3] / tile_h;
-    const uint32_t nx = (uint32_t)(tx1 - tx0 + 1);
     const uint32_t row = k / nx;
-    // stay inside the rect even if tiles_touched disagrees with it
     const int ty = min(ty0 + (int)row, ty1);
     const int tx = tx0 + (int)(k - row * nx);
-    const rade_view& vw = views[v];
-    tkeys[p] = (uint32_t)vw.tile_offset + (uint32_t)(ty * vw.tiles_x + tx);
-    pids[p] = g;
+    tk[r] = toff + (uint32_t)ty * tiles_x + (uint32_t)tx;
+    pg[r] = g;
+  }
+  if (vec_stores && pb + kEmitPerThread <= M) {
+    *reinterpret_cast<uint4*>(tkeys + pb) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+    *reinterpret_cast<uint4*>(pids + pb) = make_uint4(pg[0], pg[1], pg[2], pg[3]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kEmitPerThread; ++r)
+      if (pb + r < M) {
+        tkeys[pb + r] = tk[r];
+        pids[pb + r] = pg[r];
+      }
   }
 }
 
@@ -567,7 +598,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   if (VN > 0 && capacity > 0)
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(capacity, kEmitPairs)), dim3(kThreads), 0, st, sv,
                        offs, n_vis, m64, capacity, splats, views_dev, N, s.tile_w, s.tile_h, ek,
-                       ev);
+                       ev, (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0);
   // 5. stable sort by tile
   radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, hist, (uint32_t*)sums, st);
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;

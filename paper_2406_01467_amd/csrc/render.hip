@@ -223,8 +223,9 @@ struct FwdShared {
   uint64_t masks[TileGeom<TW, TH>::NW][TileGeom<TW, TH>::NW];
 };
 
-// Forward blend of one tile (all threads of the workgroup take part).
-template <int TW, int TH, bool DIST>
+// Forward blend of one tile (all threads of the workgroup take part).  DIST:
+// also the distortion map; CNT: also the blend-count map.
+template <int TW, int TH, bool DIST, bool CNT>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShared<TW, TH>& sh) {
   using TG = TileGeom<TW, TH>;
   const BlendParams& bp = a.bp;
@@ -290,7 +291,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
         medp = med_here ? pos : medp;
         dmed = med_here ? d : dmed;
         lastp = take ? pos : lastp;
-        cnt += take ? 1 : 0;
+        if constexpr (CNT) cnt += take ? 1 : 0;
         T = take ? Tn : T;
         if (__all(done)) { wave_live = false; break; }
       }
@@ -312,22 +313,22 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
   a.t_final[c.poff + pix] = T;
   a.last[c.poff + pix] = lastp;
   a.median[c.poff + pix] = medp >= 0 ? (int32_t)pair_ids[c.rb + medp] : -1;
-  if (a.count) a.count[c.poff + pix] = cnt;
+  if constexpr (CNT) a.count[c.poff + pix] = cnt;
   if constexpr (DIST) a.distortion[c.poff + pix] = 2.0f * A * dvar;
 }
 
 // One workgroup per tile, tiles visited in `order` (or natural) order.
-template <int TW, int TH, bool DIST>
+template <int TW, int TH, bool DIST, bool CNT>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd(FwdArgs a) {
   __shared__ FwdShared<TW, TH> sh;
   const int64_t i = blockIdx.x;
-  fwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[i] : i, sh);
+  fwd_tile<TW, TH, DIST, CNT>(a, a.order ? (int64_t)a.order[i] : i, sh);
 }
 
 // Persistent workgroups pull tiles from a device counter (zeroed before the
 // launch) in `order`; every workgroup exits once the counter passes the tile
 // count.
-template <int TW, int TH, bool DIST>
+template <int TW, int TH, bool DIST, bool CNT>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
   __shared__ FwdShared<TW, TH> sh;
   __shared__ uint32_t item_s;
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
     const uint32_t item = item_s;
     __syncthreads();
     if ((int64_t)item >= a.tiles) break;
-    fwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+    fwd_tile<TW, TH, DIST, CNT>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
   }
 }
 
@@ -580,25 +581,31 @@ unsigned resident_blocks(K kernel, int block, unsigned cap, unsigned& cached) {
   return cached < cap ? cached : cap;
 }
 
-template <int TW, int TH, bool DIST>
+template <int TW, int TH, bool DIST, bool CNT>
 void launch_fwd_d(const FwdArgs& a, int schedule, hipStream_t st) {
   constexpr int B = TileGeom<TW, TH>::BLOCK;
   if (schedule == RADE_SCHEDULE_PERSISTENT) {
     static unsigned cached = 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
-    const unsigned g =
-        resident_blocks(k_render_fwd_persistent<TW, TH, DIST>, B, (unsigned)a.tiles, cached);
-    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST>), dim3(g), dim3(B), 0, st, a);
+    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH, DIST, CNT>, B,
+                                       (unsigned)a.tiles, cached);
+    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST, CNT>), dim3(g), dim3(B), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST, CNT>), dim3((unsigned)a.tiles), dim3(B), 0,
+                       st, a);
   }
 }
 
 template <int TW, int TH>
 void launch_fwd_t(const FwdArgs& a, int schedule, hipStream_t st) {
   EventScope timing(RADE_KERNEL_RENDER_FWD, st);
-  if (a.distortion) launch_fwd_d<TW, TH, true>(a, schedule, st);
-  else launch_fwd_d<TW, TH, false>(a, schedule, st);
+  if (a.distortion) {
+    if (a.count) launch_fwd_d<TW, TH, true, true>(a, schedule, st);
+    else launch_fwd_d<TW, TH, true, false>(a, schedule, st);
+  } else {
+    if (a.count) launch_fwd_d<TW, TH, false, true>(a, schedule, st);
+    else launch_fwd_d<TW, TH, false, false>(a, schedule, st);
+  }
 }
 
 template <int TW, int TH, bool DIST>
