@@ -367,3 +367,65 @@ def normal_consistency(view, depth_med, normal, alpha, weight, magnitude=False):
     gP_m[:, :-2, 1:-1] += gdv_m
     gD_mag = (gP_m * np.abs(r)).sum(0)
     return loss, gD, gN, gA, gD_mag
+
+
+# ----------------------------------------------------------------------------
+# 3D smoothing filter (the Mip-Splatting filter the paper trains with,
+# Sec. 4.1), FP64 NumPy.
+
+def filter3d_var(views, means, near=0.2, scale=0.2, margin=0.15, return_fragile=False):
+    """Per Gaussian: rate = max over views with camera z > near whose image,
+    widened by margin x (width, height) on every side, holds the projected
+    mean, of fx / z; variance scale / rate^2 (0 when no view sees the mean).
+    With return_fragile, also flags means within 1e-6 px of a widened image
+    border or within 1e-9 of the near plane (a decision FP rounding may flip)."""
+    m = np.asarray(means, np.float32).astype(np.float64)
+    best = np.zeros(m.shape[0])
+    frag = np.zeros(m.shape[0], bool)
+    for v in views:
+        R = np.asarray(v.R, np.float32).astype(np.float64).reshape(3, 3)
+        t = np.asarray(v.t, np.float32).astype(np.float64)
+        fx, fy = float(np.float32(v.fx)), float(np.float32(v.fy))
+        cx, cy = float(np.float32(v.cx)), float(np.float32(v.cy))
+        x = m @ R.T + t
+        z = x[:, 2]
+        front = z > near
+        zs = np.where(front, z, 1.0)
+        u = fx * x[:, 0] / zs + cx
+        w = fy * x[:, 1] / zs + cy
+        mx, my = margin * v.width, margin * v.height
+        inside = (u >= -mx) & (u <= v.width + mx) & (w >= -my) & (w <= v.height + my)
+        ok = front & inside
+        best = np.where(ok, np.maximum(best, fx / zs), best)
+        edge = np.minimum.reduce([np.abs(u + mx), np.abs(u - v.width - mx), np.abs(w + my),
+                                  np.abs(w - v.height - my)])
+        frag |= (front & (edge < 1e-6)) | (np.abs(z - near) < 1e-9)
+    var = np.where(best > 0, scale / np.where(best > 0, best, 1.0) ** 2, 0.0)
+    return (var, frag) if return_fragile else var
+
+
+def filter3d_apply(scales, opacities, var):
+    """Filtered scales sqrt(s^2 + var) and opacities o sqrt(prod s^2 / prod
+    (s^2 + var)) (the convolution keeps the Gaussian's integral)."""
+    s = np.asarray(scales, np.float64)
+    o = np.asarray(opacities, np.float64)
+    f = np.asarray(var, np.float64)[:, None]
+    t2 = s * s + f
+    ratio = np.prod(np.where(t2 > 0, s * s / np.where(t2 > 0, t2, 1.0), 1.0), axis=1)
+    return np.sqrt(t2), o * np.sqrt(ratio)
+
+
+def filter3d_apply_bwd(scales, opacities, var, g_scales_f, g_opac_f):
+    """Adjoint of filter3d_apply with var constant: d s_k = g_s'_k s_k / s'_k
+    + g_o' o' var / (s_k s'_k^2), d o = g_o' sqrt(ratio)."""
+    s = np.asarray(scales, np.float64)
+    o = np.asarray(opacities, np.float64)
+    f = np.asarray(var, np.float64)[:, None]
+    gs = np.asarray(g_scales_f, np.float64)
+    go = np.asarray(g_opac_f, np.float64)
+    t2 = s * s + f
+    sf = np.sqrt(t2)
+    root = np.sqrt(np.prod(s * s / t2, axis=1))
+    of = o * root
+    ds = gs * s / sf + (go * of)[:, None] * f / (s * t2)
+    return ds, go * root
