@@ -251,6 +251,31 @@ int rade_normal_consistency(const rade_view* views_host, const rade_view* views_
                             float* d_alpha, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* 3D smoothing filter (the Mip-Splatting filter the paper trains with,
+ * Sec. 4.1).  For each Gaussian, rate = max over the views whose camera z >
+ * near_plane and whose image widened by `margin` x (width, height) on every
+ * side holds the projected mean, of fx / z (pixels per world unit at the
+ * mean); var[g] = scale / rate^2, or 0 when no view sees the mean.  means
+ * N*3, var N (device).  The variance depends on the means and cameras only;
+ * callers recompute it from time to time and treat it as a constant. */
+int rade_filter3d_var(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
+                      const float* means, float scale, float margin, float* var, void* stream);
+
+/* Convolution of each Gaussian with its filter: scales_out = sqrt(scales^2 +
+ * var) per axis (the covariance R S^2 R^T + var I keeps its rotation) and
+ * opacities_out = opacities * sqrt(prod scales^2 / prod scales_out^2), which
+ * keeps the Gaussian's integral.  Feed the outputs to rade_project. */
+int rade_filter3d_apply(int64_t N, const float* scales, const float* opacities, const float* var,
+                        float* scales_out, float* opacities_out, void* stream);
+
+/* Adjoint of rade_filter3d_apply with var held constant: from the gradients
+ * of the filtered scales (N*3) and opacities (N) to those of the unfiltered
+ * ones.  d_scales / d_opacities may alias d_scales_out / d_opacities_out. */
+int rade_filter3d_apply_bwd(int64_t N, const float* scales, const float* opacities,
+                            const float* var, const float* d_scales_out,
+                            const float* d_opacities_out, float* d_scales, float* d_opacities,
+                            void* stream);
+
 /* Kernel timing without a profiler.  After this call, every launch of the
  * kernel `kernel` (one of RADE_KERNEL_*) is bracketed by hipEventRecord of
  * `start_event` and `stop_event` (hipEvent_t passed as void*) on the stream

@@ -130,6 +130,11 @@ def load() -> ctypes.CDLL:
     lib.rade_normal_consistency.argtypes = [P, P, I32] + [P] * 3 + [ctypes.c_float] + [P] * 5 + [SZ, P]
     lib.rade_normal_consistency.restype = ctypes.c_int
     lib.rade_set_kernel_events.restype = ctypes.c_int
+    lib.rade_filter3d_var.argtypes = [P, P, I32, I64, P, ctypes.c_float, ctypes.c_float, P, P]
+    lib.rade_filter3d_apply.argtypes = [I64] + [P] * 5 + [P]
+    lib.rade_filter3d_apply_bwd.argtypes = [I64] + [P] * 7 + [P]
+    for f in ("rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd"):
+        getattr(lib, f).restype = ctypes.c_int
     for f in ("rade_views_prepare", "rade_project", "rade_bin_sort", "rade_render_fwd",
               "rade_render_bwd"):
         getattr(lib, f).restype = ctypes.c_int
@@ -140,7 +145,8 @@ def load() -> ctypes.CDLL:
 EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "rade_bin_sort",
             "rade_render_fwd", "rade_render_bwd_workspace", "rade_render_bwd", "rade_strerror",
             "rade_abi_version", "rade_set_kernel_events", "rade_tile_order_workspace",
-            "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency"]
+            "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
+            "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -299,3 +305,25 @@ def rade_normal_consistency(views_c, views_dev, depth, normal, alpha, weight: fl
         views_c, _p(views_dev), len(views_c), _p(depth), _p(normal), _p(alpha), float(weight),
         _p(loss), _p(d_depth), _p(d_normal), _p(d_alpha), _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_normal_consistency")
+
+
+def rade_filter3d_var(settings: Settings, views_dev, V: int, N: int, means, scale: float,
+                      margin: float, var, stream=None):
+    s = settings.c()
+    return _check(load().rade_filter3d_var(ctypes.byref(s), _p(views_dev), V, N, _p(means),
+                                           float(scale), float(margin), _p(var),
+                                           _stream(stream)), "rade_filter3d_var")
+
+
+def rade_filter3d_apply(N: int, scales, opacities, var, scales_out, opacities_out, stream=None):
+    return _check(load().rade_filter3d_apply(N, _p(scales), _p(opacities), _p(var),
+                                             _p(scales_out), _p(opacities_out), _stream(stream)),
+                  "rade_filter3d_apply")
+
+
+def rade_filter3d_apply_bwd(N: int, scales, opacities, var, d_scales_out, d_opacities_out,
+                            d_scales, d_opacities, stream=None):
+    return _check(load().rade_filter3d_apply_bwd(N, _p(scales), _p(opacities), _p(var),
+                                                 _p(d_scales_out), _p(d_opacities_out),
+                                                 _p(d_scales), _p(d_opacities), _stream(stream)),
+                  "rade_filter3d_apply_bwd")

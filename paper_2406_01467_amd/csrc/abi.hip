@@ -46,6 +46,16 @@ hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t tota
                                      hipStream_t st);
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st);
+hipError_t launch_filter3d_var(const rade_view* views, int V, int64_t N, const float* means,
+                               double near_plane, float scale, float margin, float* var,
+                               hipStream_t st);
+hipError_t launch_filter3d_apply(int64_t N, const float* scales, const float* opac,
+                                 const float* var, float* scales_out, float* opac_out,
+                                 hipStream_t st);
+hipError_t launch_filter3d_apply_bwd(int64_t N, const float* scales, const float* opac,
+                                     const float* var, const float* d_scales_f,
+                                     const float* d_opac_f, float* d_scales, float* d_opac,
+                                     hipStream_t st);
 }  // namespace rade
 
 namespace {
@@ -297,6 +307,37 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   e = rade::launch_project_bwd(*s, views_dev, V, N, means, scales, quats, opacities, sh, gsplat,
                                d_means, d_scales, d_quats, d_opacities, d_sh, st);
   return hip_status(e);
+}
+
+int rade_filter3d_var(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
+                      const float* means, float scale, float margin, float* var, void* stream) {
+  if (!s || !views_dev || !counts_ok(V, N)) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!means || !var)) return RADE_ERR_INVALID_ARG;
+  if (!(scale >= 0.0f) || !(margin >= 0.0f)) return RADE_ERR_INVALID_ARG;
+  return hip_status(rade::launch_filter3d_var(views_dev, V, N, means, s->near_plane, scale,
+                                              margin, var, (hipStream_t)stream));
+}
+
+int rade_filter3d_apply(int64_t N, const float* scales, const float* opacities, const float* var,
+                        float* scales_out, float* opacities_out, void* stream) {
+  if (N < 0) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!scales || !opacities || !var || !scales_out || !opacities_out))
+    return RADE_ERR_INVALID_ARG;
+  return hip_status(rade::launch_filter3d_apply(N, scales, opacities, var, scales_out,
+                                                opacities_out, (hipStream_t)stream));
+}
+
+int rade_filter3d_apply_bwd(int64_t N, const float* scales, const float* opacities,
+                            const float* var, const float* d_scales_out,
+                            const float* d_opacities_out, float* d_scales, float* d_opacities,
+                            void* stream) {
+  if (N < 0) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!scales || !opacities || !var || !d_scales_out || !d_opacities_out ||
+                !d_scales || !d_opacities))
+    return RADE_ERR_INVALID_ARG;
+  return hip_status(rade::launch_filter3d_apply_bwd(N, scales, opacities, var, d_scales_out,
+                                                    d_opacities_out, d_scales, d_opacities,
+                                                    (hipStream_t)stream));
 }
 
 }  // extern "C"
