@@ -429,3 +429,52 @@ def filter3d_apply_bwd(scales, opacities, var, g_scales_f, g_opac_f):
     of = o * root
     ds = gs * s / sf + (go * of)[:, None] * f / (s * t2)
     return ds, go * root
+
+
+# ----------------------------------------------------------------------------
+# TSDF fusion of median-depth maps (Sec. 4.1, Mesh Extraction), FP64 NumPy.
+
+def tsdf_fuse(views, depth_med, origin, voxel, dims, trunc, near=0.2, return_fragile=False):
+    """Truncated signed distance of a voxel grid from per-view median-depth
+    maps (depth_med[v]: (H, W)).  Voxel (i, j, k) has centre origin + (i +
+    1/2, j + 1/2, k + 1/2) voxel and index (k ny + j) nx + i.  For every view
+    with camera z > near whose projection of the centre falls in pixel
+    (floor(u), floor(v)) of the image and whose median depth D there is
+    positive (a surface): s = D - z; views with s >= -trunc contribute
+    min(1, s / trunc) with weight 1.  Returns (tsdf = mean contribution, 0
+    where none; weight = number of contributing views)."""
+    nx, ny, nz = (int(d) for d in dims)
+    o = np.asarray(origin, np.float64)
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X = np.stack([o[0] + (ii.ravel() + 0.5) * voxel, o[1] + (jj.ravel() + 0.5) * voxel,
+                  o[2] + (kk.ravel() + 0.5) * voxel], axis=1)
+    F = np.zeros(X.shape[0])
+    Wt = np.zeros(X.shape[0])
+    frag = np.zeros(X.shape[0], bool)
+    for v, D in zip(views, depth_med):
+        R = np.asarray(v.R, np.float32).astype(np.float64).reshape(3, 3)
+        t = np.asarray(v.t, np.float32).astype(np.float64)
+        fx, fy = float(np.float32(v.fx)), float(np.float32(v.fy))
+        cx, cy = float(np.float32(v.cx)), float(np.float32(v.cy))
+        x = X @ R.T + t
+        z = x[:, 2]
+        front = z > near
+        zs = np.where(front, z, 1.0)
+        u = fx * x[:, 0] / zs + cx
+        w = fy * x[:, 1] / zs + cy
+        px, py = np.floor(u), np.floor(w)
+        inside = front & (px >= 0) & (px < v.width) & (py >= 0) & (py < v.height)
+        pxi = np.where(inside, px, 0).astype(np.int64)
+        pyi = np.where(inside, py, 0).astype(np.int64)
+        d = np.asarray(D, np.float64)[pyi, pxi]
+        s = d - z
+        ok = inside & (d > 0) & (s >= -trunc)
+        F += np.where(ok, np.minimum(1.0, s / trunc), 0.0)
+        Wt += ok
+        # decisions rounding may flip: a centre on a pixel border, the
+        # truncation edge, the near plane
+        frag |= front & ((np.abs(u - np.round(u)) < 1e-7) | (np.abs(w - np.round(w)) < 1e-7))
+        frag |= inside & (d > 0) & (np.abs(s + trunc) < 1e-5 * (1.0 + abs(trunc)))
+        frag |= np.abs(z - near) < 1e-9
+    tsdf = np.where(Wt > 0, F / np.where(Wt > 0, Wt, 1.0), 0.0)
+    return (tsdf, Wt, frag) if return_fragile else (tsdf, Wt)
