@@ -276,6 +276,23 @@ int rade_filter3d_apply_bwd(int64_t N, const float* scales, const float* opaciti
                             const float* d_opacities_out, float* d_scales, float* d_opacities,
                             void* stream);
 
+/* TSDF fusion of rendered median-depth maps (the mesh extraction of
+ * Sec. 4.1, a truncated signed distance field in the manner of Curless and
+ * Levoy).  Voxel (i, j, k) of the nx x ny x nz grid has centre origin + (i +
+ * 1/2, j + 1/2, k + 1/2) voxel and index (k ny + j) nx + i.  For every view
+ * with camera z > near_plane whose projection of the centre falls in pixel
+ * (floor(u), floor(v)) of the image and whose median depth D there is
+ * positive: s = D - z; views with s >= -trunc contribute min(1, s / trunc)
+ * with weight 1.  tsdf (nx ny nz floats) receives the mean contribution (0
+ * where none), weight the number of contributing views.
+ *   views_host/views_dev : the V prepared views the maps were rendered for
+ *   depth                : the 2-plane depth maps of rade_render_fwd
+ *   origin               : host, 3 doubles */
+int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
+                   const rade_view* views_dev, int32_t V, const float* depth,
+                   const double* origin, double voxel, int32_t nx, int32_t ny, int32_t nz,
+                   float trunc, float* tsdf, float* weight, void* stream);
+
 /* Kernel timing without a profiler.  After this call, every launch of the
  * kernel `kernel` (one of RADE_KERNEL_*) is bracketed by hipEventRecord of
  * `start_event` and `stop_event` (hipEvent_t passed as void*) on the stream

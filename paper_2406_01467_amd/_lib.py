@@ -133,7 +133,10 @@ def load() -> ctypes.CDLL:
     lib.rade_filter3d_var.argtypes = [P, P, I32, I64, P, ctypes.c_float, ctypes.c_float, P, P]
     lib.rade_filter3d_apply.argtypes = [I64] + [P] * 5 + [P]
     lib.rade_filter3d_apply_bwd.argtypes = [I64] + [P] * 7 + [P]
-    for f in ("rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd"):
+    lib.rade_tsdf_fuse.argtypes = [P, P, P, I32, P, P, ctypes.c_double, I32, I32, I32,
+                                   ctypes.c_float, P, P, P]
+    for f in ("rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
+              "rade_tsdf_fuse"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("rade_views_prepare", "rade_project", "rade_bin_sort", "rade_render_fwd",
               "rade_render_bwd"):
@@ -146,7 +149,8 @@ EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "ra
             "rade_render_fwd", "rade_render_bwd_workspace", "rade_render_bwd", "rade_strerror",
             "rade_abi_version", "rade_set_kernel_events", "rade_tile_order_workspace",
             "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
-            "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd"]
+            "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
+            "rade_tsdf_fuse"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -327,3 +331,13 @@ def rade_filter3d_apply_bwd(N: int, scales, opacities, var, d_scales_out, d_opac
                                                  _p(d_scales_out), _p(d_opacities_out),
                                                  _p(d_scales), _p(d_opacities), _stream(stream)),
                   "rade_filter3d_apply_bwd")
+
+
+def rade_tsdf_fuse(settings: Settings, views_c, views_dev, depth, origin, voxel: float, dims,
+                   trunc: float, tsdf, weight, stream=None):
+    s = settings.c()
+    o = (ctypes.c_double * 3)(*[float(x) for x in origin])
+    nx, ny, nz = (int(d) for d in dims)
+    return _check(load().rade_tsdf_fuse(ctypes.byref(s), views_c, _p(views_dev), len(views_c),
+                                        _p(depth), o, float(voxel), nx, ny, nz, float(trunc),
+                                        _p(tsdf), _p(weight), _stream(stream)), "rade_tsdf_fuse")

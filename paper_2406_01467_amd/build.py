@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librade.so")
-SOURCES = ["abi.hip", "project.hip", "binsort.hip", "render.hip", "losses.hip", "filter3d.hip"]
+SOURCES = ["abi.hip", "project.hip", "binsort.hip", "render.hip", "losses.hip", "filter3d.hip",
+           "tsdf.hip"]
 ARCH = os.environ.get("RADE_OFFLOAD_ARCH", "gfx950")
 
 

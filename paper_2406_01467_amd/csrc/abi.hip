@@ -56,6 +56,10 @@ hipError_t launch_filter3d_apply_bwd(int64_t N, const float* scales, const float
                                      const float* var, const float* d_scales_f,
                                      const float* d_opac_f, float* d_scales, float* d_opac,
                                      hipStream_t st);
+hipError_t launch_tsdf_fuse(const rade_view* views, int V, const float* depth,
+                            const double* origin, double voxel, int64_t nx, int64_t ny,
+                            int64_t nz, double near_plane, float trunc, float* tsdf,
+                            float* weight, hipStream_t st);
 }  // namespace rade
 
 namespace {
@@ -338,6 +342,25 @@ int rade_filter3d_apply_bwd(int64_t N, const float* scales, const float* opaciti
   return hip_status(rade::launch_filter3d_apply_bwd(N, scales, opacities, var, d_scales_out,
                                                     d_opacities_out, d_scales, d_opacities,
                                                     (hipStream_t)stream));
+}
+
+int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
+                   const rade_view* views_dev, int32_t V, const float* depth,
+                   const double* origin, double voxel, int32_t nx, int32_t ny, int32_t nz,
+                   float trunc, float* tsdf, float* weight, void* stream) {
+  if (!s || !views_ok(views_host, V) || !views_dev || !origin) return RADE_ERR_INVALID_ARG;
+  if (!(voxel > 0.0) || !(trunc > 0.0f) || nx < 1 || ny < 1 || nz < 1) return RADE_ERR_INVALID_ARG;
+  if (!std::isfinite(origin[0]) || !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
+    return RADE_ERR_INVALID_ARG;
+  if (!depth || !tsdf || !weight) return RADE_ERR_INVALID_ARG;
+  int64_t total = 0;
+  for (int i = 0; i < V; ++i) {
+    if (views_host[i].pix_offset != total) return RADE_ERR_INVALID_ARG;  // not prepared
+    total += (int64_t)views_host[i].width * views_host[i].height;
+  }
+  return hip_status(rade::launch_tsdf_fuse(views_dev, V, depth, origin, voxel, nx, ny, nz,
+                                           s->near_plane, trunc, tsdf, weight,
+                                           (hipStream_t)stream));
 }
 
 }  // extern "C"
