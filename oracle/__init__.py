@@ -20,6 +20,11 @@ What each function follows (RaDe-GS, arXiv 2406.01467):
 * :func:`render_bwd`, :func:`project_bwd` -- the hand adjoint (pinned by
   central finite differences in the tests).
 * :func:`bin_pairs` -- tile lists: (tile, depth) keys ordered by a stable sort.
+* :func:`normal_consistency` -- Eq. 24 on the median-depth map.
+* :func:`filter3d_var`, :func:`filter3d_apply` -- the 3D smoothing filter
+  RaDe-GS trains with (Sec. 4.1).
+* :func:`tsdf_fuse` (NumPy) and :func:`marching_cubes` (``mc.py``, NumPy
+  plus a per-cell rule) -- mesh extraction from median-depth maps (Sec. 4.1).
 
 Parity status: every function is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (closed forms, invariants, library routines, finite
@@ -478,3 +483,6 @@ def tsdf_fuse(views, depth_med, origin, voxel, dims, trunc, near=0.2, return_fra
         frag |= np.abs(z - near) < 1e-9
     tsdf = np.where(Wt > 0, F / np.where(Wt > 0, Wt, 1.0), 0.0)
     return (tsdf, Wt, frag) if return_fragile else (tsdf, Wt)
+
+
+from .mc import cell_triangles, marching_cubes  # noqa: E402,F401  (Sec. 4.1, Marching Cubes)
