@@ -55,7 +55,7 @@ extern "C" {
 
 #define RADE_OK 0
 #define RADE_ERR_INVALID_ARG (-1)  /* bad pointer, size or setting; nothing enqueued */
-#define RADE_ERR_CAPACITY (-2)     /* more (tile, splat) pairs than `capacity` */
+#define RADE_ERR_CAPACITY (-2)     /* more output than the capacity given (pairs, mesh) */
 #define RADE_ERR_HIP (-3)          /* a HIP runtime call failed */
 #define RADE_ERR_WORKSPACE (-4)    /* workspace smaller than required */
 
@@ -292,6 +292,50 @@ int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
                    const rade_view* views_dev, int32_t V, const float* depth,
                    const double* origin, double voxel, int32_t nx, int32_t ny, int32_t nz,
                    float trunc, float* tsdf, float* weight, void* stream);
+
+/* Marching Cubes over a TSDF grid (the mesh extraction of Sec. 4.1,
+ * Lorensen and Cline): the triangle mesh of the iso level of an nx x ny x nz
+ * grid (tsdf and weight as rade_tsdf_fuse writes them, x fastest, voxel
+ * centres at origin + (i + 1/2) voxel).  Cells are the cubes between 2 x 2 x 2
+ * neighbouring centres; a cell is meshed only when its eight corners all
+ * have weight > 0.  A corner is inside when its value is below iso.
+ *
+ * Triangulation rule (the same for every cell, fixed at compile time):
+ * corner b of a cell is at offset (b & 1, b >> 1 & 1, b >> 2 & 1); local
+ * edge 4 a + o1 + 2 o2 runs along axis a at offsets o1, o2 on the other two
+ * axes (in increasing axis order).  A face with two sign changes holds one
+ * segment between its crossed edges, a face with four holds two, each
+ * cutting off one inside corner (no cracks between cells).  Segments are
+ * directed so that triangle normals point up the field (from inside to
+ * outside), close into cycles taken in the order of their smallest edge,
+ * and each cycle becomes a fan from its smallest edge whose chords to the
+ * cycle's non-adjacent edges share no cube face.
+ *
+ * Output: verts (3 floats per vertex): one vertex per grid edge that
+ * changes sign between two observed voxels and lies in a meshed cell, at the
+ * linear zero of the field along the edge, ordered by the edge's id 3 q + a
+ * (q the index of its lower voxel, a its axis); tris (3 vertex indices per
+ * triangle) cell by cell in increasing cell index ((k (ny - 1) + j)(nx - 1)
+ * + i), then in the rule's order.  Normals (v1 - v0) x (v2 - v0) point to
+ * increasing values.
+ *
+ * At most max_verts / max_tris are written.  The call SYNCHRONISES the
+ * stream to return the counts in *n_verts and *n_tris; when either exceeds
+ * its capacity it returns RADE_ERR_CAPACITY (the outputs are then
+ * incomplete; call again with buffers of the reported size).
+ * Limits: 3 nx ny nz <= 2^32 - 1.  Workspace: rade_marching_cubes_workspace
+ * bytes (about 22 bytes per voxel). */
+size_t rade_marching_cubes_workspace(int32_t nx, int32_t ny, int32_t nz);
+int rade_marching_cubes(const float* tsdf, const float* weight, int32_t nx, int32_t ny,
+                        int32_t nz, const double* origin, double voxel, float iso,
+                        void* workspace, size_t workspace_bytes, float* verts, int64_t max_verts,
+                        uint32_t* tris, int64_t max_tris, int64_t* n_verts, int64_t* n_tris,
+                        void* stream);
+
+/* The compiled triangulation table (host memory, no GPU needed): ntri[256]
+ * triangles per cell code and tri[256 * 15] local edge ids, three per
+ * triangle. */
+int rade_marching_cubes_table(uint8_t* ntri, uint8_t* tri);
 
 /* Kernel timing without a profiler.  After this call, every launch of the
  * kernel `kernel` (one of RADE_KERNEL_*) is bracketed by hipEventRecord of

@@ -135,8 +135,13 @@ def load() -> ctypes.CDLL:
     lib.rade_filter3d_apply_bwd.argtypes = [I64] + [P] * 7 + [P]
     lib.rade_tsdf_fuse.argtypes = [P, P, P, I32, P, P, ctypes.c_double, I32, I32, I32,
                                    ctypes.c_float, P, P, P]
+    lib.rade_marching_cubes_workspace.argtypes = [I32, I32, I32]
+    lib.rade_marching_cubes_workspace.restype = SZ
+    lib.rade_marching_cubes.argtypes = [P, P, I32, I32, I32, P, ctypes.c_double, ctypes.c_float,
+                                        P, SZ, P, I64, P, I64, P, P, P]
+    lib.rade_marching_cubes_table.argtypes = [P, P]
     for f in ("rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
-              "rade_tsdf_fuse"):
+              "rade_tsdf_fuse", "rade_marching_cubes", "rade_marching_cubes_table"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("rade_views_prepare", "rade_project", "rade_bin_sort", "rade_render_fwd",
               "rade_render_bwd"):
@@ -150,7 +155,8 @@ EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "ra
             "rade_abi_version", "rade_set_kernel_events", "rade_tile_order_workspace",
             "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
             "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
-            "rade_tsdf_fuse"]
+            "rade_tsdf_fuse", "rade_marching_cubes_workspace", "rade_marching_cubes",
+            "rade_marching_cubes_table"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -341,3 +347,33 @@ def rade_tsdf_fuse(settings: Settings, views_c, views_dev, depth, origin, voxel:
     return _check(load().rade_tsdf_fuse(ctypes.byref(s), views_c, _p(views_dev), len(views_c),
                                         _p(depth), o, float(voxel), nx, ny, nz, float(trunc),
                                         _p(tsdf), _p(weight), _stream(stream)), "rade_tsdf_fuse")
+
+
+def rade_marching_cubes_workspace(dims) -> int:
+    nx, ny, nz = (int(d) for d in dims)
+    return int(load().rade_marching_cubes_workspace(nx, ny, nz))
+
+
+def rade_marching_cubes(tsdf, weight, dims, origin, voxel: float, iso: float, workspace, verts,
+                        max_verts: int, tris, max_tris: int, stream=None):
+    """Returns (code, n_verts, n_tris); code is RADE_OK or RADE_ERR_CAPACITY
+    (other errors raise).  Synchronises the stream."""
+    nx, ny, nz = (int(d) for d in dims)
+    o = (ctypes.c_double * 3)(*[float(x) for x in origin])
+    nv, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    code = load().rade_marching_cubes(_p(tsdf), _p(weight), nx, ny, nz, o, float(voxel),
+                                      float(iso), _p(workspace), ws_bytes, _p(verts),
+                                      int(max_verts), _p(tris), int(max_tris), ctypes.byref(nv),
+                                      ctypes.byref(nt), _stream(stream))
+    if code not in (RADE_OK, RADE_ERR_CAPACITY):
+        _check(code, "rade_marching_cubes")
+    return code, nv.value, nt.value
+
+
+def rade_marching_cubes_table():
+    """(ntri uint8[256], tri uint8[256, 15]) compiled into the library."""
+    ntri = np.zeros(256, np.uint8)
+    tri = np.zeros((256, 15), np.uint8)
+    _check(load().rade_marching_cubes_table(_p(ntri), _p(tri)), "rade_marching_cubes_table")
+    return ntri, tri

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librade.so")
 SOURCES = ["abi.hip", "project.hip", "binsort.hip", "render.hip", "losses.hip", "filter3d.hip",
-           "tsdf.hip"]
+           "tsdf.hip", "mc.hip"]
 ARCH = os.environ.get("RADE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -60,9 +60,22 @@ hipError_t launch_tsdf_fuse(const rade_view* views, int V, const float* depth,
                             const double* origin, double voxel, int64_t nx, int64_t ny,
                             int64_t nz, double near_plane, float trunc, float* tsdf,
                             float* weight, hipStream_t st);
+size_t marching_cubes_workspace(int64_t nx, int64_t ny, int64_t nz);
+void marching_cubes_table(uint8_t* ntri, uint8_t* tri);
+hipError_t launch_marching_cubes(const float* tsdf, const float* weight, int64_t nx, int64_t ny,
+                                 int64_t nz, const double* origin, double voxel, float iso,
+                                 void* ws, float* verts, int64_t max_verts, uint32_t* tris,
+                                 int64_t max_tris, const uint32_t** nv_dev,
+                                 const uint64_t** nt_dev, hipStream_t st);
 }  // namespace rade
 
 namespace {
+
+bool grid_ok(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return false;
+  // vertex ids are 32-bit: every grid edge must have one
+  return 3 * (int64_t)nx * ny * nz <= (int64_t)UINT32_MAX;
+}
 
 bool settings_ok(const rade_settings* s) {
   if (!s) return false;
@@ -126,7 +139,7 @@ const char* rade_strerror(int code) {
   switch (code) {
     case RADE_OK: return "ok";
     case RADE_ERR_INVALID_ARG: return "invalid argument (nothing enqueued)";
-    case RADE_ERR_CAPACITY: return "pair capacity exceeded (n_pairs holds the required count)";
+    case RADE_ERR_CAPACITY: return "output capacity exceeded (the count arguments hold the required sizes)";
     case RADE_ERR_HIP: return "HIP runtime error";
     case RADE_ERR_WORKSPACE: return "workspace too small";
     default: return "unknown error";
@@ -361,6 +374,48 @@ int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
   return hip_status(rade::launch_tsdf_fuse(views_dev, V, depth, origin, voxel, nx, ny, nz,
                                            s->near_plane, trunc, tsdf, weight,
                                            (hipStream_t)stream));
+}
+
+size_t rade_marching_cubes_workspace(int32_t nx, int32_t ny, int32_t nz) {
+  if (!grid_ok(nx, ny, nz)) return 0;
+  return rade::marching_cubes_workspace(nx, ny, nz);
+}
+
+int rade_marching_cubes(const float* tsdf, const float* weight, int32_t nx, int32_t ny,
+                        int32_t nz, const double* origin, double voxel, float iso,
+                        void* workspace, size_t workspace_bytes, float* verts, int64_t max_verts,
+                        uint32_t* tris, int64_t max_tris, int64_t* n_verts, int64_t* n_tris,
+                        void* stream) {
+  if (!grid_ok(nx, ny, nz) || !tsdf || !weight || !origin || !n_verts || !n_tris)
+    return RADE_ERR_INVALID_ARG;
+  if (!(voxel > 0.0) || !std::isfinite(voxel) || !std::isfinite(iso)) return RADE_ERR_INVALID_ARG;
+  if (!std::isfinite(origin[0]) || !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
+    return RADE_ERR_INVALID_ARG;
+  if (max_verts < 0 || max_tris < 0 || (max_verts > 0 && !verts) || (max_tris > 0 && !tris))
+    return RADE_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < rade::marching_cubes_workspace(nx, ny, nz))
+    return RADE_ERR_WORKSPACE;
+  const hipStream_t st = (hipStream_t)stream;
+  const uint32_t* nv_dev = nullptr;
+  const uint64_t* nt_dev = nullptr;
+  hipError_t e = rade::launch_marching_cubes(tsdf, weight, nx, ny, nz, origin, voxel, iso,
+                                             workspace, verts, max_verts, tris, max_tris, &nv_dev,
+                                             &nt_dev, st);
+  uint32_t nv = 0;
+  uint64_t nt = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&nv, nv_dev, sizeof(nv), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nt, nt_dev, sizeof(nt), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return RADE_ERR_HIP;
+  *n_verts = (int64_t)nv;
+  *n_tris = (int64_t)nt;
+  return ((int64_t)nv > max_verts || (int64_t)nt > max_tris) ? RADE_ERR_CAPACITY : RADE_OK;
+}
+
+int rade_marching_cubes_table(uint8_t* ntri, uint8_t* tri) {
+  if (!ntri || !tri) return RADE_ERR_INVALID_ARG;
+  rade::marching_cubes_table(ntri, tri);
+  return RADE_OK;
 }
 
 }  // extern "C"

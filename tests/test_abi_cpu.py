@@ -30,7 +30,7 @@ def _declared():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = _declared()
-    assert len(names) == 18, names
+    assert len(names) == 21, names
     so = ctypes.CDLL(lib.LIB_PATH)
     for n in names:
         assert hasattr(so, n), n
@@ -114,7 +114,7 @@ def test_null_pointers_rejected():
     code = so.rade_bin_sort(ctypes.byref(s2), vc, dummy, 1, 10, dummy, dummy, dummy, dummy, None,
                             100, dummy, None, dummy, 1 << 30, None)
     assert code == lib.RADE_ERR_INVALID_ARG
-    assert lib.strerror(lib.RADE_ERR_CAPACITY).startswith("pair capacity")
+    assert lib.strerror(lib.RADE_ERR_CAPACITY).startswith("output capacity")
 
 
 def test_workspace_sizes_monotone():
@@ -126,3 +126,44 @@ def test_workspace_sizes_monotone():
     s = lib.Settings()
     assert lib.rade_render_bwd_workspace(s, 1, 1000, False) >= 1000 * 64
     assert lib.rade_render_bwd_workspace(s, 1, 1000, True) >= 1000 * (64 + 80)
+
+
+def test_marching_cubes_table_matches_the_oracle_rule():
+    """The table compiled into the library (generated at compile time from
+    the face rule) equals the oracle's per-code triangulation, triangle for
+    triangle, for all 256 cell codes."""
+    import oracle
+    lib = _lib()
+    ntri, tri = lib.rade_marching_cubes_table()
+    for code in range(256):
+        want = oracle.cell_triangles(code)
+        assert ntri[code] == len(want), code
+        got = [tuple(int(x) for x in tri[code, 3 * t: 3 * t + 3]) for t in range(ntri[code])]
+        assert got == [tuple(t) for t in want], code
+
+
+def test_marching_cubes_rejects_bad_arguments_on_the_host():
+    lib = _lib()
+    so = lib.load()
+    f = np.zeros(8, np.float32)
+    ws = np.zeros(1 << 16, np.uint8)
+    out_v = np.zeros(30, np.float32)
+    out_t = np.zeros(30, np.uint32)
+    nv, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+    o = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+
+    def call(dims=(2, 2, 2), voxel=0.1, iso=0.0, ws_bytes=ws.nbytes, origin=o, max_v=10):
+        return so.rade_marching_cubes(f.ctypes.data, f.ctypes.data, *dims, origin, voxel, iso,
+                                      ws.ctypes.data, ws_bytes, out_v.ctypes.data, max_v,
+                                      out_t.ctypes.data, 10, ctypes.byref(nv), ctypes.byref(nt),
+                                      None)
+    assert call(dims=(0, 2, 2)) == lib.RADE_ERR_INVALID_ARG
+    assert call(dims=(2048, 2048, 1024)) == lib.RADE_ERR_INVALID_ARG   # 32-bit vertex ids
+    assert call(voxel=0.0) == lib.RADE_ERR_INVALID_ARG
+    assert call(voxel=float("inf")) == lib.RADE_ERR_INVALID_ARG
+    assert call(iso=float("nan")) == lib.RADE_ERR_INVALID_ARG
+    assert call(origin=(ctypes.c_double * 3)(0.0, float("nan"), 0.0)) == lib.RADE_ERR_INVALID_ARG
+    assert call(max_v=-1) == lib.RADE_ERR_INVALID_ARG
+    assert call(ws_bytes=16) == lib.RADE_ERR_WORKSPACE
+    assert lib.rade_marching_cubes_workspace((2, 2, 2)) <= ws.nbytes
+    assert lib.rade_marching_cubes_workspace((0, 1, 1)) == 0
