@@ -50,11 +50,13 @@ _lib = None
 S_DILATION, S_NEAR, S_ALPHA_MIN, S_ALPHA_MAX, S_T_MIN, S_POWER_CUT = 0, 1, 2, 3, 4, 5
 S_FOV_CLAMP, S_DEGEN, S_BG, S_SH_DEGREE, S_TILE_W, S_TILE_H = 6, 7, 8, 11, 12, 13
 S_FRAG_POWER, S_FRAG_ALPHA, S_FRAG_T, S_FRAG_MED, S_FRAG_CLAMP = 14, 15, 16, 17, 18
-S_COUNT = 19
+S_DEPTH_EXACT = 19
+S_COUNT = 20
 
 # Record fields (doubles per (view, Gaussian)).
 R_FIELDS = ["uc", "vc", "z", "tc", "a", "b", "c", "o", "r", "g", "bl", "p0", "p1",
-            "q0", "q1", "n0", "n1", "n2", "tau", "B00", "B01", "B11", "X", "Y"]
+            "q0", "q1", "n0", "n1", "n2", "tau", "B00", "B01", "B11", "X", "Y",
+            "ai00", "ai01", "ai02", "ai11", "ai12", "ai22"]
 R = {k: i for i, k in enumerate(R_FIELDS)}
 # Gradient fields of the projected quantities.
 G_FIELDS = ["uc", "vc", "a", "b", "c", "o", "r", "g", "bl", "z", "p0", "p1", "n0", "n1", "n2"]
@@ -112,7 +114,7 @@ def _ptr(a):
 def settings(sh_degree=0, dilation=0.3, near=0.2, alpha_min=1.0 / 255.0, alpha_max=0.99,
              t_min=1e-4, power_cut=4.5, fov_clamp=1.3, degenerate=1e-6, bg=(0.0, 0.0, 0.0),
              tile=(16, 16), frag_power=2e-5, frag_alpha=1e-5, frag_t=1e-4, frag_med=1e-5,
-             frag_clamp=1e-5) -> np.ndarray:
+             frag_clamp=1e-5, depth_exact=False) -> np.ndarray:
     """Settings vector.  Defaults are the readings listed in the design notes:
     3DGS defaults for the quantities the paper leaves open."""
     s = np.zeros(S_COUNT, dtype=np.float64)
@@ -123,6 +125,7 @@ def settings(sh_degree=0, dilation=0.3, near=0.2, alpha_min=1.0 / 255.0, alpha_m
     s[S_TILE_W], s[S_TILE_H] = tile
     s[S_FRAG_POWER], s[S_FRAG_ALPHA], s[S_FRAG_T] = frag_power, frag_alpha, frag_t
     s[S_FRAG_MED], s[S_FRAG_CLAMP] = frag_med, frag_clamp
+    s[S_DEPTH_EXACT] = 1.0 if depth_exact else 0.0
     return s
 
 
@@ -197,6 +200,8 @@ def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np
     gP_abs, when given, accumulates over pixels a bound of the magnitudes of
     the quantities each per-pixel term is computed from (the same recursion
     run on absolute values): the round-off scale of those sums."""
+    if s[S_DEPTH_EXACT]:
+        raise NotImplementedError("the exact ray depth of Eq. 7 is a forward-only variant")
     lib = _load()
     N = rec.shape[0]
     vv = view_vector(view)

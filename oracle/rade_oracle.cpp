@@ -59,7 +59,8 @@ enum {
   S_FRAG_T = 16,       // relative margin around t_min
   S_FRAG_MED = 17,     // relative margin around T = 1/2
   S_FRAG_CLAMP = 18,   // relative margin around alpha_max (gradient fragility)
-  S_COUNT = 19
+  S_DEPTH_EXACT = 19,  // 1: per-pixel depth of the exact ray maximum (Eq. 7), else Eq. 4
+  S_COUNT = 20
 };
 
 // View vector layout (doubles): W, H, fx, fy, cx, cy, R[9] (row-major,
@@ -70,7 +71,8 @@ enum { V_W = 0, V_H = 1, V_FX = 2, V_FY = 3, V_CX = 4, V_CY = 5, V_R = 6, V_T = 
 enum {
   R_UC = 0, R_VC, R_Z, R_TC, R_A, R_B, R_C, R_O, R_R, R_G, R_BL, R_P0, R_P1,
   R_Q0, R_Q1, R_N0, R_N1, R_N2, R_TAU, R_B00, R_B01, R_B11, R_X, R_Y,
-  R_COUNT = 24
+  R_AI00, R_AI01, R_AI02, R_AI11, R_AI12, R_AI22,  // camera-space Sigma^-1 (Eq. 7)
+  R_COUNT = 30
 };
 
 // Per-(view, Gaussian) gradient layout of the projected quantities.
@@ -246,6 +248,7 @@ struct Proj {
   double tc;
   double qn[4], qnorm;
   M3 Rg, Sig, Sc, J, Sp;
+  M3 Sci;                // Sc^-1, for the exact ray maximum of Eq. 7
   double B0[3];          // undilated 2x2 footprint (00, 01, 11)
   double B[3];           // dilated
   double conic[3];       // B^-1 as (a, b, c)
@@ -293,6 +296,7 @@ void project_one(const View& v, const double* s, int K, const float* mean, const
     for (int k = 0; k < 3; ++k) Msc(i, k) = P.Rg(i, k) * (double)scale[k];
   P.Sig = mul(Msc, transpose(Msc));
   P.Sc = mul(mul(v.R, P.Sig), transpose(v.R));  // camera frame: W Sigma W^T
+  P.Sci = inverse3(P.Sc);
 
   // Local affine map to ray space (u, v in pixels, t = |x|).
   P.tc = std::sqrt(X * X + Y * Y + Z * Z);
@@ -388,6 +392,8 @@ void store_record(const Proj& P, double* r, int* rect, int* flags) {
   r[R_N0] = P.n[0]; r[R_N1] = P.n[1]; r[R_N2] = P.n[2]; r[R_TAU] = P.tau;
   r[R_B00] = P.B[0]; r[R_B01] = P.B[1]; r[R_B11] = P.B[2];
   r[R_X] = P.x[0]; r[R_Y] = P.x[1];
+  r[R_AI00] = P.Sci(0, 0); r[R_AI01] = P.Sci(0, 1); r[R_AI02] = P.Sci(0, 2);
+  r[R_AI11] = P.Sci(1, 1); r[R_AI12] = P.Sci(1, 2); r[R_AI22] = P.Sci(2, 2);
   for (int i = 0; i < 4; ++i) rect[i] = P.rect[i];
 }
 
@@ -423,9 +429,34 @@ inline uint64_t mix64(uint64_t h, uint64_t v) {
   return h;
 }
 
-// Front-to-back compositing of one pixel over every Gaussian (Eq. 3, Eq. 4).
-void render_pixel(const double* s, const double* rec, const std::vector<int64_t>& order,
-                  int px, int py, bool keep_list, PixelResult& R) {
+// Depth of the point where the ray through the pixel centre meets Gaussian r
+// (Sec. 3.2.1, Eq. 5-7): the camera centre is the origin, the ray direction
+// the unit vector through the pixel, the intersection the maximum of the
+// Gaussian along the ray, t* = v^T Sigma^-1 x_c / (v^T Sigma^-1 v), and the
+// depth its camera z, t* v_z.
+double exact_ray_depth(const View& v, const double* r, double pcx, double pcy) {
+  double dir[3] = {(pcx - v.cx) / v.fx, (pcy - v.cy) / v.fy, 1.0};
+  const double len = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  for (double& d : dir) d /= len;
+  const double xc[3] = {r[R_X], r[R_Y], r[R_Z]};
+  M3 A;
+  A(0, 0) = r[R_AI00]; A(0, 1) = A(1, 0) = r[R_AI01]; A(0, 2) = A(2, 0) = r[R_AI02];
+  A(1, 1) = r[R_AI11]; A(1, 2) = A(2, 1) = r[R_AI12]; A(2, 2) = r[R_AI22];
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      num += dir[i] * A(i, j) * xc[j];
+      den += dir[i] * A(i, j) * dir[j];
+    }
+  return num / den * dir[2];
+}
+
+// Front-to-back compositing of one pixel over every Gaussian (Eq. 3, Eq. 4;
+// with S_DEPTH_EXACT the per-pixel depth of Eq. 7 instead of Eq. 4).
+void render_pixel(const double* s, const View& view, const double* rec,
+                  const std::vector<int64_t>& order, int px, int py, bool keep_list,
+                  PixelResult& R) {
+  const bool exact = s[S_DEPTH_EXACT] != 0.0;
   const double cut = s[S_POWER_CUT], amin = s[S_ALPHA_MIN], amax = s[S_ALPHA_MAX];
   const double tmin = s[S_T_MIN];
   double T = 1.0;
@@ -452,7 +483,8 @@ void render_pixel(const double* s, const double* rec, const std::vector<int64_t>
     if (std::fabs(Tn - tmin) < s[S_FRAG_T] * tmin) R.fragile |= 1;
     if (Tn < tmin) { stop_g = g; break; }
     const double w = alpha * T;
-    const double d = r[R_Z] + r[R_P0] * dx + r[R_P1] * dy;  // Eq. 4, dx = u_c - u
+    const double d = exact ? exact_ray_depth(view, r, pcx, pcy)
+                           : r[R_Z] + r[R_P0] * dx + r[R_P1] * dy;  // Eq. 4, dx = u_c - u
     R.out[O_R] += w * r[R_R]; R.out[O_G] += w * r[R_G]; R.out[O_B] += w * r[R_BL];
     R.out[O_DEXP] += w * d;
     R.out[O_N0] += w * r[R_N0]; R.out[O_N1] += w * r[R_N1]; R.out[O_N2] += w * r[R_N2];
@@ -677,7 +709,7 @@ int oracle_render(const double* settings, const double* view, int64_t N, const d
     const int64_t idx = pix ? pix[i] : i;
     const int px = (int)(idx % v.W), py = (int)(idx / v.W);
     PixelResult R;
-    render_pixel(settings, rec, order, px, py, false, R);
+    render_pixel(settings, v, rec, order, px, py, false, R);
     for (int k = 0; k < O_COUNT; ++k) out[i * O_COUNT + k] = R.out[k];
     iout[i * 4 + 0] = R.count; iout[i * 4 + 1] = R.last; iout[i * 4 + 2] = R.median;
     iout[i * 4 + 3] = R.fragile;
@@ -705,7 +737,7 @@ int oracle_render_bwd(const double* settings, const double* view, int64_t N, con
     const int64_t idx = pix ? pix[i] : i;
     const int px = (int)(idx % v.W), py = (int)(idx / v.W);
     PixelResult R;
-    render_pixel(settings, rec, order, px, py, true, R);
+    render_pixel(settings, v, rec, order, px, py, true, R);
     const double* g = gout + i * GOUT;
     const double gC[3] = {g[0], g[1], g[2]}, gD = g[3], gM = g[4];
     const double gN[3] = {g[5], g[6], g[7]}, gA = g[8], gL = g[9];
