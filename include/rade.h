@@ -80,7 +80,18 @@ typedef struct rade_settings {
   double fov_clamp;        /* x/z, y/z in the Jacobian clamped to fov_clamp * W/(2 fx) (1.3) */
   double degenerate;       /* q := 0 when det(B0) <= degenerate * tr(B0)^2 (1e-6) */
   double bg[3];            /* background colour, blended with the final transmittance */
+  int32_t depth_mode;      /* RADE_DEPTH_*: per-pixel depth of Eq. 4 or of Eq. 7 */
+  int32_t reserved;        /* must be 0 */
 } rade_settings;
+
+/* Per-pixel depth of a splat.  AFFINE: the plane d = z + p . (u_c - u,
+ * v_c - v) of Sec. 3.2.2 (Eq. 4), the method's depth, forward and backward.
+ * EXACT: the camera z of the maximum of the Gaussian along the ray through
+ * the pixel centre (Sec. 3.2.1, Eq. 5-7), an accuracy reference for the
+ * plane; forward only (rade_render_bwd rejects it).  It needs the
+ * depth_quad records of rade_project. */
+#define RADE_DEPTH_AFFINE 0
+#define RADE_DEPTH_EXACT 1
 
 /* One camera.  The caller fills the first five rows; rade_views_prepare
  * fills the offsets. */
@@ -129,10 +140,19 @@ int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
  * A Gaussian is culled when a parameter is not finite, its camera z <=
  * near_plane, its quaternion is zero or 255 * opacity <= 1.  The geometry is
  * evaluated in FP64 and rounded to the FP32 fields once. */
+/* depth_quad (V*N records of 8 floats, 16-byte aligned): required when
+ * depth_mode is RADE_DEPTH_EXACT, ignored (may be NULL) otherwise.  With A
+ * the camera-space inverse covariance, r_c = (x/z, y/z, 1) the centre's ray
+ * and D0 = r_c^T A r_c, the record holds g = (A r_c)_{0,1} / D0 scaled by
+ * (1/fx, 1/fy) and H = A_{00,01,11} / D0 scaled by (1/fx^2, 2/(fx fy),
+ * 1/fy^2), then three zeros; at pixel offset (dx, dy) = (u_c - u, v_c - v)
+ * the ray maximum has depth z (1 - g.d) / (1 - 2 g.d + H0 dx^2 + H1 dx dy +
+ * H2 dy^2) (Eq. 7 rewritten around the centre).  A scale below 1e-15 counts
+ * as 1e-15 there. */
 int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
                  const float* means, const float* scales, const float* quats,
                  const float* opacities, const float* sh, rade_splat* splats,
-                 int32_t* tiles_touched, void* stream);
+                 int32_t* tiles_touched, float* depth_quad, void* stream);
 
 /* Workspace bytes for rade_bin_sort with V views, N Gaussians, `capacity`
  * pairs and `total_tiles` tiles. */
@@ -189,13 +209,18 @@ int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t
  *   splat, -1 if none); count (int32, optional, may be NULL): splats blended.
  * distortion (1 plane, optional, may be NULL): the depth distortion of
  * Sec. 3.4 Eq. 23 per pixel, sum_{i,j} w_i w_j (d_i - d_j)^2 over the blended
- * splats (d_i the depth of Eq. 4 at the pixel). */
+ * splats (d_i the depth of Eq. 4 at the pixel, or of Eq. 7 in exact mode).
+ * depth_quad: rade_project's exact-depth records, required when depth_mode
+ * is RADE_DEPTH_EXACT (both depth planes then hold the exact ray-maximum
+ * depth; weights, colour, normals and alpha are those of the affine mode),
+ * ignored otherwise. */
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
-                    int32_t* median, int32_t* count, float* distortion, void* stream);
+                    int32_t* median, int32_t* count, float* distortion,
+                    const float* depth_quad, void* stream);
 
 /* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
  * recompute the splats (splats == NULL in rade_render_bwd). */
@@ -352,7 +377,7 @@ int rade_set_kernel_events(int kernel, void* start_event, void* stop_event);
 /* Static description of an error code (never NULL). */
 const char* rade_strerror(int code);
 
-/* ABI version of this header: 2. */
+/* ABI version of this header: 3. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

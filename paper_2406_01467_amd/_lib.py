@@ -49,7 +49,8 @@ class CSettings(ctypes.Structure):
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("t_min", ctypes.c_double), ("power_cut", ctypes.c_double),
                 ("fov_clamp", ctypes.c_double), ("degenerate", ctypes.c_double),
-                ("bg", ctypes.c_double * 3)]
+                ("bg", ctypes.c_double * 3), ("depth_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CView(ctypes.Structure):
@@ -60,7 +61,9 @@ class CView(ctypes.Structure):
                 ("pix_offset", ctypes.c_int64), ("tile_offset", ctypes.c_int64)]
 
 
-assert ctypes.sizeof(CView) == 96 and ctypes.sizeof(CSettings) == 104
+assert ctypes.sizeof(CView) == 96 and ctypes.sizeof(CSettings) == 112
+
+RADE_DEPTH_AFFINE, RADE_DEPTH_EXACT = 0, 1
 
 
 @dataclasses.dataclass
@@ -79,6 +82,7 @@ class Settings:
     fov_clamp: float = 1.3
     degenerate: float = 1e-6
     bg: tuple = (0.0, 0.0, 0.0)
+    depth_mode: int = 0        # RADE_DEPTH_AFFINE (Eq. 4) or RADE_DEPTH_EXACT (Eq. 7, forward only)
 
     def c(self) -> CSettings:
         s = CSettings()
@@ -89,11 +93,12 @@ class Settings:
         s.power_cut, s.fov_clamp, s.degenerate = self.power_cut, self.fov_clamp, self.degenerate
         for i in range(3):
             s.bg[i] = float(self.bg[i])
+        s.depth_mode, s.reserved = self.depth_mode, 0
         return s
 
 
 _lib = None
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 def load() -> ctypes.CDLL:
@@ -106,11 +111,11 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     lib.rade_views_prepare.argtypes = [P, P, I32, P, P]
-    lib.rade_project.argtypes = [P, P, I32, I64] + [P] * 7 + [P]
+    lib.rade_project.argtypes = [P, P, I32, I64] + [P] * 8 + [P]
     lib.rade_bin_sort_workspace.argtypes = [I32, I64, I64, I64]
     lib.rade_bin_sort_workspace.restype = SZ
     lib.rade_bin_sort.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I64, P, P, P, SZ, P]
-    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 13 + [P]
+    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 14 + [P]
     lib.rade_tile_order_workspace.argtypes = [I64]
     lib.rade_tile_order_workspace.restype = SZ
     lib.rade_tile_order.argtypes = [P, P, I32, P, P, P, SZ, P]
@@ -231,11 +236,12 @@ def views_to_device(views_c: ctypes.Array, device):
 
 
 def rade_project(settings: Settings, views_dev, V: int, N: int, means, scales, quats, opacities,
-                 sh, splats, tiles_touched, stream=None):
+                 sh, splats, tiles_touched, stream=None, depth_quad=None):
     s = settings.c()
     return _check(load().rade_project(ctypes.byref(s), _p(views_dev), V, N, _p(means), _p(scales),
                                       _p(quats), _p(opacities), _p(sh), _p(splats),
-                                      _p(tiles_touched), _stream(stream)), "rade_project")
+                                      _p(tiles_touched), _p(depth_quad), _stream(stream)),
+                  "rade_project")
 
 
 def rade_bin_sort_workspace(V: int, N: int, capacity: int, total_tiles: int) -> int:
@@ -273,13 +279,14 @@ def rade_tile_order(settings: Settings, views_c, tile_ranges, tile_order, worksp
 
 def rade_render_fwd(settings: Settings, views_c, views_dev, V: int, N: int, splats, pair_ids,
                     tile_ranges, color, depth, normal, alpha, t_final, last, median, count=None,
-                    stream=None, tile_order=None, distortion=None):
+                    stream=None, tile_order=None, distortion=None, depth_quad=None):
     s = settings.c()
     return _check(load().rade_render_fwd(ctypes.byref(s), views_c, _p(views_dev), V, N,
                                          _p(splats), _p(pair_ids), _p(tile_ranges),
                                          _p(tile_order), _p(color),
                                          _p(depth), _p(normal), _p(alpha), _p(t_final), _p(last),
-                                         _p(median), _p(count), _p(distortion), _stream(stream)),
+                                         _p(median), _p(count), _p(distortion), _p(depth_quad),
+                                         _stream(stream)),
                   "rade_render_fwd")
 
 

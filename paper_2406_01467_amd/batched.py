@@ -43,6 +43,9 @@ class BatchedPlan:
     def __init__(self, views: Sequence, settings: Settings, params: Sequence[torch.Tensor],
                  grad_fn: Callable, capacity: Optional[int] = None, recompute: bool = False,
                  distortion: bool = False):
+        if settings.depth_mode != _lib.RADE_DEPTH_AFFINE:
+            raise ValueError("a training step needs the affine depth of Eq. 4 (the exact "
+                             "ray-maximum depth is a forward-only variant)")
         self.settings = settings
         self.params = [p.detach() for p in params]
         self.device = self.params[0].device

@@ -10,7 +10,7 @@ namespace rade {
 hipError_t launch_project(const rade_settings& st, const rade_view* views, int V, int64_t N,
                           const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, rade_splat* splats,
-                          int32_t* tiles_touched, hipStream_t stream);
+                          int32_t* tiles_touched, float* depth_quad, hipStream_t stream);
 hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, int V, int64_t N,
                               const float* means, const float* scales, const float* quats,
                               const float* opac, const float* sh, const float* gsplat,
@@ -29,7 +29,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
                              int32_t* last, int32_t* med, int32_t* cnt, float* distortion,
-                             hipStream_t st);
+                             const float* depth_quad, hipStream_t st);
 hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, const float* tf,
@@ -88,6 +88,8 @@ bool settings_ok(const rade_settings* s) {
   if (!(s->dilation >= 0.0) || !std::isfinite(s->near_plane) || !(s->fov_clamp > 0.0))
     return false;
   if (!(s->degenerate >= 0.0)) return false;
+  if (s->depth_mode != RADE_DEPTH_AFFINE && s->depth_mode != RADE_DEPTH_EXACT) return false;
+  if (s->reserved != 0) return false;
   return true;
 }
 
@@ -124,7 +126,7 @@ KernelEvents& kernel_events(int kernel) {
 
 extern "C" {
 
-int rade_abi_version(void) { return 2; }
+int rade_abi_version(void) { return 3; }
 
 int rade_set_kernel_events(int kernel, void* start_event, void* stop_event) {
   if (kernel < RADE_KERNEL_PROJECT || kernel > RADE_KERNEL_PROJECT_BWD) return RADE_ERR_INVALID_ARG;
@@ -167,13 +169,17 @@ int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
 int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
                  const float* means, const float* scales, const float* quats,
                  const float* opacities, const float* sh, rade_splat* splats,
-                 int32_t* tiles_touched, void* stream) {
+                 int32_t* tiles_touched, float* depth_quad, void* stream) {
   if (!settings_ok(s) || !views_dev || !counts_ok(V, N)) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !splats || !tiles_touched))
     return RADE_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(quats) & 15) != 0) return RADE_ERR_INVALID_ARG;
+  const bool exact = s->depth_mode == RADE_DEPTH_EXACT;
+  if (exact && N > 0 && (!depth_quad || (reinterpret_cast<uintptr_t>(depth_quad) & 15) != 0))
+    return RADE_ERR_INVALID_ARG;
   return hip_status(rade::launch_project(*s, views_dev, V, N, means, scales, quats, opacities,
-                                         sh, splats, tiles_touched, (hipStream_t)stream));
+                                         sh, splats, tiles_touched, exact ? depth_quad : nullptr,
+                                         (hipStream_t)stream));
 }
 
 size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t total_tiles) {
@@ -252,10 +258,14 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
-                    int32_t* median, int32_t* count, float* distortion, void* stream) {
+                    int32_t* median, int32_t* count, float* distortion,
+                    const float* depth_quad, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !color || !depth || !normal || !alpha || !t_final || !last || !median)
+    return RADE_ERR_INVALID_ARG;
+  const bool exact = s->depth_mode == RADE_DEPTH_EXACT;
+  if (exact && N > 0 && (!depth_quad || (reinterpret_cast<uintptr_t>(depth_quad) & 15) != 0))
     return RADE_ERR_INVALID_ARG;
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && !splats) return RADE_ERR_INVALID_ARG;
@@ -263,7 +273,7 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
   return hip_status(rade::launch_render_fwd(*s, views_dev, V, N, tiles, splats, pair_ids,
                                             tile_ranges, tile_order, color, depth, normal, alpha,
                                             t_final, last, median, count, distortion,
-                                            (hipStream_t)stream));
+                                            exact ? depth_quad : nullptr, (hipStream_t)stream));
 }
 
 size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute) {
@@ -290,6 +300,7 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !t_final || !last || !median) return RADE_ERR_INVALID_ARG;
+  if (s->depth_mode != RADE_DEPTH_AFFINE) return RADE_ERR_INVALID_ARG;  // forward-only variant
   if (d_distortion && (!depth || !alpha)) return RADE_ERR_INVALID_ARG;
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !d_means || !d_scales ||
@@ -311,7 +322,7 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
     int32_t* tt = reinterpret_cast<int32_t*>(
         w + g_bytes + (((VN * sizeof(rade_splat)) + 255) & ~size_t(255)));
     const hipError_t e = rade::launch_project(*s, views_dev, V, N, means, scales, quats,
-                                              opacities, sh, rs, tt, st);
+                                              opacities, sh, rs, tt, nullptr, st);
     if (e != hipSuccess) return RADE_ERR_HIP;
     splats = rs;
   }

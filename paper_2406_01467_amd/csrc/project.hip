@@ -326,13 +326,47 @@ __device__ __forceinline__ void store_invisible(rade_splat* out) {
   *out = s;
 }
 
-template <int KMAX, bool VEC>
+// Exact-depth record of one (view, Gaussian) (Sec. 3.2.1, Eq. 5-7).  The
+// camera-space inverse covariance is A = sum_k c_k c_k^T with c_k the k-th
+// axis of the Gaussian in camera space divided by its scale (no matrix
+// inverse, so flat Gaussians stay well conditioned).  With r_c = (x/z, y/z,
+// 1) and D0 = r_c^T A r_c, the ray r = r_c - (dx/fx, dy/fy, 0) through the
+// pixel at offset (dx, dy) = (u_c - u, v_c - v) meets the Gaussian's maximum
+// at camera z = z (1 - g.d) / (1 - 2 g.d + d^T H d) with g = (A r_c)_{0,1}/D0
+// and H = A_{0:2,0:2}/D0, d = (dx/fx, dy/fy); the record stores g and H
+// with the focal lengths folded in.
+__device__ __forceinline__ void exact_depth_record(const ViewD& v, const Params& P, const Geo& G,
+                                                   float4* rec) {
+  const double r0 = G.X / G.Z, r1 = G.Y / G.Z;
+  double D0 = 0.0, g0 = 0.0, g1 = 0.0, h00 = 0.0, h01 = 0.0, h11 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    // camera-space axis k: (R_world R_g)[:, k]
+    double c[3];
+    for (int i = 0; i < 3; ++i)
+      c[i] = v.R[3 * i + 0] * P.Rg[0 + k] + v.R[3 * i + 1] * P.Rg[3 + k] +
+             v.R[3 * i + 2] * P.Rg[6 + k];
+    const double is = 1.0 / fmax(fabs(P.s[k]), 1e-15);
+    c[0] *= is; c[1] *= is; c[2] *= is;
+    const double a = c[0] * r0 + c[1] * r1 + c[2];
+    D0 += a * a;
+    g0 += a * c[0]; g1 += a * c[1];
+    h00 += c[0] * c[0]; h01 += c[0] * c[1]; h11 += c[1] * c[1];
+  }
+  const double i0 = 1.0 / D0;
+  const double ifx = 1.0 / v.fx, ify = 1.0 / v.fy;
+  rec[0] = make_float4((float)(g0 * i0 * ifx), (float)(g1 * i0 * ify),
+                       (float)(h00 * i0 * ifx * ifx), (float)(2.0 * h01 * i0 * ifx * ify));
+  rec[1] = make_float4((float)(h11 * i0 * ify * ify), 0.0f, 0.0f, 0.0f);
+}
+
+template <int KMAX, bool VEC, bool EXACT>
 __global__ void __launch_bounds__(256)
 k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
           const float* __restrict__ means, const float* __restrict__ scales,
           const float* __restrict__ quats, const float* __restrict__ opac,
           const float* __restrict__ sh, rade_splat* __restrict__ splats,
-          int32_t* __restrict__ tiles_touched) {
+          int32_t* __restrict__ tiles_touched, float4* __restrict__ depth_quad) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   const int deg = st.sh_degree;
@@ -355,8 +389,13 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
     if (!vis) {
       store_invisible(splats + o);
       tiles_touched[o] = 0;
+      if constexpr (EXACT) {
+        depth_quad[2 * o] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        depth_quad[2 * o + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
       continue;
     }
+    if constexpr (EXACT) exact_depth_record(v, P, G, depth_quad + 2 * o);
     rade_splat out;
     out.uc = v.fx * G.X / G.Z + v.cx;
     out.vc = v.fy * G.Y / G.Z + v.cy;
@@ -664,15 +703,20 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
 hipError_t launch_project(const rade_settings& st, const rade_view* views, int V, int64_t N,
                           const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, rade_splat* splats,
-                          int32_t* tiles_touched, hipStream_t stream) {
+                          int32_t* tiles_touched, float* depth_quad, hipStream_t stream) {
   if (N == 0) return hipSuccess;
   const dim3 block(256);
   const dim3 grid((unsigned)((N + 255) / 256));
   EventScope timing(RADE_KERNEL_PROJECT, stream);
   const bool vec = (reinterpret_cast<uintptr_t>(sh) & 15) == 0;
+  float4* dq = reinterpret_cast<float4*>(depth_quad);
+#define RADE_PROJECT_E(K, V4, E)                                                             \
+  hipLaunchKernelGGL((k_project<K, V4, E>), grid, block, 0, stream, st, views, V, N, means,  \
+                     scales, quats, opac, sh, splats, tiles_touched, dq)
 #define RADE_PROJECT(K, V4)                                                                 \
-  hipLaunchKernelGGL((k_project<K, V4>), grid, block, 0, stream, st, views, V, N, means,    \
-                     scales, quats, opac, sh, splats, tiles_touched)
+  do {                                                                                      \
+    if (dq) RADE_PROJECT_E(K, V4, true); else RADE_PROJECT_E(K, V4, false);                 \
+  } while (0)
   switch (st.sh_degree) {
     case 0: RADE_PROJECT(1, false); break;
     case 1: if (vec) RADE_PROJECT(4, true); else RADE_PROJECT(4, false); break;
@@ -680,6 +724,7 @@ hipError_t launch_project(const rade_settings& st, const rade_view* views, int V
     default: if (vec) RADE_PROJECT(16, true); else RADE_PROJECT(16, false); break;
   }
 #undef RADE_PROJECT
+#undef RADE_PROJECT_E
   return hipGetLastError();
 }
 

@@ -82,6 +82,7 @@ struct FwdArgs {
   uint32_t* queue;         // work-queue counter of the persistent kernel
   float *color, *depth, *normal, *alpha, *t_final, *distortion;
   int32_t *last, *median, *count;
+  const float4* depth_quad;  // EXACT only: 2 per (view, Gaussian)
 };
 
 struct BwdArgs {
@@ -216,17 +217,22 @@ __device__ __forceinline__ void publish_masks(uint32_t bits, uint64_t (*masks)[T
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool EXACT>
 struct FwdShared {
   StagedSplat ss[TileGeom<TW, TH>::BLOCK];
   uint32_t sgid[TileGeom<TW, TH>::BLOCK];
   uint64_t masks[TileGeom<TW, TH>::NW][TileGeom<TW, TH>::NW];
+  // EXACT: the ray-maximum depth terms (g0, g1, H00, H01) and H11
+  float4 xq[EXACT ? TileGeom<TW, TH>::BLOCK : 1];
+  float xh[EXACT ? TileGeom<TW, TH>::BLOCK : 1];
 };
 
 // Forward blend of one tile (all threads of the workgroup take part).  DIST:
-// also the distortion map; CNT: also the blend-count map.
-template <int TW, int TH, bool DIST, bool CNT>
-__device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShared<TW, TH>& sh) {
+// also the distortion map; CNT: also the blend-count map; EXACT: per-pixel
+// depth of the ray maximum (Eq. 7) instead of the plane of Eq. 4.
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
+                                         FwdShared<TW, TH, EXACT>& sh) {
   using TG = TileGeom<TW, TH>;
   const BlendParams& bp = a.bp;
   const rade_splat* __restrict__ splats = a.splats;
@@ -249,7 +255,14 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
     if (__syncthreads_and(done ? 1 : 0)) break;
     const uint32_t idx = b0 + threadIdx.x;
     uint32_t bits = 0;
-    if (idx < c.re) bits = stage<TW, TH>(splats, vbase, pair_ids, idx, c, bp, ss, sgid);
+    if (idx < c.re) {
+      bits = stage<TW, TH>(splats, vbase, pair_ids, idx, c, bp, ss, sgid);
+      if constexpr (EXACT) {
+        const float4* q = a.depth_quad + 2 * (vbase + sgid[threadIdx.x]);
+        sh.xq[threadIdx.x] = q[0];
+        sh.xh[threadIdx.x] = q[1].x;
+      }
+    }
     publish_masks<TW, TH>(bits, masks);
     __syncthreads();
     bool wave_live = !__all(done);
@@ -271,7 +284,18 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
         const bool take = pass && !stop;
         done = done || stop;
         const float w = take ? al * T : 0.0f;
-        const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
+        float d;
+        if constexpr (EXACT) {
+          // z (1 - g.d) / (1 - 2 g.d + H0 dx^2 + H1 dx dy + H2 dy^2)
+          const float4 q = sh.xq[r];
+          const float h2 = sh.xh[r];
+          const float gd = fmaf(q.y, dy, q.x * dx);
+          const float quad = fmaf(h2 * dy, dy, dx * fmaf(q.z, dx, q.w * dy));
+          const float den = fmaf(-2.0f, gd, 1.0f) + quad;
+          d = s.z * (1.0f - gd) * __builtin_amdgcn_rcpf(den);
+        } else {
+          d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
+        }
         C0 = fmaf(w, s.r, C0); C1 = fmaf(w, s.g, C1); C2 = fmaf(w, s.b, C2);
         D = fmaf(w, d, D);
         N0 = fmaf(w, s.n0, N0); N1 = fmaf(w, s.n1, N1); N2 = fmaf(w, s.n2, N2);
@@ -318,19 +342,19 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile, FwdShar
 }
 
 // One workgroup per tile, tiles visited in `order` (or natural) order.
-template <int TW, int TH, bool DIST, bool CNT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd(FwdArgs a) {
-  __shared__ FwdShared<TW, TH> sh;
+  __shared__ FwdShared<TW, TH, EXACT> sh;
   const int64_t i = blockIdx.x;
-  fwd_tile<TW, TH, DIST, CNT>(a, a.order ? (int64_t)a.order[i] : i, sh);
+  fwd_tile<TW, TH, DIST, CNT, EXACT>(a, a.order ? (int64_t)a.order[i] : i, sh);
 }
 
 // Persistent workgroups pull tiles from a device counter (zeroed before the
 // launch) in `order`; every workgroup exits once the counter passes the tile
 // count.
-template <int TW, int TH, bool DIST, bool CNT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
-  __shared__ FwdShared<TW, TH> sh;
+  __shared__ FwdShared<TW, TH, EXACT> sh;
   __shared__ uint32_t item_s;
   for (;;) {
     if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1u);
@@ -338,7 +362,7 @@ __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
     const uint32_t item = item_s;
     __syncthreads();
     if ((int64_t)item >= a.tiles) break;
-    fwd_tile<TW, TH, DIST, CNT>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+    fwd_tile<TW, TH, DIST, CNT, EXACT>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
   }
 }
 
@@ -581,31 +605,38 @@ unsigned resident_blocks(K kernel, int block, unsigned cap, unsigned& cached) {
   return cached < cap ? cached : cap;
 }
 
-template <int TW, int TH, bool DIST, bool CNT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
 void launch_fwd_d(const FwdArgs& a, int schedule, hipStream_t st) {
   constexpr int B = TileGeom<TW, TH>::BLOCK;
   if (schedule == RADE_SCHEDULE_PERSISTENT) {
     static unsigned cached = 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
-    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH, DIST, CNT>, B,
+    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH, DIST, CNT, EXACT>, B,
                                        (unsigned)a.tiles, cached);
-    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST, CNT>), dim3(g), dim3(B), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST, CNT>), dim3((unsigned)a.tiles), dim3(B), 0,
+    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST, CNT, EXACT>), dim3(g), dim3(B), 0,
                        st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST, CNT, EXACT>), dim3((unsigned)a.tiles),
+                       dim3(B), 0, st, a);
+  }
+}
+
+template <int TW, int TH, bool EXACT>
+void launch_fwd_e(const FwdArgs& a, int schedule, hipStream_t st) {
+  if (a.distortion) {
+    if (a.count) launch_fwd_d<TW, TH, true, true, EXACT>(a, schedule, st);
+    else launch_fwd_d<TW, TH, true, false, EXACT>(a, schedule, st);
+  } else {
+    if (a.count) launch_fwd_d<TW, TH, false, true, EXACT>(a, schedule, st);
+    else launch_fwd_d<TW, TH, false, false, EXACT>(a, schedule, st);
   }
 }
 
 template <int TW, int TH>
 void launch_fwd_t(const FwdArgs& a, int schedule, hipStream_t st) {
   EventScope timing(RADE_KERNEL_RENDER_FWD, st);
-  if (a.distortion) {
-    if (a.count) launch_fwd_d<TW, TH, true, true>(a, schedule, st);
-    else launch_fwd_d<TW, TH, true, false>(a, schedule, st);
-  } else {
-    if (a.count) launch_fwd_d<TW, TH, false, true>(a, schedule, st);
-    else launch_fwd_d<TW, TH, false, false>(a, schedule, st);
-  }
+  if (a.depth_quad) launch_fwd_e<TW, TH, true>(a, schedule, st);
+  else launch_fwd_e<TW, TH, false>(a, schedule, st);
 }
 
 template <int TW, int TH, bool DIST>
@@ -650,7 +681,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
                              int32_t* last, int32_t* med, int32_t* cnt, float* distortion,
-                             hipStream_t st) {
+                             const float* depth_quad, hipStream_t st) {
   if (tiles == 0) return hipSuccess;
   FwdArgs a;
   a.bp = make_blend_params(s);
@@ -660,6 +691,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
   a.queue = order ? const_cast<uint32_t*>(order) + tiles : nullptr;
   a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
   a.last = last; a.median = med; a.count = cnt; a.distortion = distortion;
+  a.depth_quad = reinterpret_cast<const float4*>(depth_quad);
   RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, st))
   return hipGetLastError();
 }

@@ -97,14 +97,20 @@ class Rasterizer:
         return (f(3), f(2), f(3), f(1), f(1), i(), i(), i() if want_count else None)
 
     # -- forward -------------------------------------------------------------
-    def project(self, means, scales, quats, opacities, sh, stream=None):
+    def project(self, means, scales, quats, opacities, sh, stream=None, depth_quad=None):
+        """depth_quad: (V*N*8,) float32 buffer for the exact-depth records
+        (required in RADE_DEPTH_EXACT mode)."""
         N = means.shape[0]
         VN = self.V * N
         splats = torch.empty(max(1, VN) * _lib.SPLAT_BYTES, dtype=torch.uint8, device=self.device)
         tt = torch.empty(max(1, VN), dtype=torch.int32, device=self.device)
         _lib.rade_project(self.settings, self.views_dev, self.V, N, means, scales,
-                          _aligned16(quats), opacities, sh, splats, tt, stream)
+                          _aligned16(quats), opacities, sh, splats, tt, stream, depth_quad)
         return splats, tt
+
+    @property
+    def exact_depth(self) -> bool:
+        return self.settings.depth_mode == _lib.RADE_DEPTH_EXACT
 
     def bin_sort(self, N: int, splats, tt, want_keys: bool = False, stream=None):
         if self._pairs is None or self._n != N:
@@ -128,7 +134,9 @@ class Rasterizer:
     def forward(self, means, scales, quats, opacities, sh, want_count: bool = False,
                 keep_splats: bool = True, stream=None, want_distortion: bool = False) -> Maps:
         N = means.shape[0]
-        splats, tt = self.project(means, scales, quats, opacities, sh, stream)
+        quad = (torch.empty(max(1, self.V * N) * 8, dtype=torch.float32, device=self.device)
+                if self.exact_depth else None)
+        splats, tt = self.project(means, scales, quats, opacities, sh, stream, depth_quad=quad)
         pair_ids, ranges, M = self.bin_sort(N, splats, tt, stream=stream)
         order = self.tile_order(ranges, stream)
         color, depth, normal, alpha, tf, last, med, cnt = self._new_maps(want_count)
@@ -136,7 +144,7 @@ class Rasterizer:
                 if want_distortion else None)
         _lib.rade_render_fwd(self.settings, self.views_c, self.views_dev, self.V, N, splats,
                              pair_ids, ranges, color, depth, normal, alpha, tf, last, med, cnt,
-                             stream, tile_order=order, distortion=dist)
+                             stream, tile_order=order, distortion=dist, depth_quad=quad)
         # pair_ids are a view of a reusable buffer: keep a private copy for
         # the backward pass
         state = ForwardState(splats if keep_splats else None, pair_ids.clone(), ranges, order,
@@ -157,6 +165,9 @@ class Rasterizer:
     # -- backward ------------------------------------------------------------
     def backward(self, state: ForwardState, means, scales, quats, opacities, sh, d_color=None,
                  d_depth=None, d_normal=None, d_alpha=None, stream=None, d_distortion=None):
+        if self.exact_depth:
+            raise NotImplementedError("the exact ray-maximum depth (Eq. 7) is a forward-only "
+                                      "variant; train with the affine depth of Eq. 4")
         N = means.shape[0]
         recompute = state.splats is None
         ws = _lib.rade_render_bwd_workspace(self.settings, self.V, N, recompute)

@@ -28,7 +28,8 @@ def oracle_settings(s):
     return oracle.settings(sh_degree=s.sh_degree, dilation=s.dilation, near=s.near_plane,
                            alpha_min=s.alpha_min, alpha_max=s.alpha_max, t_min=s.t_min,
                            power_cut=s.power_cut, fov_clamp=s.fov_clamp,
-                           degenerate=s.degenerate, bg=s.bg, tile=(s.tile_w, s.tile_h))
+                           degenerate=s.degenerate, bg=s.bg, tile=(s.tile_w, s.tile_h),
+                           depth_exact=s.depth_mode == 1)
 
 
 def to_dev(scene, dev):

@@ -51,9 +51,9 @@ def test_header_is_c_and_struct_sizes(tmp_path):
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I",
                            os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     sizes = subprocess.check_output([str(exe)]).decode().split()
-    assert sizes == ["104", "96", "80", "72", "80"]
+    assert sizes == ["112", "96", "80", "72", "80"]
     lib = _lib()
-    assert ctypes.sizeof(lib.CSettings) == 104 and ctypes.sizeof(lib.CView) == 96
+    assert ctypes.sizeof(lib.CSettings) == 112 and ctypes.sizeof(lib.CView) == 96
     assert lib.SPLAT_DTYPE.itemsize == 80 and lib.SPLAT_DTYPE.fields["rect"][1] == 72
 
 
@@ -74,7 +74,8 @@ def test_views_prepare_offsets():
 
 
 @pytest.mark.parametrize("bad", [dict(tile_w=12), dict(tile_h=64), dict(sh_degree=4), dict(schedule=3),
-                                 dict(alpha_min=0.0), dict(t_min=1.5), dict(power_cut=-1.0)])
+                                 dict(alpha_min=0.0), dict(t_min=1.5), dict(power_cut=-1.0),
+                                 dict(depth_mode=3)])
 def test_invalid_settings_rejected_without_launch(bad):
     lib = _lib()
     import synth
@@ -86,7 +87,7 @@ def test_invalid_settings_rejected_without_launch(bad):
     # an invalid setting or a zero view count never reach HIP
     so = lib.load()
     s = lib.Settings(**bad).c()
-    assert so.rade_project(ctypes.byref(s), None, 1, 10, *([None] * 7), None) == \
+    assert so.rade_project(ctypes.byref(s), None, 1, 10, *([None] * 8), None) == \
         lib.RADE_ERR_INVALID_ARG
 
 
@@ -96,12 +97,27 @@ def test_null_pointers_rejected():
     s = lib.Settings().c()
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     assert so.rade_project(ctypes.byref(s), dummy, 1, 10, None, dummy, dummy, dummy, dummy,
-                           dummy, dummy, None) == lib.RADE_ERR_INVALID_ARG
-    assert so.rade_project(ctypes.byref(s), dummy, 0, 10, *([dummy] * 7), None) == \
+                           dummy, dummy, None, None) == lib.RADE_ERR_INVALID_ARG
+    assert so.rade_project(ctypes.byref(s), dummy, 0, 10, *([dummy] * 8), None) == \
         lib.RADE_ERR_INVALID_ARG
     # misaligned quaternion array
     assert so.rade_project(ctypes.byref(s), dummy, 1, 10, dummy, dummy, ctypes.c_void_p(20),
-                           dummy, dummy, dummy, dummy, None) == lib.RADE_ERR_INVALID_ARG
+                           dummy, dummy, dummy, dummy, None, None) == lib.RADE_ERR_INVALID_ARG
+    # exact depth: the depth_quad records are required and 16-byte aligned;
+    # the backward rejects the mode; unknown modes and a nonzero reserved
+    # field are rejected
+    se = lib.Settings(depth_mode=lib.RADE_DEPTH_EXACT).c()
+    assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), None, None) == \
+        lib.RADE_ERR_INVALID_ARG
+    assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), ctypes.c_void_p(24),
+                           None) == lib.RADE_ERR_INVALID_ARG
+    bad = lib.Settings(depth_mode=2).c()
+    assert so.rade_project(ctypes.byref(bad), dummy, 1, 10, *([dummy] * 8), None) == \
+        lib.RADE_ERR_INVALID_ARG
+    res = lib.Settings().c()
+    res.reserved = 1
+    assert so.rade_project(ctypes.byref(res), dummy, 1, 10, *([dummy] * 8), None) == \
+        lib.RADE_ERR_INVALID_ARG
     import synth
     vc = lib.make_views([synth.identity_view(32, 32)])
     lib.rade_views_prepare(lib.Settings(), vc)
