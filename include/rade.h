@@ -312,7 +312,8 @@ int rade_filter3d_apply_bwd(int64_t N, const float* scales, const float* opaciti
  * where none), weight the number of contributing views.
  *   views_host/views_dev : the V prepared views the maps were rendered for
  *   depth                : the 2-plane depth maps of rade_render_fwd
- *   origin               : host, 3 doubles */
+ *   origin               : host, 3 doubles
+ * Limit: nx ny nz <= 2^32 - 1. */
 int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
                    const rade_view* views_dev, int32_t V, const float* depth,
                    const double* origin, double voxel, int32_t nx, int32_t ny, int32_t nz,
@@ -349,7 +350,7 @@ int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
  * its capacity it returns RADE_ERR_CAPACITY (the outputs are then
  * incomplete; call again with buffers of the reported size).
  * Limits: 3 nx ny nz <= 2^32 - 1.  Workspace: rade_marching_cubes_workspace
- * bytes (about 22 bytes per voxel). */
+ * bytes (about 15 bytes per voxel). */
 size_t rade_marching_cubes_workspace(int32_t nx, int32_t ny, int32_t nz);
 int rade_marching_cubes(const float* tsdf, const float* weight, int32_t nx, int32_t ny,
                         int32_t nz, const double* origin, double voxel, float iso,

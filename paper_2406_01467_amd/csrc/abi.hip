@@ -374,6 +374,7 @@ int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
                    float trunc, float* tsdf, float* weight, void* stream) {
   if (!s || !views_ok(views_host, V) || !views_dev || !origin) return RADE_ERR_INVALID_ARG;
   if (!(voxel > 0.0) || !(trunc > 0.0f) || nx < 1 || ny < 1 || nz < 1) return RADE_ERR_INVALID_ARG;
+  if ((int64_t)nx * ny * nz > (int64_t)UINT32_MAX) return RADE_ERR_INVALID_ARG;
   if (!std::isfinite(origin[0]) || !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
     return RADE_ERR_INVALID_ARG;
   if (!depth || !tsdf || !weight) return RADE_ERR_INVALID_ARG;

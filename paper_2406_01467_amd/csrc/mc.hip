@@ -25,12 +25,19 @@
 //    interior keep the mesh a manifold), triangles (e0, ei, ei+1) in segment
 //    order.
 //
-// Pipeline: cell codes and triangle counts -> edge flags (crossed and used by
-// an observed cell) -> exclusive scans (vertex id per grid edge, triangle
-// offset per cell) -> vertices at the linear zero of each used edge (FP64) ->
-// triangles.  Vertices are ordered by global edge id 3 q + a, triangles by
-// cell index then the cell's rule order, so the mesh is deterministic.
+// Pipeline: one byte per voxel (observed, inside) -> cell codes (2 bytes per
+// cell) -> compaction of the voxels by their used edges (crossed between
+// observed voxels and part of an observed cell, up to three per voxel): the
+// count is evaluated on the fly in the compaction's reduce and emit
+// kernels, the emit writes each vertex (linear zero along the edge, FP64)
+// and its id in a per-edge table -> compaction of the cells by triangle
+// count, the emit writing each cell's triangles.  No count array is stored
+// or scanned: the FP32 grids are read once, the byte and code grids a few
+// times, the surface written once.  Vertices are ordered by global edge id
+// 3 q + a, triangles by cell index then the cell's rule order, so the mesh
+// is deterministic.
 #include "common.hpp"
+#include "grid.hpp"
 #include "scan.hpp"
 
 namespace rade {
@@ -171,134 +178,186 @@ __constant__ McTable kMc = make_mc_table();
 constexpr int kT = 256;
 constexpr uint16_t kObserved = 0x100;
 
+__global__ void k_mc_zero_counts(uint32_t* nv, uint64_t* nt) {
+  *nv = 0u;
+  *nt = 0u;
+}
+
 inline unsigned grid_for(int64_t n) {
   int64_t b = (n + kT - 1) / kT;
   if (b > ((int64_t)1 << 20)) b = (int64_t)1 << 20;  // grid-stride beyond
   return (unsigned)(b > 0 ? b : 1);
 }
 
-// Cell codes (bit 8: all corners observed) and triangle counts.
+// One byte per voxel: bit 0 observed (weight > 0), bit 1 inside (value
+// below the iso level).  Every later pass reads these bytes instead of the
+// two FP32 grids.
+constexpr uint8_t kSeen = 1, kIn = 2;
+
 __global__ void __launch_bounds__(kT)
-k_mc_cells(const float* __restrict__ f, const float* __restrict__ w, int64_t nx, int64_t ny,
-           int64_t nz, float iso, uint16_t* __restrict__ info, uint64_t* __restrict__ ntri) {
-  const int64_t cx = nx - 1, cy = ny - 1, ncell = cx * cy * (nz - 1);
-  for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncell;
-       c += (int64_t)gridDim.x * kT) {
-    const int64_t i = c % cx, j = (c / cx) % cy, k = c / (cx * cy);
-    const int64_t q0 = (k * ny + j) * nx + i;
-    int code = 0;
-    bool observed = true;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int64_t q = q0 + (b & 1) + ((b >> 1) & 1) * nx + ((b >> 2) & 1) * nx * ny;
-      observed = observed && w[q] > 0.0f;
-      code |= (f[q] < iso ? 1 : 0) << b;
-    }
-    info[c] = observed ? (uint16_t)(kObserved | code) : (uint16_t)0;
-    ntri[c] = observed ? (uint64_t)kMc.ntri[code] : 0;
+k_mc_bits(const float* __restrict__ f, const float* __restrict__ w, uint64_t nvox, float iso,
+          uint8_t* __restrict__ bits) {
+  for (uint64_t q = (uint64_t)blockIdx.x * kT + threadIdx.x; q < nvox;
+       q += (uint64_t)gridDim.x * kT) {
+    const float fv = f[q], wv = w[q];
+    bits[q] = (uint8_t)((wv > 0.0f ? kSeen : 0) | (fv < iso ? kIn : 0));
   }
 }
 
-// 1 for a grid edge that changes sign between two observed voxels and
-// belongs to an observed cell.
+// Cell codes (bit 8: all corners observed), one per cell.
 __global__ void __launch_bounds__(kT)
-k_mc_edges(const float* __restrict__ f, const float* __restrict__ w,
-           const uint16_t* __restrict__ info, int64_t nx, int64_t ny, int64_t nz, float iso,
-           uint32_t* __restrict__ flag) {
-  const int64_t nvox = nx * ny * nz, nedge = 3 * nvox;
-  const int64_t n[3] = {nx, ny, nz};
-  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < nedge;
-       e += (int64_t)gridDim.x * kT) {
-    const int64_t q = e / 3;
-    const int a = (int)(e - 3 * q);
-    const int64_t p[3] = {q % nx, (q / nx) % ny, q / (nx * ny)};
-    uint32_t out = 0;
-    if (p[a] + 1 < n[a]) {
-      const int64_t q1 = q + (a == 0 ? 1 : a == 1 ? nx : nx * ny);
-      const bool cross = w[q] > 0.0f && w[q1] > 0.0f && ((f[q] < iso) != (f[q1] < iso));
-      if (cross) {
-        const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
-        for (int s = 0; s < 4 && !out; ++s) {
-          int64_t c[3] = {p[0], p[1], p[2]};
-          c[u] -= s & 1;
-          c[v] -= s >> 1;
-          if (c[u] < 0 || c[u] >= n[u] - 1 || c[v] < 0 || c[v] >= n[v] - 1) continue;
-          const int64_t cell = (c[2] * (ny - 1) + c[1]) * (nx - 1) + c[0];
-          if (info[cell] & kObserved) out = 1;
+k_mc_cells(const uint8_t* __restrict__ bits, uint32_t nx, uint32_t ny, uint32_t ncell,
+           Grid3 cells, uint16_t* __restrict__ info) {
+  for (uint64_t cc = (uint64_t)blockIdx.x * kT + threadIdx.x; cc < ncell;
+       cc += (uint64_t)gridDim.x * kT) {
+    const uint32_t c = (uint32_t)cc;
+    uint32_t i, j, k;
+    cells.split(c, i, j, k);
+    const uint32_t q0 = (k * ny + j) * nx + i;
+    uint32_t bv[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      bv[b] = bits[q0 + (b & 1) + ((b >> 1) & 1) * nx + ((b >> 2) & 1) * nx * ny];
+    uint32_t code = 0, seen = kSeen;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      seen &= bv[b];
+      code |= ((bv[b] >> 1) & 1u) << b;
+    }
+    info[c] = seen ? (uint16_t)(kObserved | code) : (uint16_t)0;
+  }
+}
+
+// Edges of voxel q along +x, +y, +z (bit a) that change sign between two
+// observed voxels and belong to an observed cell: each such edge carries a
+// vertex used by that cell's triangles.
+struct VoxelEdges {
+  const uint8_t* bits;
+  const uint16_t* info;
+  Grid3 vox;
+  uint32_t nz;
+  __device__ uint32_t mask(uint32_t q) const {
+    const uint32_t nx = vox.nx, ny = vox.ny;
+    uint32_t p[3];
+    vox.split(q, p[0], p[1], p[2]);
+    const uint32_t n[3] = {nx, ny, nz};
+    const uint32_t step[3] = {1u, nx, nx * ny};
+    const uint32_t b0 = bits[q];
+    uint32_t m = 0;
+    if (!(b0 & kSeen)) return 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (p[a] + 1 >= n[a]) continue;
+      const uint32_t b1 = bits[q + step[a]];
+      if (!(b1 & kSeen) || ((b0 ^ b1) & kIn) == 0) continue;
+      const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+      for (int s = 0; s < 4; ++s) {
+        const uint32_t du = s & 1, dv = s >> 1;
+        if (du > p[u] || dv > p[v]) continue;
+        uint32_t c[3] = {p[0], p[1], p[2]};
+        c[u] -= du;
+        c[v] -= dv;
+        if (c[u] >= n[u] - 1 || c[v] >= n[v] - 1) continue;
+        if (info[(c[2] * (ny - 1) + c[1]) * (nx - 1) + c[0]] & kObserved) {
+          m |= 1u << a;
+          break;
         }
       }
     }
-    flag[e] = out;
+    return m;
   }
-}
-
-// Vertex of every used edge (vid holds the exclusive scan of the flags).
-__global__ void __launch_bounds__(kT)
-k_mc_verts(const float* __restrict__ f, int64_t nx, int64_t ny, int64_t nz, double o0, double o1,
-           double o2, double voxel, float iso, const uint32_t* __restrict__ vid,
-           const uint32_t* __restrict__ nv_total, float* __restrict__ verts, int64_t max_verts) {
-  const int64_t nedge = 3 * nx * ny * nz;
-  const uint32_t total = *nv_total;
-  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < nedge;
-       e += (int64_t)gridDim.x * kT) {
-    const uint32_t id = vid[e];
-    const uint32_t next = e + 1 < nedge ? vid[e + 1] : total;
-    if (next == id || (int64_t)id >= max_verts) continue;
-    const int64_t q = e / 3;
-    const int a = (int)(e - 3 * q);
-    const int64_t q1 = q + (a == 0 ? 1 : a == 1 ? nx : nx * ny);
-    const double f0 = f[q], f1 = f[q1];
-    const double t = ((double)iso - f0) / (f1 - f0);
-    double x = o0 + ((double)(q % nx) + 0.5) * voxel;
-    double y = o1 + ((double)((q / nx) % ny) + 0.5) * voxel;
-    double z = o2 + ((double)(q / (nx * ny)) + 0.5) * voxel;
-    if (a == 0) x += t * voxel;
-    if (a == 1) y += t * voxel;
-    if (a == 2) z += t * voxel;
-    verts[3 * (int64_t)id + 0] = (float)x;
-    verts[3 * (int64_t)id + 1] = (float)y;
-    verts[3 * (int64_t)id + 2] = (float)z;
+  __device__ uint32_t operator()(int64_t item) const {
+    return (uint32_t)__builtin_popcount(mask((uint32_t)item));
   }
-}
+};
 
-// Triangles of every observed cell (toff holds the exclusive scan of the counts).
-__global__ void __launch_bounds__(kT)
-k_mc_tris(const uint16_t* __restrict__ info, const uint64_t* __restrict__ toff,
-          const uint32_t* __restrict__ vid, int64_t nx, int64_t ny, int64_t nz,
-          uint32_t* __restrict__ tris, int64_t max_tris) {
-  const int64_t cx = nx - 1, cy = ny - 1, ncell = cx * cy * (nz - 1);
-  for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncell;
-       c += (int64_t)gridDim.x * kT) {
+// The used edges of voxel q get vertex ids first, first + 1, ... in axis
+// order (so ids follow the global edge id 3 q + a): position at the linear
+// zero of the field along the edge (FP64), id in the per-edge table the
+// triangles read.
+struct EmitVertices {
+  VoxelEdges edges;
+  const float* f;
+  double o0, o1, o2, voxel;
+  float iso;
+  uint32_t* vid;
+  float* verts;
+  int64_t max_verts;
+  __device__ void operator()(int64_t item, uint32_t first, uint32_t) const {
+    const uint32_t q = (uint32_t)item;
+    const uint32_t m = edges.mask(q);
+    const uint32_t nx = edges.vox.nx, ny = edges.vox.ny;
+    uint32_t i, j, k;
+    edges.vox.split(q, i, j, k);
+    const double f0 = f[q];
+    uint32_t id = first;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!((m >> a) & 1u)) continue;
+      vid[3u * q + (uint32_t)a] = id;
+      if ((int64_t)id < max_verts) {
+        const double f1 = f[q + (a == 0 ? 1u : a == 1 ? nx : nx * ny)];
+        const double t = ((double)iso - f0) / (f1 - f0);
+        double x = o0 + ((double)i + 0.5) * voxel;
+        double y = o1 + ((double)j + 0.5) * voxel;
+        double z = o2 + ((double)k + 0.5) * voxel;
+        if (a == 0) x += t * voxel;
+        if (a == 1) y += t * voxel;
+        if (a == 2) z += t * voxel;
+        verts[3 * (int64_t)id + 0] = (float)x;
+        verts[3 * (int64_t)id + 1] = (float)y;
+        verts[3 * (int64_t)id + 2] = (float)z;
+      }
+      ++id;
+    }
+  }
+};
+
+// Triangles of a cell (0 unless all corners were observed).
+struct CellTriangles {
+  const uint16_t* info;
+  __device__ uint64_t operator()(int64_t c) const {
     const uint16_t inf = info[c];
-    if (!(inf & kObserved)) continue;
-    const int code = inf & 0xff;
-    const int n = kMc.ntri[code];
-    if (n == 0) continue;
-    const int64_t i = c % cx, j = (c / cx) % cy, k = c / (cx * cy);
-    const int64_t base = (int64_t)toff[c];
-    for (int t = 0; t < n; ++t) {
-      if (base + t >= max_tris) break;
+    return (inf & kObserved) ? (uint64_t)kMc.ntri[inf & 0xff] : 0;
+  }
+};
+
+// The cell's triangles at `base`, vertex indices looked up per edge.
+struct EmitTriangles {
+  const uint16_t* info;
+  const uint32_t* vid;
+  Grid3 cells;
+  uint32_t nx, ny;
+  uint32_t* tris;
+  int64_t max_tris;
+  __device__ void operator()(int64_t item, uint64_t base, uint64_t n) const {
+    const uint32_t c = (uint32_t)item;
+    const int code = info[c] & 0xff;
+    uint32_t i, j, k;
+    cells.split(c, i, j, k);
+    for (int t = 0; t < (int)n; ++t) {
+      if ((int64_t)base + t >= max_tris) break;
       for (int m = 0; m < 3; ++m) {
         const int e = kMc.tri[code][3 * t + m];
         const int a = e >> 2;
-        int64_t p[3] = {i, j, k};
+        uint32_t p[3] = {i, j, k};
         p[a == 0 ? 1 : 0] += e & 1;
         p[a == 2 ? 1 : 2] += (e >> 1) & 1;
-        const int64_t ge = 3 * ((p[2] * ny + p[1]) * nx + p[0]) + a;
-        tris[3 * (base + t) + m] = vid[ge];
+        const uint32_t ge = 3u * ((p[2] * ny + p[1]) * nx + p[0]) + (uint32_t)a;
+        tris[3 * ((int64_t)base + t) + m] = vid[ge];
       }
     }
   }
-}
+};
 
 struct McLayout {
-  size_t info, toff, vid, sums, totals, total;
+  size_t bits, info, vid, sums, totals, total;
 };
 
 McLayout mc_layout(int64_t nx, int64_t ny, int64_t nz) {
   const int64_t nvox = nx * ny * nz, nedge = 3 * nvox;
   const int64_t ncell = (nx - 1) * (ny - 1) * (nz - 1);
-  const int64_t nmax = nedge > ncell ? nedge : ncell;
+  const int64_t nmax = nvox > ncell ? nvox : ncell;
   McLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -306,10 +365,10 @@ McLayout mc_layout(int64_t nx, int64_t ny, int64_t nz) {
     off += (bytes + 255) & ~(size_t)255;
     return o;
   };
+  L.bits = take((size_t)nvox);
   L.info = take(sizeof(uint16_t) * (size_t)ncell);
-  L.toff = take(sizeof(uint64_t) * (size_t)ncell);
-  L.vid = take(sizeof(uint32_t) * (size_t)nedge);
-  L.sums = take(sizeof(uint64_t) * (size_t)((nmax + kScanTile - 1) / kScanTile + 1));
+  L.vid = take(sizeof(uint32_t) * (size_t)nedge);  // written only for used edges
+  L.sums = take(sizeof(uint64_t) * (size_t)(compact_blocks(nmax) + 1));
   L.totals = take(16);
   L.total = off;
   return L;
@@ -337,31 +396,35 @@ hipError_t launch_marching_cubes(const float* tsdf, const float* weight, int64_t
                                  const uint64_t** nt_dev, hipStream_t st) {
   const McLayout L = mc_layout(nx, ny, nz);
   char* base = (char*)ws;
+  uint8_t* bits = (uint8_t*)(base + L.bits);
   uint16_t* info = (uint16_t*)(base + L.info);
-  uint64_t* toff = (uint64_t*)(base + L.toff);
   uint32_t* vid = (uint32_t*)(base + L.vid);
   void* sums = base + L.sums;
   uint64_t* nt = (uint64_t*)(base + L.totals);
   uint32_t* nv = (uint32_t*)(base + L.totals + 8);
   *nv_dev = nv;
   *nt_dev = nt;
-  const int64_t nedge = 3 * nx * ny * nz;
+  const int64_t nvox = nx * ny * nz;
   const int64_t ncell = (nx - 1) * (ny - 1) * (nz - 1);
-  if (ncell > 0) {
-    hipLaunchKernelGGL(k_mc_cells, dim3(grid_for(ncell)), dim3(kT), 0, st, tsdf, weight, nx, ny,
-                       nz, iso, info, toff);
+  if (ncell == 0) {  // a flat grid has no cell: empty mesh
+    hipLaunchKernelGGL(k_mc_zero_counts, dim3(1), dim3(1), 0, st, nv, nt);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_mc_edges, dim3(grid_for(nedge)), dim3(kT), 0, st, tsdf, weight, info, nx,
-                     ny, nz, iso, vid);
-  // in place: each scan thread reads its items before writing them
-  scan<uint32_t>(PlainInput{vid}, nedge, nullptr, vid, (uint32_t*)sums, nv, st);
-  scan<uint64_t>(PlainInput64{toff}, ncell, nullptr, toff, (uint64_t*)sums, nt, st);
-  hipLaunchKernelGGL(k_mc_verts, dim3(grid_for(nedge)), dim3(kT), 0, st, tsdf, nx, ny, nz,
-                     origin[0], origin[1], origin[2], voxel, iso, vid, nv, verts, max_verts);
-  if (ncell > 0) {
-    hipLaunchKernelGGL(k_mc_tris, dim3(grid_for(ncell)), dim3(kT), 0, st, info, toff, vid, nx, ny,
-                       nz, tris, max_tris);
-  }
+  // every index fits 32 bits: 3 nx ny nz <= 2^32 - 1 is checked by the caller
+  const Grid3 vox((uint32_t)nx, (uint32_t)ny);
+  const Grid3 cells((uint32_t)(nx - 1), (uint32_t)(ny - 1));
+  hipLaunchKernelGGL(k_mc_bits, dim3(grid_for(nvox)), dim3(kT), 0, st, tsdf, weight,
+                     (uint64_t)nvox, iso, bits);
+  hipLaunchKernelGGL(k_mc_cells, dim3(grid_for(ncell)), dim3(kT), 0, st, bits, (uint32_t)nx,
+                     (uint32_t)ny, (uint32_t)ncell, cells, info);
+  const VoxelEdges edges{bits, info, vox, (uint32_t)nz};
+  scan_emit<uint32_t>(edges, nvox, (uint32_t*)sums, nv,
+                      EmitVertices{edges, tsdf, origin[0], origin[1], origin[2], voxel, iso, vid,
+                                   verts, max_verts},
+                      st);
+  scan_emit<uint64_t>(CellTriangles{info}, ncell, (uint64_t*)sums, nt,
+                      EmitTriangles{info, vid, cells, (uint32_t)nx, (uint32_t)ny, tris, max_tris},
+                      st);
   return hipGetLastError();
 }
 

@@ -121,4 +121,111 @@ void scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T*
                      n_dev, block_sums, out);
 }
 
+// Compaction: the exclusive scan of in() is handed, for every item with a
+// nonzero count, to emit(item, offset, count) instead of being stored.  The
+// counts are evaluated twice (reduce and emit) and never stored.  A fixed
+// grid of at most kCompactBlocks workgroups each walks a contiguous chunk of
+// items in rounds of 256 consecutive items, one per thread (so a wave's
+// loads are coalesced), kCompactBatch rounds at a time: all their counts are
+// loaded first, scanned within each wave by shuffles, and combined across
+// the four waves after one barrier; a batch whose counts are all zero is
+// skipped after a single block-wide vote.  The running offset is carried from
+// batch to batch; the scan of the per-workgroup sums stays short for any
+// item count.
+constexpr int64_t kCompactBlocks = 8192;
+constexpr int64_t kCompactRound = kScanThreads;
+constexpr int kCompactBatch = 8;
+constexpr int64_t kCompactStep = kCompactRound * kCompactBatch;
+
+template <typename T, typename In>
+__global__ void __launch_bounds__(kScanThreads)
+k_compact_reduce(In in, int64_t n, int64_t chunk, T* block_sums) {
+  __shared__ T lw[kScanThreads / 64];
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  T s = 0;
+  for (int64_t r = lo; r < hi; r += kCompactStep) {
+    T v[kCompactBatch];
+#pragma unroll
+    for (int k = 0; k < kCompactBatch; ++k) {
+      const int64_t i = r + k * kCompactRound + threadIdx.x;
+      v[k] = i < hi ? in(i) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kCompactBatch; ++k) s += v[k];
+  }
+  T total;
+  block_exclusive_scan<T>(s, lw, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+template <typename T, typename In, typename Emit>
+__global__ void __launch_bounds__(kScanThreads)
+k_compact_emit(In in, int64_t n, int64_t chunk, const T* block_sums, Emit emit) {
+  constexpr int W = kScanThreads / 64;
+  __shared__ T lw[kCompactBatch][W];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  T carry = block_sums[blockIdx.x];
+  for (int64_t r = lo; r < hi; r += kCompactStep) {  // uniform trip count
+    T v[kCompactBatch], incl[kCompactBatch];
+    int any = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactBatch; ++k) {
+      const int64_t i = r + k * kCompactRound + threadIdx.x;
+      v[k] = i < hi ? in(i) : 0;
+      any |= v[k] != 0 ? 1 : 0;
+    }
+    // a batch of zero counts (most of a sparse surface's grid) emits nothing
+    if (!__syncthreads_or(any)) continue;
+#pragma unroll
+    for (int k = 0; k < kCompactBatch; ++k) {
+      T x = v[k];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const T y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      incl[k] = x;
+      if (lane == 63) lw[k][wave] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCompactBatch; ++k) {
+      T round_total = 0, before = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const T t = lw[k][w];
+        round_total += t;
+        if (w < wave) before += t;
+      }
+      if (v[k]) emit(r + k * kCompactRound + threadIdx.x, carry + before + incl[k] - v[k], v[k]);
+      carry += round_total;
+    }
+    __syncthreads();
+  }
+}
+
+// Workgroups and block-sum entries a compaction of n items uses.
+inline int64_t compact_blocks(int64_t n) {
+  const int64_t steps = (n + kCompactStep - 1) / kCompactStep;
+  return steps < kCompactBlocks ? (steps > 0 ? steps : 1) : kCompactBlocks;
+}
+
+// Enqueues the compaction of in(0..n): total into *total, emit for every
+// item with a nonzero count.  block_sums holds compact_blocks(n) entries.
+// Launch errors are left pending.
+template <typename T, typename In, typename Emit>
+void scan_emit(In in, int64_t n, T* block_sums, T* total, Emit emit, hipStream_t st) {
+  const int64_t nb = compact_blocks(n);
+  const int64_t steps = (n + kCompactStep - 1) / kCompactStep;
+  const int64_t chunk = ((steps + nb - 1) / nb) * kCompactStep;
+  hipLaunchKernelGGL((k_compact_reduce<T, In>), dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                     in, n, chunk, block_sums);
+  hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kScanThreads), 0, st, block_sums, nb, total);
+  hipLaunchKernelGGL((k_compact_emit<T, In, Emit>), dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                     in, n, chunk, (const T*)block_sums, emit);
+}
+
 }  // namespace rade

@@ -102,7 +102,8 @@ def test_tsdf_rejects_bad_arguments():
     out = torch.empty(8, device=dev)
     w = torch.empty(8, device=dev)
     for voxel, dims, trunc in [(0.0, (2, 2, 2), 0.1), (0.1, (0, 2, 2), 0.1),
-                               (0.1, (2, 2, 2), 0.0), (float("nan"), (2, 2, 2), 0.1)]:
+                               (0.1, (2, 2, 2), 0.0), (float("nan"), (2, 2, 2), 0.1),
+                               (0.1, (2048, 2048, 1025), 0.1)]:   # beyond 2^32 - 1 voxels
         with pytest.raises(RuntimeError):
             _lib.rade_tsdf_fuse(rast.settings, rast.views_c, rast.views_dev, depth, (0, 0, 0),
                                 voxel, dims, trunc, out, w)
