@@ -75,6 +75,35 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan of one digit's row of per-block counts (one workgroup per
+// digit, rows are digit-major) and the digit's total.  Together with the
+// scan of the 256 totals in the scatter's prologue this replaces a global
+// scan of the whole count matrix.
+__global__ void __launch_bounds__(kThreads)
+k_radix_colscan(uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t lw[kThreads / 64];
+  uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += kTile) {  // uniform trip count
+    const int64_t base = b0 + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems], s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      v[k] = base + k < nblocks ? row[base + k] : 0u;
+      s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_exclusive_scan<uint32_t>(s, lw, tot);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (base + k < nblocks) row[base + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
 // Shared memory of one sorting workgroup.
 struct RankShared {
   uint32_t cnt[kRadix];                  // per-digit count of the tile
@@ -170,20 +199,25 @@ __device__ __forceinline__ void scatter_tile(int64_t base, int64_t n, int shift,
   }
 }
 
-// Scatter of the multi-kernel pass: digit offsets per (digit, block) from
-// the scanned histogram.
+// Scatter of the multi-kernel pass: the global position of digit d's run of
+// this block is the exclusive scan of the digit totals at d plus the
+// row-scanned count of the blocks before it.
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int shift, int64_t nblocks,
-                const uint32_t* __restrict__ offsets) {
+                const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot) {
   __shared__ RankShared sh;
   const int64_t n = *n_dev;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   if (base >= n) return;  // uniform per block
   uint32_t key[kItems], val[kItems], pos[kItems];
   rank_tile(kin, vin, base, n, shift, sh, key, val, pos);
-  sh.dbase[threadIdx.x] = offsets[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  {
+    uint32_t tot;
+    const uint32_t dstart = block_exclusive_scan<uint32_t>(dtot[threadIdx.x], sh.lw, tot);
+    sh.dbase[threadIdx.x] = dstart + offsets[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  }
   __syncthreads();
   scatter_tile(base, n, shift, sh, key, val, pos, kout, vout);
 }
@@ -341,10 +375,10 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n
     uint32_t* vo = (p & 1) ? v0 : v1;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev, shift,
                        nb, hist);
-    scan<uint32_t>(PlainInput{hist}, nb * kRadix, nullptr, hist, hist_sums, (uint32_t*)nullptr,
-                   st);
+    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb,
+                       hist_sums);
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
-                       n_dev, shift, nb, hist);
+                       n_dev, shift, nb, hist, (const uint32_t*)hist_sums);
   }
   return passes;
 }
@@ -380,10 +414,19 @@ Layout layout(int64_t VN, int64_t capacity) {
   L.tkeys1 = take(sizeof(uint32_t) * capacity);
   L.pids1 = take(sizeof(uint32_t) * capacity);
   L.hist = take(sizeof(uint32_t) * hist_n);
-  L.sums = take(sizeof(uint64_t) * ((scan_n + kTile - 1) / kTile + 1));
+  // block sums of the scans, and the 256 digit totals of a radix pass
+  const size_t sums_bytes = sizeof(uint64_t) * ((scan_n + kTile - 1) / kTile + 1);
+  L.sums = take(sums_bytes > sizeof(uint32_t) * kRadix ? sums_bytes : sizeof(uint32_t) * kRadix);
   L.scal = take(64);
   L.total = o;
   return L;
+}
+
+// Scan block sums (unused by the radix passes now) or the 256 digit totals.
+inline size_t tile_order_sums_bytes(int64_t nb) {
+  const size_t a = sizeof(uint64_t) * (size_t)(nb * kRadix / kTile + 2);
+  const size_t b = sizeof(uint32_t) * kRadix;
+  return a > b ? a : b;
 }
 
 // Order key of a tile: 255 - 16 log2(len + 1), so longer lists come first.
@@ -404,7 +447,7 @@ k_order_keys(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __res
 size_t tile_order_workspace(int64_t tiles) {
   const int64_t nb = (tiles + kTile - 1) / kTile + 1;
   return align_up(sizeof(uint32_t) * tiles) * 3 + align_up(sizeof(uint32_t) * nb * kRadix) +
-         align_up(sizeof(uint64_t) * (nb * kRadix / kTile + 2)) + 256;
+         align_up(tile_order_sums_bytes(nb)) + 256;
 }
 
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
@@ -416,7 +459,7 @@ hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* or
   uint32_t* k1 = (uint32_t*)(w + 2 * align_up(sizeof(uint32_t) * tiles));
   uint32_t* hist = (uint32_t*)(w + 3 * align_up(sizeof(uint32_t) * tiles));
   uint32_t* sums = (uint32_t*)((char*)hist + align_up(sizeof(uint32_t) * nb * kRadix));
-  uint32_t* cnt = (uint32_t*)((char*)sums + align_up(sizeof(uint64_t) * (nb * kRadix / kTile + 2)));
+  uint32_t* cnt = (uint32_t*)((char*)sums + align_up(tile_order_sums_bytes(nb)));
   hipLaunchKernelGGL(k_order_keys, dim3(blocks_for(tiles > 0 ? tiles : 1, kThreads)),
                      dim3(kThreads), 0, st, ranges, tiles, k0, v0, cnt);
   // one 8-bit pass: the result lands in (k1, order)
