@@ -67,8 +67,8 @@ BYTES_PER_PIXEL = 52 + 52 + 36
 # on (SHA-1 of render.hip + common.hpp) and for the 1600x1064 / 1M workload
 # at 16x16 tiles; reported as null otherwise.
 MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
-                    "sources_sha1": "df2f5269e69176d149154446c5c00f0ab2de50bf",
-                    "fetch_bytes": 363075335, "write_bytes": 154785088,
+                    "sources_sha1": "b1f409bbf38706c0750f360da12547c53e591dcd",
+                    "fetch_bytes": 363054020, "write_bytes": 154785088,
                     "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
 
 

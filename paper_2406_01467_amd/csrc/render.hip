@@ -187,8 +187,10 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     const int bx = 8 * (k % TG::NWX), by = 8 * (k / TG::NWX);
     if (rx0 <= bx + 7 && rx1 >= bx && ry0 <= by + 7 && ry1 >= by) bits |= 1u << k;
   }
-  if (bits & (bits - 1)) {
-    // more than one block inside the rect: drop those the ellipse misses.
+  if (bits) {
+    // drop the blocks the ellipse misses (also when the rect touches a
+    // single block: one test per staged pair is far cheaper than a wave
+    // iteration over a splat that reaches none of its pixels).
     // Support: power <= cut and opacity 2^-power >= alpha_min.
     const float A = fmaf(s.w0, s.w0, s.w2 * s.w2), B = fmaf(s.w0, s.w1, s.w2 * s.w3);
     const float C = fmaf(s.w1, s.w1, s.w3 * s.w3);
@@ -279,6 +281,12 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         // Branch-free blend: lanes that do not take the splat add w = 0
         // (x + 0 * finite = x exactly) and keep their state.
         const bool pass = splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl) && !done;
+        // one wave per 8x8 tile: skip splats no lane blends (lists whose
+        // pixels saturate unevenly); on larger tiles the branch costs more
+        // than it saves
+        if constexpr (TG::NW == 1) {
+          if (!__any(pass)) continue;
+        }
         const float Tn = T * (1.0f - al);
         const bool stop = pass && Tn < bp.t_min;
         const bool take = pass && !stop;
