@@ -266,15 +266,27 @@ size_t rade_normal_consistency_workspace(int64_t total_pixels);
  *   n~(p) = c / |c| oriented towards the camera (0 where c = 0),
  *   loss[v] = weight / n_interior * sum_p (alpha(p) - N(p) . n~(p)),
  * which equals Eq. 24's sum_i w_i (1 - n_i . n~) because alpha and N are the
- * blended weights and normals.  loss (V floats, device) is overwritten; the
- * gradient is ADDED to d_depth (plane 1 only), d_normal and d_alpha (same
- * planar layouts as the maps), so other loss terms can be accumulated there
- * first.  n~ is not detached: the gradient reaches the median depth. */
+ * blended weights and normals.  loss (V floats, device) is overwritten.  With
+ * accumulate != 0 the gradient is ADDED to d_depth (plane 1 only), d_normal
+ * and d_alpha (same planar layouts as the maps), so other loss terms can be
+ * accumulated there first; with accumulate == 0 the three maps are
+ * OVERWRITTEN (both depth planes; entries with no gradient become 0), with
+ * the same bits as adding into zeroed maps.  n~ is not detached: the
+ * gradient reaches the median depth. */
 int rade_normal_consistency(const rade_view* views_host, const rade_view* views_dev, int32_t V,
                             const float* depth, const float* normal, const float* alpha,
                             float weight, float* loss, float* d_depth, float* d_normal,
-                            float* d_alpha, void* workspace, size_t workspace_bytes,
-                            void* stream);
+                            float* d_alpha, int32_t accumulate, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
+/* Gradient of an L1 colour loss, the mean absolute difference of each
+ * view's three colour planes to a target (the colour term of the training
+ * loss, Sec. 4.1): d_color = weight * sign(color - target) / (3 W H) per
+ * view, OVERWRITTEN for every pixel (sign(0) = 0; a NaN difference stays
+ * NaN).  color, target, d_color: 3-plane maps of the V prepared views. */
+int rade_l1_color_grad(const rade_view* views_host, const rade_view* views_dev, int32_t V,
+                       const float* color, const float* target, float weight, float* d_color,
+                       void* stream);
 
 /* 3D smoothing filter (the Mip-Splatting filter the paper trains with,
  * Sec. 4.1).  For each Gaussian, rate = max over the views whose camera z >

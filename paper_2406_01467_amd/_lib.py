@@ -132,7 +132,10 @@ def load() -> ctypes.CDLL:
     lib.rade_set_kernel_events.argtypes = [ctypes.c_int, P, P]
     lib.rade_normal_consistency_workspace.argtypes = [I64]
     lib.rade_normal_consistency_workspace.restype = SZ
-    lib.rade_normal_consistency.argtypes = [P, P, I32] + [P] * 3 + [ctypes.c_float] + [P] * 5 + [SZ, P]
+    lib.rade_normal_consistency.argtypes = [P, P, I32] + [P] * 3 + [ctypes.c_float] + [P] * 4 + \
+        [I32, P, SZ, P]
+    lib.rade_l1_color_grad.argtypes = [P, P, I32, P, P, ctypes.c_float, P, P]
+    lib.rade_l1_color_grad.restype = ctypes.c_int
     lib.rade_normal_consistency.restype = ctypes.c_int
     lib.rade_set_kernel_events.restype = ctypes.c_int
     lib.rade_filter3d_var.argtypes = [P, P, I32, I64, P, ctypes.c_float, ctypes.c_float, P, P]
@@ -161,7 +164,7 @@ EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "ra
             "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
             "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
             "rade_tsdf_fuse", "rade_marching_cubes_workspace", "rade_marching_cubes",
-            "rade_marching_cubes_table"]
+            "rade_marching_cubes_table", "rade_l1_color_grad"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -317,11 +320,17 @@ def rade_normal_consistency_workspace(total_pixels: int) -> int:
 
 
 def rade_normal_consistency(views_c, views_dev, depth, normal, alpha, weight: float, loss, d_depth,
-                            d_normal, d_alpha, workspace, stream=None):
+                            d_normal, d_alpha, workspace, stream=None, accumulate: bool = True):
     return _check(load().rade_normal_consistency(
         views_c, _p(views_dev), len(views_c), _p(depth), _p(normal), _p(alpha), float(weight),
-        _p(loss), _p(d_depth), _p(d_normal), _p(d_alpha), _p(workspace),
+        _p(loss), _p(d_depth), _p(d_normal), _p(d_alpha), 1 if accumulate else 0, _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_normal_consistency")
+
+
+def rade_l1_color_grad(views_c, views_dev, color, target, weight: float, d_color, stream=None):
+    return _check(load().rade_l1_color_grad(views_c, _p(views_dev), len(views_c), _p(color),
+                                            _p(target), float(weight), _p(d_color),
+                                            _stream(stream)), "rade_l1_color_grad")
 
 
 def rade_filter3d_var(settings: Settings, views_dev, V: int, N: int, means, scale: float,

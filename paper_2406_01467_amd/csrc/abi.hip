@@ -39,11 +39,14 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
                              float* gsplat, hipStream_t st);
 size_t tile_order_workspace(int64_t tiles);
 size_t normal_consistency_workspace(int64_t total_pixels);
+hipError_t launch_l1_color_grad(const rade_view* views, int V, int64_t total, const float* color,
+                                const float* target, double weight, float* d_color,
+                                hipStream_t st);
 hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
                                      const float* depth, const float* normal,
                                      const float* alpha, float weight, float* loss,
-                                     float* d_depth, float* d_normal, float* d_alpha, void* ws,
-                                     hipStream_t st);
+                                     float* d_depth, float* d_normal, float* d_alpha,
+                                     bool accumulate, void* ws, hipStream_t st);
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st);
 hipError_t launch_filter3d_var(const rade_view* views, int V, int64_t N, const float* means,
@@ -233,11 +236,35 @@ size_t rade_normal_consistency_workspace(int64_t total_pixels) {
   return total_pixels < 0 ? 0 : rade::normal_consistency_workspace(total_pixels);
 }
 
+namespace {
+// Pixel total of prepared views (-1 if pix_offset does not follow the order).
+int64_t prepared_pixels(const rade_view* views_host, int32_t V) {
+  int64_t total = 0;
+  for (int i = 0; i < V; ++i) {
+    if (views_host[i].pix_offset != total) return -1;
+    total += (int64_t)views_host[i].width * views_host[i].height;
+  }
+  return total;
+}
+}  // namespace
+
+int rade_l1_color_grad(const rade_view* views_host, const rade_view* views_dev, int32_t V,
+                       const float* color, const float* target, float weight, float* d_color,
+                       void* stream) {
+  if (!views_ok(views_host, V) || !views_dev || !color || !target || !d_color ||
+      !std::isfinite(weight))
+    return RADE_ERR_INVALID_ARG;
+  const int64_t total = prepared_pixels(views_host, V);
+  if (total < 0) return RADE_ERR_INVALID_ARG;  // not prepared
+  return hip_status(rade::launch_l1_color_grad(views_dev, V, total, color, target,
+                                               (double)weight, d_color, (hipStream_t)stream));
+}
+
 int rade_normal_consistency(const rade_view* views_host, const rade_view* views_dev, int32_t V,
                             const float* depth, const float* normal, const float* alpha,
                             float weight, float* loss, float* d_depth, float* d_normal,
-                            float* d_alpha, void* workspace, size_t workspace_bytes,
-                            void* stream) {
+                            float* d_alpha, int32_t accumulate, void* workspace,
+                            size_t workspace_bytes, void* stream) {
   if (!views_ok(views_host, V) || !views_dev || !depth || !normal || !alpha || !loss ||
       !d_depth || !d_normal || !d_alpha || !std::isfinite(weight))
     return RADE_ERR_INVALID_ARG;
@@ -250,7 +277,8 @@ int rade_normal_consistency(const rade_view* views_host, const rade_view* views_
     return RADE_ERR_WORKSPACE;
   return hip_status(rade::launch_normal_consistency(views_dev, V, total, depth, normal, alpha,
                                                     weight, loss, d_depth, d_normal, d_alpha,
-                                                    workspace, (hipStream_t)stream));
+                                                    accumulate != 0, workspace,
+                                                    (hipStream_t)stream));
 }
 
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,

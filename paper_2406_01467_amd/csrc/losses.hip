@@ -24,7 +24,10 @@ __device__ __forceinline__ int view_of_pixel(const rade_view* views, int V, int6
 }
 
 // Pass 1: per interior pixel, the loss term, dL/dA, dL/dN and the gradients
-// of the two difference vectors (6 floats, kept for pass 2).
+// of the two difference vectors (6 floats, kept for pass 2).  ACC adds the
+// gradients into the maps; otherwise every pixel's entries are written
+// (0 + x, so the bits equal adding into zeroed maps; border pixels get 0).
+template <bool ACC>
 __global__ void __launch_bounds__(kT)
 k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const float* __restrict__ depth,
            const float* __restrict__ normal, const float* __restrict__ alpha, float weight,
@@ -43,6 +46,12 @@ k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const floa
     const bool interior = px >= 1 && py >= 1 && px <= vw.width - 2 && py <= vw.height - 2;
     if (!interior) {
       for (int k = 0; k < 6; ++k) gd[k] = 0.0f;
+      if constexpr (!ACC) {
+        d_alpha[o + pix] = 0.0f;
+        d_normal[3 * o + pix] = 0.0f;
+        d_normal[3 * o + P + pix] = 0.0f;
+        d_normal[3 * o + 2 * P + pix] = 0.0f;
+      }
     } else {
       const float wn = weight / (float)((vw.width - 2) * (vw.height - 2));
       const float* Dm = depth + 2 * o + P;  // median plane
@@ -84,10 +93,14 @@ k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const floa
       gd[3] = gc[1] * du[2] - gc[2] * du[1];
       gd[4] = gc[2] * du[0] - gc[0] * du[2];
       gd[5] = gc[0] * du[1] - gc[1] * du[0];
-      d_alpha[o + pix] += wn;
-      d_normal[3 * o + pix] -= wn * nt[0];
-      d_normal[3 * o + P + pix] -= wn * nt[1];
-      d_normal[3 * o + 2 * P + pix] -= wn * nt[2];
+      const float a0 = ACC ? d_alpha[o + pix] : 0.0f;
+      const float n0 = ACC ? d_normal[3 * o + pix] : 0.0f;
+      const float n1 = ACC ? d_normal[3 * o + P + pix] : 0.0f;
+      const float n2 = ACC ? d_normal[3 * o + 2 * P + pix] : 0.0f;
+      d_alpha[o + pix] = a0 + wn;
+      d_normal[3 * o + pix] = n0 - wn * nt[0];
+      d_normal[3 * o + P + pix] = n1 - wn * nt[1];
+      d_normal[3 * o + 2 * P + pix] = n2 - wn * nt[2];
       term *= wn;
     }
   }
@@ -140,6 +153,8 @@ k_nc_sum(const rade_view* __restrict__ views, const float* __restrict__ partial,
 }
 
 // Pass 2: dL/dD_med(q) = r(q) . (g_du(q-x) - g_du(q+x) + g_dv(q-y) - g_dv(q+y)).
+// Without ACC both depth planes are written (the expected-depth plane gets 0).
+template <bool ACC>
 __global__ void __launch_bounds__(kT)
 k_nc_pass2(const rade_view* __restrict__ views, int V, int64_t total,
            const float* __restrict__ gdiff, float* __restrict__ d_depth) {
@@ -158,7 +173,30 @@ k_nc_pass2(const rade_view* __restrict__ views, int V, int64_t total,
   if (py + 1 < vw.height) for (int k = 0; k < 3; ++k) g[k] -= gdiff[6 * (q + vw.width) + 3 + k];
   const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
   const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
-  d_depth[2 * o + P + pix] += g[0] * rx + g[1] * ry + g[2];
+  const float prev = ACC ? d_depth[2 * o + P + pix] : 0.0f;
+  d_depth[2 * o + P + pix] = prev + (g[0] * rx + g[1] * ry + g[2]);
+  if constexpr (!ACC) d_depth[2 * o + pix] = 0.0f;
+}
+
+// Gradient of the mean absolute colour difference of each view (3 planes):
+// d_color = weight sign(color - target) / (3 W H), written for every pixel.
+__global__ void __launch_bounds__(kT)
+k_l1_color_grad(const rade_view* __restrict__ views, int V, int64_t total,
+                const float* __restrict__ color, const float* __restrict__ target, double weight,
+                float* __restrict__ d_color) {
+  const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (q >= total) return;
+  const rade_view& vw = views[view_of_pixel(views, V, q)];
+  const int64_t o = vw.pix_offset, P = (int64_t)vw.width * vw.height;
+  const int64_t pix = q - o;
+  const float w = (float)(weight / (3.0 * (double)P));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t i = 3 * o + c * P + pix;
+    const float d = color[i] - target[i];
+    const float s = d > 0.0f ? 1.0f : d < 0.0f ? -1.0f : d;  // sign, NaN kept
+    d_color[i] = s * w;
+  }
 }
 
 __global__ void k_zero_f(float* __restrict__ a, int n) {
@@ -176,17 +214,35 @@ size_t normal_consistency_workspace(int64_t total_pixels) {
 hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
                                      const float* depth, const float* normal,
                                      const float* alpha, float weight, float* loss,
-                                     float* d_depth, float* d_normal, float* d_alpha, void* ws,
-                                     hipStream_t st) {
+                                     float* d_depth, float* d_normal, float* d_alpha,
+                                     bool accumulate, void* ws, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_f, dim3((V + 255) / 256), dim3(256), 0, st, loss, V);
   if (total == 0) return hipGetLastError();
   float* gdiff = static_cast<float*>(ws);
   const unsigned blocks = (unsigned)((total + kT - 1) / kT);
   float* partial = gdiff + 6 * total;
-  hipLaunchKernelGGL(k_nc_pass1, dim3(blocks), dim3(kT), 0, st, views, V, total, depth, normal,
-                     alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
+  if (accumulate)
+    hipLaunchKernelGGL(k_nc_pass1<true>, dim3(blocks), dim3(kT), 0, st, views, V, total, depth,
+                       normal, alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
+  else
+    hipLaunchKernelGGL(k_nc_pass1<false>, dim3(blocks), dim3(kT), 0, st, views, V, total, depth,
+                       normal, alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
   hipLaunchKernelGGL(k_nc_sum, dim3(V, kSumChunks), dim3(kT), 0, st, views, partial, loss);
-  hipLaunchKernelGGL(k_nc_pass2, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff, d_depth);
+  if (accumulate)
+    hipLaunchKernelGGL(k_nc_pass2<true>, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff,
+                       d_depth);
+  else
+    hipLaunchKernelGGL(k_nc_pass2<false>, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff,
+                       d_depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_color_grad(const rade_view* views, int V, int64_t total, const float* color,
+                                const float* target, double weight, float* d_color,
+                                hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_l1_color_grad, dim3((unsigned)((total + kT - 1) / kT)), dim3(kT), 0, st,
+                     views, V, total, color, target, weight, d_color);
   return hipGetLastError();
 }
 

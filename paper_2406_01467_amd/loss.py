@@ -6,9 +6,9 @@ pixels of the depth distortion of Eq. 23 (w_d = 100 in Sec. 4.1; its
 gradient holds the blend weights constant).
 
 `make_grad_fn` returns the upstream gradients into pre-allocated buffers
-(torch elementwise ops for L1, the library's fused kernel for Eq. 24), safe
-under HIP-graph capture; `torch_loss` is the same loss in torch ops for the
-autograd path.
+(the library's kernels for the L1 term and for Eq. 24, both writing their
+maps whole, so nothing is cleared first), safe under HIP-graph capture;
+`torch_loss` is the same loss in torch ops for the autograd path.
 """
 from __future__ import annotations
 
@@ -23,19 +23,13 @@ W_DIST = 100.0
 
 def make_grad_fn(rast, target, w_normal: float = W_NORMAL, w_dist: float = 0.0):
     """Upstream gradients of the benchmark loss into pre-allocated buffers:
-    L1 colour (torch elementwise, mean per view) + w_normal x Eq. 24 (fused
-    library kernel) [+ w_dist x mean distortion (Eq. 23): a constant
-    gradient map, returned fifth].  Safe inside a HIP graph: no allocation,
-    no host sync."""
+    L1 colour (library kernel, mean per view) + w_normal x Eq. 24 (fused
+    library kernel, overwriting the depth, normal and alpha gradient maps)
+    [+ w_dist x mean distortion (Eq. 23): a constant gradient map, returned
+    fifth].  Safe inside a HIP graph: no allocation, no host sync."""
     dev, P = rast.device, rast.total_pixels
-    wvec = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    for vc in rast.views_c:
-        n = vc.width * vc.height
-        wvec[3 * vc.pix_offset: 3 * vc.pix_offset + 3 * n] = 1.0 / (3 * n)
-    tmp = torch.empty(3 * P, dtype=torch.float32, device=dev)
+    target = target.contiguous()
     dC = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    # dD, dN, dA share one buffer so one fill clears them before the Eq. 24
-    # kernel adds into them
     dDNA = torch.empty(6 * P, dtype=torch.float32, device=dev)
     dD, dN, dA = dDNA[:2 * P], dDNA[2 * P:5 * P], dDNA[5 * P:]
     loss = torch.empty(rast.V, dtype=torch.float32, device=dev)
@@ -49,12 +43,10 @@ def make_grad_fn(rast, target, w_normal: float = W_NORMAL, w_dist: float = 0.0):
                      device=dev)
 
     def grad_fn(maps):
-        torch.sub(maps["color"], target, out=tmp)
-        torch.sign(tmp, out=tmp)
-        torch.mul(tmp, wvec, out=dC)
-        dDNA.zero_()
+        _lib.rade_l1_color_grad(rast.views_c, rast.views_dev, maps["color"], target, 1.0, dC)
         _lib.rade_normal_consistency(rast.views_c, rast.views_dev, maps["depth"], maps["normal"],
-                                     maps["alpha"], w_normal, loss, dD, dN, dA, ws)
+                                     maps["alpha"], w_normal, loss, dD, dN, dA, ws,
+                                     accumulate=False)
         if dL is not None:
             return dC, dD, dN, dA, dL
         return dC, dD, dN, dA

@@ -49,6 +49,15 @@ def _run(views, depth, normal, alpha, weight, dev):
     np.testing.assert_allclose(l1, l0, rtol=1e-6)  # order of the FP32 atomic adds may differ
     for a, b, z in zip(g0, g1, b1):
         assert np.array_equal(b, (z + a).astype(np.float32))  # accumulated, not overwritten
+    # overwrite mode: whatever the maps held (NaN here), the result has the
+    # bits of the accumulation into zeroed maps
+    loss = torch.zeros(len(views), device=dev)
+    gD, gN, gA = (torch.full((k * P,), float("nan"), device=dev) for k in (2, 3, 1))
+    _lib.rade_normal_consistency(vc, vdev, D, N, A, weight, loss, gD, gN, gA, ws,
+                                 accumulate=False)
+    torch.cuda.synchronize()
+    for a, b in zip(g0, (gD, gN, gA)):
+        assert np.array_equal(a.view(np.uint32), b.cpu().numpy().view(np.uint32))
     return l0, g0[0], g0[1], g0[2], vc
 
 
@@ -97,3 +106,34 @@ def test_normal_consistency_smooth_surface():
     _check(gD[H * W:].reshape(H, W), rD, "d depth_med", mag=mD)
     _check(gN.reshape(3, H, W), rN, "d normal")
     _check(gA.reshape(H, W), rA, "d alpha")
+
+
+def test_l1_color_gradient_matches_its_definition():
+    """weight sign(C - T) / (3 W H) per view, written over every pixel
+    (NaN-filled output), bit for bit the torch expression of the same
+    definition; ties give 0."""
+    import torch
+    from paper_2406_01467_amd import _lib
+    dev = device()
+    views = [synth.identity_view(37, 23), synth.identity_view(64, 48), synth.identity_view(5, 7)]
+    vc = _lib.make_views(views)
+    P, _ = _lib.rade_views_prepare(_lib.Settings(), vc)
+    vdev = _lib.views_to_device(vc, dev)
+    rng = np.random.default_rng(19)
+    C = rng.uniform(0, 1, 3 * P).astype(np.float32)
+    T = rng.uniform(0, 1, 3 * P).astype(np.float32)
+    T[::5] = C[::5]  # ties
+    Cd, Td = torch.from_numpy(C).to(dev), torch.from_numpy(T).to(dev)
+    for weight in (1.0, 0.37):
+        out = torch.full((3 * P,), float("nan"), device=dev)
+        _lib.rade_l1_color_grad(vc, vdev, Cd, Td, weight, out)
+        torch.cuda.synchronize()
+        want = np.zeros(3 * P, np.float32)
+        for v in vc:
+            n = v.width * v.height
+            sl = slice(3 * v.pix_offset, 3 * v.pix_offset + 3 * n)
+            w = np.float32(float(np.float32(weight)) / (3.0 * n))
+            want[sl] = np.sign(C[sl] - T[sl]).astype(np.float32) * w
+        got = out.cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), weight
+        assert (got == 0).sum() >= 3 * P // 5
