@@ -25,6 +25,7 @@ timed on a bounded pixel sample.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -295,9 +296,11 @@ def main():
                                      distortion=args.distortion)
     rast = Rasterizer(views, settings, dev)
 
-    # blends and pairs per step (deterministic for fixed inputs)
+    # blends and pairs per step (deterministic for fixed inputs; the blend
+    # count is compiled for the default wave shape, and does not depend on it)
     with torch.no_grad():
-        maps = rast.forward(*params, want_count=True)
+        counter = Rasterizer(views, dataclasses.replace(settings, wave_w=0, batch=0), dev)
+        maps = counter.forward(*params, want_count=True)
         torch.cuda.synchronize()
         blends = int(maps.count.sum().item())
         pairs = int(maps.state.n_pairs)
@@ -410,6 +413,8 @@ def main():
         "config": {"workload": args.workload, "gaussians": scene.n, "views": V,
                    "pixels": rast.total_pixels, "sh_degree": scene.sh_degree,
                    "tile": f"{settings.tile_w}x{settings.tile_h}",
+                   "wave": f"{settings.wave_w or 8}x{64 // (settings.wave_w or 8)}",
+                   "batch": settings.batch or settings.tile_w * settings.tile_h,
                    "schedule": settings.schedule,
                    "loss": "L1 colour + 5 x normal consistency (Eq. 24, median depth)" +
                            (" + 100 x depth distortion (Eq. 23)" if args.distortion else ""),

@@ -81,6 +81,15 @@ typedef struct rade_settings {
   double degenerate;       /* q := 0 when det(B0) <= degenerate * tr(B0)^2 (1e-6) */
   double bg[3];            /* background colour, blended with the final transmittance */
   int32_t depth_mode;      /* RADE_DEPTH_*: per-pixel depth of Eq. 4 or of Eq. 7 */
+  int32_t wave_w;          /* pixels per wavefront row: 8 (8x8), 16 (16x4) or 32 (32x2);
+                              0 = 8.  The blocks must tile the tile exactly. */
+  int32_t batch;           /* splats staged per round: 64, 128 or 256; 0 = one per thread
+                              of the tile workgroup (tile_w * tile_h).  Shapes other than
+                              8x8 waves with one splat per thread are compiled for the
+                              plain forward and backward only: with a distortion map, a
+                              blend count or the exact depth, the render calls return
+                              RADE_ERR_INVALID_ARG.  Maps do not depend on either field;
+                              gradients only up to the order of FP32 additions. */
   int32_t reserved;        /* must be 0 */
 } rade_settings;
 
@@ -390,7 +399,7 @@ int rade_set_kernel_events(int kernel, void* start_event, void* stop_event);
 /* Static description of an error code (never NULL). */
 const char* rade_strerror(int code);
 
-/* ABI version of this header: 3. */
+/* ABI version of this header: 4. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

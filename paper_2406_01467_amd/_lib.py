@@ -50,6 +50,7 @@ class CSettings(ctypes.Structure):
                 ("t_min", ctypes.c_double), ("power_cut", ctypes.c_double),
                 ("fov_clamp", ctypes.c_double), ("degenerate", ctypes.c_double),
                 ("bg", ctypes.c_double * 3), ("depth_mode", ctypes.c_int32),
+                ("wave_w", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -61,7 +62,7 @@ class CView(ctypes.Structure):
                 ("pix_offset", ctypes.c_int64), ("tile_offset", ctypes.c_int64)]
 
 
-assert ctypes.sizeof(CView) == 96 and ctypes.sizeof(CSettings) == 112
+assert ctypes.sizeof(CView) == 96 and ctypes.sizeof(CSettings) == 120
 
 RADE_DEPTH_AFFINE, RADE_DEPTH_EXACT = 0, 1
 
@@ -83,6 +84,8 @@ class Settings:
     degenerate: float = 1e-6
     bg: tuple = (0.0, 0.0, 0.0)
     depth_mode: int = 0        # RADE_DEPTH_AFFINE (Eq. 4) or RADE_DEPTH_EXACT (Eq. 7, forward only)
+    wave_w: int = 0            # pixels per wave row: 8 (8x8), 16 (16x4), 32 (32x2); 0 = 8
+    batch: int = 0             # splats staged per round: 64..512; 0 = tile_w * tile_h
 
     def c(self) -> CSettings:
         s = CSettings()
@@ -93,12 +96,12 @@ class Settings:
         s.power_cut, s.fov_clamp, s.degenerate = self.power_cut, self.fov_clamp, self.degenerate
         for i in range(3):
             s.bg[i] = float(self.bg[i])
-        s.depth_mode, s.reserved = self.depth_mode, 0
+        s.depth_mode, s.wave_w, s.batch, s.reserved = self.depth_mode, self.wave_w, self.batch, 0
         return s
 
 
 _lib = None
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 def load() -> ctypes.CDLL:

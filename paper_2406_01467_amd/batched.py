@@ -1,6 +1,7 @@
 """Batched multi-view rendering: one launch per kernel over many views of
 uneven size, the whole forward + backward captured in a HIP graph, and an
-autotuner for the tile size and the work schedule.
+autotuner for the tile size, the work schedule, the wave shape and the staging
+batch.
 
 All views share one key space (global tile = view's tile offset + tile), so
 each kernel of the path is launched once for the whole batch; the render
@@ -180,13 +181,26 @@ def signature(views: Sequence, n: int, sh_degree: int) -> str:
     return f"{dev}|{h.hexdigest()[:16]}"
 
 
+WAVE_WIDTHS = (8, 16, 32)   # 8x8, 16x4, 32x2 pixels per wavefront
+BATCHES = (0, 64, 128, 256)  # splats staged per round (0: one per thread)
+
+
+def _shape_fits(tw: int, th: int, ww: int) -> bool:
+    return tw % ww == 0 and th % (64 // ww) == 0
+
+
 def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, grad_fn: Callable,
-             tiles=TILES, schedules=SCHEDULES, reps: int = 3, use_cache: bool = True,
-             log: Optional[Callable] = None, distortion: bool = False) -> tuple:
-    """Time the graph-replayed fwd+bwd for every (tile, schedule) candidate
-    and return (best Settings, {candidate: ms}).  Results are cached in a JSON
-    file keyed by device name and workload signature."""
+             tiles=TILES, schedules=SCHEDULES, wave_widths=WAVE_WIDTHS, batches=BATCHES,
+             reps: int = 3, use_cache: bool = True, log: Optional[Callable] = None,
+             distortion: bool = False) -> tuple:
+    """Time the graph-replayed fwd+bwd over the candidates and return (best
+    Settings, {candidate: ms}).  Two stages: every (tile, schedule), then,
+    for the best of those, every wave shape the tile holds x staging batch
+    (these exist for the plain path only, so not with the distortion term).
+    Results are cached in a JSON file keyed by device name and workload
+    signature."""
     sig = signature(views, params[0].shape[0], base.sh_degree) + ("|dist" if distortion else "")
+    sig += "|shape"
     path = _cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -198,30 +212,49 @@ def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, gr
     if use_cache and sig in cache:
         c = cache[sig]
         return Settings(**{**base.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"],
-                           "schedule": c["schedule"]}), c.get("timings", {})
+                           "schedule": c["schedule"], "wave_w": c.get("wave_w", 0),
+                           "batch": c.get("batch", 0)}), c.get("timings", {})
     timings = {}
+
+    def timed(st: Settings, key: str) -> float:
+        plan = BatchedPlan(views, st, params, grad_fn, distortion=distortion)
+        plan.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.replay()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        del plan
+        timings[key] = ms
+        if log:
+            log(f"autotune {key}: {ms:.3f} ms")
+        return ms
+
     best = None
     for tw, th in tiles:
         for sch in schedules:
-            st = Settings(**{**base.__dict__, "tile_w": tw, "tile_h": th, "schedule": sch})
-            plan = BatchedPlan(views, st, params, grad_fn, distortion=distortion)
-            plan.step()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                plan.replay()
-            torch.cuda.synchronize()
-            ms = 1e3 * (time.perf_counter() - t0) / reps
-            key = f"{tw}x{th}/{sch}"
-            timings[key] = ms
-            if log:
-                log(f"autotune {key}: {ms:.3f} ms")
+            st = Settings(**{**base.__dict__, "tile_w": tw, "tile_h": th, "schedule": sch,
+                             "wave_w": 0, "batch": 0})
+            ms = timed(st, f"{tw}x{th}/{sch}")
             if best is None or ms < best[0]:
                 best = (ms, st)
-            del plan
+    if not distortion:
+        b = best[1]
+        for ww in wave_widths:
+            if not _shape_fits(b.tile_w, b.tile_h, ww):
+                continue
+            for bt in batches:
+                if (ww == 8 and bt in (0, b.tile_w * b.tile_h)):
+                    continue  # the default shape, timed in the first stage
+                st = Settings(**{**b.__dict__, "wave_w": ww, "batch": bt})
+                ms = timed(st, f"{b.tile_w}x{b.tile_h}/{b.schedule}/w{ww}/b{bt}")
+                if ms < best[0]:
+                    best = (ms, st)
     if use_cache:
         cache[sig] = dict(tile_w=best[1].tile_w, tile_h=best[1].tile_h,
-                          schedule=best[1].schedule, timings=timings)
+                          schedule=best[1].schedule, wave_w=best[1].wave_w,
+                          batch=best[1].batch, timings=timings)
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path, "w") as f:

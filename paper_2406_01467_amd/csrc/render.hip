@@ -39,13 +39,21 @@
 namespace rade {
 namespace {
 
-template <int TW, int TH>
+// Tile of TW x TH pixels, wavefronts of WW x WH = 64 pixels (row-major in
+// the tile), BATCH splats staged per round (0: one per thread), in NCH
+// chunks of 64.
+template <int TW, int TH, int WW = 8, int BATCH_ = 0>
 struct TileGeom {
-  static constexpr int NWX = TW / 8;
-  static constexpr int NWY = TH / 8;
+  static constexpr int WH = 64 / WW;
+  static constexpr int LW = WW == 32 ? 5 : WW == 16 ? 4 : 3;
+  static constexpr int NWX = TW / WW;
+  static constexpr int NWY = TH / WH;
   static constexpr int NW = NWX * NWY;
   static constexpr int BLOCK = 64 * NW;
-  static_assert(TW % 8 == 0 && TH % 8 == 0 && BLOCK <= 1024, "tile");
+  static constexpr int BATCH = BATCH_ > 0 ? BATCH_ : BLOCK;
+  static constexpr int NCH = BATCH / 64;
+  static_assert(WW == 8 || WW == 16 || WW == 32, "wave width");
+  static_assert(TW % WW == 0 && TH % WH == 0 && BLOCK <= 1024 && BATCH % 64 == 0, "tile");
 };
 
 // A value every lane of the wavefront holds alike, moved to scalar registers
@@ -102,10 +110,10 @@ struct BwdArgs {
   float* gsplat;
 };
 
-template <int TW, int TH>
+template <int TW, int TH, int WW, int BT>
 __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
                                               const uint32_t* ranges, int64_t tile) {
-  using TG = TileGeom<TW, TH>;
+  using TG = TileGeom<TW, TH, WW, BT>;
   PixelCtx c;
   c.tile = tile;
   c.v = view_of_tile(views, V, c.tile);
@@ -115,8 +123,8 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
   c.x0 = tx * TW;
   c.y0 = ty * TH;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  c.lxi = 8 * (wave % TG::NWX) + (lane & 7);
-  c.lyi = 8 * (wave / TG::NWX) + (lane >> 3);
+  c.lxi = WW * (wave % TG::NWX) + (lane & (WW - 1));
+  c.lyi = TG::WH * (wave / TG::NWX) + (lane >> TG::LW);
   c.px = c.x0 + c.lxi;
   c.py = c.y0 + c.lyi;
   c.inside = c.px < vw.width && c.py < vw.height;
@@ -128,8 +136,8 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
   return c;
 }
 
-// Does the splat's support reach the 8x8 block of pixel offsets [bx, bx+7] x
-// [by, by+7] (relative to the tile's first pixel centre)?  The factored
+// Does the splat's support reach the block of pixel offsets [bx, bx+bw-1] x
+// [by, by+bh-1] (relative to the tile's first pixel centre)?  The factored
 // power Q = (w0 dx + w1 dy)^2 + (w2 dx + w3 dy)^2, dx = ur - x, dy = vr - y,
 // is convex, so its minimum over the block's rectangle is 0 when the centre
 // lies inside and is otherwise reached on an edge, where it is a 1-D
@@ -138,9 +146,10 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
 // skipping a block must never drop a blend the pixel loop would take).
 __device__ __forceinline__ bool block_reached(float ur, float vr, float w0, float w1, float w2,
                                               float w3, float A, float B, float C, float invA,
-                                              float invC, float tau2, int bx, int by) {
-  const float xlo = ur - (float)(bx + 7), xhi = ur - (float)bx;
-  const float ylo = vr - (float)(by + 7), yhi = vr - (float)by;
+                                              float invC, float tau2, int bx, int by, int bw,
+                                              int bh) {
+  const float xlo = ur - (float)(bx + bw - 1), xhi = ur - (float)bx;
+  const float ylo = vr - (float)(by + bh - 1), yhi = vr - (float)by;
   if (xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f) return true;
   auto q = [&](float dx, float dy) {
     const float t1 = fmaf(w0, dx, w1 * dy), t2 = fmaf(w2, dx, w3 * dy);
@@ -158,15 +167,15 @@ __device__ __forceinline__ bool block_reached(float ur, float vr, float w0, floa
   return m <= tau2;
 }
 
-// Stage splat `idx` of the tile list into LDS slot threadIdx.x and return
-// the bit set of 8x8 blocks its support reaches (support rect first, then
-// the exact ellipse-against-block test).
-template <int TW, int TH>
+// Stage splat `idx` of the tile list into LDS slot `slot` and return the
+// bit set of wave blocks its support reaches (support rect first, then the
+// exact ellipse-against-block test).
+template <int TW, int TH, int WW, int BT>
 __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats, int64_t vbase,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
-                                          const PixelCtx& c, const BlendParams& bp,
+                                          int slot, const PixelCtx& c, const BlendParams& bp,
                                           StagedSplat* ss, uint32_t* sgid) {
-  using TG = TileGeom<TW, TH>;
+  using TG = TileGeom<TW, TH, WW, BT>;
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
   StagedSplat s;
@@ -177,15 +186,15 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
   s.r = sp.rgb[0]; s.g = sp.rgb[1]; s.b = sp.rgb[2];
   s.p0 = sp.p[0]; s.p1 = sp.p[1];
   s.n0 = sp.n[0]; s.n1 = sp.n[1]; s.n2 = sp.n[2];
-  ss[threadIdx.x] = s;
-  sgid[threadIdx.x] = g;
+  ss[slot] = s;
+  sgid[slot] = g;
   const int rx0 = sp.rect[0] - c.x0, rx1 = sp.rect[1] - c.x0;
   const int ry0 = sp.rect[2] - c.y0, ry1 = sp.rect[3] - c.y0;
   uint32_t bits = 0;
 #pragma unroll
   for (int k = 0; k < TG::NW; ++k) {
-    const int bx = 8 * (k % TG::NWX), by = 8 * (k / TG::NWX);
-    if (rx0 <= bx + 7 && rx1 >= bx && ry0 <= by + 7 && ry1 >= by) bits |= 1u << k;
+    const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
+    if (rx0 <= bx + WW - 1 && rx1 >= bx && ry0 <= by + TG::WH - 1 && ry1 >= by) bits |= 1u << k;
   }
   if (bits) {
     // drop the blocks the ellipse misses (also when the rect touches a
@@ -199,50 +208,55 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     const float tau2 = fminf(bp.cut2, lo) * 1.001f + 0.01f;
 #pragma unroll
     for (int k = 0; k < TG::NW; ++k) {
-      const int bx = 8 * (k % TG::NWX), by = 8 * (k / TG::NWX);
-      if (((bits >> k) & 1u) &&
-          !block_reached(s.ur, s.vr, s.w0, s.w1, s.w2, s.w3, A, B, C, invA, invC, tau2, bx, by))
+      const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
+      if (((bits >> k) & 1u) && !block_reached(s.ur, s.vr, s.w0, s.w1, s.w2, s.w3, A, B, C, invA,
+                                               invC, tau2, bx, by, WW, TG::WH))
         bits &= ~(1u << k);
     }
   }
   return bits;
 }
 
-template <int TW, int TH>
-__device__ __forceinline__ void publish_masks(uint32_t bits, uint64_t (*masks)[TileGeom<TW, TH>::NW]) {
-  using TG = TileGeom<TW, TH>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// masks[k][chunk]: which splats of a chunk of 64 staged ones reach wave k's
+// block (called by whole waves: the ballot needs every lane).
+template <int TW, int TH, int WW, int BT>
+__device__ __forceinline__ void publish_masks(
+    uint32_t bits, int chunk,
+    uint64_t (*masks)[TileGeom<TW, TH, WW, BT>::NCH]) {
+  using TG = TileGeom<TW, TH, WW, BT>;
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < TG::NW; ++k) {
     const uint64_t m = __ballot((bits >> k) & 1u);
-    if (lane == 0) masks[k][wave] = m;
+    if (lane == 0) masks[k][chunk] = m;
   }
 }
 
-template <int TW, int TH, bool EXACT>
+template <int TW, int TH, bool EXACT, int WW, int BT>
 struct FwdShared {
-  StagedSplat ss[TileGeom<TW, TH>::BLOCK];
-  uint32_t sgid[TileGeom<TW, TH>::BLOCK];
-  uint64_t masks[TileGeom<TW, TH>::NW][TileGeom<TW, TH>::NW];
+  using TG = TileGeom<TW, TH, WW, BT>;
+  StagedSplat ss[TG::BATCH];
+  uint32_t sgid[TG::BATCH];
+  uint64_t masks[TG::NW][TG::NCH];
   // EXACT: the ray-maximum depth terms (g0, g1, H00, H01) and H11
-  float4 xq[EXACT ? TileGeom<TW, TH>::BLOCK : 1];
-  float xh[EXACT ? TileGeom<TW, TH>::BLOCK : 1];
+  float4 xq[EXACT ? TG::BATCH : 1];
+  float xh[EXACT ? TG::BATCH : 1];
 };
 
 // Forward blend of one tile (all threads of the workgroup take part).  DIST:
 // also the distortion map; CNT: also the blend-count map; EXACT: per-pixel
 // depth of the ray maximum (Eq. 7) instead of the plane of Eq. 4.
-template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT, int WW, int BT>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
-                                         FwdShared<TW, TH, EXACT>& sh) {
-  using TG = TileGeom<TW, TH>;
+                                         FwdShared<TW, TH, EXACT, WW, BT>& sh) {
+  using TG = TileGeom<TW, TH, WW, BT>;
   const BlendParams& bp = a.bp;
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
   StagedSplat* ss = sh.ss;
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
-  const PixelCtx c = pixel_ctx<TW, TH>(a.views, a.V, a.ranges, tile);
+  const PixelCtx c = pixel_ctx<TW, TH, WW, BT>(a.views, a.V, a.ranges, tile);
   const int wave = wave_index();
   const int64_t vbase = (int64_t)c.v * a.N;
   const float fx = (float)c.lxi, fy = (float)c.lyi;
@@ -253,22 +267,28 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   int cnt = 0, lastp = -1, medp = -1;
   bool done = !c.inside;
 
-  for (uint32_t b0 = c.rb; b0 < c.re; b0 += TG::BLOCK) {
+  for (uint32_t b0 = c.rb; b0 < c.re; b0 += TG::BATCH) {
     if (__syncthreads_and(done ? 1 : 0)) break;
-    const uint32_t idx = b0 + threadIdx.x;
-    uint32_t bits = 0;
-    if (idx < c.re) {
-      bits = stage<TW, TH>(splats, vbase, pair_ids, idx, c, bp, ss, sgid);
-      if constexpr (EXACT) {
-        const float4* q = a.depth_quad + 2 * (vbase + sgid[threadIdx.x]);
-        sh.xq[threadIdx.x] = q[0];
-        sh.xh[threadIdx.x] = q[1].x;
+    // stage the batch: slot = thread + k * BLOCK (each wave's slots share a chunk)
+#pragma unroll
+    for (int k = 0; k < (TG::BATCH + TG::BLOCK - 1) / TG::BLOCK; ++k) {
+      const int slot = (int)threadIdx.x + k * TG::BLOCK;
+      if (TG::BATCH % TG::BLOCK != 0 && slot >= TG::BATCH) break;  // wave-uniform
+      const uint32_t idx = b0 + (uint32_t)slot;
+      uint32_t bits = 0;
+      if (idx < c.re) {
+        bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, idx, slot, c, bp, ss, sgid);
+        if constexpr (EXACT) {
+          const float4* q = a.depth_quad + 2 * (vbase + sgid[slot]);
+          sh.xq[slot] = q[0];
+          sh.xh[slot] = q[1].x;
+        }
       }
+      publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
-    publish_masks<TW, TH>(bits, masks);
     __syncthreads();
     bool wave_live = !__all(done);
-    for (int cw = 0; cw < TG::NW && wave_live; ++cw) {
+    for (int cw = 0; cw < TG::NCH && wave_live; ++cw) {
       uint64_t m = uniform_u64(masks[wave][cw]);
       while (m) {
         const int j = __builtin_ctzll(m);
@@ -350,19 +370,19 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
 }
 
 // One workgroup per tile, tiles visited in `order` (or natural) order.
-template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT, int WW, int BT>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd(FwdArgs a) {
-  __shared__ FwdShared<TW, TH, EXACT> sh;
+  __shared__ FwdShared<TW, TH, EXACT, WW, BT> sh;
   const int64_t i = blockIdx.x;
-  fwd_tile<TW, TH, DIST, CNT, EXACT>(a, a.order ? (int64_t)a.order[i] : i, sh);
+  fwd_tile<TW, TH, DIST, CNT, EXACT, WW, BT>(a, a.order ? (int64_t)a.order[i] : i, sh);
 }
 
 // Persistent workgroups pull tiles from a device counter (zeroed before the
 // launch) in `order`; every workgroup exits once the counter passes the tile
 // count.
-template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT, int WW, int BT>
 __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
-  __shared__ FwdShared<TW, TH, EXACT> sh;
+  __shared__ FwdShared<TW, TH, EXACT, WW, BT> sh;
   __shared__ uint32_t item_s;
   for (;;) {
     if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1u);
@@ -370,7 +390,8 @@ __global__ void __launch_bounds__(TW * TH) k_render_fwd_persistent(FwdArgs a) {
     const uint32_t item = item_s;
     __syncthreads();
     if ((int64_t)item >= a.tiles) break;
-    fwd_tile<TW, TH, DIST, CNT, EXACT>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+    fwd_tile<TW, TH, DIST, CNT, EXACT, WW, BT>(a, a.order ? (int64_t)a.order[item] : (int64_t)item,
+                                               sh);
   }
 }
 
@@ -420,18 +441,20 @@ __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
 
 constexpr float kTwoOverLog2e = 2.0f / kLog2e;
 
-template <int TW, int TH>
+template <int TW, int TH, int WW, int BT>
 struct BwdShared {
-  StagedSplat ss[TileGeom<TW, TH>::BLOCK];
-  uint32_t sgid[TileGeom<TW, TH>::BLOCK];
-  uint64_t masks[TileGeom<TW, TH>::NW][TileGeom<TW, TH>::NW];
+  using TG = TileGeom<TW, TH, WW, BT>;
+  StagedSplat ss[TG::BATCH];
+  uint32_t sgid[TG::BATCH];
+  uint64_t masks[TG::NW][TG::NCH];
   int smax;
 };
 
 // Backward pass of one tile (all threads of the workgroup take part).
-template <int TW, int TH, bool DIST>
-__device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShared<TW, TH>& sh) {
-  using TG = TileGeom<TW, TH>;
+template <int TW, int TH, bool DIST, int WW, int BT>
+__device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
+                                         BwdShared<TW, TH, WW, BT>& sh) {
+  using TG = TileGeom<TW, TH, WW, BT>;
   const BlendParams& bp = a.bp;
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
@@ -447,7 +470,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
   int& smax = sh.smax;
-  const PixelCtx c = pixel_ctx<TW, TH>(a.views, a.V, a.ranges, tile);
+  const PixelCtx c = pixel_ctx<TW, TH, WW, BT>(a.views, a.V, a.ranges, tile);
   const int wave = wave_index(), lane = threadIdx.x & 63;
   const int64_t vbase = (int64_t)c.v * a.N;
   const float fx = (float)c.lxi, fy = (float)c.lyi;
@@ -493,14 +516,21 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
   // the list length in case the saved state does not match the lists)
   const int nrec = min(smax + 1, (int)(c.re - c.rb));
 
-  for (int bend = nrec; bend > 0; bend -= TG::BLOCK) {
-    const int bstart = bend > TG::BLOCK ? bend - TG::BLOCK : 0;
-    const int li = bstart + (int)threadIdx.x;
-    uint32_t bits = 0;
-    if (li < bend) bits = stage<TW, TH>(splats, vbase, pair_ids, c.rb + (uint32_t)li, c, bp, ss, sgid);
-    publish_masks<TW, TH>(bits, masks);
+  for (int bend = nrec; bend > 0; bend -= TG::BATCH) {
+    const int bstart = bend > TG::BATCH ? bend - TG::BATCH : 0;
+#pragma unroll
+    for (int k = 0; k < (TG::BATCH + TG::BLOCK - 1) / TG::BLOCK; ++k) {
+      const int slot = (int)threadIdx.x + k * TG::BLOCK;
+      if (TG::BATCH % TG::BLOCK != 0 && slot >= TG::BATCH) break;  // wave-uniform
+      const int li = bstart + slot;
+      uint32_t bits = 0;
+      if (li < bend)
+        bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot, c, bp,
+                                     ss, sgid);
+      publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
+    }
     __syncthreads();
-    for (int cw = TG::NW - 1; cw >= 0; --cw) {
+    for (int cw = TG::NCH - 1; cw >= 0; --cw) {
       const int lim = wlast - (bstart + cw * 64);  // wave-uniform
       if (lim < 0) continue;  // nothing at or below our last blend
       uint64_t m = uniform_u64(masks[wave][cw]);
@@ -570,17 +600,17 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile, BwdShar
 }
 
 // One workgroup per tile, in `order` (or natural) order.
-template <int TW, int TH, bool DIST>
+template <int TW, int TH, bool DIST, int WW, int BT>
 __global__ void __launch_bounds__(TW * TH) k_render_bwd(BwdArgs a) {
-  __shared__ BwdShared<TW, TH> sh;
+  __shared__ BwdShared<TW, TH, WW, BT> sh;
   const int64_t i = blockIdx.x;
-  bwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[i] : i, sh);
+  bwd_tile<TW, TH, DIST, WW, BT>(a, a.order ? (int64_t)a.order[i] : i, sh);
 }
 
 // Persistent workgroups over a device work queue (see k_render_fwd_persistent).
-template <int TW, int TH, bool DIST>
+template <int TW, int TH, bool DIST, int WW, int BT>
 __global__ void __launch_bounds__(TW * TH) k_render_bwd_persistent(BwdArgs a) {
-  __shared__ BwdShared<TW, TH> sh;
+  __shared__ BwdShared<TW, TH, WW, BT> sh;
   __shared__ uint32_t item_s;
   for (;;) {
     if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1u);
@@ -588,7 +618,7 @@ __global__ void __launch_bounds__(TW * TH) k_render_bwd_persistent(BwdArgs a) {
     const uint32_t item = item_s;
     __syncthreads();
     if ((int64_t)item >= a.tiles) break;
-    bwd_tile<TW, TH, DIST>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
+    bwd_tile<TW, TH, DIST, WW, BT>(a, a.order ? (int64_t)a.order[item] : (int64_t)item, sh);
   }
 }
 
@@ -613,19 +643,19 @@ unsigned resident_blocks(K kernel, int block, unsigned cap, unsigned& cached) {
   return cached < cap ? cached : cap;
 }
 
-template <int TW, int TH, bool DIST, bool CNT, bool EXACT>
+template <int TW, int TH, bool DIST, bool CNT, bool EXACT, int WW = 8, int BT = 0>
 void launch_fwd_d(const FwdArgs& a, int schedule, hipStream_t st) {
-  constexpr int B = TileGeom<TW, TH>::BLOCK;
+  constexpr int B = TileGeom<TW, TH, WW, BT>::BLOCK;
   if (schedule == RADE_SCHEDULE_PERSISTENT) {
     static unsigned cached = 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
-    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH, DIST, CNT, EXACT>, B,
-                                       (unsigned)a.tiles, cached);
-    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST, CNT, EXACT>), dim3(g), dim3(B), 0,
-                       st, a);
-  } else {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST, CNT, EXACT>), dim3((unsigned)a.tiles),
+    const unsigned g = resident_blocks(k_render_fwd_persistent<TW, TH, DIST, CNT, EXACT, WW, BT>,
+                                       B, (unsigned)a.tiles, cached);
+    hipLaunchKernelGGL((k_render_fwd_persistent<TW, TH, DIST, CNT, EXACT, WW, BT>), dim3(g),
                        dim3(B), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, DIST, CNT, EXACT, WW, BT>),
+                       dim3((unsigned)a.tiles), dim3(B), 0, st, a);
   }
 }
 
@@ -640,49 +670,118 @@ void launch_fwd_e(const FwdArgs& a, int schedule, hipStream_t st) {
   }
 }
 
-template <int TW, int TH>
-void launch_fwd_t(const FwdArgs& a, int schedule, hipStream_t st) {
-  EventScope timing(RADE_KERNEL_RENDER_FWD, st);
-  if (a.depth_quad) launch_fwd_e<TW, TH, true>(a, schedule, st);
-  else launch_fwd_e<TW, TH, false>(a, schedule, st);
-}
-
-template <int TW, int TH, bool DIST>
+template <int TW, int TH, bool DIST, int WW = 8, int BT = 0>
 void launch_bwd_d(const BwdArgs& a, int schedule, hipStream_t st) {
-  constexpr int B = TileGeom<TW, TH>::BLOCK;
+  constexpr int B = TileGeom<TW, TH, WW, BT>::BLOCK;
   if (schedule == RADE_SCHEDULE_PERSISTENT) {
     static unsigned cached = 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, a.queue);
-    const unsigned g =
-        resident_blocks(k_render_bwd_persistent<TW, TH, DIST>, B, (unsigned)a.tiles, cached);
-    hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH, DIST>), dim3(g), dim3(B), 0, st, a);
+    const unsigned g = resident_blocks(k_render_bwd_persistent<TW, TH, DIST, WW, BT>, B,
+                                       (unsigned)a.tiles, cached);
+    hipLaunchKernelGGL((k_render_bwd_persistent<TW, TH, DIST, WW, BT>), dim3(g), dim3(B), 0, st,
+                       a);
   } else {
-    hipLaunchKernelGGL((k_render_bwd<TW, TH, DIST>), dim3((unsigned)a.tiles), dim3(B), 0, st, a);
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, DIST, WW, BT>), dim3((unsigned)a.tiles), dim3(B), 0,
+                       st, a);
   }
 }
 
+// Wave shapes and batches other than the default (8x8 waves, one splat per
+// thread) are compiled for the plain forward and backward only (no
+// distortion, blend count or exact depth); the caller checks this.
+constexpr bool shape_fits(int tw, int th, int ww) { return tw % ww == 0 && th % (64 / ww) == 0; }
+
+inline bool default_shape(int tw, int th, int wave_w, int batch) {
+  return (wave_w == 0 || wave_w == 8) && (batch == 0 || batch == tw * th);
+}
+
+template <int TW, int TH, int WW>
+bool launch_fwd_shape_b(const FwdArgs& a, int schedule, int batch, hipStream_t st) {
+  if constexpr (shape_fits(TW, TH, WW)) {
+    switch (batch) {
+      case 0: launch_fwd_d<TW, TH, false, false, false, WW, 0>(a, schedule, st); return true;
+      case 64: launch_fwd_d<TW, TH, false, false, false, WW, 64>(a, schedule, st); return true;
+      case 128: launch_fwd_d<TW, TH, false, false, false, WW, 128>(a, schedule, st); return true;
+      case 256: launch_fwd_d<TW, TH, false, false, false, WW, 256>(a, schedule, st); return true;
+      default: return false;
+    }
+  }
+  return false;
+}
+
+template <int TW, int TH, int WW>
+bool launch_bwd_shape_b(const BwdArgs& a, int schedule, int batch, hipStream_t st) {
+  if constexpr (shape_fits(TW, TH, WW)) {
+    switch (batch) {
+      case 0: launch_bwd_d<TW, TH, false, WW, 0>(a, schedule, st); return true;
+      case 64: launch_bwd_d<TW, TH, false, WW, 64>(a, schedule, st); return true;
+      case 128: launch_bwd_d<TW, TH, false, WW, 128>(a, schedule, st); return true;
+      case 256: launch_bwd_d<TW, TH, false, WW, 256>(a, schedule, st); return true;
+      default: return false;
+    }
+  }
+  return false;
+}
+
 template <int TW, int TH>
-void launch_bwd_t(const BwdArgs& a, int schedule, hipStream_t st) {
+hipError_t launch_fwd_t(const FwdArgs& a, int schedule, int wave_w, int batch, hipStream_t st) {
+  EventScope timing(RADE_KERNEL_RENDER_FWD, st);
+  if (default_shape(TW, TH, wave_w, batch)) {
+    if (a.depth_quad) launch_fwd_e<TW, TH, true>(a, schedule, st);
+    else launch_fwd_e<TW, TH, false>(a, schedule, st);
+    return hipSuccess;
+  }
+  if (a.depth_quad || a.distortion || a.count) return hipErrorInvalidValue;
+  bool ok = false;
+  if (wave_w == 0 || wave_w == 8) ok = launch_fwd_shape_b<TW, TH, 8>(a, schedule, batch, st);
+  else if (wave_w == 16) ok = launch_fwd_shape_b<TW, TH, 16>(a, schedule, batch, st);
+  else if (wave_w == 32) ok = launch_fwd_shape_b<TW, TH, 32>(a, schedule, batch, st);
+  return ok ? hipSuccess : hipErrorInvalidValue;
+}
+
+template <int TW, int TH>
+hipError_t launch_bwd_t(const BwdArgs& a, int schedule, int wave_w, int batch, hipStream_t st) {
   EventScope timing(RADE_KERNEL_RENDER_BWD, st);
-  if (a.d_distortion) launch_bwd_d<TW, TH, true>(a, schedule, st);
-  else launch_bwd_d<TW, TH, false>(a, schedule, st);
+  if (default_shape(TW, TH, wave_w, batch)) {
+    if (a.d_distortion) launch_bwd_d<TW, TH, true>(a, schedule, st);
+    else launch_bwd_d<TW, TH, false>(a, schedule, st);
+    return hipSuccess;
+  }
+  if (a.d_distortion) return hipErrorInvalidValue;
+  bool ok = false;
+  if (wave_w == 0 || wave_w == 8) ok = launch_bwd_shape_b<TW, TH, 8>(a, schedule, batch, st);
+  else if (wave_w == 16) ok = launch_bwd_shape_b<TW, TH, 16>(a, schedule, batch, st);
+  else if (wave_w == 32) ok = launch_bwd_shape_b<TW, TH, 32>(a, schedule, batch, st);
+  return ok ? hipSuccess : hipErrorInvalidValue;
 }
 
 }  // namespace
+
+// Wave shapes a tile can hold: ww x (64 / ww) blocks tiling it exactly.
+bool wave_shape_supported(int tw, int th, int wave_w) {
+  const int ww = wave_w > 0 ? wave_w : 8;
+  if (ww != 8 && ww != 16 && ww != 32) return false;
+  return shape_fits(tw, th, ww);
+}
+
+bool render_shape_is_default(int tw, int th, int wave_w, int batch) {
+  return default_shape(tw, th, wave_w, batch);
+}
 
 bool tile_supported(int tw, int th) {
   return (tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 16 && th == 32) ||
          (tw == 32 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 16);
 }
 
-#define RADE_TILE_DISPATCH(FN, ARGS)                          \
-  if (s.tile_w == 8 && s.tile_h == 8) FN<8, 8> ARGS;          \
-  else if (s.tile_w == 16 && s.tile_h == 16) FN<16, 16> ARGS; \
-  else if (s.tile_w == 16 && s.tile_h == 32) FN<16, 32> ARGS; \
-  else if (s.tile_w == 32 && s.tile_h == 16) FN<32, 16> ARGS; \
-  else if (s.tile_w == 16 && s.tile_h == 8) FN<16, 8> ARGS;   \
-  else if (s.tile_w == 8 && s.tile_h == 16) FN<8, 16> ARGS;   \
-  else return hipErrorInvalidValue;
+#define RADE_TILE_DISPATCH(FN, ARGS)                                     \
+  hipError_t de = hipErrorInvalidValue;                                  \
+  if (s.tile_w == 8 && s.tile_h == 8) de = FN<8, 8> ARGS;                \
+  else if (s.tile_w == 16 && s.tile_h == 16) de = FN<16, 16> ARGS;       \
+  else if (s.tile_w == 16 && s.tile_h == 32) de = FN<16, 32> ARGS;       \
+  else if (s.tile_w == 32 && s.tile_h == 16) de = FN<32, 16> ARGS;       \
+  else if (s.tile_w == 16 && s.tile_h == 8) de = FN<16, 8> ARGS;         \
+  else if (s.tile_w == 8 && s.tile_h == 16) de = FN<8, 16> ARGS;         \
+  if (de != hipSuccess) return de;
 
 hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
@@ -700,7 +799,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
   a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
   a.last = last; a.median = med; a.count = cnt; a.distortion = distortion;
   a.depth_quad = reinterpret_cast<const float4*>(depth_quad);
-  RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, st))
+  RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, s.wave_w, s.batch, st))
   return hipGetLastError();
 }
 
@@ -725,7 +824,7 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
   a.d_color = dc; a.d_depth = dd; a.d_normal = dn; a.d_alpha = da;
   a.d_distortion = ddist; a.fwd_depth = fwd_depth; a.fwd_alpha = fwd_alpha;
   a.gsplat = gsplat;
-  RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, st))
+  RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, s.wave_w, s.batch, st))
   return hipGetLastError();
 }
 

@@ -51,9 +51,9 @@ def test_header_is_c_and_struct_sizes(tmp_path):
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I",
                            os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     sizes = subprocess.check_output([str(exe)]).decode().split()
-    assert sizes == ["112", "96", "80", "72", "80"]
+    assert sizes == ["120", "96", "80", "72", "80"]
     lib = _lib()
-    assert ctypes.sizeof(lib.CSettings) == 112 and ctypes.sizeof(lib.CView) == 96
+    assert ctypes.sizeof(lib.CSettings) == 120 and ctypes.sizeof(lib.CView) == 96
     assert lib.SPLAT_DTYPE.itemsize == 80 and lib.SPLAT_DTYPE.fields["rect"][1] == 72
 
 
@@ -75,7 +75,9 @@ def test_views_prepare_offsets():
 
 @pytest.mark.parametrize("bad", [dict(tile_w=12), dict(tile_h=64), dict(sh_degree=4), dict(schedule=3),
                                  dict(alpha_min=0.0), dict(t_min=1.5), dict(power_cut=-1.0),
-                                 dict(depth_mode=3)])
+                                 dict(depth_mode=3), dict(wave_w=12), dict(batch=96),
+                                 dict(tile_w=8, tile_h=8, wave_w=16),
+                                 dict(tile_w=16, tile_h=32, wave_w=32)])
 def test_invalid_settings_rejected_without_launch(bad):
     lib = _lib()
     import synth

@@ -107,8 +107,18 @@ def test_autotuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     g = _fixed_grads(P, dev)
     best, timings = autotune(views, params, Settings(sh_degree=3), lambda m: g,
                              tiles=[(8, 8), (16, 16)], schedules=[0, 2], reps=2)
-    assert len(timings) == 4 and f"{best.tile_w}x{best.tile_h}/{best.schedule}" in timings
+    # stage 1: every (tile, schedule); stage 2: wave shapes x batches of the best
+    stage1 = {k: v for k, v in timings.items() if "/w" not in k}
+    assert len(stage1) == 4
+    b1 = min(stage1, key=stage1.get)
+    stage2 = [k for k in timings if "/w" in k]
+    assert stage2 and all(k.startswith(b1 + "/w") for k in stage2)
+    key = f"{best.tile_w}x{best.tile_h}/{best.schedule}"
+    if best.wave_w or best.batch:
+        key += f"/w{best.wave_w}/b{best.batch}"
+    assert key in timings and timings[key] == min(timings.values())
     again, t2 = autotune(views, params, Settings(sh_degree=3), lambda m: g,
                          tiles=[(8, 8), (16, 16)], schedules=[0, 2], reps=2)
-    assert (again.tile_w, again.tile_h, again.schedule) == (best.tile_w, best.tile_h, best.schedule)
+    assert (again.tile_w, again.tile_h, again.schedule, again.wave_w, again.batch) == \
+        (best.tile_w, best.tile_h, best.schedule, best.wave_w, best.batch)
     say("autotune", timings)
