@@ -217,3 +217,69 @@ def test_cull_rules():
     sc.quats[4] = 0.0
     _, _, flags = _proj(oracle.settings(), v, sc)
     assert [bool(f & oracle.F_CULLED) for f in flags] == [True, False, True, True, True]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_ray_space_maxima_are_coplanar(seed):
+    """Under the local affine projection (Sec. 3.2.2), the maximum of the
+    ray-space Gaussian along t at pixel offset D = (u_c - u, v_c - v) lies
+    on the plane t = t_c + q . D (Eq. 12-17) for any D, not only to first
+    order: a bounded 1D search of the Gaussian built here from J and Sigma
+    (J from the pinhole derivatives and t = |x|, Sigma from scipy's
+    rotation) against the oracle's q, at offsets up to 20 pixels."""
+    from scipy.optimize import minimize_scalar
+    rng = np.random.default_rng(300 + seed)
+    f = 160.0
+    v = view(200, 160, f)
+    xc = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(2.0, 4.0)])
+    scales = np.exp(rng.normal(-2.5, 0.6, 3))
+    q = rng.normal(size=4)
+    sc = scene_from([xc], [scales], [q / np.linalg.norm(q)], opac=[0.9])
+    rec, _, flags = _proj(oracle.settings(dilation=0.0, fov_clamp=1e6), v, sc)
+    assert not flags[0] & oracle.F_DEGENERATE
+    x, y, z = sc.means[0].astype(np.float64)
+    t = np.sqrt(x * x + y * y + z * z)
+    J = np.array([[f / z, 0.0, -f * x / z**2], [0.0, f / z, -f * y / z**2], [x / t, y / t, z / t]])
+    Rg = rotation_wxyz(sc.quats[0])
+    Sig = Rg @ np.diag(sc.scales[0].astype(np.float64) ** 2) @ Rg.T
+    A = np.linalg.inv(J @ Sig @ J.T)
+    qv = np.array([rec[0, R["q0"]], rec[0, R["q1"]]])
+    for D in rng.uniform(-20, 20, (8, 2)):
+        def energy(tt):
+            w = np.array([-D[0], -D[1], tt - t])   # (u - u_c, v - v_c, t - t_c)
+            return w @ A @ w
+        res = minimize_scalar(energy, bounds=(t - 5.0, t + 5.0), method="bounded",
+                              options={"xatol": 1e-13})
+        assert res.x == pytest.approx(t + qv @ D, rel=1e-10, abs=1e-10)
+
+
+def test_rigid_motion_invariance():
+    """Rotating and translating the Gaussians and the camera by one rigid
+    motion leaves every map unchanged (SH degree 0: colour does not depend
+    on the view direction); FP32 storage of the moved inputs perturbs the
+    maps at the 1e-6 level, pixels on a discrete threshold excepted."""
+    import synth
+    from scipy.spatial.transform import Rotation
+    scene = synth.make_scene_uniform_cube(200, seed=11, sh_degree=0)
+    rng = np.random.default_rng(12)
+    Q = Rotation.from_rotvec(rng.normal(size=3)).as_matrix()
+    s = np.array([0.3, -0.2, 0.5])
+    means = scene.means.astype(np.float64) @ Q.T + s
+    rot = Rotation.from_matrix(Q) * Rotation.from_quat(
+        np.concatenate([scene.quats[:, 1:], scene.quats[:, :1]], axis=1).astype(np.float64))
+    qxyzw = rot.as_quat()
+    quats = np.concatenate([qxyzw[:, 3:], qxyzw[:, :3]], axis=1)
+    moved = scene_from(means, scene.scales, quats, scene.opacities, sh=scene.sh, degree=0)
+    v0 = view(48, 48, 48.0)
+    v1 = view(48, 48, 48.0, R=np.eye(3) @ Q.T, t=-(Q.T @ s))
+    st = oracle.settings(sh_degree=0)
+    _, _, _, oa = oracle.forward(st, [v0], scene)
+    _, _, _, ob = oracle.forward(st, [v1], moved)
+    keep = ((oa[0]["fragile"] | ob[0]["fragile"]) & 1) == 0
+    assert keep.mean() > 0.98
+    for k in ("color", "depth_exp", "normal", "alpha"):
+        a = np.asarray(oa[0][k]).reshape(len(keep), -1)[keep]
+        b = np.asarray(ob[0][k]).reshape(len(keep), -1)[keep]
+        np.testing.assert_allclose(b, a, rtol=0, atol=2e-4 * max(1.0, np.abs(a).max()))
+    # and the maps are not trivially empty
+    assert oa[0]["alpha"].max() > 0.5
