@@ -66,8 +66,10 @@ BYTES_PER_PIXEL = 52 + 52 + 36
 # of known size (FETCH_SIZE reads half of the bytes a plain copy moves,
 # WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
 # on (SHA-1 of render.hip + common.hpp) and for the 1600x1064 / 1M workload
-# at 16x16 tiles; reported as null otherwise.
+# in the launch configuration it was measured in (tile, schedule, wave shape,
+# batch); reported as null otherwise.
 MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
+                    "schedule": 0, "wave_w": 0, "batch": 0,
                     "sources_sha1": "b1f409bbf38706c0750f360da12547c53e591dcd",
                     "fetch_bytes": 363054020, "write_bytes": 154785088,
                     "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
@@ -82,10 +84,12 @@ def _render_sources_sha1() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, tile: str):
+def measured_traffic(kernel: str, workload: str, settings):
     t = MEASURED_TRAFFIC
+    tile = f"{settings.tile_w}x{settings.tile_h}"
     if (t is None or t["kernel"] != kernel or t["workload"] != workload or t["tile"] != tile
-            or t["sources_sha1"] != _render_sources_sha1()):
+            or t["schedule"] != settings.schedule or t["wave_w"] != settings.wave_w
+            or t["batch"] != settings.batch or t["sources_sha1"] != _render_sources_sha1()):
         return None
     return t["fetch_bytes"] + t["write_bytes"]
 
@@ -97,8 +101,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="plain_1600x1064_1m")
     ap.add_argument("--tile", default="16x16", help="WxH, or 'auto' (autotune)")
-    ap.add_argument("--schedule", type=int, default=0,
-                    help="0: one workgroup per tile, 1: heavy first, 2: persistent")
+    ap.add_argument("--schedule", type=int, default=1,
+                    help="0: one workgroup per tile, 1: heavy first (default, the autotuner's choice "
+                         "for the default workload), 2: persistent")
     ap.add_argument("--cpu-pixels", type=int, default=4096,
                     help="pixels of the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--eager-steps", type=int, default=5,
@@ -312,15 +317,21 @@ def main():
     plan.step()  # capture, replay, grow on overflow
     for _ in range(args.warmup):
         plan.replay()
+    # per-step HIP events on the replay stream (recorded between replays, no
+    # host synchronisation inside the timed window)
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    step_ev[0].record()
+    for i in range(args.steps):
         plan.replay()
+        step_ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if plan.overflowed():
         raise RuntimeError("pair capacity overflow during the timed replays")
     ms_step = 1e3 * (t1 - t0) / args.steps
+    per_step = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
 
     # per-kernel durations: HIP events recorded by the library around each
     # launch, over the same steps enqueued eagerly on the same stream
@@ -405,6 +416,9 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "ms_per_view": ms_step / V,
+        "step_ms_percentiles": {"p10": float(np.percentile(per_step, 10)),
+                                "p50": float(np.percentile(per_step, 50)),
+                                "p90": float(np.percentile(per_step, 90))},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -423,8 +437,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(dom, args.workload,
-                                                 f"{settings.tile_w}x{settings.tile_h}")},
+                     "traffic": measured_traffic(dom, args.workload, settings)},
         "blends_per_view": blends / V,
         "pairs_per_view": pairs / V,
         "kernel_ms": kernel_ms,

@@ -29,7 +29,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="plain_1600x1064_1m")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
     args = ap.parse_args(argv)
 
