@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "grid.hpp"
 #include "scan.hpp"
 
 namespace rade {
@@ -28,60 +29,137 @@ constexpr int kTile = kScanTile;                // items per block (2048)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-// Inputs of the scans, as functors over the item index.
-struct FlagInput {  // 1 when the splat touches at least one tile
+constexpr int kEmitPairs = 1024;                 // pairs per emission block
+
+// Compaction of the visible splats (tiles touched > 0) into the depth sort's
+// (key, value) arrays: key = bits of the float32 view depth, value = index.
+struct Visible {
   const int32_t* tt;
   __device__ uint32_t operator()(int64_t i) const { return tt[i] > 0 ? 1u : 0u; }
 };
-struct GatherCount {  // tiles touched by the j-th depth-sorted splat
+struct VisibleOut {
+  const rade_splat* splats;
+  uint32_t* keys;
+  uint32_t* vals;
+  __device__ void operator()(int64_t i, uint32_t p, uint32_t) const {
+    keys[p] = __float_as_uint(splats[i].z);  // z > near > 0: bits order like values
+    vals[p] = (uint32_t)i;
+  }
+};
+
+// Tiles touched by the j-th depth-sorted splat.
+struct GatherCount {
   const int32_t* tt;
   const uint32_t* vals;
   __device__ uint64_t operator()(int64_t j) const { return (uint64_t)tt[vals[j]]; }
 };
+// Pair offsets of the depth-sorted splats, and for every emission block the
+// splat that holds its first pair: block b starts in splat j when
+// offs[j] <= b * kEmitPairs < offs[j] + count[j].
+struct OffsetsOut {
+  uint64_t* offs;
+  uint32_t* starts;
+  int64_t nstarts;
+  __device__ void operator()(int64_t j, uint64_t off, uint64_t cnt) const {
+    offs[j] = off;
+    const uint64_t end = off + cnt;
+    for (uint64_t b = (off + kEmitPairs - 1) / kEmitPairs;
+         b * kEmitPairs < end && b < (uint64_t)nstarts; ++b)
+      starts[b] = (uint32_t)j;
+  }
+};
 
 // ---------------------------------------------------------------------------
-// Compaction of visible splats with their depth keys.
-__global__ void __launch_bounds__(kThreads)
-k_compact(const int32_t* __restrict__ tt, const uint32_t* __restrict__ pos,
-          const rade_splat* __restrict__ splats, int64_t n, uint32_t* __restrict__ keys,
-          uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n || tt[i] <= 0) return;
-  const uint32_t p = pos[i];
-  keys[p] = __float_as_uint(splats[i].z);  // z > near > 0: bits order like values
-  vals[p] = (uint32_t)i;
-}
-
-// ---------------------------------------------------------------------------
-// LSD radix sort pass, 8-bit digit at `shift`, stable.
+// LSD radix sort, 8-bit digits, stable.  Each pass counts the digits of
+// every block of kTile consecutive items (k_radix_hist, counts stored
+// digit-major: hist[d * nblocks + block]), scans each digit's row of counts
+// (k_radix_colscan) and scatters (k_radix_scatter).
+//
+// Workgroups are dealt to the XCDs round-robin, so the sort kernels remap
+// the workgroup index to a block index such that each XCD takes one
+// contiguous run of blocks: the counts of neighbouring blocks (which share
+// cache lines of the digit-major rows) then meet in one L2 instead of up to
+// eight.
 __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
   return (k >> shift) & (kRadix - 1);
 }
 
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t wg, int64_t grid) {
+  const int64_t x = wg % kXcds, k = wg / kXcds;
+  const int64_t q = grid / kXcds, r = grid % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// Items of a radix block: wave w holds the kItems rounds of 64 consecutive
+// items [base + w*64*kItems, base + (w+1)*64*kItems), round r at offset
+// r*64 + lane.  Block order is then (wave, round, lane), so ranks counted
+// per wave, round after round, and combined across waves in wave order are
+// stable.  All loads of a thread are issued before any ranking.
+constexpr int kWaves = kThreads / 64;
+static_assert(kRadix == kThreads, "one digit per thread in the block-wide steps");
+
+__device__ __forceinline__ int64_t item_index(int64_t base, int r) {
+  return base + (int64_t)(threadIdx.x >> 6) * (64 * kItems) + (int64_t)r * 64 +
+         (threadIdx.x & 63);
+}
+
+// Lanes of the wave whose item is valid and has digit d: one ballot per
+// digit bit, each lane keeping the lanes that agree with its own bit.  With
+// s = 0 or ~0 from the lane's bit, the lanes that agree are ~(m ^ s); the
+// halves are kept apart so the selection stays a few 32-bit logic ops.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  const uint64_t v = __ballot(valid);
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const uint32_t s = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(s != 0u);
+    lo &= ~((uint32_t)m ^ s);
+    hi &= ~((uint32_t)(m >> 32) ^ s);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Per-block digit counts (LDS atomics; lanes that hit one counter are
+// serialised by the LDS, not by vector instructions).
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-             int shift, int64_t nblocks, uint32_t* __restrict__ hist) {
+             int64_t n_max, int shift, int64_t nblocks, uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[kRadix];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t n = *n_dev;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
+  // the loads are bounded by the buffer size, so they need not wait for
+  // the item count; items past it are not counted
+  uint32_t key[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of(keys[i], shift)], 1u);
+    const int64_t i = item_index(base, r);
+    key[r] = i < n_max ? keys[i] : 0u;
   }
+  const int64_t n = *n_dev;
+  h[threadIdx.x] = 0;
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r)
+    if (item_index(base, r) < n) atomicAdd(&h[digit_of(key[r], shift)], 1u);
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
 }
 
 // Exclusive scan of one digit's row of per-block counts (one workgroup per
-// digit, rows are digit-major) and the digit's total.  Together with the
-// scan of the 256 totals in the scatter's prologue this replaces a global
-// scan of the whole count matrix.
+// digit) and the digit's total.  Together with the scan of the 256 totals
+// in the scatter's prologue this replaces a global scan of the whole count
+// matrix.
 __global__ void __launch_bounds__(kThreads)
 k_radix_colscan(uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restrict__ dtot) {
-  __shared__ uint32_t lw[kThreads / 64];
+  __shared__ uint32_t lw[kWaves];
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
   uint32_t carry = 0;
   for (int64_t b0 = 0; b0 < nblocks; b0 += kTile) {  // uniform trip count
@@ -106,120 +184,97 @@ k_radix_colscan(uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restri
 
 // Shared memory of one sorting workgroup.
 struct RankShared {
-  uint32_t cnt[kRadix];                  // per-digit count of the tile
-  uint32_t wcnt[kThreads / 64][kRadix];  // per-round per-wave counts
-  uint32_t lstart[kRadix];               // first local position of each digit
-  uint32_t dbase[kRadix];                // global position of each digit's run
+  uint32_t wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave digit starts
+  uint32_t lstart[kRadix];        // first local position of each digit
+  uint32_t dbase[kRadix];         // global position of each digit's run
   uint32_t skey[kTile];
   uint32_t sval[kTile];
-  uint32_t lw[kThreads / 64];
+  uint64_t lw[kWaves];
 };
 
-// Stable ranks of the tile's items [base, min(base + kTile, n)) among equal
-// digits (wave match masks: 8 ballots per item), the per-digit counts in
-// sh.cnt and the local digit starts in sh.lstart.  On return the items sit
-// in key/val with their local sorted positions in pos.
-__device__ __forceinline__ void rank_tile(const uint32_t* __restrict__ kin,
-                                          const uint32_t* __restrict__ vin, int64_t base,
-                                          int64_t n, int shift, RankShared& sh,
-                                          uint32_t (&key)[kItems], uint32_t (&val)[kItems],
-                                          uint32_t (&pos)[kItems]) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  sh.cnt[threadIdx.x] = 0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) sh.wcnt[w][threadIdx.x] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    const bool valid = i < n;
-    key[r] = valid ? kin[i] : 0u;
-    val[r] = valid ? vin[i] : 0u;
-    const uint32_t d = digit_of(key[r], shift);
-    // lanes of this wave holding the same digit
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? m : ~m;
-    }
-    const uint32_t lr = (uint32_t)__popcll(peers & lt);
-    if (valid && lr == 0) sh.wcnt[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    uint32_t pre = sh.cnt[d];
-    for (int w = 0; w < wave; ++w) pre += sh.wcnt[w][d];
-    pos[r] = pre + lr;
-    __syncthreads();
-    {
-      uint32_t add = 0;
-#pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w) {
-        add += sh.wcnt[w][threadIdx.x];
-        sh.wcnt[w][threadIdx.x] = 0;
-      }
-      sh.cnt[threadIdx.x] += add;
-    }
-    __syncthreads();
-  }
-  {
-    uint32_t tot;
-    sh.lstart[threadIdx.x] = block_exclusive_scan<uint32_t>(sh.cnt[threadIdx.x], sh.lw, tot);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) pos[r] += sh.lstart[digit_of(key[r], shift)];
-}
-
-// Local sort in LDS, then each digit's run written out contiguously at
-// sh.dbase[digit].
-__device__ __forceinline__ void scatter_tile(int64_t base, int64_t n, int shift,
-                                             RankShared& sh, const uint32_t (&key)[kItems],
-                                             const uint32_t (&val)[kItems],
-                                             const uint32_t (&pos)[kItems],
-                                             uint32_t* __restrict__ kout,
-                                             uint32_t* __restrict__ vout) {
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    if (i < n) {
-      sh.skey[pos[r]] = key[r];
-      sh.sval[pos[r]] = val[r];
-    }
-  }
-  __syncthreads();
-  const int64_t nb = (n - base) < kTile ? (n - base) : kTile;
-  for (int64_t i = threadIdx.x; i < nb; i += kThreads) {
-    const uint32_t k = sh.skey[i];
-    const uint32_t d = digit_of(k, shift);
-    const uint64_t dst = (uint64_t)sh.dbase[d] + (uint64_t)(i - sh.lstart[d]);
-    kout[dst] = k;
-    vout[dst] = sh.sval[i];
-  }
-}
-
-// Scatter of the multi-kernel pass: the global position of digit d's run of
-// this block is the exclusive scan of the digit totals at d plus the
-// row-scanned count of the blocks before it.
+// Scatter of one pass.  The block is ranked stably: each wave counts its
+// rounds' digits in its own LDS row (a running count, so no block barrier
+// between rounds), one pass per digit turns the rows into per-wave starts,
+// and one block scan of (digit total << 32 | local count) gives both the
+// start of each digit's region in the output and the block's local digit
+// starts (the local counts sum to at most kTile, so the halves never carry
+// into each other).  The block is then sorted in LDS and each digit's run
+// written contiguously at its region start plus the row-scanned count of
+// the blocks before this one.
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                const uint32_t* __restrict__ n_dev, int shift, int64_t nblocks,
+                const uint32_t* __restrict__ n_dev, int64_t n_max, int shift, int64_t nblocks,
                 const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot) {
   __shared__ RankShared sh;
-  const int64_t n = *n_dev;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  if (base >= n) return;  // uniform per block
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = blk * kTile;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  // all loads are issued before the item count is known (bounded by the
+  // buffer size instead)
   uint32_t key[kItems], val[kItems], pos[kItems];
-  rank_tile(kin, vin, base, n, shift, sh, key, val, pos);
-  {
-    uint32_t tot;
-    const uint32_t dstart = block_exclusive_scan<uint32_t>(dtot[threadIdx.x], sh.lw, tot);
-    sh.dbase[threadIdx.x] = dstart + offsets[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = item_index(base, r);
+    const bool inb = i < n_max;
+    key[r] = inb ? kin[i] : 0u;
+    val[r] = inb ? vin[i] : 0u;
+  }
+  const uint32_t dtot_d = dtot[threadIdx.x];
+  const uint32_t goff_d = offsets[(int64_t)threadIdx.x * nblocks + blk];
+  const int64_t n = *n_dev;
+  if (base >= n) return;  // uniform per block
+  uint32_t* wc = sh.wcnt[wave];
+#pragma unroll
+  for (int k = 0; k < kRadix / 64; ++k) wc[k * 64 + lane] = 0;
+  const uint64_t lt = lanes_below();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const bool valid = item_index(base, r) < n;
+    const uint32_t d = digit_of(key[r], shift);
+    const uint64_t peers = digit_peers(d, valid);
+    // LDS operations of one wave complete in issue order; the leader's
+    // store depends on the value every lane read
+    const uint32_t pre = wc[d];
+    pos[r] = pre + (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0) wc[d] = pre + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  scatter_tile(base, n, shift, sh, key, val, pos, kout, vout);
+  {
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t x = sh.wcnt[w][d];
+      sh.wcnt[w][d] = c;
+      c += x;
+    }
+    uint64_t tot;
+    const uint64_t ex =
+        block_exclusive_scan<uint64_t>(((uint64_t)dtot_d << 32) | c, sh.lw, tot);
+    sh.lstart[d] = (uint32_t)ex;
+    sh.dbase[d] = (uint32_t)(ex >> 32) + goff_d;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    if (item_index(base, r) < n) {
+      const uint32_t d = digit_of(key[r], shift);
+      const uint32_t p = pos[r] + sh.lstart[d] + sh.wcnt[wave][d];
+      sh.skey[p] = key[r];
+      sh.sval[p] = val[r];
+    }
+  }
+  __syncthreads();
+  const int nb = (n - base) < kTile ? (int)(n - base) : kTile;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    const uint32_t k = sh.skey[i];
+    const uint32_t d = digit_of(k, shift);
+    const uint32_t dst = sh.dbase[d] + ((uint32_t)i - sh.lstart[d]);
+    kout[dst] = k;
+    vout[dst] = sh.sval[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -227,38 +282,31 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 // depth-sorted splat j with offs[j] <= p < offs[j + 1] and is its
 // (p - offs[j])-th tile in row-major order of its tile rect.  A block covers
 // kEmitPairs consecutive pairs, hence at most kEmitPairs consecutive splats
-// (each has >= 1 pair): their offsets are staged in LDS.  Writes are
-// coalesced and the work is balanced whatever the splat sizes.
-constexpr int kEmitPairs = 1024;
+// (each has >= 1 pair), starting with starts[block]: their offsets are
+// staged in LDS.  Writes are coalesced and the work is balanced whatever the
+// splat sizes.
 constexpr int kEmitPerThread = kEmitPairs / kThreads;  // 4 consecutive pairs
 static_assert(kEmitPerThread == 4, "emit stores four pairs as one 16-byte word");
 
 __global__ void __launch_bounds__(kThreads)
 k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
-       const uint32_t* __restrict__ n_dev, const uint64_t* __restrict__ m_dev,
-       int64_t capacity, const rade_splat* __restrict__ splats,
-       const rade_view* __restrict__ views, int64_t N, int tile_w, int tile_h,
-       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids, int vec_stores) {
+       const uint32_t* __restrict__ starts, const uint32_t* __restrict__ n_dev,
+       const uint64_t* __restrict__ m_dev, int64_t capacity,
+       const rade_splat* __restrict__ splats, const rade_view* __restrict__ views, FastDiv div_n,
+       int log2_tw, int log2_th, uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids,
+       int vec_stores) {
   __shared__ uint64_t win[kEmitPairs + 1];
-  __shared__ int64_t j0_s;
+  __shared__ uint32_t wid[kEmitPairs + 1];
   const uint64_t M = *m_dev;
   const int64_t nvis = *n_dev;
+  const int64_t j0 = starts[blockIdx.x];
   const uint64_t P0 = (uint64_t)blockIdx.x * kEmitPairs;
   if (P0 >= M || M > (uint64_t)capacity) return;  // uniform per block
-  if (threadIdx.x == 0) {
-    // last j with offs[j] <= P0
-    int64_t lo = 0, hi = nvis - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (offs[mid] <= P0) lo = mid; else hi = mid - 1;
-    }
-    j0_s = lo;
-  }
-  __syncthreads();
-  const int64_t j0 = j0_s;
   for (int w = threadIdx.x; w <= kEmitPairs; w += kThreads) {
     const int64_t j = j0 + w;
-    win[w] = j < nvis ? offs[j] : M;
+    const bool in = j < nvis;
+    win[w] = in ? offs[j] : M;
+    wid[w] = in ? svals[j] : 0u;
   }
   __syncthreads();
   // Four consecutive pairs per thread: the first one's splat by binary
@@ -274,8 +322,7 @@ k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
   }
   uint32_t tk[kEmitPerThread], pg[kEmitPerThread];
   int cur = -1;
-  int tx0 = 0, ty0 = 0, ty1 = 0;
-  uint32_t nx = 1, g = 0, toff = 0, tiles_x = 0;
+  uint32_t tx0 = 0, ty0 = 0, ty1 = 0, nx = 1, g = 0, toff = 0, tiles_x = 0, row = 0, col = 0;
 #pragma unroll
   for (int r = 0; r < kEmitPerThread; ++r) {
     const uint64_t p = pb + r;
@@ -285,27 +332,32 @@ k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
     while (lo < kEmitPairs && win[lo + 1] <= p) ++lo;
     if (lo != cur) {
       cur = lo;
-      // V*N < 2^32 (32-bit ids): 32-bit divisions
-      const uint32_t i = svals[j0 + lo];
-      const uint32_t v = i / (uint32_t)N;
-      g = i - v * (uint32_t)N;
+      // V*N < 2^32 (32-bit ids); a visible splat's rect lies inside its
+      // view, so its pixel bounds are non-negative and the tile bounds are
+      // shifts (tile sizes are powers of two)
+      const uint32_t i = wid[lo];
+      const uint32_t v = div_n.div(i);
+      g = i - v * div_n.d;
       const rade_splat& sp = splats[i];
-      tx0 = sp.rect[0] / tile_w;
-      const int tx1 = sp.rect[1] / tile_w;
-      ty0 = sp.rect[2] / tile_h;
-      ty1 = sp.rect[3] / tile_h;
-      nx = (uint32_t)(tx1 - tx0 + 1);
+      tx0 = (uint32_t)sp.rect[0] >> log2_tw;
+      const uint32_t tx1 = (uint32_t)sp.rect[1] >> log2_tw;
+      ty0 = (uint32_t)sp.rect[2] >> log2_th;
+      ty1 = (uint32_t)sp.rect[3] >> log2_th;
+      nx = tx1 - tx0 + 1;
       toff = (uint32_t)views[v].tile_offset;
       tiles_x = (uint32_t)views[v].tiles_x;
+      // pair k of the splat is its k-th tile in row-major order of its rect
+      // (k > 0 only for the thread's first pair)
+      const uint32_t k = (uint32_t)(p - win[lo]);
+      row = k / nx;
+      col = k - row * nx;
+    } else if (++col == nx) {
+      col = 0;
+      ++row;
     }
-    // pair k of the splat is its k-th tile in row-major order of its rect (a
-    // splat covers fewer than 2^31 tiles); stay inside the rect even if
-    // tiles_touched disagrees with it
-    const uint32_t k = (uint32_t)(p - win[lo]);
-    const uint32_t row = k / nx;
-    const int ty = min(ty0 + (int)row, ty1);
-    const int tx = tx0 + (int)(k - row * nx);
-    tk[r] = toff + (uint32_t)ty * tiles_x + (uint32_t)tx;
+    // stay inside the rect even if tiles_touched disagrees with it
+    const uint32_t ty = min(ty0 + row, ty1);
+    tk[r] = toff + ty * tiles_x + tx0 + col;
     pg[r] = g;
   }
   if (vec_stores && pb + kEmitPerThread <= M) {
@@ -334,15 +386,53 @@ __global__ void k_finish_counts(const uint64_t* __restrict__ m_dev, int64_t capa
   *n_pairs_out = (int64_t)m;
 }
 
+// Tile ranges from the sorted tile keys: [first, end) of each tile's run of
+// pairs, [0, 0) for a tile without pairs.  Item boundary i (0 <= i <= m)
+// sits between the tiles prev = key[i - 1] (-1 for i = 0) and cur = key[i]
+// (`tiles` for i = m); where they differ it ends prev's range, starts cur's
+// and clears the tiles in between.  Each thread takes four boundaries.
+__device__ __forceinline__ void range_edge(uint32_t* __restrict__ ranges, int64_t i, int64_t m,
+                                           int64_t prev, int64_t cur) {
+  if (prev == cur) return;
+  if (prev >= 0) ranges[2 * prev + 1] = (uint32_t)i;
+  if (i < m) ranges[2 * cur] = (uint32_t)i;
+  for (int64_t t = prev + 1; t < cur; ++t) {
+    ranges[2 * t] = 0u;
+    ranges[2 * t + 1] = 0u;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
-k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32,
+k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32, int64_t tiles,
          uint32_t* __restrict__ ranges) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t m = *m32;
-  if (i >= m) return;
-  const uint32_t t = tkeys[i];
-  if (i == 0 || tkeys[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-  if (i == m - 1 || tkeys[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+  if (m == 0) {  // no pairs (or too many for the capacity): every range empty
+    for (int64_t t = g; t < tiles; t += (int64_t)gridDim.x * kThreads) {
+      ranges[2 * t] = 0u;
+      ranges[2 * t + 1] = 0u;
+    }
+    return;
+  }
+  const int64_t i0 = 4 * g;
+  if (i0 > m) return;
+  uint32_t k[4];
+  if (i0 + 4 <= m) {  // tkeys is 16-byte aligned
+    const uint4 q = *reinterpret_cast<const uint4*>(tkeys + i0);
+    k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) k[r] = i0 + r < m ? tkeys[i0 + r] : 0u;
+  }
+  int64_t prev = i0 > 0 ? (int64_t)tkeys[i0 - 1] : -1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + r;
+    if (i > m) break;
+    const int64_t cur = i < m ? (int64_t)k[r] : tiles;
+    range_edge(ranges, i, m, prev, cur);
+    prev = cur;
+  }
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -359,34 +449,54 @@ k_keys(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ pids,
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// Sorts (keys, vals) of *n_dev items (at most n_max) by the low `bits` bits
-// of the keys; on return the sorted data are in (k0, v0) when the number of
-// passes is even, else in (k1, v1).  Returns the number of passes.
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Work space of one radix sort of at most n_max items: the digit-major
+// per-block counts and the 256 digit totals.
+struct SortSpace {
+  uint32_t* hist;
+  uint32_t* dtot;
+};
+
+inline int64_t sort_blocks(int64_t n_max) { return n_max > 0 ? (n_max + kTile - 1) / kTile : 1; }
+
+inline size_t sort_space_bytes(int64_t n_max) {
+  return align_up(sizeof(uint32_t) * sort_blocks(n_max) * kRadix) +
+         align_up(sizeof(uint32_t) * kRadix);
+}
+
+inline SortSpace sort_space(char* w, int64_t n_max) {
+  SortSpace sp;
+  sp.hist = (uint32_t*)w;
+  sp.dtot = (uint32_t*)(w + align_up(sizeof(uint32_t) * sort_blocks(n_max) * kRadix));
+  return sp;
+}
+
+// Sorts (keys, vals) of *n_dev items (at most n_max < 2^32) by the low
+// `bits` bits of the keys; on return the sorted data are in (k0, v0) when the
+// number of passes is even, else in (k1, v1).  Returns the number of passes.
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
-               const uint32_t* n_dev, int bits, uint32_t* hist, uint32_t* hist_sums,
-               hipStream_t st) {
-  const int64_t nb = n_max > 0 ? (n_max + kTile - 1) / kTile : 1;
-  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+               const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st) {
+  const int64_t nb = sort_blocks(n_max);
+  const int passes = bits > kRadixBits ? (bits + kRadixBits - 1) / kRadixBits : 1;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * kRadixBits;
     uint32_t* ki = (p & 1) ? k1 : k0;
     uint32_t* vi = (p & 1) ? v1 : v0;
     uint32_t* ko = (p & 1) ? k0 : k1;
     uint32_t* vo = (p & 1) ? v0 : v1;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev, shift,
-                       nb, hist);
-    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadix), dim3(kThreads), 0, st, hist, nb,
-                       hist_sums);
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev, n_max,
+                       shift, nb, sp.hist);
+    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadix), dim3(kThreads), 0, st, sp.hist, nb, sp.dtot);
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
-                       n_dev, shift, nb, hist, (const uint32_t*)hist_sums);
+                       n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
+                       (const uint32_t*)sp.dtot);
   }
   return passes;
 }
 
-inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-
 struct Layout {
-  size_t vis_pos, dkeys0, dvals0, dkeys1, dvals1, offs, tkeys0, tkeys1, pids1, hist, sums, scal;
+  size_t starts, dkeys0, dvals0, dkeys1, dvals1, offs, tkeys0, tkeys1, pids1, sort, sums, scal;
   size_t total;
 };
 
@@ -401,10 +511,7 @@ Layout layout(int64_t VN, int64_t capacity) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   const int64_t nmax = VN > capacity ? VN : capacity;
-  const int64_t nb = (nmax + kTile - 1) / kTile + 1;
-  const int64_t hist_n = nb * kRadix;
-  const int64_t scan_n = (hist_n > nmax ? hist_n : nmax);
-  L.vis_pos = take(sizeof(uint32_t) * VN);
+  L.starts = take(sizeof(uint32_t) * ((capacity + kEmitPairs - 1) / kEmitPairs + 1));
   L.dkeys0 = take(sizeof(uint32_t) * VN);
   L.dvals0 = take(sizeof(uint32_t) * VN);
   L.dkeys1 = take(sizeof(uint32_t) * VN);
@@ -413,20 +520,12 @@ Layout layout(int64_t VN, int64_t capacity) {
   L.tkeys0 = take(sizeof(uint32_t) * capacity);
   L.tkeys1 = take(sizeof(uint32_t) * capacity);
   L.pids1 = take(sizeof(uint32_t) * capacity);
-  L.hist = take(sizeof(uint32_t) * hist_n);
-  // block sums of the scans, and the 256 digit totals of a radix pass
-  const size_t sums_bytes = sizeof(uint64_t) * ((scan_n + kTile - 1) / kTile + 1);
-  L.sums = take(sums_bytes > sizeof(uint32_t) * kRadix ? sums_bytes : sizeof(uint32_t) * kRadix);
+  L.sort = take(sort_space_bytes(nmax));  // the depth sort's, then the tile sort's
+  // block sums of the scans
+  L.sums = take(sizeof(uint64_t) * ((nmax + kTile - 1) / kTile + 1));
   L.scal = take(64);
   L.total = o;
   return L;
-}
-
-// Scan block sums (unused by the radix passes now) or the 256 digit totals.
-inline size_t tile_order_sums_bytes(int64_t nb) {
-  const size_t a = sizeof(uint64_t) * (size_t)(nb * kRadix / kTile + 2);
-  const size_t b = sizeof(uint32_t) * kRadix;
-  return a > b ? a : b;
 }
 
 // Order key of a tile: 255 - 16 log2(len + 1), so longer lists come first.
@@ -445,25 +544,21 @@ k_order_keys(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __res
 }  // namespace
 
 size_t tile_order_workspace(int64_t tiles) {
-  const int64_t nb = (tiles + kTile - 1) / kTile + 1;
-  return align_up(sizeof(uint32_t) * tiles) * 3 + align_up(sizeof(uint32_t) * nb * kRadix) +
-         align_up(tile_order_sums_bytes(nb)) + 256;
+  return align_up(sizeof(uint32_t) * tiles) * 3 + sort_space_bytes(tiles) + 256;
 }
 
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st) {
   char* w = static_cast<char*>(ws);
-  const int64_t nb = (tiles + kTile - 1) / kTile + 1;
   uint32_t* k0 = (uint32_t*)w;
   uint32_t* v0 = (uint32_t*)(w + align_up(sizeof(uint32_t) * tiles));
   uint32_t* k1 = (uint32_t*)(w + 2 * align_up(sizeof(uint32_t) * tiles));
-  uint32_t* hist = (uint32_t*)(w + 3 * align_up(sizeof(uint32_t) * tiles));
-  uint32_t* sums = (uint32_t*)((char*)hist + align_up(sizeof(uint32_t) * nb * kRadix));
-  uint32_t* cnt = (uint32_t*)((char*)sums + align_up(tile_order_sums_bytes(nb)));
+  char* sw = w + 3 * align_up(sizeof(uint32_t) * tiles);
+  uint32_t* cnt = (uint32_t*)(sw + sort_space_bytes(tiles));
   hipLaunchKernelGGL(k_order_keys, dim3(blocks_for(tiles > 0 ? tiles : 1, kThreads)),
                      dim3(kThreads), 0, st, ranges, tiles, k0, v0, cnt);
   // one 8-bit pass: the result lands in (k1, order)
-  radix_sort(k0, v0, k1, order, tiles, cnt, 8, hist, sums, st);
+  radix_sort(k0, v0, k1, order, tiles, cnt, 8, sort_space(sw, tiles), st);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, order + tiles, 1, 0u);
   return hipGetLastError();
 }
@@ -480,7 +575,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   const int64_t VN = (int64_t)V * N;
   const Layout L = layout(VN, capacity);
   char* w = static_cast<char*>(ws);
-  uint32_t* vis_pos = (uint32_t*)(w + L.vis_pos);
+  uint32_t* starts = (uint32_t*)(w + L.starts);
   uint32_t* dk0 = (uint32_t*)(w + L.dkeys0);
   uint32_t* dv0 = (uint32_t*)(w + L.dvals0);
   uint32_t* dk1 = (uint32_t*)(w + L.dkeys1);
@@ -489,7 +584,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* tk0 = (uint32_t*)(w + L.tkeys0);
   uint32_t* tk1 = (uint32_t*)(w + L.tkeys1);
   uint32_t* pid1 = (uint32_t*)(w + L.pids1);
-  uint32_t* hist = (uint32_t*)(w + L.hist);
+  char* sortw = w + L.sort;
   void* sums = (void*)(w + L.sums);
   uint32_t* n_vis = (uint32_t*)(w + L.scal);
   uint64_t* m64 = (uint64_t*)(w + L.scal + 8);
@@ -501,18 +596,19 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
 
   // 1. visible splats -> compact (depth key, index) list
   if (VN > 0) {
-    scan<uint32_t>(FlagInput{tt}, VN, nullptr, vis_pos, (uint32_t*)sums, n_vis, st);
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(VN, kThreads)), dim3(kThreads), 0, st, tt,
-                       vis_pos, splats, VN, dk0, dv0);
+    scan_emit<uint32_t>(Visible{tt}, VN, (uint32_t*)sums, n_vis, VisibleOut{splats, dk0, dv0},
+                        st);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, n_vis, 1, 0u);
   }
   // 2. depth sort
-  const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, hist, (uint32_t*)sums, st);
+  const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st);
   uint32_t* sv = (dpasses & 1) ? dv1 : dv0;
   // 3. pair offsets in depth order
   if (VN > 0) {
-    scan<uint64_t>(GatherCount{tt, sv}, VN, n_vis, offs, (uint64_t*)sums, m64, st);
+    scan_to<uint64_t>(GatherCount{tt, sv}, VN, n_vis,
+                      OffsetsOut{offs, starts, (capacity + kEmitPairs - 1) / kEmitPairs},
+                      (uint64_t*)sums, m64, st);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, (uint32_t*)m64, 2, 0u);
   }
@@ -540,17 +636,19 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* ov = (tpasses & 1) ? pair_ids : pid1;
   if (VN > 0 && capacity > 0)
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(capacity, kEmitPairs)), dim3(kThreads), 0, st, sv,
-                       offs, n_vis, m64, capacity, splats, views_dev, N, s.tile_w, s.tile_h, ek,
-                       ev, (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0);
+                       offs, starts, n_vis, m64, capacity, splats, views_dev,
+                       FastDiv((uint32_t)(N > 0 ? N : 1)), ceil_log2(s.tile_w), ceil_log2(s.tile_h),
+                       ek, ev, (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0);
   // 5. stable sort by tile
-  radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, hist, (uint32_t*)sums, st);
+  radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, sort_space(sortw, capacity), st);
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;
   // 6. tile ranges
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * total_tiles, kThreads)), dim3(kThreads), 0,
-                     st, ranges, 2 * total_tiles, 0u);
   if (capacity > 0)
-    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(capacity, kThreads)), dim3(kThreads), 0, st, sk,
-                       m32, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(capacity + 1, 4 * kThreads)), dim3(kThreads), 0,
+                       st, sk, m32, total_tiles, ranges);
+  else
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * total_tiles, kThreads)), dim3(kThreads), 0,
+                       st, ranges, 2 * total_tiles, 0u);
   // 7. optional 64-bit keys
   if (keys && capacity > 0)
     hipLaunchKernelGGL(k_keys, dim3(blocks_for(capacity, kThreads)), dim3(kThreads), 0, st, sk,

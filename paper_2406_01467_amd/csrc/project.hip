@@ -514,7 +514,12 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     Geo G;
     if (!geometry(v, P, st, G) || !(G.detD > 0.0)) continue;
     go += gO;
-
+    {
+    // The backward's own arithmetic may use fused multiply-adds: its
+    // results are compared within a tolerance, while the shared pieces
+    // whose decisions must match the forward (the geometry, the colour sum
+    // for the clamp) are compiled in their own functions without.
+#pragma clang fp contract(fast)
     const double X = G.X, Yc = G.Y, Z = G.Z, tc = G.tc;
     const double iz = 1.0 / Z, iz2 = iz * iz;
     double gx[3];
@@ -674,6 +679,7 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
       sh_grad(deg, u[0], u[1], u[2], cw, gu);
       const double ud = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
       for (int i = 0; i < 3; ++i) gmu[i] += (gu[i] - u[i] * ud) * idn;
+    }
     }
   }
   // unit quaternion -> raw quaternion

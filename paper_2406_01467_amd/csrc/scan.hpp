@@ -83,10 +83,17 @@ k_scan_top(T* block_sums, int64_t nb, T* total_out) {
   if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
-// Phase 3: per-block exclusive scan plus the block's offset.
-template <typename T, typename In>
+// Phase 3: per-block exclusive scan plus the block's offset, handed to
+// out(item, offset, count).
+template <typename T>
+struct StoreOut {
+  T* a;
+  __device__ void operator()(int64_t i, T offset, T) const { a[i] = offset; }
+};
+
+template <typename T, typename In, typename Out>
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, T* out) {
+k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, Out out) {
   __shared__ T lw[kScanThreads / 64];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -102,23 +109,30 @@ k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, T*
   T run = block_exclusive_scan<T>(s, lw, total) + block_sums[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
+    if (base + k < n) out(base + k, run, v[k]);
     run += v[k];
   }
 }
 
-// Exclusive scan of in(0..n) into out (n = *n_dev, or n_max when n_dev is
-// NULL), total into *total.  Launch errors are left pending for the
+// Exclusive scan of in(0..n) handed to out (n = *n_dev, or n_max when n_dev
+// is NULL), total into *total.  Launch errors are left pending for the
 // caller's final hipGetLastError.
-template <typename T, typename In>
-void scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
-          hipStream_t st) {
+template <typename T, typename In, typename Out>
+void scan_to(In in, int64_t n_max, const uint32_t* n_dev, Out out, T* block_sums, T* total,
+             hipStream_t st) {
   const int64_t nb = n_max > 0 ? (n_max + kScanTile - 1) / kScanTile : 1;
   hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in,
                      n_max, n_dev, block_sums);
   hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kScanThreads), 0, st, block_sums, nb, total);
-  hipLaunchKernelGGL((k_scan_down<T, In>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n_max,
-                     n_dev, block_sums, out);
+  hipLaunchKernelGGL((k_scan_down<T, In, Out>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in,
+                     n_max, n_dev, (const T*)block_sums, out);
+}
+
+// The same, stored into out[0..n).
+template <typename T, typename In>
+void scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
+          hipStream_t st) {
+  scan_to<T>(in, n_max, n_dev, StoreOut<T>{out}, block_sums, total, st);
 }
 
 // Compaction: the exclusive scan of in() is handed, for every item with a
