@@ -29,7 +29,7 @@ constexpr int kTile = kScanTile;                // items per block (2048)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-constexpr int kEmitPairs = 1024;                 // pairs per emission block
+constexpr int kEmitPairs = kTile;                // pairs per emission block (one radix block)
 
 // Compaction of the visible splats (tiles touched > 0) into the depth sort's
 // (key, value) arrays: key = bits of the float32 view depth, value = index.
@@ -47,11 +47,11 @@ struct VisibleOut {
   }
 };
 
-// Tiles touched by the j-th depth-sorted splat.
-struct GatherCount {
-  const int32_t* tt;
-  const uint32_t* vals;
-  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)tt[vals[j]]; }
+// Tiles touched by the j-th depth-sorted splat (gathered by the depth
+// sort's last pass).
+struct SortedCount {
+  const uint32_t* cnt;
+  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)cnt[j]; }
 };
 // Pair offsets of the depth-sorted splats, and for every emission block the
 // splat that holds its first pair: block b starts in splat j when
@@ -150,7 +150,7 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
   for (int r = 0; r < kItems; ++r)
     if (item_index(base, r) < n) atomicAdd(&h[digit_of(key[r], shift)], 1u);
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
+  if (threadIdx.x < kRadix) hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
 }
 
 // Exclusive scan of one digit's row of per-block counts (one workgroup per
@@ -182,13 +182,16 @@ k_radix_colscan(uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restri
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// Shared memory of one sorting workgroup.
+// Shared memory of one sorting workgroup (GATHER: also the gathered
+// companion values).
+template <bool GATHER>
 struct RankShared {
   uint32_t wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave digit starts
   uint32_t lstart[kRadix];        // first local position of each digit
   uint32_t dbase[kRadix];         // global position of each digit's run
   uint32_t skey[kTile];
   uint32_t sval[kTile];
+  uint32_t sgat[GATHER ? kTile : 1];
   uint64_t lw[kWaves];
 };
 
@@ -200,13 +203,16 @@ struct RankShared {
 // starts (the local counts sum to at most kTile, so the halves never carry
 // into each other).  The block is then sorted in LDS and each digit's run
 // written contiguously at its region start plus the row-scanned count of
-// the blocks before this one.
+// the blocks before this one.  GATHER: each item also carries gsrc[value]
+// (gsrc has gn entries), written to gout in the sorted order.
+template <bool GATHER>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int64_t n_max, int shift, int64_t nblocks,
-                const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot) {
-  __shared__ RankShared sh;
+                const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot,
+                const int32_t* __restrict__ gsrc, int64_t gn, uint32_t* __restrict__ gout) {
+  __shared__ RankShared<GATHER> sh;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t base = blk * kTile;
   const int lane = threadIdx.x & 63;
@@ -220,6 +226,15 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     const bool inb = i < n_max;
     key[r] = inb ? kin[i] : 0u;
     val[r] = inb ? vin[i] : 0u;
+  }
+  uint32_t gat[GATHER ? kItems : 1];
+  if constexpr (GATHER) {
+    // values past the item count are not indices: clamped into the source
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+      gat[r] = item_index(base, r) < n_max
+                   ? (uint32_t)gsrc[val[r] < (uint64_t)gn ? val[r] : (uint32_t)(gn - 1)]
+                   : 0u;
   }
   const uint32_t dtot_d = dtot[threadIdx.x];
   const uint32_t goff_d = offsets[(int64_t)threadIdx.x * nblocks + blk];
@@ -264,6 +279,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
       const uint32_t p = pos[r] + sh.lstart[d] + sh.wcnt[wave][d];
       sh.skey[p] = key[r];
       sh.sval[p] = val[r];
+      if constexpr (GATHER) sh.sgat[p] = gat[r];
     }
   }
   __syncthreads();
@@ -274,103 +290,116 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     const uint32_t dst = sh.dbase[d] + ((uint32_t)i - sh.lstart[d]);
     kout[dst] = k;
     vout[dst] = sh.sval[i];
+    if constexpr (GATHER) gout[dst] = sh.sgat[i];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pair emission, four consecutive pairs per thread: pair p belongs to the
 // depth-sorted splat j with offs[j] <= p < offs[j + 1] and is its
-// (p - offs[j])-th tile in row-major order of its tile rect.  A block covers
+// (p - offs[j])-th tile in row-major order of its tile rect.  Block b (a
+// radix block of the tile sort, remapped like the sort's blocks) covers
 // kEmitPairs consecutive pairs, hence at most kEmitPairs consecutive splats
-// (each has >= 1 pair), starting with starts[block]: their offsets are
+// (each has >= 1 pair), starting with starts[b]: their offsets and ids are
 // staged in LDS.  Writes are coalesced and the work is balanced whatever the
-// splat sizes.
-constexpr int kEmitPerThread = kEmitPairs / kThreads;  // 4 consecutive pairs
+// splat sizes.  The block also counts the low 8 bits of its tile keys, the
+// per-block digit counts of the tile sort's first pass.
+constexpr int kEmitThreads = 512;
+constexpr int kEmitPerThread = kEmitPairs / kEmitThreads;  // 4 consecutive pairs
 static_assert(kEmitPerThread == 4, "emit stores four pairs as one 16-byte word");
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kEmitThreads)
 k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
        const uint32_t* __restrict__ starts, const uint32_t* __restrict__ n_dev,
        const uint64_t* __restrict__ m_dev, int64_t capacity,
        const rade_splat* __restrict__ splats, const rade_view* __restrict__ views, FastDiv div_n,
        int log2_tw, int log2_th, uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids,
-       int vec_stores) {
+       int vec_stores, int64_t nblocks, uint32_t* __restrict__ hist) {
   __shared__ uint64_t win[kEmitPairs + 1];
   __shared__ uint32_t wid[kEmitPairs + 1];
+  __shared__ uint32_t h[kRadix];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint64_t M = *m_dev;
   const int64_t nvis = *n_dev;
-  const int64_t j0 = starts[blockIdx.x];
-  const uint64_t P0 = (uint64_t)blockIdx.x * kEmitPairs;
-  if (P0 >= M || M > (uint64_t)capacity) return;  // uniform per block
-  for (int w = threadIdx.x; w <= kEmitPairs; w += kThreads) {
+  const int64_t j0 = starts[blk];
+  const uint64_t P0 = (uint64_t)blk * kEmitPairs;
+  if (threadIdx.x < kRadix) h[threadIdx.x] = 0u;
+  if (P0 >= M || M > (uint64_t)capacity) {  // uniform per block
+    if (threadIdx.x < kRadix) hist[(int64_t)threadIdx.x * nblocks + blk] = 0u;
+    return;
+  }
+  for (int w = threadIdx.x; w <= kEmitPairs; w += kEmitThreads) {
     const int64_t j = j0 + w;
     const bool in = j < nvis;
     win[w] = in ? offs[j] : M;
     wid[w] = in ? svals[j] : 0u;
   }
   __syncthreads();
-  // Four consecutive pairs per thread: the first one's splat by binary
-  // search in the window, the next ones by stepping forward (every listed
-  // splat has at least one pair, so this is at most one step per pair); one
-  // 16-byte store per output array when all four exist.
+  // The first pair's splat by binary search in the window, the next ones by
+  // stepping forward (every listed splat has at least one pair, so this is
+  // at most one step per pair).
   const uint64_t pb = P0 + (uint64_t)kEmitPerThread * threadIdx.x;
-  if (pb >= M) return;
-  int lo = 0, hi = kEmitPairs;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (win[mid] <= pb) lo = mid; else hi = mid - 1;
-  }
   uint32_t tk[kEmitPerThread], pg[kEmitPerThread];
-  int cur = -1;
-  uint32_t tx0 = 0, ty0 = 0, ty1 = 0, nx = 1, g = 0, toff = 0, tiles_x = 0, row = 0, col = 0;
-#pragma unroll
-  for (int r = 0; r < kEmitPerThread; ++r) {
-    const uint64_t p = pb + r;
-    tk[r] = 0u;
-    pg[r] = 0u;
-    if (p >= M) continue;
-    while (lo < kEmitPairs && win[lo + 1] <= p) ++lo;
-    if (lo != cur) {
-      cur = lo;
-      // V*N < 2^32 (32-bit ids); a visible splat's rect lies inside its
-      // view, so its pixel bounds are non-negative and the tile bounds are
-      // shifts (tile sizes are powers of two)
-      const uint32_t i = wid[lo];
-      const uint32_t v = div_n.div(i);
-      g = i - v * div_n.d;
-      const rade_splat& sp = splats[i];
-      tx0 = (uint32_t)sp.rect[0] >> log2_tw;
-      const uint32_t tx1 = (uint32_t)sp.rect[1] >> log2_tw;
-      ty0 = (uint32_t)sp.rect[2] >> log2_th;
-      ty1 = (uint32_t)sp.rect[3] >> log2_th;
-      nx = tx1 - tx0 + 1;
-      toff = (uint32_t)views[v].tile_offset;
-      tiles_x = (uint32_t)views[v].tiles_x;
-      // pair k of the splat is its k-th tile in row-major order of its rect
-      // (k > 0 only for the thread's first pair)
-      const uint32_t k = (uint32_t)(p - win[lo]);
-      row = k / nx;
-      col = k - row * nx;
-    } else if (++col == nx) {
-      col = 0;
-      ++row;
+  if (pb < M) {
+    int lo = 0, hi = kEmitPairs;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (win[mid] <= pb) lo = mid; else hi = mid - 1;
     }
-    // stay inside the rect even if tiles_touched disagrees with it
-    const uint32_t ty = min(ty0 + row, ty1);
-    tk[r] = toff + ty * tiles_x + tx0 + col;
-    pg[r] = g;
-  }
-  if (vec_stores && pb + kEmitPerThread <= M) {
-    *reinterpret_cast<uint4*>(tkeys + pb) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
-    *reinterpret_cast<uint4*>(pids + pb) = make_uint4(pg[0], pg[1], pg[2], pg[3]);
-  } else {
+    int cur = -1;
+    uint32_t tx0 = 0, ty0 = 0, ty1 = 0, nx = 1, g = 0, toff = 0, tiles_x = 0, row = 0, col = 0;
 #pragma unroll
-    for (int r = 0; r < kEmitPerThread; ++r)
-      if (pb + r < M) {
-        tkeys[pb + r] = tk[r];
-        pids[pb + r] = pg[r];
+    for (int r = 0; r < kEmitPerThread; ++r) {
+      const uint64_t p = pb + r;
+      tk[r] = 0u;
+      pg[r] = 0u;
+      if (p >= M) continue;
+      while (lo < kEmitPairs && win[lo + 1] <= p) ++lo;
+      if (lo != cur) {
+        cur = lo;
+        // V*N < 2^32 (32-bit ids); a visible splat's rect lies inside its
+        // view, so its pixel bounds are non-negative and the tile bounds are
+        // shifts (tile sizes are powers of two)
+        const uint32_t i = wid[lo];
+        const uint32_t v = div_n.div(i);
+        g = i - v * div_n.d;
+        const rade_splat& sp = splats[i];
+        tx0 = (uint32_t)sp.rect[0] >> log2_tw;
+        const uint32_t tx1 = (uint32_t)sp.rect[1] >> log2_tw;
+        ty0 = (uint32_t)sp.rect[2] >> log2_th;
+        ty1 = (uint32_t)sp.rect[3] >> log2_th;
+        nx = tx1 - tx0 + 1;
+        toff = (uint32_t)views[v].tile_offset;
+        tiles_x = (uint32_t)views[v].tiles_x;
+        // pair k of the splat is its k-th tile in row-major order of its
+        // rect (k > 0 only for the thread's first pair)
+        const uint32_t k = (uint32_t)(p - win[lo]);
+        row = k / nx;
+        col = k - row * nx;
+      } else if (++col == nx) {
+        col = 0;
+        ++row;
       }
+      // stay inside the rect even if tiles_touched disagrees with it
+      const uint32_t ty = min(ty0 + row, ty1);
+      tk[r] = toff + ty * tiles_x + tx0 + col;
+      pg[r] = g;
+      atomicAdd(&h[tk[r] & (kRadix - 1)], 1u);
+    }
+    if (vec_stores && pb + kEmitPerThread <= M) {
+      *reinterpret_cast<uint4*>(tkeys + pb) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+      *reinterpret_cast<uint4*>(pids + pb) = make_uint4(pg[0], pg[1], pg[2], pg[3]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kEmitPerThread; ++r)
+        if (pb + r < M) {
+          tkeys[pb + r] = tk[r];
+          pids[pb + r] = pg[r];
+        }
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < kRadix) hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -475,8 +504,13 @@ inline SortSpace sort_space(char* w, int64_t n_max) {
 // Sorts (keys, vals) of *n_dev items (at most n_max < 2^32) by the low
 // `bits` bits of the keys; on return the sorted data are in (k0, v0) when the
 // number of passes is even, else in (k1, v1).  Returns the number of passes.
+// first_counted: the first pass's per-block counts are already in sp.hist.
+// gsrc: the last pass also writes gsrc[value] of every item, in the sorted
+// order, to gout.
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
-               const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st) {
+               const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
+               bool first_counted = false, const int32_t* gsrc = nullptr, int64_t gn = 0,
+               uint32_t* gout = nullptr) {
   const int64_t nb = sort_blocks(n_max);
   const int passes = bits > kRadixBits ? (bits + kRadixBits - 1) / kRadixBits : 1;
   for (int p = 0; p < passes; ++p) {
@@ -485,18 +519,25 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n
     uint32_t* vi = (p & 1) ? v1 : v0;
     uint32_t* ko = (p & 1) ? k0 : k1;
     uint32_t* vo = (p & 1) ? v0 : v1;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev, n_max,
-                       shift, nb, sp.hist);
+    if (p > 0 || !first_counted)
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev,
+                         n_max, shift, nb, sp.hist);
     hipLaunchKernelGGL(k_radix_colscan, dim3(kRadix), dim3(kThreads), 0, st, sp.hist, nb, sp.dtot);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
-                       n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
-                       (const uint32_t*)sp.dtot);
+    if (gsrc && p == passes - 1)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi,
+                         ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
+                         (const uint32_t*)sp.dtot, gsrc, gn, gout);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki,
+                         vi, ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
+                         (const uint32_t*)sp.dtot, (const int32_t*)nullptr, (int64_t)0,
+                         (uint32_t*)nullptr);
   }
   return passes;
 }
 
 struct Layout {
-  size_t starts, dkeys0, dvals0, dkeys1, dvals1, offs, tkeys0, tkeys1, pids1, sort, sums, scal;
+  size_t starts, dkeys0, dvals0, dkeys1, dvals1, dcnt, offs, tkeys0, tkeys1, pids1, sort, sums, scal;
   size_t total;
 };
 
@@ -516,6 +557,7 @@ Layout layout(int64_t VN, int64_t capacity) {
   L.dvals0 = take(sizeof(uint32_t) * VN);
   L.dkeys1 = take(sizeof(uint32_t) * VN);
   L.dvals1 = take(sizeof(uint32_t) * VN);
+  L.dcnt = take(sizeof(uint32_t) * VN);
   L.offs = take(sizeof(uint64_t) * VN);
   L.tkeys0 = take(sizeof(uint32_t) * capacity);
   L.tkeys1 = take(sizeof(uint32_t) * capacity);
@@ -580,6 +622,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* dv0 = (uint32_t*)(w + L.dvals0);
   uint32_t* dk1 = (uint32_t*)(w + L.dkeys1);
   uint32_t* dv1 = (uint32_t*)(w + L.dvals1);
+  uint32_t* dcnt = (uint32_t*)(w + L.dcnt);
   uint64_t* offs = (uint64_t*)(w + L.offs);
   uint32_t* tk0 = (uint32_t*)(w + L.tkeys0);
   uint32_t* tk1 = (uint32_t*)(w + L.tkeys1);
@@ -602,11 +645,12 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, n_vis, 1, 0u);
   }
   // 2. depth sort
-  const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st);
+  const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st,
+                                 false, tt, VN, dcnt);
   uint32_t* sv = (dpasses & 1) ? dv1 : dv0;
   // 3. pair offsets in depth order
   if (VN > 0) {
-    scan_to<uint64_t>(GatherCount{tt, sv}, VN, n_vis,
+    scan_to<uint64_t>(SortedCount{dcnt}, VN, n_vis,
                       OffsetsOut{offs, starts, (capacity + kEmitPairs - 1) / kEmitPairs},
                       (uint64_t*)sums, m64, st);
   } else {
@@ -634,13 +678,18 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* ev = (tpasses & 1) ? pid1 : pair_ids;
   uint32_t* ok_ = tk1;
   uint32_t* ov = (tpasses & 1) ? pair_ids : pid1;
-  if (VN > 0 && capacity > 0)
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(capacity, kEmitPairs)), dim3(kThreads), 0, st, sv,
+  // (the emission also counts the tile sort's first digits, per block)
+  const SortSpace tsp = sort_space(sortw, capacity);
+  const bool emitted = VN > 0 && capacity > 0;
+  static_assert(kEmitPairs == kTile, "emission blocks are the tile sort's blocks");
+  if (emitted)
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)sort_blocks(capacity)), dim3(kEmitThreads), 0, st, sv,
                        offs, starts, n_vis, m64, capacity, splats, views_dev,
                        FastDiv((uint32_t)(N > 0 ? N : 1)), ceil_log2(s.tile_w), ceil_log2(s.tile_h),
-                       ek, ev, (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0);
+                       ek, ev, (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0,
+                       sort_blocks(capacity), tsp.hist);
   // 5. stable sort by tile
-  radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, sort_space(sortw, capacity), st);
+  radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, tsp, st, emitted);
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;
   // 6. tile ranges
   if (capacity > 0)
