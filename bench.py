@@ -69,9 +69,9 @@ BYTES_PER_PIXEL = 52 + 52 + 36
 # in the launch configuration it was measured in (tile, schedule, wave shape,
 # batch); reported as null otherwise.
 MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
-                    "schedule": 0, "wave_w": 0, "batch": 0,
-                    "sources_sha1": "b1f409bbf38706c0750f360da12547c53e591dcd",
-                    "fetch_bytes": 363054020, "write_bytes": 154785088,
+                    "schedule": 1, "wave_w": 0, "batch": 0,
+                    "sources_sha1": "3e7df1bc5e0559767445eb3d878e6f5f03abd41f",
+                    "fetch_bytes": 375021493, "write_bytes": 154785088,
                     "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
 
 
