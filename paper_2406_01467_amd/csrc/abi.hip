@@ -44,7 +44,8 @@ size_t normal_consistency_workspace(int64_t total_pixels);
 hipError_t launch_l1_color_grad(const rade_view* views, int V, int64_t total, const float* color,
                                 const float* target, double weight, float* d_color,
                                 hipStream_t st);
-hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
+hipError_t launch_normal_consistency(const rade_view* views_host, const rade_view* views, int V,
+                                     int64_t total,
                                      const float* depth, const float* normal,
                                      const float* alpha, float weight, float* loss,
                                      float* d_depth, float* d_normal, float* d_alpha,
@@ -279,7 +280,8 @@ int rade_normal_consistency(const rade_view* views_host, const rade_view* views_
   }
   if (!workspace || workspace_bytes < rade_normal_consistency_workspace(total))
     return RADE_ERR_WORKSPACE;
-  return hip_status(rade::launch_normal_consistency(views_dev, V, total, depth, normal, alpha,
+  return hip_status(rade::launch_normal_consistency(views_host, views_dev, V, total, depth,
+                                                    normal, alpha,
                                                     weight, loss, d_depth, d_normal, d_alpha,
                                                     accumulate != 0, workspace,
                                                     (hipStream_t)stream));

@@ -23,69 +23,110 @@ __device__ __forceinline__ int view_of_pixel(const rade_view* views, int V, int6
   return v;
 }
 
-// Pass 1: per interior pixel, the loss term, dL/dA, dL/dN and the gradients
-// of the two difference vectors (6 floats, kept for pass 2).  ACC adds the
-// gradients into the maps; otherwise every pixel's entries are written
-// (0 + x, so the bits equal adding into zeroed maps; border pixels get 0).
+// The loss and its gradient in one kernel over 16 x 16 pixel blocks of each
+// view (blocks of the views back to back).  Per pixel the arithmetic is that
+// of the two passes it replaces: the loss term, dL/dA, dL/dN and the
+// gradients of the two difference vectors (6 floats) for every interior
+// pixel, then dL/dD_med(q) = r(q) . (g_du(q-x) - g_du(q+x) + g_dv(q-y) -
+// g_dv(q+y)).  The block computes the difference-vector gradients for itself
+// and a one-pixel ring around it (from the median depths of a two-pixel
+// ring, staged in LDS), so none of them goes through memory.  ACC adds the
+// gradients into the maps; otherwise every pixel's entries are written (0 +
+// x, so the bits equal adding into zeroed maps; border pixels and the
+// expected-depth plane get 0).  The block's loss sum goes to partial[block].
+constexpr int kNB = 16;           // block side in pixels (kNB * kNB == kT)
+constexpr int kNG = kNB + 2;      // with the ring of difference-vector gradients
+constexpr int kNDp = kNB + 4;     // with the ring of depths they read
+static_assert(kNB * kNB == kT, "one thread per pixel of a block");
+
+__device__ __forceinline__ int nc_blocks_x(const rade_view& vw) { return (vw.width + kNB - 1) / kNB; }
+__device__ __forceinline__ int64_t nc_blocks(const rade_view& vw) {
+  return (int64_t)nc_blocks_x(vw) * ((vw.height + kNB - 1) / kNB);
+}
+
+// View of block b and the view's first block index.
+__device__ __forceinline__ int nc_view_of_block(const rade_view* views, int V, int64_t b,
+                                                int64_t& first) {
+  int64_t acc = 0;
+  for (int v = 0; v < V; ++v) {
+    const int64_t n = nc_blocks(views[v]);
+    if (b < acc + n || v == V - 1) {
+      first = acc;
+      return v;
+    }
+    acc += n;
+  }
+  first = 0;
+  return 0;
+}
+
 template <bool ACC>
 __global__ void __launch_bounds__(kT)
-k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const float* __restrict__ depth,
-           const float* __restrict__ normal, const float* __restrict__ alpha, float weight,
-           float* __restrict__ loss, float* __restrict__ d_normal, float* __restrict__ d_alpha,
-           float* __restrict__ gdiff, float* __restrict__ partial) {
-  const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* __restrict__ depth,
+     const float* __restrict__ normal, const float* __restrict__ alpha, float weight,
+     float* __restrict__ d_depth, float* __restrict__ d_normal, float* __restrict__ d_alpha,
+     float* __restrict__ partial) {
+  __shared__ float sD[kNDp * kNDp];
+  __shared__ float sG[6][kNG * kNG];
+  __shared__ float red[kT / 64];
+  const int64_t b = blockIdx.x;
+  if (b >= nblocks) return;  // uniform per block
+  int64_t first;
+  const int v = nc_view_of_block(views, V, b, first);
+  const rade_view& vw = views[v];
+  const int W = vw.width, H = vw.height;
+  const int nbx = nc_blocks_x(vw);
+  const int bi = (int)(b - first);
+  const int x0 = (bi % nbx) * kNB, y0 = (bi / nbx) * kNB;
+  const int64_t o = vw.pix_offset, P = (int64_t)W * H;
+  const float* Dm = depth + 2 * o + P;  // median plane
+  const float wn = weight / (float)((W - 2) * (H - 2));
+  // median depths of the block and a two-pixel ring (0 outside the view)
+  for (int i = threadIdx.x; i < kNDp * kNDp; i += kT) {
+    const int x = x0 - 2 + i % kNDp, y = y0 - 2 + i / kNDp;
+    sD[i] = (x >= 0 && y >= 0 && x < W && y < H) ? Dm[(int64_t)y * W + x] : 0.0f;
+  }
+  __syncthreads();
   float term = 0.0f;
-  int v = 0;
-  if (q < total) {
-    v = view_of_pixel(views, V, q);
-    const rade_view& vw = views[v];
-    const int64_t o = vw.pix_offset, P = (int64_t)vw.width * vw.height;
-    const int64_t pix = q - o;
-    const int px = (int)(pix % vw.width), py = (int)(pix / vw.width);
-    float* gd = gdiff + 6 * q;
-    const bool interior = px >= 1 && py >= 1 && px <= vw.width - 2 && py <= vw.height - 2;
-    if (!interior) {
-      for (int k = 0; k < 6; ++k) gd[k] = 0.0f;
-      if constexpr (!ACC) {
-        d_alpha[o + pix] = 0.0f;
-        d_normal[3 * o + pix] = 0.0f;
-        d_normal[3 * o + P + pix] = 0.0f;
-        d_normal[3 * o + 2 * P + pix] = 0.0f;
-      }
-    } else {
-      const float wn = weight / (float)((vw.width - 2) * (vw.height - 2));
-      const float* Dm = depth + 2 * o + P;  // median plane
-      // Central differences of the back-projected points, written through
+  // pass 1 over the block and a one-pixel ring; region pixel i = (gx, gy)
+  for (int i = threadIdx.x; i < kNG * kNG; i += kT) {
+    const int gx = i % kNG, gy = i / kNG;
+    const int px = x0 - 1 + gx, py = y0 - 1 + gy;
+    const bool own = gx >= 1 && gy >= 1 && gx <= kNB && gy <= kNB && px < W && py < H;
+    const bool interior = px >= 1 && py >= 1 && px <= W - 2 && py <= H - 2;
+    float gd[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int64_t pix = (int64_t)py * W + px;
+    if (interior) {
+      // central differences of the back-projected points, written through
       // depth differences so FP32 does not cancel |P| ~ D against |dP| ~ D/f:
-      // P(p +- x) = D(p +- x) (r(p) +- (1/fx, 0, 0)), r(p) = (rx, ry, 1).
+      // P(p +- x) = D(p +- x) (r(p) +- (1/fx, 0, 0)), r(p) = (rx, ry, 1)
       const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
       const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
-      const float Dl = Dm[pix - 1], Dr = Dm[pix + 1];
-      const float Du = Dm[pix - vw.width], Dd = Dm[pix + vw.width];
+      const int c = (gy + 1) * kNDp + (gx + 1);  // this pixel in sD
+      const float Dl = sD[c - 1], Dr = sD[c + 1];
+      const float Du = sD[c - kNDp], Dd = sD[c + kNDp];
       const float dx_ = Dr - Dl, sx = Dr + Dl;
       const float dy_ = Dd - Du, sy = Dd + Du;
       const float du[3] = {dx_ * rx + sx / vw.fx, dx_ * ry, dx_};
       const float dv[3] = {dy_ * rx, dy_ * ry + sy / vw.fy, dy_};
-      const float Pc[3] = {Dm[pix] * rx, Dm[pix] * ry, Dm[pix]};
-      const float c[3] = {du[1] * dv[2] - du[2] * dv[1], du[2] * dv[0] - du[0] * dv[2],
-                          du[0] * dv[1] - du[1] * dv[0]};
-      const float cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+      const float Pc[3] = {sD[c] * rx, sD[c] * ry, sD[c]};
+      const float cr[3] = {du[1] * dv[2] - du[2] * dv[1], du[2] * dv[0] - du[0] * dv[2],
+                           du[0] * dv[1] - du[1] * dv[0]};
+      const float cc = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
       const float N0 = normal[3 * o + pix], N1 = normal[3 * o + P + pix],
                   N2 = normal[3 * o + 2 * P + pix];
-      const float A = alpha[o + pix];
       float nt[3] = {0.f, 0.f, 0.f};
       float gc[3] = {0.f, 0.f, 0.f};
       if (cc > 1e-30f) {
         const float inv = rsqrtf(cc);
-        const float s = (c[0] * Pc[0] + c[1] * Pc[1] + c[2] * Pc[2]) > 0.0f ? -1.0f : 1.0f;
-        const float ch[3] = {c[0] * inv, c[1] * inv, c[2] * inv};
+        const float s = (cr[0] * Pc[0] + cr[1] * Pc[1] + cr[2] * Pc[2]) > 0.0f ? -1.0f : 1.0f;
+        const float ch[3] = {cr[0] * inv, cr[1] * inv, cr[2] * inv};
         for (int k = 0; k < 3; ++k) nt[k] = s * ch[k];
         // dL/dc = -wn d(N . n~)/dc = -wn s (N - (N . c^) c^) / |c|
         const float nd = N0 * ch[0] + N1 * ch[1] + N2 * ch[2];
         const float Nv[3] = {N0, N1, N2};
         for (int k = 0; k < 3; ++k) gc[k] = -wn * s * (Nv[k] - nd * ch[k]) * inv;
       }
-      term = A - (N0 * nt[0] + N1 * nt[1] + N2 * nt[2]);
       // d/d(du) = dv x gc, d/d(dv) = gc x du
       gd[0] = dv[1] * gc[2] - dv[2] * gc[1];
       gd[1] = dv[2] * gc[0] - dv[0] * gc[2];
@@ -93,41 +134,61 @@ k_nc_pass1(const rade_view* __restrict__ views, int V, int64_t total, const floa
       gd[3] = gc[1] * du[2] - gc[2] * du[1];
       gd[4] = gc[2] * du[0] - gc[0] * du[2];
       gd[5] = gc[0] * du[1] - gc[1] * du[0];
-      const float a0 = ACC ? d_alpha[o + pix] : 0.0f;
-      const float n0 = ACC ? d_normal[3 * o + pix] : 0.0f;
-      const float n1 = ACC ? d_normal[3 * o + P + pix] : 0.0f;
-      const float n2 = ACC ? d_normal[3 * o + 2 * P + pix] : 0.0f;
-      d_alpha[o + pix] = a0 + wn;
-      d_normal[3 * o + pix] = n0 - wn * nt[0];
-      d_normal[3 * o + P + pix] = n1 - wn * nt[1];
-      d_normal[3 * o + 2 * P + pix] = n2 - wn * nt[2];
-      term *= wn;
+      if (own) {
+        const float A = alpha[o + pix];
+        term += (A - (N0 * nt[0] + N1 * nt[1] + N2 * nt[2])) * wn;
+        const float a0 = ACC ? d_alpha[o + pix] : 0.0f;
+        const float n0 = ACC ? d_normal[3 * o + pix] : 0.0f;
+        const float n1 = ACC ? d_normal[3 * o + P + pix] : 0.0f;
+        const float n2 = ACC ? d_normal[3 * o + 2 * P + pix] : 0.0f;
+        d_alpha[o + pix] = a0 + wn;
+        d_normal[3 * o + pix] = n0 - wn * nt[0];
+        d_normal[3 * o + P + pix] = n1 - wn * nt[1];
+        d_normal[3 * o + 2 * P + pix] = n2 - wn * nt[2];
+      }
+    } else if (own && !ACC) {
+      d_alpha[o + pix] = 0.0f;
+      d_normal[3 * o + pix] = 0.0f;
+      d_normal[3 * o + P + pix] = 0.0f;
+      d_normal[3 * o + 2 * P + pix] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sG[k][i] = gd[k];
+  }
+  __syncthreads();
+  // pass 2 for the block's own pixels
+  {
+    const int lx = threadIdx.x % kNB, ly = threadIdx.x / kNB;
+    const int px = x0 + lx, py = y0 + ly;
+    if (px < W && py < H) {
+      const int i = (ly + 1) * kNG + (lx + 1);
+      float g[3] = {0.f, 0.f, 0.f};
+      // a neighbour's entries are zero when it is not interior
+      if (px >= 1) for (int k = 0; k < 3; ++k) g[k] += sG[k][i - 1];
+      if (px + 1 < W) for (int k = 0; k < 3; ++k) g[k] -= sG[k][i + 1];
+      if (py >= 1) for (int k = 0; k < 3; ++k) g[k] += sG[3 + k][i - kNG];
+      if (py + 1 < H) for (int k = 0; k < 3; ++k) g[k] -= sG[3 + k][i + kNG];
+      const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
+      const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
+      const int64_t pix = (int64_t)py * W + px;
+      const float prev = ACC ? d_depth[2 * o + P + pix] : 0.0f;
+      d_depth[2 * o + P + pix] = prev + (g[0] * rx + g[1] * ry + g[2]);
+      if constexpr (!ACC) d_depth[2 * o + pix] = 0.0f;
     }
   }
-  // loss value: a workgroup inside one view writes its sum to partial[block]
-  // (added up per view by k_nc_sum); a workgroup that straddles two views
-  // (rare) writes 0 there and adds its terms per lane.
-  __shared__ float red[kT / 64];
-  const int64_t q0 = (int64_t)blockIdx.x * kT;
-  const int64_t q1 = min(total, q0 + kT) - 1;
-  const int v0 = view_of_pixel(views, V, q0), v1 = view_of_pixel(views, V, q1);
-  if (v0 == v1) {
-    float x = term;
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float t = 0.0f;
-      for (int i = 0; i < kT / 64; ++i) t += red[i];
-      partial[blockIdx.x] = t;
-    }
-  } else {
-    if (threadIdx.x == 0) partial[blockIdx.x] = 0.0f;
-    if (term != 0.0f) atomicAdd(loss + v, term);
+  // the block's loss sum (a thread's terms are those of its own pixels)
+  float x = term;
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int k = 0; k < kT / 64; ++k) t += red[k];
+    partial[b] = t;
   }
 }
 
-// Loss per view: workgroup (v, c) sums chunk c of view v's pass-1 partials
+// Loss per view: workgroup (v, c) sums chunk c of view v's block partials
 // and adds it to loss[v] (kSumChunks atomics per view).
 constexpr int kSumChunks = 32;
 
@@ -135,9 +196,9 @@ __global__ void __launch_bounds__(kT)
 k_nc_sum(const rade_view* __restrict__ views, const float* __restrict__ partial,
          float* __restrict__ loss) {
   __shared__ float red[kT / 64];
-  const rade_view& vw = views[blockIdx.x];
-  const int64_t b0 = vw.pix_offset / kT;
-  const int64_t b1 = (vw.pix_offset + (int64_t)vw.width * vw.height + kT - 1) / kT;
+  int64_t b0 = 0;
+  for (int v = 0; v < (int)blockIdx.x; ++v) b0 += nc_blocks(views[v]);
+  const int64_t b1 = b0 + nc_blocks(views[blockIdx.x]);
   const int64_t per = (b1 - b0 + kSumChunks - 1) / kSumChunks;
   const int64_t c0 = b0 + (int64_t)blockIdx.y * per, c1 = min(b1, c0 + per);
   float x = 0.0f;
@@ -150,32 +211,6 @@ k_nc_sum(const rade_view* __restrict__ views, const float* __restrict__ partial,
     for (int i = 0; i < kT / 64; ++i) t += red[i];
     if (c0 < c1) atomicAdd(loss + blockIdx.x, t);
   }
-}
-
-// Pass 2: dL/dD_med(q) = r(q) . (g_du(q-x) - g_du(q+x) + g_dv(q-y) - g_dv(q+y)).
-// Without ACC both depth planes are written (the expected-depth plane gets 0).
-template <bool ACC>
-__global__ void __launch_bounds__(kT)
-k_nc_pass2(const rade_view* __restrict__ views, int V, int64_t total,
-           const float* __restrict__ gdiff, float* __restrict__ d_depth) {
-  const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (q >= total) return;
-  const int v = view_of_pixel(views, V, q);
-  const rade_view& vw = views[v];
-  const int64_t o = vw.pix_offset, P = (int64_t)vw.width * vw.height;
-  const int64_t pix = q - o;
-  const int px = (int)(pix % vw.width), py = (int)(pix / vw.width);
-  float g[3] = {0.f, 0.f, 0.f};
-  // each neighbour's entry is zero when that neighbour is not interior
-  if (px >= 1) for (int k = 0; k < 3; ++k) g[k] += gdiff[6 * (q - 1) + k];
-  if (px + 1 < vw.width) for (int k = 0; k < 3; ++k) g[k] -= gdiff[6 * (q + 1) + k];
-  if (py >= 1) for (int k = 0; k < 3; ++k) g[k] += gdiff[6 * (q - vw.width) + 3 + k];
-  if (py + 1 < vw.height) for (int k = 0; k < 3; ++k) g[k] -= gdiff[6 * (q + vw.width) + 3 + k];
-  const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
-  const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
-  const float prev = ACC ? d_depth[2 * o + P + pix] : 0.0f;
-  d_depth[2 * o + P + pix] = prev + (g[0] * rx + g[1] * ry + g[2]);
-  if constexpr (!ACC) d_depth[2 * o + pix] = 0.0f;
 }
 
 // Gradient of the mean absolute colour difference of each view (3 planes):
@@ -206,34 +241,29 @@ __global__ void k_zero_f(float* __restrict__ a, int n) {
 
 }  // namespace
 
+// One loss partial per 16 x 16 block; every block holds at least one pixel.
 size_t normal_consistency_workspace(int64_t total_pixels) {
-  const int64_t blocks = (total_pixels + kT - 1) / kT;
-  return (size_t)total_pixels * 6 * sizeof(float) + (size_t)blocks * sizeof(float) + 256;
+  return (size_t)total_pixels * sizeof(float) + 256;
 }
 
-hipError_t launch_normal_consistency(const rade_view* views, int V, int64_t total,
-                                     const float* depth, const float* normal,
+hipError_t launch_normal_consistency(const rade_view* views_host, const rade_view* views, int V,
+                                     int64_t total, const float* depth, const float* normal,
                                      const float* alpha, float weight, float* loss,
                                      float* d_depth, float* d_normal, float* d_alpha,
                                      bool accumulate, void* ws, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_f, dim3((V + 255) / 256), dim3(256), 0, st, loss, V);
   if (total == 0) return hipGetLastError();
-  float* gdiff = static_cast<float*>(ws);
-  const unsigned blocks = (unsigned)((total + kT - 1) / kT);
-  float* partial = gdiff + 6 * total;
+  int64_t nb = 0;
+  for (int v = 0; v < V; ++v)
+    nb += (int64_t)((views_host[v].width + kNB - 1) / kNB) * ((views_host[v].height + kNB - 1) / kNB);
+  float* partial = static_cast<float*>(ws);
   if (accumulate)
-    hipLaunchKernelGGL(k_nc_pass1<true>, dim3(blocks), dim3(kT), 0, st, views, V, total, depth,
-                       normal, alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
+    hipLaunchKernelGGL(k_nc<true>, dim3((unsigned)nb), dim3(kT), 0, st, views, V, nb, depth,
+                       normal, alpha, weight, d_depth, d_normal, d_alpha, partial);
   else
-    hipLaunchKernelGGL(k_nc_pass1<false>, dim3(blocks), dim3(kT), 0, st, views, V, total, depth,
-                       normal, alpha, weight, loss, d_normal, d_alpha, gdiff, partial);
+    hipLaunchKernelGGL(k_nc<false>, dim3((unsigned)nb), dim3(kT), 0, st, views, V, nb, depth,
+                       normal, alpha, weight, d_depth, d_normal, d_alpha, partial);
   hipLaunchKernelGGL(k_nc_sum, dim3(V, kSumChunks), dim3(kT), 0, st, views, partial, loss);
-  if (accumulate)
-    hipLaunchKernelGGL(k_nc_pass2<true>, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff,
-                       d_depth);
-  else
-    hipLaunchKernelGGL(k_nc_pass2<false>, dim3(blocks), dim3(kT), 0, st, views, V, total, gdiff,
-                       d_depth);
   return hipGetLastError();
 }
 
