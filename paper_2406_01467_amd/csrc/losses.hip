@@ -23,7 +23,7 @@ __device__ __forceinline__ int view_of_pixel(const rade_view* views, int V, int6
   return v;
 }
 
-// The loss and its gradient in one kernel over 16 x 16 pixel blocks of each
+// The loss and its gradient in one kernel over 32 x 8 pixel blocks of each
 // view (blocks of the views back to back).  Per pixel the arithmetic is that
 // of the two passes it replaces: the loss term, dL/dA, dL/dN and the
 // gradients of the two difference vectors (6 floats) for every interior
@@ -34,14 +34,15 @@ __device__ __forceinline__ int view_of_pixel(const rade_view* views, int V, int6
 // gradients into the maps; otherwise every pixel's entries are written (0 +
 // x, so the bits equal adding into zeroed maps; border pixels and the
 // expected-depth plane get 0).  The block's loss sum goes to partial[block].
-constexpr int kNB = 16;           // block side in pixels (kNB * kNB == kT)
-constexpr int kNG = kNB + 2;      // with the ring of difference-vector gradients
-constexpr int kNDp = kNB + 4;     // with the ring of depths they read
-static_assert(kNB * kNB == kT, "one thread per pixel of a block");
+// A block is 32 x 8 pixels (a row of it is one 128-byte line of a map).
+constexpr int kBX = 32, kBY = 8;
+constexpr int kGX = kBX + 2, kGY = kBY + 2;  // with the ring of difference-vector gradients
+constexpr int kDX = kBX + 4, kDY = kBY + 4;  // with the ring of depths they read
+static_assert(kBX * kBY == kT, "one thread per pixel of a block");
 
-__device__ __forceinline__ int nc_blocks_x(const rade_view& vw) { return (vw.width + kNB - 1) / kNB; }
+__device__ __forceinline__ int nc_blocks_x(const rade_view& vw) { return (vw.width + kBX - 1) / kBX; }
 __device__ __forceinline__ int64_t nc_blocks(const rade_view& vw) {
-  return (int64_t)nc_blocks_x(vw) * ((vw.height + kNB - 1) / kNB);
+  return (int64_t)nc_blocks_x(vw) * ((vw.height + kBY - 1) / kBY);
 }
 
 // View of block b and the view's first block index.
@@ -66,8 +67,8 @@ k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* _
      const float* __restrict__ normal, const float* __restrict__ alpha, float weight,
      float* __restrict__ d_depth, float* __restrict__ d_normal, float* __restrict__ d_alpha,
      float* __restrict__ partial) {
-  __shared__ float sD[kNDp * kNDp];
-  __shared__ float sG[6][kNG * kNG];
+  __shared__ float sD[kDX * kDY];
+  __shared__ float sG[6][kGX * kGY];
   __shared__ float red[kT / 64];
   const int64_t b = blockIdx.x;
   if (b >= nblocks) return;  // uniform per block
@@ -77,22 +78,45 @@ k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* _
   const int W = vw.width, H = vw.height;
   const int nbx = nc_blocks_x(vw);
   const int bi = (int)(b - first);
-  const int x0 = (bi % nbx) * kNB, y0 = (bi / nbx) * kNB;
+  const int x0 = (bi % nbx) * kBX, y0 = (bi / nbx) * kBY;
   const int64_t o = vw.pix_offset, P = (int64_t)W * H;
   const float* Dm = depth + 2 * o + P;  // median plane
   const float wn = weight / (float)((W - 2) * (H - 2));
-  // median depths of the block and a two-pixel ring (0 outside the view)
-  for (int i = threadIdx.x; i < kNDp * kNDp; i += kT) {
-    const int x = x0 - 2 + i % kNDp, y = y0 - 2 + i / kNDp;
+  const float ifx = 1.0f / vw.fx, ify = 1.0f / vw.fy;  // one division per block
+  // Region pixels (the block and a one-pixel ring) of this thread: i = t and
+  // i = t + kT.  Their normals and alphas are loaded first, together with
+  // the median depths of the block and a two-pixel ring (0 outside the
+  // view), so every global load of the block is in flight at once.
+  constexpr int kR = (kGX * kGY + kT - 1) / kT;
+  float Nr[kR][3], Ar[kR];
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    const int i = threadIdx.x + k * kT;
+    const int gx = i % kGX, gy = i / kGX;
+    const int px = x0 - 1 + gx, py = y0 - 1 + gy;
+    const bool interior =
+        i < kGX * kGY && px >= 1 && py >= 1 && px <= W - 2 && py <= H - 2;
+    const bool own = gx >= 1 && gy >= 1 && gx <= kBX && gy <= kBY;
+    const int64_t pix = (int64_t)py * W + px;
+    Nr[k][0] = interior ? normal[3 * o + pix] : 0.0f;
+    Nr[k][1] = interior ? normal[3 * o + P + pix] : 0.0f;
+    Nr[k][2] = interior ? normal[3 * o + 2 * P + pix] : 0.0f;
+    Ar[k] = interior && own ? alpha[o + pix] : 0.0f;
+  }
+  for (int i = threadIdx.x; i < kDX * kDY; i += kT) {
+    const int x = x0 - 2 + i % kDX, y = y0 - 2 + i / kDX;
     sD[i] = (x >= 0 && y >= 0 && x < W && y < H) ? Dm[(int64_t)y * W + x] : 0.0f;
   }
   __syncthreads();
   float term = 0.0f;
-  // pass 1 over the block and a one-pixel ring; region pixel i = (gx, gy)
-  for (int i = threadIdx.x; i < kNG * kNG; i += kT) {
-    const int gx = i % kNG, gy = i / kNG;
+  // pass 1 over the block and the ring; region pixel i = (gx, gy)
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    const int i = threadIdx.x + k * kT;
+    if (i >= kGX * kGY) break;
+    const int gx = i % kGX, gy = i / kGX;
     const int px = x0 - 1 + gx, py = y0 - 1 + gy;
-    const bool own = gx >= 1 && gy >= 1 && gx <= kNB && gy <= kNB && px < W && py < H;
+    const bool own = gx >= 1 && gy >= 1 && gx <= kBX && gy <= kBY && px < W && py < H;
     const bool interior = px >= 1 && py >= 1 && px <= W - 2 && py <= H - 2;
     float gd[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int64_t pix = (int64_t)py * W + px;
@@ -100,32 +124,31 @@ k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* _
       // central differences of the back-projected points, written through
       // depth differences so FP32 does not cancel |P| ~ D against |dP| ~ D/f:
       // P(p +- x) = D(p +- x) (r(p) +- (1/fx, 0, 0)), r(p) = (rx, ry, 1)
-      const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
-      const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
-      const int c = (gy + 1) * kNDp + (gx + 1);  // this pixel in sD
+      const float rx = ((float)px + 0.5f - vw.cx) * ifx;
+      const float ry = ((float)py + 0.5f - vw.cy) * ify;
+      const int c = (gy + 1) * kDX + (gx + 1);  // this pixel in sD
       const float Dl = sD[c - 1], Dr = sD[c + 1];
-      const float Du = sD[c - kNDp], Dd = sD[c + kNDp];
+      const float Du = sD[c - kDX], Dd = sD[c + kDX];
       const float dx_ = Dr - Dl, sx = Dr + Dl;
       const float dy_ = Dd - Du, sy = Dd + Du;
-      const float du[3] = {dx_ * rx + sx / vw.fx, dx_ * ry, dx_};
-      const float dv[3] = {dy_ * rx, dy_ * ry + sy / vw.fy, dy_};
+      const float du[3] = {dx_ * rx + sx * ifx, dx_ * ry, dx_};
+      const float dv[3] = {dy_ * rx, dy_ * ry + sy * ify, dy_};
       const float Pc[3] = {sD[c] * rx, sD[c] * ry, sD[c]};
       const float cr[3] = {du[1] * dv[2] - du[2] * dv[1], du[2] * dv[0] - du[0] * dv[2],
                            du[0] * dv[1] - du[1] * dv[0]};
       const float cc = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
-      const float N0 = normal[3 * o + pix], N1 = normal[3 * o + P + pix],
-                  N2 = normal[3 * o + 2 * P + pix];
+      const float N0 = Nr[k][0], N1 = Nr[k][1], N2 = Nr[k][2];
       float nt[3] = {0.f, 0.f, 0.f};
       float gc[3] = {0.f, 0.f, 0.f};
       if (cc > 1e-30f) {
         const float inv = rsqrtf(cc);
         const float s = (cr[0] * Pc[0] + cr[1] * Pc[1] + cr[2] * Pc[2]) > 0.0f ? -1.0f : 1.0f;
         const float ch[3] = {cr[0] * inv, cr[1] * inv, cr[2] * inv};
-        for (int k = 0; k < 3; ++k) nt[k] = s * ch[k];
+        for (int j = 0; j < 3; ++j) nt[j] = s * ch[j];
         // dL/dc = -wn d(N . n~)/dc = -wn s (N - (N . c^) c^) / |c|
         const float nd = N0 * ch[0] + N1 * ch[1] + N2 * ch[2];
         const float Nv[3] = {N0, N1, N2};
-        for (int k = 0; k < 3; ++k) gc[k] = -wn * s * (Nv[k] - nd * ch[k]) * inv;
+        for (int j = 0; j < 3; ++j) gc[j] = -wn * s * (Nv[j] - nd * ch[j]) * inv;
       }
       // d/d(du) = dv x gc, d/d(dv) = gc x du
       gd[0] = dv[1] * gc[2] - dv[2] * gc[1];
@@ -135,8 +158,7 @@ k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* _
       gd[4] = gc[2] * du[0] - gc[0] * du[2];
       gd[5] = gc[0] * du[1] - gc[1] * du[0];
       if (own) {
-        const float A = alpha[o + pix];
-        term += (A - (N0 * nt[0] + N1 * nt[1] + N2 * nt[2])) * wn;
+        term += (Ar[k] - (N0 * nt[0] + N1 * nt[1] + N2 * nt[2])) * wn;
         const float a0 = ACC ? d_alpha[o + pix] : 0.0f;
         const float n0 = ACC ? d_normal[3 * o + pix] : 0.0f;
         const float n1 = ACC ? d_normal[3 * o + P + pix] : 0.0f;
@@ -153,23 +175,23 @@ k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* _
       d_normal[3 * o + 2 * P + pix] = 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) sG[k][i] = gd[k];
+    for (int j = 0; j < 6; ++j) sG[j][i] = gd[j];
   }
   __syncthreads();
   // pass 2 for the block's own pixels
   {
-    const int lx = threadIdx.x % kNB, ly = threadIdx.x / kNB;
+    const int lx = threadIdx.x % kBX, ly = threadIdx.x / kBX;
     const int px = x0 + lx, py = y0 + ly;
     if (px < W && py < H) {
-      const int i = (ly + 1) * kNG + (lx + 1);
+      const int i = (ly + 1) * kGX + (lx + 1);
       float g[3] = {0.f, 0.f, 0.f};
       // a neighbour's entries are zero when it is not interior
       if (px >= 1) for (int k = 0; k < 3; ++k) g[k] += sG[k][i - 1];
       if (px + 1 < W) for (int k = 0; k < 3; ++k) g[k] -= sG[k][i + 1];
-      if (py >= 1) for (int k = 0; k < 3; ++k) g[k] += sG[3 + k][i - kNG];
-      if (py + 1 < H) for (int k = 0; k < 3; ++k) g[k] -= sG[3 + k][i + kNG];
-      const float rx = ((float)px + 0.5f - vw.cx) / vw.fx;
-      const float ry = ((float)py + 0.5f - vw.cy) / vw.fy;
+      if (py >= 1) for (int k = 0; k < 3; ++k) g[k] += sG[3 + k][i - kGX];
+      if (py + 1 < H) for (int k = 0; k < 3; ++k) g[k] -= sG[3 + k][i + kGX];
+      const float rx = ((float)px + 0.5f - vw.cx) * ifx;
+      const float ry = ((float)py + 0.5f - vw.cy) * ify;
       const int64_t pix = (int64_t)py * W + px;
       const float prev = ACC ? d_depth[2 * o + P + pix] : 0.0f;
       d_depth[2 * o + P + pix] = prev + (g[0] * rx + g[1] * ry + g[2]);
@@ -241,7 +263,7 @@ __global__ void k_zero_f(float* __restrict__ a, int n) {
 
 }  // namespace
 
-// One loss partial per 16 x 16 block; every block holds at least one pixel.
+// One loss partial per block; every block holds at least one pixel.
 size_t normal_consistency_workspace(int64_t total_pixels) {
   return (size_t)total_pixels * sizeof(float) + 256;
 }
@@ -255,7 +277,7 @@ hipError_t launch_normal_consistency(const rade_view* views_host, const rade_vie
   if (total == 0) return hipGetLastError();
   int64_t nb = 0;
   for (int v = 0; v < V; ++v)
-    nb += (int64_t)((views_host[v].width + kNB - 1) / kNB) * ((views_host[v].height + kNB - 1) / kNB);
+    nb += (int64_t)((views_host[v].width + kBX - 1) / kBX) * ((views_host[v].height + kBY - 1) / kBY);
   float* partial = static_cast<float*>(ws);
   if (accumulate)
     hipLaunchKernelGGL(k_nc<true>, dim3((unsigned)nb), dim3(kT), 0, st, views, V, nb, depth,
