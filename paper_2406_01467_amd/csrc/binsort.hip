@@ -53,6 +53,21 @@ struct SortedCount {
   const uint32_t* cnt;
   __device__ uint64_t operator()(int64_t j) const { return (uint64_t)cnt[j]; }
 };
+// Total pair count: stored as 64 bits, as the count the tile sort processes
+// (0 when it exceeds the capacity, so nothing is written) and as the
+// caller's pair count.
+struct PairsTotal {
+  uint64_t* m64;
+  uint32_t* m32;
+  int64_t capacity;
+  int64_t* n_pairs_out;
+  __device__ void operator()(uint64_t m) const {
+    *m64 = m;
+    *m32 = m > (uint64_t)capacity ? 0u : (uint32_t)m;
+    *n_pairs_out = (int64_t)m;
+  }
+};
+
 // Pair offsets of the depth-sorted splats, and for every emission block the
 // splat that holds its first pair: block b starts in splat j when
 // offs[j] <= b * kEmitPairs < offs[j] + count[j].
@@ -583,6 +598,71 @@ k_order_keys(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __res
   vals[t] = (uint32_t)t;
 }
 
+// Heavy-first order of up to kOrderOneBlock tiles in one workgroup: a stable
+// counting sort by the order key (the same key as k_order_keys).  The tiles
+// are taken in chunks of 1024, wave w holding tiles [64 w, 64 w + 64) of a
+// chunk, so ranks counted per wave and combined in wave order are stable.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderWaves = kOrderThreads / 64;
+constexpr int64_t kOrderOneBlock = 16384;
+
+__device__ __forceinline__ uint32_t order_key(const uint32_t* __restrict__ ranges, int64_t t) {
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  const int b = len == 0 ? 0 : min(255, (int)(16.0f * __log2f((float)len + 1.0f)));
+  return (uint32_t)(255 - b);
+}
+
+__global__ void __launch_bounds__(kOrderThreads)
+k_tile_order(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __restrict__ order) {
+  __shared__ uint32_t base[kRadix];                 // next position of each key
+  __shared__ uint32_t wcnt[kOrderWaves][kRadix];    // per-wave key counts of a chunk
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < kRadix) base[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < tiles; t += kOrderThreads)
+    atomicAdd(&base[order_key(ranges, t)], 1u);
+  __syncthreads();
+  if (threadIdx.x < 64) {  // exclusive scan of the 256 key counts by wave 0
+    uint32_t c[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { c[k] = base[4 * lane + k]; s += c[k]; }
+    uint32_t x = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    uint32_t run = x - s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { base[4 * lane + k] = run; run += c[k]; }
+  }
+  const uint64_t lt = lanes_below();
+  for (int64_t c0 = 0; c0 < tiles; c0 += kOrderThreads) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRadix / 64; ++k) wcnt[wave][k * 64 + lane] = 0u;
+    const int64_t t = c0 + threadIdx.x;
+    const bool valid = t < tiles;
+    const uint32_t d = valid ? order_key(ranges, t) : 0u;
+    const uint64_t peers = digit_peers(d, valid);
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (threadIdx.x < kRadix) {  // per-wave starts of each key in this chunk
+      uint32_t run = base[threadIdx.x];
+      for (int w = 0; w < kOrderWaves; ++w) {
+        const uint32_t x = wcnt[w][threadIdx.x];
+        wcnt[w][threadIdx.x] = run;
+        run += x;
+      }
+      base[threadIdx.x] = run;
+    }
+    __syncthreads();
+    if (valid) order[wcnt[wave][d] + rank] = (uint32_t)t;
+  }
+  if (threadIdx.x == 0) order[tiles] = 0u;  // the work-queue counter's slot
+}
+
 }  // namespace
 
 size_t tile_order_workspace(int64_t tiles) {
@@ -597,6 +677,10 @@ hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* or
   uint32_t* k1 = (uint32_t*)(w + 2 * align_up(sizeof(uint32_t) * tiles));
   char* sw = w + 3 * align_up(sizeof(uint32_t) * tiles);
   uint32_t* cnt = (uint32_t*)(sw + sort_space_bytes(tiles));
+  if (tiles <= kOrderOneBlock) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, ranges, tiles, order);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_order_keys, dim3(blocks_for(tiles > 0 ? tiles : 1, kThreads)),
                      dim3(kThreads), 0, st, ranges, tiles, k0, v0, cnt);
   // one 8-bit pass: the result lands in (k1, order)
@@ -648,15 +732,15 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st,
                                  false, tt, VN, dcnt);
   uint32_t* sv = (dpasses & 1) ? dv1 : dv0;
-  // 3. pair offsets in depth order
+  // 3. pair offsets in depth order (and the pair counts)
   if (VN > 0) {
     scan_to<uint64_t>(SortedCount{dcnt}, VN, n_vis,
                       OffsetsOut{offs, starts, (capacity + kEmitPairs - 1) / kEmitPairs},
-                      (uint64_t*)sums, m64, st);
+                      (uint64_t*)sums, PairsTotal{m64, m32, capacity, n_pairs_dev}, st);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, (uint32_t*)m64, 2, 0u);
+    hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(1), 0, st, m64, capacity, m32, n_pairs_dev);
   }
-  hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(1), 0, st, m64, capacity, m32, n_pairs_dev);
   if (n_pairs_host) {
     hipError_t e = hipMemcpyAsync(n_pairs_host, n_pairs_dev, sizeof(int64_t),
                                   hipMemcpyDeviceToHost, st);

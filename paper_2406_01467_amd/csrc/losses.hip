@@ -210,10 +210,7 @@ k_nc(const rade_view* __restrict__ views, int V, int64_t nblocks, const float* _
   }
 }
 
-// Loss per view: workgroup (v, c) sums chunk c of view v's block partials
-// and adds it to loss[v] (kSumChunks atomics per view).
-constexpr int kSumChunks = 32;
-
+// Loss per view: workgroup v sums view v's block partials and writes loss[v].
 __global__ void __launch_bounds__(kT)
 k_nc_sum(const rade_view* __restrict__ views, const float* __restrict__ partial,
          float* __restrict__ loss) {
@@ -221,17 +218,16 @@ k_nc_sum(const rade_view* __restrict__ views, const float* __restrict__ partial,
   int64_t b0 = 0;
   for (int v = 0; v < (int)blockIdx.x; ++v) b0 += nc_blocks(views[v]);
   const int64_t b1 = b0 + nc_blocks(views[blockIdx.x]);
-  const int64_t per = (b1 - b0 + kSumChunks - 1) / kSumChunks;
-  const int64_t c0 = b0 + (int64_t)blockIdx.y * per, c1 = min(b1, c0 + per);
   float x = 0.0f;
-  for (int64_t b = c0 + threadIdx.x; b < c1; b += kT) x += partial[b];
+#pragma unroll 4
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += kT) x += partial[b];
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
     float t = 0.0f;
     for (int i = 0; i < kT / 64; ++i) t += red[i];
-    if (c0 < c1) atomicAdd(loss + blockIdx.x, t);
+    loss[blockIdx.x] = t;
   }
 }
 
@@ -273,8 +269,10 @@ hipError_t launch_normal_consistency(const rade_view* views_host, const rade_vie
                                      const float* alpha, float weight, float* loss,
                                      float* d_depth, float* d_normal, float* d_alpha,
                                      bool accumulate, void* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_f, dim3((V + 255) / 256), dim3(256), 0, st, loss, V);
-  if (total == 0) return hipGetLastError();
+  if (total == 0) {
+    hipLaunchKernelGGL(k_zero_f, dim3((V + 255) / 256), dim3(256), 0, st, loss, V);
+    return hipGetLastError();
+  }
   int64_t nb = 0;
   for (int v = 0; v < V; ++v)
     nb += (int64_t)((views_host[v].width + kBX - 1) / kBX) * ((views_host[v].height + kBY - 1) / kBY);
@@ -285,7 +283,7 @@ hipError_t launch_normal_consistency(const rade_view* views_host, const rade_vie
   else
     hipLaunchKernelGGL(k_nc<false>, dim3((unsigned)nb), dim3(kT), 0, st, views, V, nb, depth,
                        normal, alpha, weight, d_depth, d_normal, d_alpha, partial);
-  hipLaunchKernelGGL(k_nc_sum, dim3(V, kSumChunks), dim3(kT), 0, st, views, partial, loss);
+  hipLaunchKernelGGL(k_nc_sum, dim3(V), dim3(kT), 0, st, views, partial, loss);
   return hipGetLastError();
 }
 

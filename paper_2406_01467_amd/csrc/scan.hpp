@@ -41,6 +41,31 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds_waves, T& total) {
   return pre + x - v;
 }
 
+// Sum of sums[0..b) by the whole workgroup (every thread gets it): the
+// exclusive prefix of block b among the block sums, for scans whose blocks
+// are few enough that each can add up those before it (kFoldBlocks), which
+// saves the separate kernel that scans the block sums.
+constexpr int64_t kFoldBlocks = 1024;
+
+template <typename T>
+__device__ __forceinline__ T block_prefix(const T* __restrict__ sums, int64_t b, T* lds_waves) {
+  T s = 0;
+#pragma unroll 4
+  for (int64_t i = threadIdx.x; i < b; i += kScanThreads) s += sums[i];
+  T tot;
+  block_exclusive_scan<T>(s, lds_waves, tot);
+  return tot;
+}
+
+// Where a scan's total goes.
+template <typename T>
+struct TotalStore {
+  T* p;
+  __device__ void operator()(T t) const {
+    if (p) *p = t;
+  }
+};
+
 struct PlainInput64 {
   const uint64_t* a;
   __device__ uint64_t operator()(int64_t i) const { return a[i]; }
@@ -91,12 +116,17 @@ struct StoreOut {
   __device__ void operator()(int64_t i, T offset, T) const { a[i] = offset; }
 };
 
-template <typename T, typename In, typename Out>
+template <typename T, typename In, typename Out, typename Tot>
 __global__ void __launch_bounds__(kScanThreads)
-k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, Out out) {
+k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, int fold, Out out,
+            Tot total) {
   __shared__ T lw[kScanThreads / 64];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) total(T(0));
+    return;
+  }
   if ((int64_t)blockIdx.x * kScanTile >= n) return;  // uniform per block
   T v[kScanItems];
   T s = 0;
@@ -105,34 +135,42 @@ k_scan_down(In in, int64_t n_max, const uint32_t* n_dev, const T* block_sums, Ou
     v[k] = (base + k < n) ? in(base + k) : 0;
     s += v[k];
   }
-  T total;
-  T run = block_exclusive_scan<T>(s, lw, total) + block_sums[blockIdx.x];
+  T sum;
+  const T ex = block_exclusive_scan<T>(s, lw, sum);
+  const T pre = fold ? block_prefix<T>(block_sums, blockIdx.x, lw) : block_sums[blockIdx.x];
+  T run = ex + pre;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < n) out(base + k, run, v[k]);
     run += v[k];
   }
+  // the block holding the last item has the total
+  if (threadIdx.x == 0 && (int64_t)blockIdx.x == (n - 1) / kScanTile) total(pre + sum);
 }
 
 // Exclusive scan of in(0..n) handed to out (n = *n_dev, or n_max when n_dev
-// is NULL), total into *total.  Launch errors are left pending for the
-// caller's final hipGetLastError.
-template <typename T, typename In, typename Out>
-void scan_to(In in, int64_t n_max, const uint32_t* n_dev, Out out, T* block_sums, T* total,
+// is NULL), the total handed to total().  Two kernels when the blocks are
+// few enough (kFoldBlocks), else three.  Launch errors are left pending for
+// the caller's final hipGetLastError.
+template <typename T, typename In, typename Out, typename Tot>
+void scan_to(In in, int64_t n_max, const uint32_t* n_dev, Out out, T* block_sums, Tot total,
              hipStream_t st) {
   const int64_t nb = n_max > 0 ? (n_max + kScanTile - 1) / kScanTile : 1;
+  const int fold = nb <= kFoldBlocks ? 1 : 0;
   hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in,
                      n_max, n_dev, block_sums);
-  hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kScanThreads), 0, st, block_sums, nb, total);
-  hipLaunchKernelGGL((k_scan_down<T, In, Out>), dim3((unsigned)nb), dim3(kScanThreads), 0, st, in,
-                     n_max, n_dev, (const T*)block_sums, out);
+  if (!fold)
+    hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kScanThreads), 0, st, block_sums, nb,
+                       (T*)nullptr);
+  hipLaunchKernelGGL((k_scan_down<T, In, Out, Tot>), dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                     in, n_max, n_dev, (const T*)block_sums, fold, out, total);
 }
 
 // The same, stored into out[0..n).
 template <typename T, typename In>
 void scan(In in, int64_t n_max, const uint32_t* n_dev, T* out, T* block_sums, T* total,
           hipStream_t st) {
-  scan_to<T>(in, n_max, n_dev, StoreOut<T>{out}, block_sums, total, st);
+  scan_to<T>(in, n_max, n_dev, StoreOut<T>{out}, block_sums, TotalStore<T>{total}, st);
 }
 
 // Compaction: the exclusive scan of in() is handed, for every item with a
@@ -175,13 +213,15 @@ k_compact_reduce(In in, int64_t n, int64_t chunk, T* block_sums) {
 
 template <typename T, typename In, typename Emit>
 __global__ void __launch_bounds__(kScanThreads)
-k_compact_emit(In in, int64_t n, int64_t chunk, const T* block_sums, Emit emit) {
+k_compact_emit(In in, int64_t n, int64_t chunk, const T* block_sums, int fold, Emit emit,
+               T* total) {
   constexpr int W = kScanThreads / 64;
   __shared__ T lw[kCompactBatch][W];
+  __shared__ T lwp[W];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  T carry = block_sums[blockIdx.x];
+  T carry = fold ? block_prefix<T>(block_sums, blockIdx.x, lwp) : block_sums[blockIdx.x];
   for (int64_t r = lo; r < hi; r += kCompactStep) {  // uniform trip count
     T v[kCompactBatch], incl[kCompactBatch];
     int any = 0;
@@ -219,6 +259,8 @@ k_compact_emit(In in, int64_t n, int64_t chunk, const T* block_sums, Emit emit) 
     }
     __syncthreads();
   }
+  // the last workgroup's carry is the total
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = carry;
 }
 
 // Workgroups and block-sum entries a compaction of n items uses.
@@ -229,17 +271,21 @@ inline int64_t compact_blocks(int64_t n) {
 
 // Enqueues the compaction of in(0..n): total into *total, emit for every
 // item with a nonzero count.  block_sums holds compact_blocks(n) entries.
+// Two kernels when the workgroups are few enough (kFoldBlocks), else three.
 // Launch errors are left pending.
 template <typename T, typename In, typename Emit>
 void scan_emit(In in, int64_t n, T* block_sums, T* total, Emit emit, hipStream_t st) {
   const int64_t nb = compact_blocks(n);
   const int64_t steps = (n + kCompactStep - 1) / kCompactStep;
   const int64_t chunk = ((steps + nb - 1) / nb) * kCompactStep;
+  const int fold = nb <= kFoldBlocks ? 1 : 0;
   hipLaunchKernelGGL((k_compact_reduce<T, In>), dim3((unsigned)nb), dim3(kScanThreads), 0, st,
                      in, n, chunk, block_sums);
-  hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kScanThreads), 0, st, block_sums, nb, total);
+  if (!fold)
+    hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(kScanThreads), 0, st, block_sums, nb,
+                       (T*)nullptr);
   hipLaunchKernelGGL((k_compact_emit<T, In, Emit>), dim3((unsigned)nb), dim3(kScanThreads), 0, st,
-                     in, n, chunk, (const T*)block_sums, emit);
+                     in, n, chunk, (const T*)block_sums, fold, emit, total);
 }
 
 }  // namespace rade

@@ -72,13 +72,21 @@ def test_capacity_overflow_grows_and_recaptures():
     assert torch.equal(plan.maps["color"], ref.color)
 
 
-def test_tile_order_is_heavy_first_permutation():
+@pytest.mark.parametrize("large", [False, True])
+def test_tile_order_is_heavy_first_permutation(large):
+    # small: one workgroup sorts all tiles; large (more than 16384 tiles of
+    # 8x8 pixels): the radix pass over a key array
     import torch
     from paper_2406_01467_amd import Settings, _lib
     from paper_2406_01467_amd.raster import Rasterizer
     dev = device()
     scene, views = _scene_views(10000, seed=41)
-    rast = Rasterizer(views, Settings(sh_degree=3, schedule=1), dev)
+    st = Settings(sh_degree=3, schedule=1)
+    if large:
+        views = [synth.identity_view(1200, 900)]
+        st = Settings(sh_degree=3, schedule=1, tile_w=8, tile_h=8)
+    rast = Rasterizer(views, st, dev)
+    assert (rast.total_tiles > 16384) == large
     splats, tt = rast.project(*to_dev(scene, dev))
     _, ranges, M = rast.bin_sort(scene.n, splats, tt)
     order = rast.tile_order(ranges)
