@@ -232,7 +232,9 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const float* depth_quad, void* stream);
 
 /* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
- * recompute the splats (splats == NULL in rade_render_bwd). */
+ * recompute the splats (splats == NULL in rade_render_bwd).  The workspace
+ * must be 16-byte aligned (device allocations are); RADE_ERR_INVALID_ARG
+ * otherwise. */
 size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute);
 
 /* Backward pass: gradients of the Gaussian parameters from the upstream

@@ -352,6 +352,8 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   const int recompute = splats == nullptr ? 1 : 0;
   if (!workspace || workspace_bytes < rade_render_bwd_workspace(s, V, N, recompute))
     return RADE_ERR_WORKSPACE;
+  // the per-(view, Gaussian) gradient records move in 16-byte words
+  if ((reinterpret_cast<uintptr_t>(workspace) & 15) != 0) return RADE_ERR_INVALID_ARG;
   const hipStream_t st = (hipStream_t)stream;
   const size_t VN = (size_t)V * (size_t)N;
   char* w = static_cast<char*>(workspace);

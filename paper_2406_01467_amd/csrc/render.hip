@@ -622,9 +622,13 @@ __global__ void __launch_bounds__(TW * TH) k_render_bwd_persistent(BwdArgs a) {
   }
 }
 
-__global__ void k_zero(float* __restrict__ a, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = 0.0f;
+// Clears n4 16-byte words (grid-stride, one 16-byte store per iteration).
+constexpr int kZeroThreads = 256;
+constexpr int64_t kZeroBlocks = 4096;
+__global__ void __launch_bounds__(kZeroThreads) k_zero(float4* __restrict__ a, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * kZeroThreads + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * kZeroThreads)
+    a[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
@@ -810,9 +814,12 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
                              const float* dd, const float* dn, const float* da,
                              const float* ddist, const float* fwd_depth, const float* fwd_alpha,
                              float* gsplat, hipStream_t st) {
-  const int64_t ng = (int64_t)V * N * 16;
-  if (ng > 0)
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, gsplat, ng);
+  const int64_t ng4 = (int64_t)V * N * 4;  // 16 floats per (view, Gaussian)
+  if (ng4 > 0) {
+    const int64_t blocks = (ng4 + kZeroThreads - 1) / kZeroThreads;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)(blocks < kZeroBlocks ? blocks : kZeroBlocks)),
+                       dim3(kZeroThreads), 0, st, reinterpret_cast<float4*>(gsplat), ng4);
+  }
   if (tiles == 0) return hipGetLastError();
   BwdArgs a;
   a.bp = make_blend_params(s);

@@ -185,3 +185,22 @@ def test_marching_cubes_rejects_bad_arguments_on_the_host():
     assert call(ws_bytes=16) == lib.RADE_ERR_WORKSPACE
     assert lib.rade_marching_cubes_workspace((2, 2, 2)) <= ws.nbytes
     assert lib.rade_marching_cubes_workspace((0, 1, 1)) == 0
+
+
+def test_render_bwd_rejects_a_misaligned_workspace():
+    """The gradient records in the workspace move in 16-byte words: a
+    workspace that is not 16-byte aligned is rejected before any launch
+    (the device pointers here are never dereferenced)."""
+    lib = _lib()
+    import synth
+    so = lib.load()
+    s = lib.Settings()
+    vc = lib.make_views([synth.identity_view(32, 32)])
+    lib.rade_views_prepare(s, vc)
+    d = ctypes.c_void_p(256)
+    args = [ctypes.byref(s.c()), vc, d, 1, 10] + [d] * 5 + [d, d, d, d, d, d, d] + [d] * 4 + \
+        [None, None, None] + [d] * 5
+    big = 1 << 30
+    assert so.rade_render_bwd(*args, ctypes.c_void_p(256 + 4), big, None) == \
+        lib.RADE_ERR_INVALID_ARG
+    assert so.rade_render_bwd(*args, None, big, None) == lib.RADE_ERR_WORKSPACE
