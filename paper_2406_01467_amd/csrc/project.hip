@@ -361,7 +361,7 @@ __device__ __forceinline__ void exact_depth_record(const ViewD& v, const Params&
 }
 
 template <int KMAX, bool VEC, bool EXACT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
           const float* __restrict__ means, const float* __restrict__ scales,
           const float* __restrict__ quats, const float* __restrict__ opac,
@@ -374,18 +374,16 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   const float* __restrict__ coef_g = sh + 3 * K * g;
   Params P;
   const bool ok = load_params(g, means, scales, quats, opac, P);
+  // the coefficients are loaded with the parameters, so their latency
+  // overlaps the FP64 geometry (the registers fit two waves per SIMD)
+  float coef[3 * K];
+  load_row<K, VEC>(coef_g, coef);
+  const bool rok = row_finite<K>(coef);
   for (int vi = 0; vi < V; ++vi) {
     const int64_t o = (int64_t)vi * N + g;
     const ViewD v = load_view(views[vi], st.fov_clamp);
     Geo G;
-    // coefficients loaded per view, after the geometry (L1/L2 after the
-    // first view), so they are not live across it
-    float coef[3 * K];
-    bool vis = ok && geometry(v, P, st, G) && G.detD > 0.0;
-    if (vis) {
-      load_row<K, VEC>(coef_g, coef);
-      vis = row_finite<K>(coef);
-    }
+    const bool vis = ok && rok && geometry(v, P, st, G) && G.detD > 0.0;
     if (!vis) {
       store_invisible(splats + o);
       tiles_touched[o] = 0;
