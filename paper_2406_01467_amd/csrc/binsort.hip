@@ -31,27 +31,40 @@ constexpr int kRadix = 1 << kRadixBits;
 
 constexpr int kEmitPairs = kTile;                // pairs per emission block (one radix block)
 
-// Compaction of the visible splats (tiles touched > 0) into the depth sort's
-// (key, value) arrays: key = bits of the float32 view depth, value = index.
+// Compaction of the visible splats (tiles touched > 0), read in index order:
+// the depth sort's keys (bits of the float32 view depth) and values (the
+// compaction position p), and a 16-byte record per visible splat: its index
+// and tile rect (tx0 | ty0 << 16, tx1 | ty1 << 16; a visible splat's pixel
+// rect lies inside its view, so the tile bounds are shifts of it, tile sizes
+// being powers of two) and its tile count.  The depth sort's last pass
+// gathers the records into depth order, so the pair emission reads them in
+// order instead of gathering 80-byte splat records.
 struct Visible {
   const int32_t* tt;
   __device__ uint32_t operator()(int64_t i) const { return tt[i] > 0 ? 1u : 0u; }
 };
 struct VisibleOut {
   const rade_splat* splats;
+  int log2_tw, log2_th;
   uint32_t* keys;
   uint32_t* vals;
+  uint4* recs;
   __device__ void operator()(int64_t i, uint32_t p, uint32_t) const {
-    keys[p] = __float_as_uint(splats[i].z);  // z > near > 0: bits order like values
-    vals[p] = (uint32_t)i;
+    const rade_splat& sp = splats[i];
+    keys[p] = __float_as_uint(sp.z);  // z > near > 0: bits order like values
+    vals[p] = p;
+    const uint32_t tx0 = (uint32_t)sp.rect[0] >> log2_tw, tx1 = (uint32_t)sp.rect[1] >> log2_tw;
+    const uint32_t ty0 = (uint32_t)sp.rect[2] >> log2_th, ty1 = (uint32_t)sp.rect[3] >> log2_th;
+    // the tile count, as the projection counts it from the same rect
+    recs[p] = make_uint4((uint32_t)i, tx0 | (ty0 << 16), tx1 | (ty1 << 16),
+                         (tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   }
 };
 
-// Tiles touched by the j-th depth-sorted splat (gathered by the depth
-// sort's last pass).
+// Tiles touched by the j-th depth-sorted splat (its record's count).
 struct SortedCount {
-  const uint32_t* cnt;
-  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)cnt[j]; }
+  const uint4* recs;
+  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)recs[j].w; }
 };
 // Total pair count: stored as 64 bits, as the count the tile sort processes
 // (0 when it exceeds the capacity, so nothing is written) and as the
@@ -197,16 +210,13 @@ k_radix_colscan(uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restri
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// Shared memory of one sorting workgroup (GATHER: also the gathered
-// companion values).
-template <bool GATHER>
+// Shared memory of one sorting workgroup.
 struct RankShared {
   uint32_t wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave digit starts
   uint32_t lstart[kRadix];        // first local position of each digit
   uint32_t dbase[kRadix];         // global position of each digit's run
   uint32_t skey[kTile];
   uint32_t sval[kTile];
-  uint32_t sgat[GATHER ? kTile : 1];
   uint64_t lw[kWaves];
 };
 
@@ -218,16 +228,16 @@ struct RankShared {
 // starts (the local counts sum to at most kTile, so the halves never carry
 // into each other).  The block is then sorted in LDS and each digit's run
 // written contiguously at its region start plus the row-scanned count of
-// the blocks before this one.  GATHER: each item also carries gsrc[value]
-// (gsrc has gn entries), written to gout in the sorted order.
+// the blocks before this one.  GATHER: each item also carries the record
+// gsrc[value] (values index gsrc), written to gout in the sorted order.
 template <bool GATHER>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int64_t n_max, int shift, int64_t nblocks,
                 const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot,
-                const int32_t* __restrict__ gsrc, int64_t gn, uint32_t* __restrict__ gout) {
-  __shared__ RankShared<GATHER> sh;
+                const uint4* __restrict__ gsrc, uint4* __restrict__ gout) {
+  __shared__ RankShared sh;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t base = blk * kTile;
   const int lane = threadIdx.x & 63;
@@ -241,15 +251,6 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     const bool inb = i < n_max;
     key[r] = inb ? kin[i] : 0u;
     val[r] = inb ? vin[i] : 0u;
-  }
-  uint32_t gat[GATHER ? kItems : 1];
-  if constexpr (GATHER) {
-    // values past the item count are not indices: clamped into the source
-#pragma unroll
-    for (int r = 0; r < kItems; ++r)
-      gat[r] = item_index(base, r) < n_max
-                   ? (uint32_t)gsrc[val[r] < (uint64_t)gn ? val[r] : (uint32_t)(gn - 1)]
-                   : 0u;
   }
   const uint32_t dtot_d = dtot[threadIdx.x];
   const uint32_t goff_d = offsets[(int64_t)threadIdx.x * nblocks + blk];
@@ -294,18 +295,22 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
       const uint32_t p = pos[r] + sh.lstart[d] + sh.wcnt[wave][d];
       sh.skey[p] = key[r];
       sh.sval[p] = val[r];
-      if constexpr (GATHER) sh.sgat[p] = gat[r];
     }
   }
   __syncthreads();
   const int nb = (n - base) < kTile ? (int)(n - base) : kTile;
-  for (int i = threadIdx.x; i < nb; i += kThreads) {
-    const uint32_t k = sh.skey[i];
-    const uint32_t d = digit_of(k, shift);
-    const uint32_t dst = sh.dbase[d] + ((uint32_t)i - sh.lstart[d]);
-    kout[dst] = k;
-    vout[dst] = sh.sval[i];
-    if constexpr (GATHER) gout[dst] = sh.sgat[i];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {  // unrolled: the gathers are issued together
+    const int i = (int)threadIdx.x + r * kThreads;
+    if (i < nb) {
+      const uint32_t k = sh.skey[i];
+      const uint32_t v = sh.sval[i];
+      const uint32_t d = digit_of(k, shift);
+      const uint32_t dst = sh.dbase[d] + ((uint32_t)i - sh.lstart[d]);
+      kout[dst] = k;
+      vout[dst] = v;
+      if constexpr (GATHER) gout[dst] = gsrc[v];
+    }
   }
 }
 
@@ -324,14 +329,12 @@ constexpr int kEmitPerThread = kEmitPairs / kEmitThreads;  // 4 consecutive pair
 static_assert(kEmitPerThread == 4, "emit stores four pairs as one 16-byte word");
 
 __global__ void __launch_bounds__(kEmitThreads)
-k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
+k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
        const uint32_t* __restrict__ starts, const uint32_t* __restrict__ n_dev,
        const uint64_t* __restrict__ m_dev, int64_t capacity,
-       const rade_splat* __restrict__ splats, const rade_view* __restrict__ views, FastDiv div_n,
-       int log2_tw, int log2_th, uint32_t* __restrict__ tkeys, uint32_t* __restrict__ pids,
-       int vec_stores, int64_t nblocks, uint32_t* __restrict__ hist) {
+       const rade_view* __restrict__ views, FastDiv div_n, uint32_t* __restrict__ tkeys,
+       uint32_t* __restrict__ pids, int vec_stores, int64_t nblocks, uint32_t* __restrict__ hist) {
   __shared__ uint64_t win[kEmitPairs + 1];
-  __shared__ uint32_t wid[kEmitPairs + 1];
   __shared__ uint32_t h[kRadix];
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint64_t M = *m_dev;
@@ -347,7 +350,6 @@ k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
     const int64_t j = j0 + w;
     const bool in = j < nvis;
     win[w] = in ? offs[j] : M;
-    wid[w] = in ? svals[j] : 0u;
   }
   __syncthreads();
   // The first pair's splat by binary search in the window, the next ones by
@@ -372,17 +374,16 @@ k_emit(const uint32_t* __restrict__ svals, const uint64_t* __restrict__ offs,
       while (lo < kEmitPairs && win[lo + 1] <= p) ++lo;
       if (lo != cur) {
         cur = lo;
-        // V*N < 2^32 (32-bit ids); a visible splat's rect lies inside its
-        // view, so its pixel bounds are non-negative and the tile bounds are
-        // shifts (tile sizes are powers of two)
-        const uint32_t i = wid[lo];
+        // the splat's record in depth order (index, tile rect); V*N < 2^32
+        // (32-bit ids)
+        const uint4 rec = drecs[j0 + lo];
+        const uint32_t i = rec.x;
         const uint32_t v = div_n.div(i);
         g = i - v * div_n.d;
-        const rade_splat& sp = splats[i];
-        tx0 = (uint32_t)sp.rect[0] >> log2_tw;
-        const uint32_t tx1 = (uint32_t)sp.rect[1] >> log2_tw;
-        ty0 = (uint32_t)sp.rect[2] >> log2_th;
-        ty1 = (uint32_t)sp.rect[3] >> log2_th;
+        tx0 = rec.y & 0xFFFFu;
+        ty0 = rec.y >> 16;
+        const uint32_t tx1 = rec.z & 0xFFFFu;
+        ty1 = rec.z >> 16;
         nx = tx1 - tx0 + 1;
         toff = (uint32_t)views[v].tile_offset;
         tiles_x = (uint32_t)views[v].tiles_x;
@@ -520,12 +521,12 @@ inline SortSpace sort_space(char* w, int64_t n_max) {
 // `bits` bits of the keys; on return the sorted data are in (k0, v0) when the
 // number of passes is even, else in (k1, v1).  Returns the number of passes.
 // first_counted: the first pass's per-block counts are already in sp.hist.
-// gsrc: the last pass also writes gsrc[value] of every item, in the sorted
-// order, to gout.
+// gsrc: the last pass also writes the record gsrc[value] of every item (the
+// values index gsrc), in the sorted order, to gout.
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
                const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
-               bool first_counted = false, const int32_t* gsrc = nullptr, int64_t gn = 0,
-               uint32_t* gout = nullptr) {
+               bool first_counted = false, const uint4* gsrc = nullptr,
+               uint4* gout = nullptr) {
   const int64_t nb = sort_blocks(n_max);
   const int passes = bits > kRadixBits ? (bits + kRadixBits - 1) / kRadixBits : 1;
   for (int p = 0; p < passes; ++p) {
@@ -541,18 +542,17 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n
     if (gsrc && p == passes - 1)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi,
                          ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
-                         (const uint32_t*)sp.dtot, gsrc, gn, gout);
+                         (const uint32_t*)sp.dtot, gsrc, gout);
     else
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki,
                          vi, ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
-                         (const uint32_t*)sp.dtot, (const int32_t*)nullptr, (int64_t)0,
-                         (uint32_t*)nullptr);
+                         (const uint32_t*)sp.dtot, (const uint4*)nullptr, (uint4*)nullptr);
   }
   return passes;
 }
 
 struct Layout {
-  size_t starts, dkeys0, dvals0, dkeys1, dvals1, dcnt, offs, tkeys0, tkeys1, pids1, sort, sums, scal;
+  size_t starts, dkeys0, dvals0, dkeys1, dvals1, crec, drec, offs, tkeys0, tkeys1, pids1, sort, sums, scal;
   size_t total;
 };
 
@@ -572,7 +572,8 @@ Layout layout(int64_t VN, int64_t capacity) {
   L.dvals0 = take(sizeof(uint32_t) * VN);
   L.dkeys1 = take(sizeof(uint32_t) * VN);
   L.dvals1 = take(sizeof(uint32_t) * VN);
-  L.dcnt = take(sizeof(uint32_t) * VN);
+  L.crec = take(sizeof(uint4) * VN);
+  L.drec = take(sizeof(uint4) * VN);
   L.offs = take(sizeof(uint64_t) * VN);
   L.tkeys0 = take(sizeof(uint32_t) * capacity);
   L.tkeys1 = take(sizeof(uint32_t) * capacity);
@@ -706,7 +707,8 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* dv0 = (uint32_t*)(w + L.dvals0);
   uint32_t* dk1 = (uint32_t*)(w + L.dkeys1);
   uint32_t* dv1 = (uint32_t*)(w + L.dvals1);
-  uint32_t* dcnt = (uint32_t*)(w + L.dcnt);
+  uint4* crec = (uint4*)(w + L.crec);
+  uint4* drec = (uint4*)(w + L.drec);
   uint64_t* offs = (uint64_t*)(w + L.offs);
   uint32_t* tk0 = (uint32_t*)(w + L.tkeys0);
   uint32_t* tk1 = (uint32_t*)(w + L.tkeys1);
@@ -723,18 +725,17 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
 
   // 1. visible splats -> compact (depth key, index) list
   if (VN > 0) {
-    scan_emit<uint32_t>(Visible{tt}, VN, (uint32_t*)sums, n_vis, VisibleOut{splats, dk0, dv0},
+    scan_emit<uint32_t>(Visible{tt}, VN, (uint32_t*)sums, n_vis,
+                        VisibleOut{splats, ceil_log2(s.tile_w), ceil_log2(s.tile_h), dk0, dv0, crec},
                         st);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, n_vis, 1, 0u);
   }
   // 2. depth sort
-  const int dpasses = radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st,
-                                 false, tt, VN, dcnt);
-  uint32_t* sv = (dpasses & 1) ? dv1 : dv0;
+  radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st, false, crec, drec);
   // 3. pair offsets in depth order (and the pair counts)
   if (VN > 0) {
-    scan_to<uint64_t>(SortedCount{dcnt}, VN, n_vis,
+    scan_to<uint64_t>(SortedCount{drec}, VN, n_vis,
                       OffsetsOut{offs, starts, (capacity + kEmitPairs - 1) / kEmitPairs},
                       (uint64_t*)sums, PairsTotal{m64, m32, capacity, n_pairs_dev}, st);
   } else {
@@ -767,11 +768,11 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   const bool emitted = VN > 0 && capacity > 0;
   static_assert(kEmitPairs == kTile, "emission blocks are the tile sort's blocks");
   if (emitted)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)sort_blocks(capacity)), dim3(kEmitThreads), 0, st, sv,
-                       offs, starts, n_vis, m64, capacity, splats, views_dev,
-                       FastDiv((uint32_t)(N > 0 ? N : 1)), ceil_log2(s.tile_w), ceil_log2(s.tile_h),
-                       ek, ev, (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0,
-                       sort_blocks(capacity), tsp.hist);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)sort_blocks(capacity)), dim3(kEmitThreads), 0, st,
+                       (const uint4*)drec, offs, starts, n_vis, m64, capacity, views_dev,
+                       FastDiv((uint32_t)(N > 0 ? N : 1)), ek, ev,
+                       (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0, sort_blocks(capacity),
+                       tsp.hist);
   // 5. stable sort by tile
   radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, tsp, st, emitted);
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;
