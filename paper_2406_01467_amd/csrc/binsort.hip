@@ -617,11 +617,16 @@ __global__ void __launch_bounds__(kOrderThreads)
 k_tile_order(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __restrict__ order) {
   __shared__ uint32_t base[kRadix];                 // next position of each key
   __shared__ uint32_t wcnt[kOrderWaves][kRadix];    // per-wave key counts of a chunk
+  __shared__ uint8_t keys[kOrderOneBlock];          // every tile's key, computed once
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x < kRadix) base[threadIdx.x] = 0u;
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < tiles; t += kOrderThreads)
-    atomicAdd(&base[order_key(ranges, t)], 1u);
+#pragma unroll 8
+  for (int64_t t = threadIdx.x; t < tiles; t += kOrderThreads) {
+    const uint32_t k = order_key(ranges, t);
+    keys[t] = (uint8_t)k;
+    atomicAdd(&base[k], 1u);
+  }
   __syncthreads();
   if (threadIdx.x < 64) {  // exclusive scan of the 256 key counts by wave 0
     uint32_t c[4], s = 0;
@@ -644,7 +649,7 @@ k_tile_order(const uint32_t* __restrict__ ranges, int64_t tiles, uint32_t* __res
     for (int k = 0; k < kRadix / 64; ++k) wcnt[wave][k * 64 + lane] = 0u;
     const int64_t t = c0 + threadIdx.x;
     const bool valid = t < tiles;
-    const uint32_t d = valid ? order_key(ranges, t) : 0u;
+    const uint32_t d = valid ? (uint32_t)keys[t] : 0u;
     const uint64_t peers = digit_peers(d, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
