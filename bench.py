@@ -71,7 +71,7 @@ BYTES_PER_PIXEL = 52 + 52 + 36
 MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
                     "schedule": 1, "wave_w": 0, "batch": 0,
                     "sources_sha1": "7be857b646154b0f9b9b6f37eaee9cdeda433d70",
-                    "fetch_bytes": 374811920, "write_bytes": 154785088,
+                    "fetch_bytes": 374969220, "write_bytes": 154785088,
                     "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
 
 

@@ -361,7 +361,7 @@ __device__ __forceinline__ void exact_depth_record(const ViewD& v, const Params&
 }
 
 template <int KMAX, bool VEC, bool EXACT>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, EXACT ? 1 : 2)
 k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
           const float* __restrict__ means, const float* __restrict__ scales,
           const float* __restrict__ quats, const float* __restrict__ opac,
@@ -374,16 +374,27 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   const float* __restrict__ coef_g = sh + 3 * K * g;
   Params P;
   const bool ok = load_params(g, means, scales, quats, opac, P);
-  // the coefficients are loaded with the parameters, so their latency
-  // overlaps the FP64 geometry (the registers fit two waves per SIMD)
+  // Affine depth: the coefficients are loaded with the parameters, so their
+  // latency overlaps the FP64 geometry (the registers fit two waves per
+  // SIMD).  Exact depth: they are loaded per view after the geometry, as its
+  // extra registers leave no room to hold them across it.
   float coef[3 * K];
-  load_row<K, VEC>(coef_g, coef);
-  const bool rok = row_finite<K>(coef);
+  bool rok = true;
+  if constexpr (!EXACT) {
+    load_row<K, VEC>(coef_g, coef);
+    rok = row_finite<K>(coef);
+  }
   for (int vi = 0; vi < V; ++vi) {
     const int64_t o = (int64_t)vi * N + g;
     const ViewD v = load_view(views[vi], st.fov_clamp);
     Geo G;
-    const bool vis = ok && rok && geometry(v, P, st, G) && G.detD > 0.0;
+    bool vis = ok && rok && geometry(v, P, st, G) && G.detD > 0.0;
+    if constexpr (EXACT) {
+      if (vis) {
+        load_row<K, VEC>(coef_g, coef);
+        vis = row_finite<K>(coef);
+      }
+    }
     if (!vis) {
       store_invisible(splats + o);
       tiles_touched[o] = 0;
