@@ -496,6 +496,10 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
   constexpr int K = KMAX;
   const float* __restrict__ coef_g = sh + 3 * K * g;
   float* __restrict__ gcoef = d_sh + 3 * K * g;
+  // the first view's gradient record is loaded together with the
+  // parameters and the SH row, so its latency is not paid after theirs
+  const float4* gr0 = reinterpret_cast<const float4*>(gsplat + g * kGradStride);
+  const float4 g0a = gr0[0], g0b = gr0[1], g0c = gr0[2], g0d = gr0[3];
   Params P;
   bool ok = load_params(g, means, scales, quats, opac, P);
   {
@@ -506,11 +510,11 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
   bool sh_written = false;
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gqn[4] = {0, 0, 0, 0}, go = 0.0;
   for (int vi = 0; ok && vi < V; ++vi) {
-    const float* gr = gsplat + ((int64_t)vi * N + g) * kGradStride;
-    const float4 ga = *reinterpret_cast<const float4*>(gr);
-    const float4 gb = *reinterpret_cast<const float4*>(gr + 4);
-    const float4 gc = *reinterpret_cast<const float4*>(gr + 8);
-    const float4 gd = *reinterpret_cast<const float4*>(gr + 12);
+    float4 ga = g0a, gb = g0b, gc = g0c, gd = g0d;
+    if (vi > 0) {
+      const float4* gr = reinterpret_cast<const float4*>(gsplat + ((int64_t)vi * N + g) * kGradStride);
+      ga = gr[0]; gb = gr[1]; gc = gr[2]; gd = gr[3];
+    }
     const double guc = ga.x, gvc = ga.y, gA = ga.z, gB = ga.w;
     const double gC = gb.x, gO = gb.y;
     const double gZd = gc.y, gp0 = gc.z, gp1 = gc.w;
