@@ -74,7 +74,7 @@ typedef struct rade_settings {
   double dilation;         /* added to the 2x2 footprint covariance, px^2 (0.3) */
   double near_plane;       /* Gaussians with camera z <= near are culled (0.2) */
   double alpha_min;        /* blends with alpha < alpha_min are skipped (1/255) */
-  double alpha_max;        /* alpha is clamped to alpha_max (0.99) */
+  double alpha_max;        /* alpha is clamped to alpha_max (0.99); below 1 in FP32 */
   double t_min;            /* a pixel stops before the blend that would leave T < t_min (1e-4) */
   double power_cut;        /* blends with 1/2 d^T conic d > power_cut are skipped (4.5, 3 sigma) */
   double fov_clamp;        /* x/z, y/z in the Jacobian clamped to fov_clamp * W/(2 fx) (1.3) */

@@ -88,7 +88,8 @@ bool settings_ok(const rade_settings* s) {
   if (!rade::tile_supported(s->tile_w, s->tile_h)) return false;
   if (s->sh_degree < 0 || s->sh_degree > 3) return false;
   if (s->schedule < RADE_SCHEDULE_TILE || s->schedule > RADE_SCHEDULE_PERSISTENT) return false;
-  if (!(s->alpha_min > 0.0) || !(s->alpha_max <= 1.0) || !(s->alpha_min < s->alpha_max))
+  // the backward divides by 1 - alpha, so the clamp must stay below 1 in FP32
+  if (!(s->alpha_min > 0.0) || !((float)s->alpha_max < 1.0f) || !(s->alpha_min < s->alpha_max))
     return false;
   if (!(s->t_min > 0.0 && s->t_min < 1.0) || !(s->power_cut > 0.0)) return false;
   if (!(s->dilation >= 0.0) || !std::isfinite(s->near_plane) || !(s->fov_clamp > 0.0))

@@ -59,7 +59,7 @@ __device__ __forceinline__ bool splat_alpha(const StagedSplat& s, float dx, floa
   e = __builtin_amdgcn_exp2f(-pw);
   const float raw = s.o * e;
   clamped = raw > bp.alpha_max;
-  alpha = clamped ? bp.alpha_max : raw;
+  alpha = fminf(raw, bp.alpha_max);
   return pw <= bp.cut2 && alpha >= bp.alpha_min;
 }
 

@@ -478,7 +478,9 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
 }
 
 // Gradient record of one (view, Gaussian) from the render backward:
-// du, dv, da, db, dc (conic), do, drgb[3], dz, dp[2], dn[3], pad.
+// du, dv (through the footprint only), 2 da, db, 2 dc (conic a, b, c of the power a dx^2 / 2 + b dx dy +
+// c dy^2 / 2, i.e. the sums of g_p dx^2, g_p dx dy, g_p dy^2), do, drgb[3],
+// dz, dp[2], dn[3], pad.
 constexpr int kGradStride = 16;
 
 template <int KMAX, bool VEC>
@@ -535,12 +537,17 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
 #pragma clang fp contract(fast)
     const double X = G.X, Yc = G.Y, Z = G.Z, tc = G.tc;
     const double iz = 1.0 / Z, iz2 = iz * iz;
+    // the record's centre gradient leaves out the depth plane's share: the
+    // plane depth z + p . (u_c - u) moves with the centre by p, so that share
+    // is p times the summed depth gradient
+    const double zt = Z / tc;
+    const double gu = guc + zt * G.q0 * gZd, gv = gvc + zt * G.q1 * gZd;
     double gx[3];
-    gx[0] = guc * v.fx * iz;
-    gx[1] = gvc * v.fy * iz;
-    gx[2] = -(guc * v.fx * X + gvc * v.fy * Yc) * iz2 + gZd;
+    gx[0] = gu * v.fx * iz;
+    gx[1] = gv * v.fy * iz;
+    gx[2] = -(gu * v.fx * X + gv * v.fy * Yc) * iz2 + gZd;
     // p = (Z / tc) q
-    double gq0 = Z / tc * gp0, gq1 = Z / tc * gp1;
+    double gq0 = zt * gp0, gq1 = zt * gp1;
     const double pq = gp0 * G.q0 + gp1 * G.q1;
     gx[2] += pq / tc;
     double gtc = -Z * pq / (tc * tc);
@@ -579,7 +586,7 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     {
       const double idt = 1.0 / G.detD;
       const double ca = G.D11 * idt, cb = -G.B01 * idt, cc = G.D00 * idt;
-      const double G00 = gA, G01 = 0.5 * gB, G11 = gC;
+      const double G00 = 0.5 * gA, G01 = 0.5 * gB, G11 = 0.5 * gC;
       const double m00 = ca * G00 + cb * G01, m01 = ca * G01 + cb * G11;
       const double m10 = cb * G00 + cc * G01, m11 = cb * G01 + cc * G11;
       g00 += -(m00 * ca + m01 * cb);

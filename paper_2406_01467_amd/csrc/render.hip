@@ -287,10 +287,12 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
     __syncthreads();
-    bool wave_live = !__all(done);
-    for (int cw = 0; cw < TG::NCH && wave_live; ++cw) {
+    // lanes of this wave that have stopped, kept as a scalar mask so the
+    // per-splat exit test costs no vector instruction
+    uint64_t wdone = __ballot(done);
+    for (int cw = 0; cw < TG::NCH && wdone != ~0ull; ++cw) {
       uint64_t m = uniform_u64(masks[wave][cw]);
-      while (m) {
+      while (m && wdone != ~0ull) {
         const int j = __builtin_ctzll(m);
         m &= m - 1;
         const int r = cw * 64 + j;
@@ -307,9 +309,9 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         if constexpr (TG::NW == 1) {
           if (!__any(pass)) continue;
         }
-        const float Tn = T * (1.0f - al);
+        const float Tn = fmaf(-al, T, T);  // T (1 - alpha), rounded once
         const bool stop = pass && Tn < bp.t_min;
-        const bool take = pass && !stop;
+        const bool take = pass != stop;  // stop implies pass
         done = done || stop;
         const float w = take ? al * T : 0.0f;
         float d;
@@ -345,7 +347,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         lastp = take ? pos : lastp;
         if constexpr (CNT) cnt += take ? 1 : 0;
         T = take ? Tn : T;
-        if (__all(done)) { wave_live = false; break; }
+        wdone |= __ballot(stop);
       }
     }
     __syncthreads();
@@ -535,16 +537,27 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
       if (lim < 0) continue;  // nothing at or below our last blend
       uint64_t m = uniform_u64(masks[wave][cw]);
       if (lim < 63) m &= (2ull << lim) - 1;  // positions up to wlast
+      // the chunk's Gaussian ids, one per lane; a splat's id is read from
+      // its lane
+      const int cgid = (int)sgid[cw * 64 + lane];
       while (m) {
         const int j = 63 - __builtin_clzll(m);
         m &= ~(1ull << j);
         const int r = cw * 64 + j;
         const int pos = bstart + r;
-        const StagedSplat s = ss[r];
+        const float4* s4 = reinterpret_cast<const float4*>(ss + r);
+        const float4 q0 = s4[0], q1 = s4[1], q2 = s4[2], q3 = s4[3];
+        const StagedSplat s{q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, e, al;
         bool cl;
         const bool has = splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl) && pos <= lastp;
+        // all four 16-byte reads are issued before the branch below (left to
+        // itself the compiler splits the second half into 4-byte reads inside
+        // it, each needing its own address register)
+        asm volatile("" ::"v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w), "v"(q3.x), "v"(q3.y),
+                     "v"(q3.z), "v"(q3.w));
         if (!__any(has)) continue;
         // Branch-free adjoint: every lane evaluates, lanes without this
         // splat contribute zeros and keep their state (alpha <= alpha_max,
@@ -565,22 +578,23 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         const float ga = fmaf(Ti, sf, -(Racc * inv));
         T = has ? Ti : T;
         Racc = has ? fmaf(w, sf, Racc) : Racc;
-        const int gid = __builtin_amdgcn_readfirstlane((int)sgid[r]);
-        const float hm = has ? 1.0f : 0.0f;
-        const float wg = hm * w;
+        const int gid = __builtin_amdgcn_readlane(cgid, j);
+        const float wg = has ? w : 0.0f;
         float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         if constexpr (DIST) gd = fmaf(kdist * wg, d - mdist, gd);
         // d power / d(dx, dy) = (t1 w0 + t2 w2, t1 w1 + t2 w3) 2 / log2(e)
         const float gp = (has && !cl) ? -ga * al : 0.0f;
         const float gpk = gp * kTwoOverLog2e;
-        const float hg = 0.5f * gp;
         float g[16];
-        g[0] = fmaf(gpk, fmaf(t1, s.w0, t2 * s.w2), gd * s.p0);
-        g[1] = fmaf(gpk, fmaf(t1, s.w1, t2 * s.w3), gd * s.p1);
-        const float hdx = hg * dx;
-        g[2] = hdx * dx;
-        g[3] = (gp * dx) * dy;
-        g[4] = (hg * dy) * dy;
+        // centre gradient through the footprint; the depth plane's share,
+        // p times the summed g[9], is added by the projection backward
+        g[0] = gpk * fmaf(t1, s.w0, t2 * s.w2);
+        g[1] = gpk * fmaf(t1, s.w1, t2 * s.w3);
+        // twice the conic gradient (the projection backward halves it)
+        const float gpx = gp * dx;
+        g[2] = gpx * dx;
+        g[3] = gpx * dy;
+        g[4] = (gp * dy) * dy;
         g[5] = (has && !cl) ? ga * e : 0.0f;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;

@@ -75,6 +75,9 @@ def test_views_prepare_offsets():
 
 @pytest.mark.parametrize("bad", [dict(tile_w=12), dict(tile_h=64), dict(sh_degree=4), dict(schedule=3),
                                  dict(alpha_min=0.0), dict(t_min=1.5), dict(power_cut=-1.0),
+                                 # the backward divides by 1 - alpha: the clamp must stay
+                                 # below 1, also after rounding to FP32
+                                 dict(alpha_max=1.0), dict(alpha_max=1.0 - 1e-9),
                                  dict(depth_mode=3), dict(wave_w=12), dict(batch=96),
                                  dict(tile_w=8, tile_h=8, wave_w=16),
                                  dict(tile_w=16, tile_h=32, wave_w=32)])
