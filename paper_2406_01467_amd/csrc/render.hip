@@ -583,7 +583,10 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         if constexpr (DIST) gd = fmaf(kdist * wg, d - mdist, gd);
         // d power / d(dx, dy) = (t1 w0 + t2 w2, t1 w1 + t2 w3) 2 / log2(e)
-        const float gp = (has && !cl) ? -ga * al : 0.0f;
+        // opacity gradient ga e and, since alpha = o e where it is not
+        // clamped, the power gradient -ga alpha = -o (ga e)
+        const float gop = (has && !cl) ? ga * e : 0.0f;
+        const float gp = gop * -s.o;
         const float gpk = gp * kTwoOverLog2e;
         float g[16];
         // centre gradient through the footprint; the depth plane's share,
@@ -595,7 +598,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         g[2] = gpx * dx;
         g[3] = gpx * dy;
         g[4] = (gp * dy) * dy;
-        g[5] = (has && !cl) ? ga * e : 0.0f;
+        g[5] = gop;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;
         g[10] = gd * dx; g[11] = gd * dy;
