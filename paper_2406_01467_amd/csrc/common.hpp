@@ -49,17 +49,26 @@ struct alignas(16) StagedSplat {
 // when the splat is skipped (outside the cut or below alpha_min).  The
 // forward and backward kernels both call exactly this function, compiled
 // without floating-point contraction, so their decisions match bit for bit.
-__device__ __forceinline__ bool splat_alpha(const StagedSplat& s, float dx, float dy,
-                                            const BlendParams& bp, float& t1, float& t2,
-                                            float& e, float& alpha, bool& clamped) {
+// splat_eval computes the pieces and leaves the decision to the caller, which
+// must take it as splat_alpha does: pw <= cut2 and alpha >= alpha_min.
+__device__ __forceinline__ void splat_eval(const StagedSplat& s, float dx, float dy,
+                                           const BlendParams& bp, float& t1, float& t2,
+                                           float& pw, float& e, float& alpha, bool& clamped) {
   t1 = fmaf(s.w0, dx, s.w1 * dy);
   t2 = fmaf(s.w2, dx, s.w3 * dy);
-  const float pw = fmaf(t1, t1, t2 * t2);
+  pw = fmaf(t1, t1, t2 * t2);
   // evaluated on every lane (no branch): alpha <= alpha_max < 1 always
   e = __builtin_amdgcn_exp2f(-pw);
   const float raw = s.o * e;
   clamped = raw > bp.alpha_max;
   alpha = fminf(raw, bp.alpha_max);
+}
+
+__device__ __forceinline__ bool splat_alpha(const StagedSplat& s, float dx, float dy,
+                                            const BlendParams& bp, float& t1, float& t2,
+                                            float& e, float& alpha, bool& clamped) {
+  float pw;
+  splat_eval(s, dx, dy, bp, t1, t2, pw, e, alpha, clamped);
   return pw <= bp.cut2 && alpha >= bp.alpha_min;
 }
 

@@ -265,10 +265,14 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   float dmed = 0.f;
   float dmean = 0.f, dvar = 0.f;  // DIST: weighted mean depth and sum w (d - mean)^2
   int cnt = 0, lastp = -1, medp = -1;
-  bool done = !c.inside;
+  // Lane state of this wave as uniform masks (bit l: lane l), so the
+  // per-splat decisions are scalar operations on the compare results and a
+  // lane's flag is its bit (inverse ballot): wdone, the lanes that have
+  // stopped or lie outside the image.
+  uint64_t wdone = __builtin_amdgcn_ballot_w64(!c.inside);
 
   for (uint32_t b0 = c.rb; b0 < c.re; b0 += TG::BATCH) {
-    if (__syncthreads_and(done ? 1 : 0)) break;
+    if (__syncthreads_and(wdone == ~0ull ? 1 : 0)) break;
     // stage the batch: slot = thread + k * BLOCK (each wave's slots share a chunk)
 #pragma unroll
     for (int k = 0; k < (TG::BATCH + TG::BLOCK - 1) / TG::BLOCK; ++k) {
@@ -287,32 +291,33 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
     __syncthreads();
-    // lanes of this wave that have stopped, kept as a scalar mask so the
-    // per-splat exit test costs no vector instruction
-    uint64_t wdone = __ballot(done);
     for (int cw = 0; cw < TG::NCH && wdone != ~0ull; ++cw) {
       uint64_t m = uniform_u64(masks[wave][cw]);
       while (m && wdone != ~0ull) {
         const int j = __builtin_ctzll(m);
-        m &= m - 1;
+        m &= ~(1ull << j);
         const int r = cw * 64 + j;
         const StagedSplat s = ss[r];
         const float dx = s.ur - fx, dy = s.vr - fy;
-        float t1, t2, e, al;
+        float t1, t2, pw, e, al;
         bool cl;
-        // Branch-free blend: lanes that do not take the splat add w = 0
-        // (x + 0 * finite = x exactly) and keep their state.
-        const bool pass = splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl) && !done;
+        splat_eval(s, dx, dy, bp, t1, t2, pw, e, al, cl);
+        // the decision of splat_alpha, per lane, as masks
+        const uint64_t pass = __builtin_amdgcn_ballot_w64(pw <= bp.cut2) &
+                              __builtin_amdgcn_ballot_w64(al >= bp.alpha_min) & ~wdone;
         // one wave per 8x8 tile: skip splats no lane blends (lists whose
         // pixels saturate unevenly); on larger tiles the branch costs more
         // than it saves
         if constexpr (TG::NW == 1) {
-          if (!__any(pass)) continue;
+          if (!pass) continue;
         }
+        // Branch-free blend: lanes that do not take the splat add w = 0
+        // (x + 0 * finite = x exactly) and keep their state.
         const float Tn = fmaf(-al, T, T);  // T (1 - alpha), rounded once
-        const bool stop = pass && Tn < bp.t_min;
-        const bool take = pass != stop;  // stop implies pass
-        done = done || stop;
+        const uint64_t stop = pass & __builtin_amdgcn_ballot_w64(Tn < bp.t_min);
+        const uint64_t takes = pass & ~stop;
+        wdone |= stop;
+        const bool take = __builtin_amdgcn_inverse_ballot_w64(takes);
         const float w = take ? al * T : 0.0f;
         float d;
         if constexpr (EXACT) {
@@ -341,13 +346,13 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         }
         A += w;
         const int pos = (int)(b0 - c.rb) + r;
-        const bool med_here = take && T > 0.5f;
+        const bool med_here =
+            __builtin_amdgcn_inverse_ballot_w64(takes & __builtin_amdgcn_ballot_w64(T > 0.5f));
         medp = med_here ? pos : medp;
-        dmed = med_here ? d : dmed;
+        if constexpr (EXACT) dmed = med_here ? d : dmed;
         lastp = take ? pos : lastp;
         if constexpr (CNT) cnt += take ? 1 : 0;
         T = take ? Tn : T;
-        wdone |= __ballot(stop);
       }
     }
     __syncthreads();
@@ -359,6 +364,17 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   a.color[3 * c.poff + P + pix] = C1;
   a.color[3 * c.poff + 2 * P + pix] = C2;
   a.depth[2 * c.poff + pix] = D;
+  if constexpr (!EXACT) {
+    // the median splat's plane depth, evaluated once here with the same
+    // operations as in the loop (bit-identical to tracking it per blend)
+    if (medp >= 0) {
+      const rade_splat& sp = splats[vbase + pair_ids[c.rb + medp]];
+      const float ur = (float)(sp.uc - ((double)c.x0 + 0.5));
+      const float vr = (float)(sp.vc - ((double)c.y0 + 0.5));
+      const float dx = ur - fx, dy = vr - fy;
+      dmed = fmaf(sp.p[1], dy, fmaf(sp.p[0], dx, sp.z));
+    }
+  }
   a.depth[2 * c.poff + P + pix] = medp >= 0 ? dmed : 0.0f;
   a.normal[3 * c.poff + pix] = N0;
   a.normal[3 * c.poff + P + pix] = N1;
