@@ -70,8 +70,8 @@ BYTES_PER_PIXEL = 52 + 52 + 36
 # batch); reported as null otherwise.
 MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
                     "schedule": 1, "wave_w": 0, "batch": 0,
-                    "sources_sha1": "d5dc5610b24cf4e6f46a79e509a0ea4ae3a4e1c6",
-                    "fetch_bytes": 375428057, "write_bytes": 154785088,
+                    "sources_sha1": "b0a199b33eccdf631439c5b0de8c37afe06f6e31",
+                    "fetch_bytes": 375196176, "write_bytes": 154785088,
                     "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
 
 

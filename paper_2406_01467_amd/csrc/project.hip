@@ -477,10 +477,13 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   }
 }
 
-// Gradient record of one (view, Gaussian) from the render backward:
-// du, dv (through the footprint only), 2 da, db, 2 dc (conic a, b, c of the power a dx^2 / 2 + b dx dy +
-// c dy^2 / 2, i.e. the sums of g_p dx^2, g_p dx dy, g_p dy^2), do, drgb[3],
-// dz, dp[2], dn[3], pad.
+// Gradient record of one (view, Gaussian) from the render backward, with
+// g_o = dL/d opacity per pixel (zero where alpha is clamped):
+//   0, 1   sums of g_o (t1 w0 + t2 w2), g_o (t1 w1 + t2 w3): the centre
+//          gradient through the footprint is -o 2 / log2(e) times these
+//   2-4    sums of g_o dx^2, g_o dx dy, g_o dy^2: the gradient of the conic
+//          (power a dx^2 / 2 + b dx dy + c dy^2 / 2) is -o (s2 / 2, s3, s4 / 2)
+//   5      do;  6-8 drgb;  9 dz;  10, 11 dp;  12-14 dn;  15 pad.
 constexpr int kGradStride = 16;
 
 template <int KMAX, bool VEC>
@@ -517,8 +520,11 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
       const float4* gr = reinterpret_cast<const float4*>(gsplat + ((int64_t)vi * N + g) * kGradStride);
       ga = gr[0]; gb = gr[1]; gc = gr[2]; gd = gr[3];
     }
-    const double guc = ga.x, gvc = ga.y, gA = ga.z, gB = ga.w;
-    const double gC = gb.x, gO = gb.y;
+    // the power gradient is -o g_o: the per-Gaussian factor of the
+    // footprint terms
+    const double mo = -(double)P.o, mok = mo * (2.0 / kLog2eD);
+    const double guc = ga.x * mok, gvc = ga.y * mok, gA = ga.z * mo, gB = ga.w * mo;
+    const double gC = gb.x * mo, gO = gb.y;
     const double gZd = gc.y, gp0 = gc.z, gp1 = gc.w;
     const double gn0 = gd.x, gn1 = gd.y, gn2 = gd.z;
     if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gb.x == 0.f &&

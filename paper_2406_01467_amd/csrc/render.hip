@@ -457,8 +457,6 @@ __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
   return y;
 }
 
-constexpr float kTwoOverLog2e = 2.0f / kLog2e;
-
 template <int TW, int TH, int WW, int BT>
 struct BwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
@@ -598,22 +596,23 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         const float wg = has ? w : 0.0f;
         float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         if constexpr (DIST) gd = fmaf(kdist * wg, d - mdist, gd);
-        // d power / d(dx, dy) = (t1 w0 + t2 w2, t1 w1 + t2 w3) 2 / log2(e)
-        // opacity gradient ga e and, since alpha = o e where it is not
-        // clamped, the power gradient -ga alpha = -o (ga e)
+        // opacity gradient ga e.  Where alpha is not clamped, alpha = o e, so
+        // the power gradient is -ga alpha = -o (ga e): the footprint terms
+        // below are sums of products with ga e, and the projection backward
+        // applies the per-Gaussian factor -o (times 2 / log2(e) for the
+        // centre, since d power / d(dx, dy) = (t1 w0 + t2 w2, t1 w1 + t2 w3)
+        // 2 / log2(e)).
         const float gop = (has && !cl) ? ga * e : 0.0f;
-        const float gp = gop * -s.o;
-        const float gpk = gp * kTwoOverLog2e;
         float g[16];
         // centre gradient through the footprint; the depth plane's share,
         // p times the summed g[9], is added by the projection backward
-        g[0] = gpk * fmaf(t1, s.w0, t2 * s.w2);
-        g[1] = gpk * fmaf(t1, s.w1, t2 * s.w3);
-        // twice the conic gradient (the projection backward halves it)
-        const float gpx = gp * dx;
+        g[0] = gop * fmaf(t1, s.w0, t2 * s.w2);
+        g[1] = gop * fmaf(t1, s.w1, t2 * s.w3);
+        // conic terms: sums of ga e dx^2, ga e dx dy, ga e dy^2
+        const float gpx = gop * dx;
         g[2] = gpx * dx;
         g[3] = gpx * dy;
-        g[4] = (gp * dy) * dy;
+        g[4] = (gop * dy) * dy;
         g[5] = gop;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;
