@@ -28,8 +28,12 @@ What each function follows (RaDe-GS, arXiv 2406.01467):
 
 Parity status: every function is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (closed forms, invariants, library routines, finite
-differences); nothing is "parity unpinned" except the absolute agreement
-with the authors' unpublished CUDA code.
+differences), the tolerance helpers that set the GPU comparisons' floors and
+exclusions included (:func:`gradient_error_scale`, the distortion's
+``distortion_mag``, the magnitude bound of :func:`normal_consistency`, the
+fragile-pixel flags: ``tests/test_oracle_tolerances.py``); nothing is "parity
+unpinned" except the absolute agreement with the authors' unpublished CUDA
+code.
 """
 from __future__ import annotations
 
@@ -207,12 +211,14 @@ def render_bwd(s: np.ndarray, view, rec: np.ndarray, flags: np.ndarray, gout: np
     vv = view_vector(view)
     pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
     npix = view.width * view.height if pix is None else pix.shape[0]
+    if gP is None:
+        gP = np.zeros((N, len(G_FIELDS)), np.float64)
+    if npix == 0:  # an empty pixel list contributes nothing
+        return gP
     gout = np.asarray(gout, np.float64).reshape(npix, -1)
     if gout.shape[1] == 9:
         gout = np.concatenate([gout, np.zeros((npix, 1))], axis=1)
     gout = np.ascontiguousarray(gout).reshape(npix, GOUT)
-    if gP is None:
-        gP = np.zeros((N, len(G_FIELDS)), np.float64)
     lib.oracle_render_bwd(_ptr(s), _ptr(vv), N, _ptr(np.ascontiguousarray(rec, np.float64)),
                           _ptr(np.ascontiguousarray(flags, np.int32)), _ptr(pix), npix,
                           _ptr(gout), _ptr(gP), _ptr(gP_abs))

@@ -282,7 +282,8 @@ void project_one(const View& v, const double* s, int K, const float* mean, const
     P.x[i] = ((v.R(i, 0) * mu[0] + v.R(i, 1) * mu[1]) + v.R(i, 2) * mu[2]) + v.t[i];
   const double X = P.x[0], Y = P.x[1], Z = P.x[2];
   if (!(Z > s[S_NEAR])) { P.flags = F_CULLED; return; }
-  if (!(255.0 * (double)opac > 1.0)) { P.flags = F_CULLED; return; }  // support would be empty
+  // alpha = o e^-power >= alpha_min needs o > alpha_min: otherwise the support is empty
+  if (!((double)opac > s[S_ALPHA_MIN])) { P.flags = F_CULLED; return; }
   P.o = opac;
 
   // Eq. 1: Sigma = R S S^T R^T with R from the normalised quaternion.
@@ -360,9 +361,10 @@ void project_one(const View& v, const double* s, int K, const float* mean, const
     else P.rgb[c] = P.rgb_raw[c];
   }
 
-  // Support: power <= tau, tau = min(cut, ln(255 o)) (alpha >= 1/255 there);
-  // conservative axis-aligned pixel rect of that ellipse.
-  P.tau = std::min(s[S_POWER_CUT], std::log(255.0 * P.o));
+  // Support: power <= tau, tau = min(cut, ln(o / alpha_min)) (alpha >= alpha_min
+  // there, before the clamp at alpha_max); conservative axis-aligned pixel rect
+  // of that ellipse.
+  P.tau = std::min(s[S_POWER_CUT], std::log(P.o / s[S_ALPHA_MIN]));
   const double rx = std::sqrt(2.0 * P.tau * P.B[0]) * (1.0 + 1e-6) + 1e-3;
   const double ry = std::sqrt(2.0 * P.tau * P.B[2]) * (1.0 + 1e-6) + 1e-3;
   const double xlo = (P.uc - rx) - 0.5, xhi = (P.uc + rx) - 0.5;
@@ -500,9 +502,10 @@ void render_pixel(const double* s, const View& view, const double* rec,
     T = Tn;
   }
   // Eq. 23: sum over all ordered pairs of blended splats.  dist_mag =
-  // sum w_i w_j |d_i - d_j| (|d_i| + |d_j|) bounds the first-order change of
-  // the sum per unit relative perturbation of the depths: the round-off scale
-  // of an evaluation from depths rounded to a lower precision.
+  // sum w_i w_j |d_i - d_j| (|d_i| + |d_j|): when every depth moves by a
+  // relative amount of at most eps the sum moves by at most 2 eps dist_mag
+  // to first order (attained with two splats moved apart), the round-off
+  // scale of an evaluation from depths rounded to a lower precision.
   double dist = 0.0, mag = 0.0;
   for (size_t i = 0; i < ws.size(); ++i)
     for (size_t j = 0; j < ws.size(); ++j) {

@@ -178,18 +178,27 @@ def test_world_to_camera_transform():
         np.testing.assert_allclose(ra[:, R[f]], rb[:, R[f]], rtol=2e-5, atol=2e-5, err_msg=f)
 
 
-def test_support_rect_is_conservative_and_tight():
-    # The pixel rect contains every pixel with power <= tau (alpha >= 1/255
-    # and inside 3 sigma) and extends at most one pixel beyond the ellipse's
-    # exact bounding box.
+@pytest.mark.parametrize("alpha_min", [1.0 / 255.0, 1e-3, 0.05])
+def test_support_rect_is_conservative_and_tight(alpha_min):
+    # The pixel rect contains every pixel the per-pixel rule can blend --
+    # power <= cut (3 sigma) and alpha = o e^-power >= alpha_min, evaluated
+    # here from the definition, not from the oracle's support tau -- and
+    # extends at most one pixel beyond the ellipse's exact bounding box.
+    # Opacities at or below alpha_min leave no such pixel: those Gaussians
+    # are culled.
     rng = np.random.default_rng(5)
     v = view(80, 70, 80.0)
     n = 60
     means = rng.uniform(-0.6, 0.6, (n, 3)) + np.array([0, 0, 2.5])
     q = rng.normal(size=(n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
-    sc = scene_from(means, np.exp(rng.normal(-3.0, 0.6, (n, 3))), q, opac=rng.uniform(0.01, 1, n))
-    rec, rect, flags = _proj(oracle.settings(), v, sc)
+    opac = rng.uniform(0.0005, 1, n)
+    opac[:4] = [alpha_min * 0.999, alpha_min * 1.001, alpha_min * 1.5, alpha_min * 3.0]
+    sc = scene_from(means, np.exp(rng.normal(-3.0, 0.6, (n, 3))), q, opac=opac)
+    s = oracle.settings(alpha_min=alpha_min)
+    rec, rect, flags = _proj(s, v, sc)
+    o32 = sc.opacities.astype(np.float64)
+    assert (((flags & oracle.F_CULLED) != 0) == (o32 <= alpha_min)).all()
     yy, xx = np.mgrid[0:v.height, 0:v.width]
     for g in range(n):
         if flags[g] & oracle.F_CULLED:
@@ -198,7 +207,8 @@ def test_support_rect_is_conservative_and_tight():
         dx = r[R["uc"]] - (xx + 0.5)
         dy = r[R["vc"]] - (yy + 0.5)
         power = 0.5 * (r[R["a"]] * dx * dx + 2 * r[R["b"]] * dx * dy + r[R["c"]] * dy * dy)
-        inside = power <= r[R["tau"]]
+        inside = (power <= 4.5) & (o32[g] * np.exp(-power) >= alpha_min)
+        assert np.isclose(r[R["tau"]], min(4.5, np.log(o32[g] / alpha_min)), rtol=1e-14)
         if inside.any():
             assert flags[g] & oracle.F_VISIBLE
             ys, xs = np.nonzero(inside)
