@@ -17,10 +17,15 @@ Default workload: 1,000,000 Gaussians (64 anisotropic clusters at distance
 2..20, SH degree 3) seen by one 1600x1064 view.
 
 Prints one JSON line: value = splat-pixel blends per second, ms_per_step =
-fwd+bwd milliseconds per step (all views), ms_per_view = the same per view; roofline of the dominant kernel (HIP events
-recorded by the library around its launches); the eager autograd path
-(torch.autograd.Function + torch loss) for comparison; the FP64 CPU oracle
-timed on a bounded pixel sample.
+fwd+bwd milliseconds per step (all views), ms_per_view = the same per view;
+the roofline of the dominant kernel (its duration from HIP events the library
+records around its launches; algorithmic flops against the FP32 vector peak
+and algorithmic bytes against the HBM peak) and of the whole step; the
+evaluations per blend (splats the pixels evaluated over splats they blended);
+the eager autograd path (torch.autograd.Function + torch loss) for
+comparison; the many-view leg: 16 uneven views of the same scene rendered as
+one batch, against the same views unbatched; the FP64 CPU oracle timed on a
+bounded pixel sample.
 """
 from __future__ import annotations
 
@@ -38,7 +43,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd ms/view and splat-pixel blends/s, 1M Gaussians, 1600x1064"
-PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed)
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed FP32 instructions)
+# The FP32 vector peak without packed instructions (this library emits none):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6
 PEAK_HBM_GBS = 8000.0         # MI355X published HBM3E bandwidth
 
 # Algorithmic FP32 operations per blended (pixel, splat) pair, counted from
@@ -50,29 +58,66 @@ PEAK_HBM_GBS = 8000.0         # MI355X published HBM3E bandwidth
 # centre grads (8), conic grads (7), opacity (1), colour (3), depth/plane (3),
 # normal (3) = 74.
 FLOPS_PER_BLEND = {"render_fwd": 34, "render_bwd": 74}
-# Algorithmic HBM bytes (minimum traffic), per Gaussian and view, per pair
-# and per pixel: params read 236 B (SH degree 3) in the forward and again in
-# the backward, splat write 80 + read 80, tile count 4+4, splat-gradient
-# record write+read 128, parameter gradients 236; per pair: emit 8, two sort
-# passes x 16, ranges 4, gather fwd 84, gather bwd 84; per pixel: maps and
-# state written 52, read back 52, upstream gradients 36.
-BYTES_PER_GAUSSIAN = 236 * 2 + 80 * 2 + 8 + 128 + 236
-BYTES_PER_PAIR = 8 + 32 + 4 + 84 + 84
-BYTES_PER_PIXEL = 52 + 52 + 36
+
+# Algorithmic HBM bytes of one fwd+bwd step: the least traffic the method
+# moves, ignoring multiple radix passes and atomics.
+#  - per Gaussian, once per batch of views: parameters read, read again by the
+#    backward, parameter gradients written: 3 x 4 (11 + 3K) bytes (708 at SH
+#    degree 3, K = 16);
+#  - per (Gaussian, view): splat record written 68, tile count written and
+#    scanned 8, support rect read 16, splat-gradient record written and read
+#    60 + 60 = 212;
+#  - per (tile, splat) pair: emitted 12, sorted 24, ranges 8, gathered by the
+#    forward 68 and by the backward 68 = 180;
+#  - per pixel: maps and saved state written by the forward 48, read by the
+#    backward 48 = 96.
+# The rasterizer backward alone moves 68 per pair (gather), 48 per pixel
+# (upstream gradients and saved state) and 60 per (Gaussian, view) (its
+# gradient-record writes).
+def param_bytes(sh_degree: int) -> int:
+    return 4 * (11 + 3 * (sh_degree + 1) ** 2)
+
+
+BYTES_PER_GAUSSIAN_VIEW = 68 + 8 + 16 + 60 + 60
+BYTES_PER_PAIR = 12 + 24 + 8 + 68 + 68
+BYTES_PER_PIXEL = 48 + 48
+RENDER_BWD_BYTES = {"pair": 68, "pixel": 48, "gaussian_view": 60}
+RENDER_FWD_BYTES = {"pair": 68, "pixel": 48, "gaussian_view": 0}
+
+
+def step_bytes(n: int, views: int, pairs: int, pixels: int, sh_degree: int) -> int:
+    return (3 * param_bytes(sh_degree) * n + BYTES_PER_GAUSSIAN_VIEW * n * views +
+            BYTES_PER_PAIR * pairs + BYTES_PER_PIXEL * pixels)
+
+
+def kernel_bytes(kernel: str, n: int, views: int, pairs: int, pixels: int) -> int:
+    c = RENDER_BWD_BYTES if kernel == "render_bwd" else RENDER_FWD_BYTES
+    return c["pair"] * pairs + c["pixel"] * pixels + c["gaussian_view"] * n * views
+
 
 # HBM traffic of one launch of the dominant kernel, from two rocprofv3 --pmc
 # runs of paper_2406_01467_amd/profile_step.py (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch), each scaled by what the counter reads for a copy kernel
 # of known size (FETCH_SIZE reads half of the bytes a plain copy moves,
-# WRITE_SIZE all of them).  Valid only for the kernel sources it was measured
-# on (SHA-1 of render.hip + common.hpp) and for the 1600x1064 / 1M workload
-# in the launch configuration it was measured in (tile, schedule, wave shape,
-# batch); reported as null otherwise.
-MEASURED_TRAFFIC = {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
-                    "schedule": 1, "wave_w": 0, "batch": 0,
-                    "sources_sha1": "b0a199b33eccdf631439c5b0de8c37afe06f6e31",
-                    "fetch_bytes": 375196176, "write_bytes": 154785088,
-                    "profile": "profiles/kernels_1600x1064_1m_pmc.md"}
+# WRITE_SIZE all of them), and its VALU counters from a third run (VALU
+# issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x duration x 2.4 GHz)).
+# Valid only for the kernel sources they were measured on (SHA-1 of
+# render.hip + common.hpp) and for the workload in the launch configuration
+# they were measured in (tile, schedule, wave shape, batch); reported as null
+# otherwise.
+MEASURED = [
+    {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
+     "schedule": 1, "wave_w": 0, "batch": 0,
+     "sources_sha1": "b0a199b33eccdf631439c5b0de8c37afe06f6e31",
+     "fetch_bytes": 375196176, "write_bytes": 154785088, "valu_issue": 0.84,
+     "profile": "profiles/kernels_1600x1064_1m_pmc.md"},
+]
+
+
+# Launch settings of the 16-view batch, as the autotuner chose them over tile
+# size x schedule, then wave shape x staging batch (`--tile auto` with
+# `--workload batched_16views_1m`); fixed here so the timed run does no tuning.
+BATCHED_TUNED = {"tile": "8x8", "schedule": 1, "batch": 128, "wave_w": 0}
 
 
 def _render_sources_sha1() -> str:
@@ -84,14 +129,15 @@ def _render_sources_sha1() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, settings):
-    t = MEASURED_TRAFFIC
+def measured(kernel: str, workload: str, settings):
     tile = f"{settings.tile_w}x{settings.tile_h}"
-    if (t is None or t["kernel"] != kernel or t["workload"] != workload or t["tile"] != tile
-            or t["schedule"] != settings.schedule or t["wave_w"] != settings.wave_w
-            or t["batch"] != settings.batch or t["sources_sha1"] != _render_sources_sha1()):
-        return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    sha = _render_sources_sha1()
+    for t in MEASURED:
+        if (t["kernel"] == kernel and t["workload"] == workload and t["tile"] == tile
+                and t["schedule"] == settings.schedule and t["wave_w"] == settings.wave_w
+                and t["batch"] == settings.batch and t["sources_sha1"] == sha):
+            return t
+    return None
 
 
 def parse():
@@ -121,6 +167,14 @@ def parse():
     ap.add_argument("--unbatched-steps", type=int, default=5,
                     help="with several views: steps of the unbatched form (each view its own "
                          "graph-replayed plan, run one after another) for comparison (0: skip)")
+    ap.add_argument("--batched-workload", default="batched_16views_1m",
+                    help="the many-view leg reported beside the headline line: a workload of "
+                         "several uneven views rendered as one batch ('none' to skip)")
+    ap.add_argument("--batched-tile", default=BATCHED_TUNED["tile"],
+                    help="tile of the many-view leg (its autotuned choice by default)")
+    ap.add_argument("--batched-schedule", type=int, default=BATCHED_TUNED["schedule"])
+    ap.add_argument("--batched-batch", type=int, default=BATCHED_TUNED["batch"])
+    ap.add_argument("--batched-wave", type=int, default=BATCHED_TUNED["wave_w"])
     return ap.parse_args()
 
 
@@ -268,6 +322,177 @@ def cpu_baseline(scene, views, settings, npix: int, seed: int = 0):
     }
 
 
+def count_pass(views, settings, params, dev):
+    """Blends, evaluations and pairs of one forward (deterministic for fixed
+    inputs; counted with the default wave shape, which the blend count does
+    not depend on)."""
+    import torch
+
+    from paper_2406_01467_amd.raster import Rasterizer
+    with torch.no_grad():
+        counter = Rasterizer(views, dataclasses.replace(settings, wave_w=0, batch=0), dev)
+        maps = counter.forward(*params, want_count=True, want_evals=True)
+        torch.cuda.synchronize()
+        blends = int(maps.count.sum().item())
+        evals = int(maps.evals.to(torch.int64).sum().item())
+        pairs = int(maps.state.n_pairs)
+        del maps
+    return blends, evals, pairs
+
+
+def time_plan(plan, steps: int, warmup: int):
+    """Replay a captured plan: wall ms per step and per-step HIP-event ms."""
+    import torch
+    plan.step()  # capture, replay, grow on overflow
+    for _ in range(warmup):
+        plan.replay()
+    # per-step HIP events on the replay stream (recorded between replays, no
+    # host synchronisation inside the timed window)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        plan.replay()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if plan.overflowed():
+        raise RuntimeError("pair capacity overflow during the timed replays")
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return 1e3 * (t1 - t0) / steps, per
+
+
+def kernel_times(plan, ksteps: int) -> dict:
+    """Mean duration of each rasterizer kernel: HIP events the library
+    records around each of its launches, on the stream it launches on, over
+    steps enqueued eagerly."""
+    import torch
+
+    from paper_2406_01467_amd import _lib
+    kinds = {"project": _lib.RADE_KERNEL_PROJECT, "render_fwd": _lib.RADE_KERNEL_RENDER_FWD,
+             "render_bwd": _lib.RADE_KERNEL_RENDER_BWD,
+             "project_bwd": _lib.RADE_KERNEL_PROJECT_BWD}
+    events = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(ksteps)] for k in kinds}
+    for lst in events.values():  # torch creates the HIP event on first record
+        for a, b in lst:
+            a.record()
+            b.record()
+    torch.cuda.synchronize()
+    for i in range(ksteps):
+        for k, kid in kinds.items():
+            _lib.rade_set_kernel_events(kid, *events[k][i])
+        plan.enqueue()
+    torch.cuda.synchronize()
+    for kid in kinds.values():
+        _lib.rade_set_kernel_events(kid, None, None)
+    return {k: float(np.mean([a.elapsed_time(b) for a, b in events[k]])) for k in kinds}
+
+
+def unbatched_ms(views, settings, params, target, vcs, steps: int, recompute=False,
+                 distortion=False, w_dist=0.0):
+    """The same step unbatched: one graph-replayed plan per view, replayed
+    one after another; ms for all views together."""
+    import torch
+
+    from paper_2406_01467_amd.batched import BatchedPlan
+    from paper_2406_01467_amd.loss import make_grad_fn
+    from paper_2406_01467_amd.raster import Rasterizer
+    singles = []
+    for vc, v in zip(vcs, views):
+        r1 = Rasterizer([v], settings, params[0].device)
+        tv = target[3 * vc.pix_offset: 3 * (vc.pix_offset + vc.width * vc.height)]
+        p1 = BatchedPlan([v], settings, params, make_grad_fn(r1, tv, w_dist=w_dist),
+                         recompute=recompute, distortion=distortion)
+        p1.step()
+        singles.append(p1)
+    for p1 in singles:
+        p1.replay()
+    torch.cuda.synchronize()
+    tu = time.perf_counter()
+    for _ in range(steps):
+        for p1 in singles:
+            p1.replay()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - tu) / steps
+    if any(p1.overflowed() for p1 in singles):
+        raise RuntimeError("pair capacity overflow in the unbatched plans")
+    del singles
+    return ms
+
+
+def rooflines(kernel_ms: dict, blends: int, n: int, views: int, pairs: int, pixels: int,
+              sh_degree: int, ms_step: float, workload: str, settings) -> tuple:
+    """(roofline object of the dominant render kernel, whole-step HBM
+    roofline) from the algorithmic flop and byte counts above."""
+    dom = max(("render_fwd", "render_bwd"), key=lambda k: kernel_ms[k])
+    dur = kernel_ms[dom] * 1e-3
+    achieved = blends * FLOPS_PER_BLEND[dom] / dur / 1e12
+    kb = kernel_bytes(dom, n, views, pairs, pixels)
+    meas = measured(dom, workload, settings)
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved,
+            "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "peak_packed_fp32": PEAK_FP32_TFLOPS,
+            "frac_of_packed_peak": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None if meas is None else meas["fetch_bytes"] + meas["write_bytes"],
+            "valu_issue": None if meas is None else meas["valu_issue"],
+            "hbm": {"algorithmic_bytes": kb, "achieved_GBs": kb / dur / 1e9,
+                    "peak_GBs": PEAK_HBM_GBS, "frac": kb / dur / 1e9 / PEAK_HBM_GBS}}
+    sb = step_bytes(n, views, pairs, pixels, sh_degree)
+    whole = {"algorithmic_bytes": sb, "floor_ms": sb / (PEAK_HBM_GBS * 1e9) * 1e3,
+             "achieved_GBs": sb / (ms_step * 1e-3) / 1e9,
+             "frac": sb / (PEAK_HBM_GBS * 1e9) / (ms_step * 1e-3)}
+    return roof, whole
+
+
+def batched_leg(args, params, scene_n: int, sh_degree: int, dev) -> dict:
+    """The many-view workload as one batch (one launch per kernel over all
+    views, graph-replayed) against the same views unbatched."""
+    import torch
+
+    import synth
+    from paper_2406_01467_amd import Settings
+    from paper_2406_01467_amd.batched import BatchedPlan
+    from paper_2406_01467_amd.loss import make_grad_fn
+    from paper_2406_01467_amd.raster import Rasterizer
+    scene, views = synth.make_workload(args.batched_workload)
+    if scene.n != scene_n:
+        raise RuntimeError("the many-view leg renders the headline workload's scene")
+    tw, th = (int(x) for x in args.batched_tile.split("x"))
+    st = Settings(tile_w=tw, tile_h=th, sh_degree=sh_degree, schedule=args.batched_schedule,
+                  batch=args.batched_batch, wave_w=args.batched_wave)
+    V = len(views)
+    target = torch.from_numpy(synth.random_targets(views, seed=7)["color"]).to(dev)
+    rast = Rasterizer(views, st, dev)
+    blends, evals, pairs = count_pass(views, st, params, dev)
+    plan = BatchedPlan(views, st, params, make_grad_fn(rast, target))
+    ms, per = time_plan(plan, args.steps, args.warmup)
+    kms = kernel_times(plan, max(3, min(args.steps, 5)))
+    del plan
+    ub = None
+    if args.unbatched_steps > 0:
+        ub = unbatched_ms(views, st, params, target, rast.views_c, args.unbatched_steps)
+    roof, whole = rooflines(kms, blends, scene.n, V, pairs, rast.total_pixels, sh_degree, ms,
+                            args.batched_workload, st)
+    return {"workload": args.batched_workload, "views": V,
+            "sizes": [[v.width, v.height] for v in views], "pixels": rast.total_pixels,
+            "tile": args.batched_tile, "schedule": st.schedule,
+            "batch": st.batch or tw * th, "wave": f"{st.wave_w or 8}x{64 // (st.wave_w or 8)}",
+            "mode": "all views in one launch per kernel, whole fwd+bwd step replayed as one "
+                    "HIP graph",
+            "ms_per_step": ms, "ms_per_view": ms / V,
+            "step_ms_percentiles": {"p10": float(np.percentile(per, 10)),
+                                    "p50": float(np.percentile(per, 50)),
+                                    "p90": float(np.percentile(per, 90))},
+            "ms_per_view_unbatched": None if ub is None else ub / V,
+            "unbatched_mode": "one graph-replayed plan per view, replayed one after another",
+            "blends_per_s": blends / (ms * 1e-3), "blends_per_view": blends / V,
+            "pairs_per_view": pairs / V, "evals_per_blend": evals / max(1, blends),
+            "kernel_ms": kms, "roofline": roof, "hbm_roofline_whole_step": whole}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -277,7 +502,7 @@ def main():
     import torch
 
     import synth
-    from paper_2406_01467_amd import Settings, _lib
+    from paper_2406_01467_amd import Settings
     from paper_2406_01467_amd.batched import BatchedPlan, autotune
     from paper_2406_01467_amd.loss import W_DIST, make_grad_fn, torch_loss
     from paper_2406_01467_amd.raster import Rasterizer, render
@@ -300,85 +525,24 @@ def main():
                                      make_grad_fn(probe, target, w_dist=w_dist),
                                      distortion=args.distortion)
     rast = Rasterizer(views, settings, dev)
-
-    # blends and pairs per step (deterministic for fixed inputs; the blend
-    # count is compiled for the default wave shape, and does not depend on it)
-    with torch.no_grad():
-        counter = Rasterizer(views, dataclasses.replace(settings, wave_w=0, batch=0), dev)
-        maps = counter.forward(*params, want_count=True)
-        torch.cuda.synchronize()
-        blends = int(maps.count.sum().item())
-        pairs = int(maps.state.n_pairs)
-        del maps
+    blends, evals, pairs = count_pass(views, settings, params, dev)
 
     grad_fn = make_grad_fn(rast, target, w_dist=w_dist)
     plan = BatchedPlan(views, settings, params, grad_fn, recompute=args.recompute,
                        distortion=args.distortion)
-    plan.step()  # capture, replay, grow on overflow
-    for _ in range(args.warmup):
-        plan.replay()
-    # per-step HIP events on the replay stream (recorded between replays, no
-    # host synchronisation inside the timed window)
-    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    step_ev[0].record()
-    for i in range(args.steps):
-        plan.replay()
-        step_ev[i + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if plan.overflowed():
-        raise RuntimeError("pair capacity overflow during the timed replays")
-    ms_step = 1e3 * (t1 - t0) / args.steps
-    per_step = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
+    ms_step, per_step = time_plan(plan, args.steps, args.warmup)
+    kernel_ms = kernel_times(plan, max(3, min(args.steps, 10)))
+    loss_val = [float(x) for x in grad_fn.loss.cpu()]
+    peak_mem = None
+    if args.recompute:
+        peak_mem = int(torch.cuda.max_memory_allocated())
+    del plan
 
-    # per-kernel durations: HIP events recorded by the library around each
-    # launch, over the same steps enqueued eagerly on the same stream
-    kinds = {"project": _lib.RADE_KERNEL_PROJECT, "render_fwd": _lib.RADE_KERNEL_RENDER_FWD,
-             "render_bwd": _lib.RADE_KERNEL_RENDER_BWD,
-             "project_bwd": _lib.RADE_KERNEL_PROJECT_BWD}
-    ksteps = max(3, min(args.steps, 10))
-    events = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(ksteps)] for k in kinds}
-    for lst in events.values():  # torch creates the HIP event on first record
-        for a, b in lst:
-            a.record()
-            b.record()
-    torch.cuda.synchronize()
-    for i in range(ksteps):
-        for k, kid in kinds.items():
-            _lib.rade_set_kernel_events(kid, *events[k][i])
-        plan.enqueue()
-    torch.cuda.synchronize()
-    for kid in kinds.values():
-        _lib.rade_set_kernel_events(kid, None, None)
-    kernel_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in events[k]])) for k in kinds}
-
-    # several views: the same step unbatched (one plan per view, replayed
-    # one after another) for comparison with the one-launch-per-kernel batch
-    unbatched_ms = None
+    # several views: the same step unbatched for comparison with the batch
+    ub_ms = None
     if V > 1 and args.unbatched_steps > 0:
-        singles = []
-        for vc, v in zip(rast.views_c, views):
-            r1 = Rasterizer([v], settings, dev)
-            tv = target[3 * vc.pix_offset: 3 * (vc.pix_offset + vc.width * vc.height)]
-            p1 = BatchedPlan([v], settings, params, make_grad_fn(r1, tv, w_dist=w_dist),
-                             recompute=args.recompute, distortion=args.distortion)
-            p1.step()
-            singles.append(p1)
-        for p1 in singles:
-            p1.replay()
-        torch.cuda.synchronize()
-        tu = time.perf_counter()
-        for _ in range(args.unbatched_steps):
-            for p1 in singles:
-                p1.replay()
-        torch.cuda.synchronize()
-        unbatched_ms = 1e3 * (time.perf_counter() - tu) / args.unbatched_steps
-        if any(p1.overflowed() for p1 in singles):
-            raise RuntimeError("pair capacity overflow in the unbatched plans")
-        del singles
+        ub_ms = unbatched_ms(views, settings, params, target, rast.views_c,
+                             args.unbatched_steps, args.recompute, args.distortion, w_dist)
 
     # the eager autograd path (user-facing API, torch loss) for comparison
     eager_ms = None
@@ -401,12 +565,11 @@ def main():
             eager_step()
         torch.cuda.synchronize()
         eager_ms = 1e3 * (time.perf_counter() - te) / args.eager_steps
+        del leaves
 
     value = blends / (ms_step * 1e-3)
-    dom = max(("render_fwd", "render_bwd"), key=lambda k: kernel_ms[k])
-    achieved = blends * FLOPS_PER_BLEND[dom] / (kernel_ms[dom] * 1e-3) / 1e12
-    alg_bytes = (BYTES_PER_GAUSSIAN * scene.n * V + BYTES_PER_PAIR * pairs +
-                 BYTES_PER_PIXEL * rast.total_pixels)
+    roof, whole = rooflines(kernel_ms, blends, scene.n, V, pairs, rast.total_pixels,
+                            scene.sh_degree, ms_step, args.workload, settings)
     line = {
         "metric": METRIC,
         "value": value,
@@ -434,22 +597,22 @@ def main():
                            (" + 100 x depth distortion (Eq. 23)" if args.distortion else ""),
                    "mode": "whole fwd+bwd step replayed as one HIP graph",
                    "recompute_splats": bool(args.recompute)},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(dom, args.workload, settings)},
+        "roofline": roof,
         "blends_per_view": blends / V,
         "pairs_per_view": pairs / V,
+        "evals_per_blend": evals / max(1, blends),
         "kernel_ms": kernel_ms,
         "ms_per_view_eager_autograd": None if eager_ms is None else eager_ms / V,
-        "ms_per_view_unbatched": None if unbatched_ms is None else unbatched_ms / V,
-        "hbm_roofline_whole_step": {"algorithmic_bytes": alg_bytes,
-                                    "floor_ms": alg_bytes / (PEAK_HBM_GBS * 1e9) * 1e3,
-                                    "frac": alg_bytes / (PEAK_HBM_GBS * 1e9) / (ms_step * 1e-3)},
-        "loss": [float(x) for x in grad_fn.loss.cpu()],
+        "ms_per_view_unbatched": None if ub_ms is None else ub_ms / V,
+        "hbm_roofline_whole_step": whole,
+        "loss": loss_val,
     }
+    if peak_mem is not None:
+        line["peak_memory_bytes"] = peak_mem
     if timings:
         line["autotune_ms"] = timings
+    if args.batched_workload != "none" and V == 1:
+        line["batched"] = batched_leg(args, params, scene.n, scene.sh_degree, dev)
     if args.depth_ablation > 0:
         line["depth_ablation"] = depth_ablation(params, views, settings, args.depth_ablation, dev)
     if args.mesh_grid > 0:

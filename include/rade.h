@@ -42,6 +42,17 @@
  *   C channels holds, for view v, C planes of W_v * H_v floats starting at
  *   C * views[v].pix_offset.  For one view this is the CHW layout.
  * - Return value: RADE_OK (0) or a negative error code (rade_strerror).
+ *   Every entry point that enqueues GPU work checks its arguments first
+ *   (RADE_ERR_INVALID_ARG, RADE_ERR_WORKSPACE), then that the calling
+ *   thread's current HIP device is a gfx950 GPU (RADE_ERR_UNSUPPORTED_DEVICE;
+ *   the kernels are compiled for gfx950 only).  The device is queried once
+ *   per device ordinal and the answer cached.
+ * - Workspaces: each entry point that needs scratch memory has its own size
+ *   function (rade_bin_sort_workspace, rade_tile_order_workspace,
+ *   rade_render_bwd_workspace, rade_normal_consistency_workspace,
+ *   rade_marching_cubes_workspace) taking exactly the sizes that call
+ *   depends on, in place of one rade_workspace_bytes(which, ...) selector.
+ *   They are host functions, need no GPU and return 0 for invalid sizes.
  */
 #ifndef RADE_H
 #define RADE_H
@@ -54,10 +65,12 @@ extern "C" {
 #endif
 
 #define RADE_OK 0
-#define RADE_ERR_INVALID_ARG (-1)  /* bad pointer, size or setting; nothing enqueued */
-#define RADE_ERR_CAPACITY (-2)     /* more output than the capacity given (pairs, mesh) */
-#define RADE_ERR_HIP (-3)          /* a HIP runtime call failed */
-#define RADE_ERR_WORKSPACE (-4)    /* workspace smaller than required */
+#define RADE_ERR_INVALID_ARG (-1)        /* bad pointer, size or setting; nothing enqueued */
+#define RADE_ERR_CAPACITY (-2)           /* more output than the capacity given (pairs, mesh) */
+#define RADE_ERR_HIP (-3)                /* a HIP runtime call failed */
+#define RADE_ERR_UNSUPPORTED_DEVICE (-4) /* the current device is not a gfx950 GPU (or there
+                                            is none); nothing enqueued */
+#define RADE_ERR_WORKSPACE (-5)          /* workspace smaller than required; nothing enqueued */
 
 /* Rasterizer settings.  Quantities the paper leaves open default to the
  * values of the 3D Gaussian Splatting code base the paper builds on (it
@@ -87,9 +100,10 @@ typedef struct rade_settings {
                               of the tile workgroup (tile_w * tile_h).  Shapes other than
                               8x8 waves with one splat per thread are compiled for the
                               plain forward and backward only: with a distortion map, a
-                              blend count or the exact depth, the render calls return
-                              RADE_ERR_INVALID_ARG.  Maps do not depend on either field;
-                              gradients only up to the order of FP32 additions. */
+                              blend count, an evaluation count or the exact depth, the
+                              render calls return RADE_ERR_INVALID_ARG.  Maps do not
+                              depend on either field; gradients only up to the order of
+                              FP32 additions. */
   int32_t reserved;        /* must be 0 */
 } rade_settings;
 
@@ -147,8 +161,11 @@ int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
  *   views_dev : V rade_view structs in device memory (after views_prepare)
  *   means N*3, scales N*3, quats N*4, opacities N, sh N*K*3 (see above)
  * A Gaussian is culled when a parameter is not finite, its camera z <=
- * near_plane, its quaternion is zero or 255 * opacity <= 1.  The geometry is
- * evaluated in FP64 and rounded to the FP32 fields once. */
+ * near_plane, its quaternion is zero or opacity <= alpha_min (then no pixel
+ * reaches alpha >= alpha_min).  The rect holds every pixel centre where
+ * power <= min(power_cut, ln(opacity / alpha_min)), i.e. every pixel the
+ * per-pixel rule of rade_render_fwd can blend.  The geometry is evaluated in
+ * FP64 and rounded to the FP32 fields once. */
 /* depth_quad (V*N records of 8 floats, 16-byte aligned): required when
  * depth_mode is RADE_DEPTH_EXACT, ignored (may be NULL) otherwise.  With A
  * the camera-space inverse covariance, r_c = (x/z, y/z, 1) the centre's ray
@@ -216,6 +233,18 @@ int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t
  *   t_final (float), last (int32: position of the last blended splat within
  *   its tile's list, -1 if none), median (int32: Gaussian id of the median
  *   splat, -1 if none); count (int32, optional, may be NULL): splats blended.
+ * evals (int32, 1 plane, optional, may be NULL): splats the pixel evaluated
+ *   (power and alpha computed) while it was still blending, i.e. the work the
+ *   tile lists and the per-wavefront culling leave to the pixel; sum(evals) /
+ *   sum(count) measures how much of that work blends.  A splat counts for
+ *   every pixel of a wavefront that evaluates it, whether or not it passes
+ *   the per-pixel tests.  Unlike every other output it depends on the tile
+ *   size, the wave shape and the staging batch.
+ * Every output except evals is independent of the tile size, wave shape,
+ * batch and schedule, bit for bit: a pixel blends the same splats in the same
+ * order with the same FP32 operations whichever tile holds it (each splat's
+ * centre is rounded relative to a 32-pixel-aligned origin that depends on the
+ * pixel only).
  * distortion (1 plane, optional, may be NULL): the depth distortion of
  * Sec. 3.4 Eq. 23 per pixel, sum_{i,j} w_i w_j (d_i - d_j)^2 over the blended
  * splats (d_i the depth of Eq. 4 at the pixel, or of Eq. 7 in exact mode).
@@ -228,7 +257,7 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
-                    int32_t* median, int32_t* count, float* distortion,
+                    int32_t* median, int32_t* count, int32_t* evals, float* distortion,
                     const float* depth_quad, void* stream);
 
 /* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
@@ -401,7 +430,12 @@ int rade_set_kernel_events(int kernel, void* start_event, void* stop_event);
 /* Static description of an error code (never NULL). */
 const char* rade_strerror(int code);
 
-/* ABI version of this header: 4. */
+/* Device check: RADE_OK when the calling thread's current HIP device is a
+ * gfx950 GPU, RADE_ERR_UNSUPPORTED_DEVICE otherwise (also when no device is
+ * present).  The entry points above make the same check themselves. */
+int rade_device_check(void);
+
+/* ABI version of this header: 5. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

@@ -22,7 +22,8 @@ RADE_OK = 0
 RADE_ERR_INVALID_ARG = -1
 RADE_ERR_CAPACITY = -2
 RADE_ERR_HIP = -3
-RADE_ERR_WORKSPACE = -4
+RADE_ERR_UNSUPPORTED_DEVICE = -4
+RADE_ERR_WORKSPACE = -5
 
 RADE_SCHEDULE_TILE, RADE_SCHEDULE_HEAVY_FIRST, RADE_SCHEDULE_PERSISTENT = 0, 1, 2
 
@@ -101,7 +102,7 @@ class Settings:
 
 
 _lib = None
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 def load() -> ctypes.CDLL:
@@ -118,7 +119,7 @@ def load() -> ctypes.CDLL:
     lib.rade_bin_sort_workspace.argtypes = [I32, I64, I64, I64]
     lib.rade_bin_sort_workspace.restype = SZ
     lib.rade_bin_sort.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I64, P, P, P, SZ, P]
-    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 14 + [P]
+    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 15 + [P]
     lib.rade_tile_order_workspace.argtypes = [I64]
     lib.rade_tile_order_workspace.restype = SZ
     lib.rade_tile_order.argtypes = [P, P, I32, P, P, P, SZ, P]
@@ -129,6 +130,8 @@ def load() -> ctypes.CDLL:
     lib.rade_strerror.argtypes = [ctypes.c_int]
     lib.rade_strerror.restype = ctypes.c_char_p
     lib.rade_abi_version.restype = ctypes.c_int
+    lib.rade_device_check.argtypes = []
+    lib.rade_device_check.restype = ctypes.c_int
     if lib.rade_abi_version() != ABI_VERSION:
         raise RuntimeError(f"{LIB_PATH} implements ABI {lib.rade_abi_version()}, this binding "
                            f"needs {ABI_VERSION}: rebuild with `python -m paper_2406_01467_amd.build`")
@@ -167,7 +170,7 @@ EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "ra
             "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
             "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
             "rade_tsdf_fuse", "rade_marching_cubes_workspace", "rade_marching_cubes",
-            "rade_marching_cubes_table", "rade_l1_color_grad"]
+            "rade_marching_cubes_table", "rade_l1_color_grad", "rade_device_check"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -285,15 +288,21 @@ def rade_tile_order(settings: Settings, views_c, tile_ranges, tile_order, worksp
 
 def rade_render_fwd(settings: Settings, views_c, views_dev, V: int, N: int, splats, pair_ids,
                     tile_ranges, color, depth, normal, alpha, t_final, last, median, count=None,
-                    stream=None, tile_order=None, distortion=None, depth_quad=None):
+                    stream=None, tile_order=None, distortion=None, depth_quad=None, evals=None):
     s = settings.c()
     return _check(load().rade_render_fwd(ctypes.byref(s), views_c, _p(views_dev), V, N,
                                          _p(splats), _p(pair_ids), _p(tile_ranges),
                                          _p(tile_order), _p(color),
                                          _p(depth), _p(normal), _p(alpha), _p(t_final), _p(last),
-                                         _p(median), _p(count), _p(distortion), _p(depth_quad),
-                                         _stream(stream)),
+                                         _p(median), _p(count), _p(evals), _p(distortion),
+                                         _p(depth_quad), _stream(stream)),
                   "rade_render_fwd")
+
+
+def rade_device_check() -> int:
+    """RADE_OK when the current HIP device is a gfx950 GPU, else
+    RADE_ERR_UNSUPPORTED_DEVICE (returned, not raised)."""
+    return int(load().rade_device_check())
 
 
 def rade_render_bwd_workspace(settings: Settings, V: int, N: int, recompute: bool) -> int:

@@ -2,7 +2,9 @@
 // Declarations and documentation: include/rade.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
+#include <cstring>
 
 #include "common.hpp"
 
@@ -30,8 +32,8 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
-                             int32_t* last, int32_t* med, int32_t* cnt, float* distortion,
-                             const float* depth_quad, hipStream_t st);
+                             int32_t* last, int32_t* med, int32_t* cnt, int32_t* evals,
+                             float* distortion, const float* depth_quad, hipStream_t st);
 hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, const float* tf,
@@ -52,6 +54,7 @@ hipError_t launch_normal_consistency(const rade_view* views_host, const rade_vie
                                      bool accumulate, void* ws, hipStream_t st);
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st);
+int64_t normal_consistency_blocks(const rade_view* views_host, int V);
 hipError_t launch_filter3d_var(const rade_view* views, int V, int64_t N, const float* means,
                                double near_plane, float scale, float margin, float* var,
                                hipStream_t st);
@@ -124,6 +127,33 @@ int64_t total_tiles(const rade_view* v, int32_t V) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? RADE_OK : RADE_ERR_HIP; }
 
+// Is the calling thread's current device a gfx950 GPU?  Queried once per
+// device ordinal (the answer cannot change while the process runs).
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_device_state[kMaxDevices];  // 0 unknown, 1 gfx950, 2 other
+
+int device_status() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();  // leave no sticky error for the caller's next call
+    return RADE_ERR_UNSUPPORTED_DEVICE;
+  }
+  int st = g_device_state[dev].load(std::memory_order_relaxed);
+  if (st == 0) {
+    hipDeviceProp_t prop;
+    st = 2;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      // gcnArchName is "gfx950" followed by optional ":feature" suffixes
+      const char* a = prop.gcnArchName;
+      if (std::strncmp(a, "gfx950", 6) == 0 && (a[6] == '\0' || a[6] == ':')) st = 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    g_device_state[dev].store(st, std::memory_order_relaxed);
+  }
+  return st == 1 ? RADE_OK : RADE_ERR_UNSUPPORTED_DEVICE;
+}
+
 }  // namespace
 
 namespace rade {
@@ -135,7 +165,9 @@ KernelEvents& kernel_events(int kernel) {
 
 extern "C" {
 
-int rade_abi_version(void) { return 4; }
+int rade_abi_version(void) { return 5; }
+
+int rade_device_check(void) { return device_status(); }
 
 int rade_set_kernel_events(int kernel, void* start_event, void* stop_event) {
   if (kernel < RADE_KERNEL_PROJECT || kernel > RADE_KERNEL_PROJECT_BWD) return RADE_ERR_INVALID_ARG;
@@ -152,6 +184,7 @@ const char* rade_strerror(int code) {
     case RADE_ERR_INVALID_ARG: return "invalid argument (nothing enqueued)";
     case RADE_ERR_CAPACITY: return "output capacity exceeded (the count arguments hold the required sizes)";
     case RADE_ERR_HIP: return "HIP runtime error";
+    case RADE_ERR_UNSUPPORTED_DEVICE: return "unsupported device (the library runs on gfx950 GPUs only)";
     case RADE_ERR_WORKSPACE: return "workspace too small";
     default: return "unknown error";
   }
@@ -186,6 +219,7 @@ int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, 
   const bool exact = s->depth_mode == RADE_DEPTH_EXACT;
   if (exact && N > 0 && (!depth_quad || (reinterpret_cast<uintptr_t>(depth_quad) & 15) != 0))
     return RADE_ERR_INVALID_ARG;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_project(*s, views_dev, V, N, means, scales, quats, opacities,
                                          sh, splats, tiles_touched, exact ? depth_quad : nullptr,
                                          (hipStream_t)stream));
@@ -214,6 +248,7 @@ int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
       return RADE_ERR_INVALID_ARG;  // views not prepared for this tile size
   if (!workspace || workspace_bytes < rade_bin_sort_workspace(V, N, capacity, 0))
     return RADE_ERR_WORKSPACE;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   int exceeded = 0;
   const hipError_t e = rade::launch_bin_sort(*s, views_host, views_dev, V, N, splats,
                                              tiles_touched, pair_ids, tile_ranges, keys, capacity,
@@ -234,6 +269,7 @@ int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t
     return RADE_ERR_INVALID_ARG;
   const int64_t tiles = total_tiles(views_host, V);
   if (!workspace || workspace_bytes < rade_tile_order_workspace(tiles)) return RADE_ERR_WORKSPACE;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_tile_order(tile_ranges, tiles, tile_order, workspace,
                                             (hipStream_t)stream));
 }
@@ -262,6 +298,7 @@ int rade_l1_color_grad(const rade_view* views_host, const rade_view* views_dev, 
     return RADE_ERR_INVALID_ARG;
   const int64_t total = prepared_pixels(views_host, V);
   if (total < 0) return RADE_ERR_INVALID_ARG;  // not prepared
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_l1_color_grad(views_dev, V, total, color, target,
                                                (double)weight, d_color, (hipStream_t)stream));
 }
@@ -281,6 +318,7 @@ int rade_normal_consistency(const rade_view* views_host, const rade_view* views_
   }
   if (!workspace || workspace_bytes < rade_normal_consistency_workspace(total))
     return RADE_ERR_WORKSPACE;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_normal_consistency(views_host, views_dev, V, total, depth,
                                                     normal, alpha,
                                                     weight, loss, d_depth, d_normal, d_alpha,
@@ -293,7 +331,7 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
-                    int32_t* median, int32_t* count, float* distortion,
+                    int32_t* median, int32_t* count, int32_t* evals, float* distortion,
                     const float* depth_quad, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
@@ -304,14 +342,15 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
     return RADE_ERR_INVALID_ARG;
   // tuned wave shapes / batches exist for the plain forward only
   if (!rade::render_shape_is_default(s->tile_w, s->tile_h, s->wave_w, s->batch) &&
-      (exact || distortion || count))
+      (exact || distortion || count || evals))
     return RADE_ERR_INVALID_ARG;
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && !splats) return RADE_ERR_INVALID_ARG;
   const int64_t tiles = total_tiles(views_host, V);
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_render_fwd(*s, views_dev, V, N, tiles, splats, pair_ids,
                                             tile_ranges, tile_order, color, depth, normal, alpha,
-                                            t_final, last, median, count, distortion,
+                                            t_final, last, median, count, evals, distortion,
                                             exact ? depth_quad : nullptr, (hipStream_t)stream));
 }
 
@@ -355,6 +394,7 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
     return RADE_ERR_WORKSPACE;
   // the per-(view, Gaussian) gradient records move in 16-byte words
   if ((reinterpret_cast<uintptr_t>(workspace) & 15) != 0) return RADE_ERR_INVALID_ARG;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   const hipStream_t st = (hipStream_t)stream;
   const size_t VN = (size_t)V * (size_t)N;
   char* w = static_cast<char*>(workspace);
@@ -385,6 +425,7 @@ int rade_filter3d_var(const rade_settings* s, const rade_view* views_dev, int32_
   if (!s || !views_dev || !counts_ok(V, N)) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !var)) return RADE_ERR_INVALID_ARG;
   if (!(scale >= 0.0f) || !(margin >= 0.0f)) return RADE_ERR_INVALID_ARG;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_filter3d_var(views_dev, V, N, means, s->near_plane, scale,
                                               margin, var, (hipStream_t)stream));
 }
@@ -394,6 +435,7 @@ int rade_filter3d_apply(int64_t N, const float* scales, const float* opacities, 
   if (N < 0) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!scales || !opacities || !var || !scales_out || !opacities_out))
     return RADE_ERR_INVALID_ARG;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_filter3d_apply(N, scales, opacities, var, scales_out,
                                                 opacities_out, (hipStream_t)stream));
 }
@@ -406,6 +448,7 @@ int rade_filter3d_apply_bwd(int64_t N, const float* scales, const float* opaciti
   if (N > 0 && (!scales || !opacities || !var || !d_scales_out || !d_opacities_out ||
                 !d_scales || !d_opacities))
     return RADE_ERR_INVALID_ARG;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_filter3d_apply_bwd(N, scales, opacities, var, d_scales_out,
                                                     d_opacities_out, d_scales, d_opacities,
                                                     (hipStream_t)stream));
@@ -426,6 +469,7 @@ int rade_tsdf_fuse(const rade_settings* s, const rade_view* views_host,
     if (views_host[i].pix_offset != total) return RADE_ERR_INVALID_ARG;  // not prepared
     total += (int64_t)views_host[i].width * views_host[i].height;
   }
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_tsdf_fuse(views_dev, V, depth, origin, voxel, nx, ny, nz,
                                            s->near_plane, trunc, tsdf, weight,
                                            (hipStream_t)stream));
@@ -450,6 +494,7 @@ int rade_marching_cubes(const float* tsdf, const float* weight, int32_t nx, int3
     return RADE_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < rade::marching_cubes_workspace(nx, ny, nz))
     return RADE_ERR_WORKSPACE;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
   const hipStream_t st = (hipStream_t)stream;
   const uint32_t* nv_dev = nullptr;
   const uint64_t* nt_dev = nullptr;

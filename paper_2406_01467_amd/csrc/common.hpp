@@ -10,6 +10,12 @@ namespace rade {
 
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr float kLog2e = 1.4426950408889634f;
+// The render kernels round a splat's centre to FP32 relative to the centre of
+// the pixel (px & ~31, py & ~31) of each pixel (px, py); every tile size they
+// support (at most 32 pixels per side, powers of two) keeps its pixels inside
+// one such 32x32 block, so a tile shares one origin and the rounded offsets do
+// not depend on the tile size.
+constexpr int kOriginAlign = 32;
 constexpr double kLog2eD = 1.4426950408889634;
 
 static_assert(sizeof(rade_splat) == 80, "splat record must be 80 bytes");
@@ -35,9 +41,9 @@ inline BlendParams make_blend_params(const rade_settings& s) {
   return b;
 }
 
-// Splat as staged in LDS for one tile: centre relative to the tile's first
-// pixel centre, factored quadratic form, opacity, depth, colour, plane,
-// normal.  64 bytes = 4 x 16-byte broadcast reads.
+// Splat as staged in LDS for one tile: centre relative to the pixel centre of
+// the tile's 32-pixel-aligned origin, factored quadratic form, opacity, depth,
+// colour, plane, normal.  64 bytes = 4 x 16-byte broadcast reads.
 struct alignas(16) StagedSplat {
   float ur, vr, w0, w1;
   float w2, w3, o, z;

@@ -259,6 +259,14 @@ __global__ void k_zero_f(float* __restrict__ a, int n) {
 
 }  // namespace
 
+// Number of 32x8 pixel blocks (one loss partial each) over the views.
+int64_t normal_consistency_blocks(const rade_view* views_host, int V) {
+  int64_t nb = 0;
+  for (int v = 0; v < V; ++v)
+    nb += (int64_t)((views_host[v].width + kBX - 1) / kBX) * ((views_host[v].height + kBY - 1) / kBY);
+  return nb;
+}
+
 // One loss partial per block; every block holds at least one pixel.
 size_t normal_consistency_workspace(int64_t total_pixels) {
   return (size_t)total_pixels * sizeof(float) + 256;
@@ -273,9 +281,7 @@ hipError_t launch_normal_consistency(const rade_view* views_host, const rade_vie
     hipLaunchKernelGGL(k_zero_f, dim3((V + 255) / 256), dim3(256), 0, st, loss, V);
     return hipGetLastError();
   }
-  int64_t nb = 0;
-  for (int v = 0; v < V; ++v)
-    nb += (int64_t)((views_host[v].width + kBX - 1) / kBX) * ((views_host[v].height + kBY - 1) / kBY);
+  const int64_t nb = normal_consistency_blocks(views_host, V);
   float* partial = static_cast<float*>(ws);
   if (accumulate)
     hipLaunchKernelGGL(k_nc<true>, dim3((unsigned)nb), dim3(kT), 0, st, views, V, nb, depth,

@@ -299,8 +299,12 @@ __device__ bool geometry(const ViewD& v, const Params& P, const rade_settings& s
   return true;
 }
 
+// Loads Gaussian g; false when it is culled (a parameter not finite, a zero
+// quaternion, or opacity <= alpha_min, which leaves no pixel with alpha >=
+// alpha_min).
 __device__ __forceinline__ bool load_params(int64_t g, const float* means, const float* scales,
-                                            const float* quats, const float* opac, Params& P) {
+                                            const float* quats, const float* opac,
+                                            double alpha_min, Params& P) {
   const float m0 = means[3 * g], m1 = means[3 * g + 1], m2 = means[3 * g + 2];
   const float s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
   const float4 q = *reinterpret_cast<const float4*>(quats + 4 * g);
@@ -313,7 +317,7 @@ __device__ __forceinline__ bool load_params(int64_t g, const float* means, const
   P.o = o;
   const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
   const double qq = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  ok = ok && qq > 0.0 && (255.0 * (double)o > 1.0);
+  ok = ok && qq > 0.0 && ((double)o > alpha_min);
   P.qinv = ok ? 1.0 / qq : 0.0;
   P.qn[0] = qw * P.qinv; P.qn[1] = qx * P.qinv; P.qn[2] = qy * P.qinv; P.qn[3] = qz * P.qinv;
   quat_to_mat(P.qn, P.Rg);
@@ -373,7 +377,7 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   constexpr int K = KMAX;
   const float* __restrict__ coef_g = sh + 3 * K * g;
   Params P;
-  const bool ok = load_params(g, means, scales, quats, opac, P);
+  const bool ok = load_params(g, means, scales, quats, opac, st.alpha_min, P);
   // Affine depth: the coefficients are loaded with the parameters, so their
   // latency overlaps the FP64 geometry (the registers fit two waves per
   // SIMD).  Exact depth: they are loaded per view after the geometry, as its
@@ -448,8 +452,8 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
       out.rgb[1] = (float)fmax(raw[1], 0.0);
       out.rgb[2] = (float)fmax(raw[2], 0.0);
     }
-    // support rect: alpha >= alpha_min inside power <= tau
-    const double tau = fmin(st.power_cut, log(255.0 * (double)P.o));
+    // support rect: alpha = o e^-power >= alpha_min inside power <= tau
+    const double tau = fmin(st.power_cut, log((double)P.o / st.alpha_min));
     const double rx = sqrt(2.0 * tau * G.D00) * (1.0 + 1e-6) + 1e-3;
     const double ry = sqrt(2.0 * tau * G.D11) * (1.0 + 1e-6) + 1e-3;
     const double xlo = (out.uc - rx) - 0.5, xhi = (out.uc + rx) - 0.5;
@@ -506,7 +510,7 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
   const float4* gr0 = reinterpret_cast<const float4*>(gsplat + g * kGradStride);
   const float4 g0a = gr0[0], g0b = gr0[1], g0c = gr0[2], g0d = gr0[3];
   Params P;
-  bool ok = load_params(g, means, scales, quats, opac, P);
+  bool ok = load_params(g, means, scales, quats, opac, st.alpha_min, P);
   {
     float coef[3 * K];
     load_row<K, VEC>(coef_g, coef);

@@ -3,7 +3,9 @@
 // One workgroup per screen tile; each wavefront owns an 8x8 block of pixels
 // of the tile and each lane one pixel.  The tile's list of splats (depth
 // order) is walked in batches: every thread stages one splat into LDS (its
-// centre made tile-relative in FP64 before rounding to FP32), and tests the
+// centre made relative to the pixel centre of the tile's 32-pixel-aligned
+// origin in FP64 before rounding to FP32: that origin, and so every FP32
+// operation of a pixel, is the same for every tile size), and tests the
 // splat's support rect against every wavefront's 8x8 block; a ballot per
 // block turns this into a 64-bit mask per (wavefront, stager wavefront), so
 // each wavefront only evaluates splats that can touch its pixels.  A
@@ -71,7 +73,8 @@ __device__ __forceinline__ int wave_index() {
 struct PixelCtx {
   int v;
   int64_t tile;
-  int x0, y0;
+  int x0, y0;  // the tile's first pixel
+  int ox, oy;  // the 32-pixel-aligned origin splat centres are made relative to
   int lxi, lyi, px, py;
   bool inside;
   int64_t P, poff, pix;
@@ -89,7 +92,7 @@ struct FwdArgs {
   const uint32_t* order;   // tile visiting order (NULL: natural)
   uint32_t* queue;         // work-queue counter of the persistent kernel
   float *color, *depth, *normal, *alpha, *t_final, *distortion;
-  int32_t *last, *median, *count;
+  int32_t *last, *median, *count, *evals;
   const float4* depth_quad;  // EXACT only: 2 per (view, Gaussian)
 };
 
@@ -122,6 +125,8 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
   const int tx = (int)(lt % vw.tiles_x), ty = (int)(lt / vw.tiles_x);
   c.x0 = tx * TW;
   c.y0 = ty * TH;
+  c.ox = c.x0 & ~(kOriginAlign - 1);
+  c.oy = c.y0 & ~(kOriginAlign - 1);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   c.lxi = WW * (wave % TG::NWX) + (lane & (WW - 1));
   c.lyi = TG::WH * (wave / TG::NWX) + (lane >> TG::LW);
@@ -137,7 +142,7 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
 }
 
 // Does the splat's support reach the block of pixel offsets [bx, bx+bw-1] x
-// [by, by+bh-1] (relative to the tile's first pixel centre)?  The factored
+// [by, by+bh-1] (relative to the pixel centre of the origin (ox, oy))?  The factored
 // power Q = (w0 dx + w1 dy)^2 + (w2 dx + w3 dy)^2, dx = ur - x, dy = vr - y,
 // is convex, so its minimum over the block's rectangle is 0 when the centre
 // lies inside and is otherwise reached on an edge, where it is a 1-D
@@ -179,8 +184,8 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
   StagedSplat s;
-  s.ur = (float)(sp.uc - ((double)c.x0 + 0.5));
-  s.vr = (float)(sp.vc - ((double)c.y0 + 0.5));
+  s.ur = (float)(sp.uc - ((double)c.ox + 0.5));
+  s.vr = (float)(sp.vc - ((double)c.oy + 0.5));
   s.w0 = sp.w[0]; s.w1 = sp.w[1]; s.w2 = sp.w[2]; s.w3 = sp.w[3];
   s.o = sp.opacity; s.z = sp.z;
   s.r = sp.rgb[0]; s.g = sp.rgb[1]; s.b = sp.rgb[2];
@@ -206,9 +211,10 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     const float invA = A > 0.0f ? 1.0f / A : 0.0f, invC = C > 0.0f ? 1.0f / C : 0.0f;
     const float lo = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
     const float tau2 = fminf(bp.cut2, lo) * 1.001f + 0.01f;
+    const int sx = c.x0 - c.ox, sy = c.y0 - c.oy;  // tile start relative to the origin
 #pragma unroll
     for (int k = 0; k < TG::NW; ++k) {
-      const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
+      const int bx = sx + WW * (k % TG::NWX), by = sy + TG::WH * (k / TG::NWX);
       if (((bits >> k) & 1u) && !block_reached(s.ur, s.vr, s.w0, s.w1, s.w2, s.w3, A, B, C, invA,
                                                invC, tau2, bx, by, WW, TG::WH))
         bits &= ~(1u << k);
@@ -244,7 +250,8 @@ struct FwdShared {
 };
 
 // Forward blend of one tile (all threads of the workgroup take part).  DIST:
-// also the distortion map; CNT: also the blend-count map; EXACT: per-pixel
+// also the distortion map; CNT: also the blend-count and evaluation-count
+// maps (either may be NULL); EXACT: per-pixel
 // depth of the ray maximum (Eq. 7) instead of the plane of Eq. 4.
 template <int TW, int TH, bool DIST, bool CNT, bool EXACT, int WW, int BT>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
@@ -259,12 +266,13 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   const PixelCtx c = pixel_ctx<TW, TH, WW, BT>(a.views, a.V, a.ranges, tile);
   const int wave = wave_index();
   const int64_t vbase = (int64_t)c.v * a.N;
-  const float fx = (float)c.lxi, fy = (float)c.lyi;
+  // the lane's pixel centre relative to the origin's (exact in FP32)
+  const float fx = (float)(c.px - c.ox), fy = (float)(c.py - c.oy);
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f, A = 0.f;
   float dmed = 0.f;
   float dmean = 0.f, dvar = 0.f;  // DIST: weighted mean depth and sum w (d - mean)^2
-  int cnt = 0, lastp = -1, medp = -1;
+  int cnt = 0, evl = 0, lastp = -1, medp = -1;
   // Lane state of this wave as uniform masks (bit l: lane l), so the
   // per-splat decisions are scalar operations on the compare results and a
   // lane's flag is its bit (inverse ballot): wdone, the lanes that have
@@ -302,6 +310,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         float t1, t2, pw, e, al;
         bool cl;
         splat_eval(s, dx, dy, bp, t1, t2, pw, e, al, cl);
+        if constexpr (CNT) evl += __builtin_amdgcn_inverse_ballot_w64(~wdone) ? 1 : 0;
         // the decision of splat_alpha, per lane, as masks
         const uint64_t pass = __builtin_amdgcn_ballot_w64(pw <= bp.cut2) &
                               __builtin_amdgcn_ballot_w64(al >= bp.alpha_min) & ~wdone;
@@ -369,8 +378,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
     // operations as in the loop (bit-identical to tracking it per blend)
     if (medp >= 0) {
       const rade_splat& sp = splats[vbase + pair_ids[c.rb + medp]];
-      const float ur = (float)(sp.uc - ((double)c.x0 + 0.5));
-      const float vr = (float)(sp.vc - ((double)c.y0 + 0.5));
+      const float ur = (float)(sp.uc - ((double)c.ox + 0.5));
+      const float vr = (float)(sp.vc - ((double)c.oy + 0.5));
       const float dx = ur - fx, dy = vr - fy;
       dmed = fmaf(sp.p[1], dy, fmaf(sp.p[0], dx, sp.z));
     }
@@ -383,7 +392,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   a.t_final[c.poff + pix] = T;
   a.last[c.poff + pix] = lastp;
   a.median[c.poff + pix] = medp >= 0 ? (int32_t)pair_ids[c.rb + medp] : -1;
-  if constexpr (CNT) a.count[c.poff + pix] = cnt;
+  if constexpr (CNT) {
+    if (a.count) a.count[c.poff + pix] = cnt;
+    if (a.evals) a.evals[c.poff + pix] = evl;
+  }
   if constexpr (DIST) a.distortion[c.poff + pix] = 2.0f * A * dvar;
 }
 
@@ -489,7 +501,8 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
   const PixelCtx c = pixel_ctx<TW, TH, WW, BT>(a.views, a.V, a.ranges, tile);
   const int wave = wave_index(), lane = threadIdx.x & 63;
   const int64_t vbase = (int64_t)c.v * a.N;
-  const float fx = (float)c.lxi, fy = (float)c.lyi;
+  // the lane's pixel centre relative to the origin's (exact in FP32)
+  const float fx = (float)(c.px - c.ox), fy = (float)(c.py - c.oy);
 
   float T = 0.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gM = 0.f;
   float gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gA = 0.f;
@@ -697,11 +710,12 @@ void launch_fwd_d(const FwdArgs& a, int schedule, hipStream_t st) {
 
 template <int TW, int TH, bool EXACT>
 void launch_fwd_e(const FwdArgs& a, int schedule, hipStream_t st) {
+  const bool cnt = a.count || a.evals;
   if (a.distortion) {
-    if (a.count) launch_fwd_d<TW, TH, true, true, EXACT>(a, schedule, st);
+    if (cnt) launch_fwd_d<TW, TH, true, true, EXACT>(a, schedule, st);
     else launch_fwd_d<TW, TH, true, false, EXACT>(a, schedule, st);
   } else {
-    if (a.count) launch_fwd_d<TW, TH, false, true, EXACT>(a, schedule, st);
+    if (cnt) launch_fwd_d<TW, TH, false, true, EXACT>(a, schedule, st);
     else launch_fwd_d<TW, TH, false, false, EXACT>(a, schedule, st);
   }
 }
@@ -767,7 +781,7 @@ hipError_t launch_fwd_t(const FwdArgs& a, int schedule, int wave_w, int batch, h
     else launch_fwd_e<TW, TH, false>(a, schedule, st);
     return hipSuccess;
   }
-  if (a.depth_quad || a.distortion || a.count) return hipErrorInvalidValue;
+  if (a.depth_quad || a.distortion || a.count || a.evals) return hipErrorInvalidValue;
   bool ok = false;
   if (wave_w == 0 || wave_w == 8) ok = launch_fwd_shape_b<TW, TH, 8>(a, schedule, batch, st);
   else if (wave_w == 16) ok = launch_fwd_shape_b<TW, TH, 16>(a, schedule, batch, st);
@@ -823,8 +837,8 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
-                             int32_t* last, int32_t* med, int32_t* cnt, float* distortion,
-                             const float* depth_quad, hipStream_t st) {
+                             int32_t* last, int32_t* med, int32_t* cnt, int32_t* evals,
+                             float* distortion, const float* depth_quad, hipStream_t st) {
   if (tiles == 0) return hipSuccess;
   FwdArgs a;
   a.bp = make_blend_params(s);
@@ -833,7 +847,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
   a.order = s.schedule == RADE_SCHEDULE_TILE ? nullptr : order;
   a.queue = order ? const_cast<uint32_t*>(order) + tiles : nullptr;
   a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
-  a.last = last; a.median = med; a.count = cnt; a.distortion = distortion;
+  a.last = last; a.median = med; a.count = cnt; a.evals = evals; a.distortion = distortion;
   a.depth_quad = reinterpret_cast<const float4*>(depth_quad);
   RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, s.wave_w, s.batch, st))
   return hipGetLastError();

@@ -40,6 +40,7 @@ class Maps:
     count: Optional[torch.Tensor]
     state: ForwardState
     distortion: Optional[torch.Tensor] = None  # 1 plane per view (Eq. 23), if asked for
+    evals: Optional[torch.Tensor] = None       # splats evaluated per pixel, if asked for
 
     def view_planes(self, rast: "Rasterizer", v: int) -> dict:
         """Per-view (C, H, W) tensors of view v."""
@@ -53,6 +54,8 @@ class Maps:
                    last=cut(self.state.last, 1), median=cut(self.state.median, 1))
         if self.count is not None:
             out["count"] = cut(self.count, 1)
+        if self.evals is not None:
+            out["evals"] = cut(self.evals, 1)
         if self.distortion is not None:
             out["distortion"] = cut(self.distortion, 1)
         return out
@@ -132,7 +135,8 @@ class Rasterizer:
         return pair_ids, ranges, M
 
     def forward(self, means, scales, quats, opacities, sh, want_count: bool = False,
-                keep_splats: bool = True, stream=None, want_distortion: bool = False) -> Maps:
+                keep_splats: bool = True, stream=None, want_distortion: bool = False,
+                want_evals: bool = False) -> Maps:
         N = means.shape[0]
         quad = (torch.empty(max(1, self.V * N) * 8, dtype=torch.float32, device=self.device)
                 if self.exact_depth else None)
@@ -142,14 +146,17 @@ class Rasterizer:
         color, depth, normal, alpha, tf, last, med, cnt = self._new_maps(want_count)
         dist = (torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
                 if want_distortion else None)
+        evals = (torch.empty(self.total_pixels, dtype=torch.int32, device=self.device)
+                 if want_evals else None)
         _lib.rade_render_fwd(self.settings, self.views_c, self.views_dev, self.V, N, splats,
                              pair_ids, ranges, color, depth, normal, alpha, tf, last, med, cnt,
-                             stream, tile_order=order, distortion=dist, depth_quad=quad)
+                             stream, tile_order=order, distortion=dist, depth_quad=quad,
+                             evals=evals)
         # pair_ids are a view of a reusable buffer: keep a private copy for
         # the backward pass
         state = ForwardState(splats if keep_splats else None, pair_ids.clone(), ranges, order,
                              tf, last, med, M, depth, alpha)
-        return Maps(color, depth, normal, alpha, cnt, state, dist)
+        return Maps(color, depth, normal, alpha, cnt, state, dist, evals)
 
     def tile_order(self, ranges, stream=None):
         """Heavy-first tile order (None for the plain one-workgroup-per-tile

@@ -30,7 +30,7 @@ def _declared():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = _declared()
-    assert len(names) == 22, names
+    assert len(names) == 23, names
     so = ctypes.CDLL(lib.LIB_PATH)
     for n in names:
         assert hasattr(so, n), n
@@ -207,3 +207,46 @@ def test_render_bwd_rejects_a_misaligned_workspace():
     assert so.rade_render_bwd(*args, ctypes.c_void_p(256 + 4), big, None) == \
         lib.RADE_ERR_INVALID_ARG
     assert so.rade_render_bwd(*args, None, big, None) == lib.RADE_ERR_WORKSPACE
+
+
+def _no_gpu() -> bool:
+    import torch
+    return not torch.cuda.is_available()
+
+
+def test_error_codes_are_distinct():
+    lib = _lib()
+    codes = [lib.RADE_ERR_INVALID_ARG, lib.RADE_ERR_CAPACITY, lib.RADE_ERR_HIP,
+             lib.RADE_ERR_UNSUPPORTED_DEVICE, lib.RADE_ERR_WORKSPACE]
+    assert len(set(codes)) == len(codes) and lib.RADE_OK not in codes
+    assert lib.RADE_ERR_UNSUPPORTED_DEVICE == -4 and lib.RADE_ERR_WORKSPACE == -5
+    msgs = {lib.strerror(c) for c in codes}
+    assert len(msgs) == len(codes) and "gfx950" in lib.strerror(lib.RADE_ERR_UNSUPPORTED_DEVICE)
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="checks the no-device path")
+def test_no_device_is_unsupported_and_nothing_launches():
+    """Without a gfx950 device (here: none at all) every call whose arguments
+    are valid stops at the device check with RADE_ERR_UNSUPPORTED_DEVICE,
+    after argument validation and before any launch (the dummy device
+    pointers are never dereferenced); invalid arguments still report
+    RADE_ERR_INVALID_ARG first."""
+    lib = _lib()
+    import synth
+    so = lib.load()
+    assert lib.rade_device_check() == lib.RADE_ERR_UNSUPPORTED_DEVICE
+    assert lib.rade_device_check() == lib.RADE_ERR_UNSUPPORTED_DEVICE  # cached answer
+    s = lib.Settings().c()
+    d = ctypes.c_void_p(256)
+    assert so.rade_project(ctypes.byref(s), d, 1, 10, *([d] * 7), None, None) == \
+        lib.RADE_ERR_UNSUPPORTED_DEVICE
+    assert so.rade_project(ctypes.byref(s), d, 0, 10, *([d] * 7), None, None) == \
+        lib.RADE_ERR_INVALID_ARG
+    vc = lib.make_views([synth.identity_view(32, 32)])
+    lib.rade_views_prepare(lib.Settings(), vc)
+    assert so.rade_render_fwd(ctypes.byref(s), vc, d, 1, 10, d, d, d, None, *([d] * 7),
+                              None, None, None, None, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
+    ws = lib.rade_bin_sort_workspace(1, 10, 100, 4)
+    assert so.rade_bin_sort(ctypes.byref(s), vc, d, 1, 10, d, d, d, d, None, 100, d, None, d,
+                            ws, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
+    assert so.rade_filter3d_apply(10, d, d, d, d, d, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE

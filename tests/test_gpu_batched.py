@@ -130,3 +130,82 @@ def test_autotuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     assert (again.tile_w, again.tile_h, again.schedule, again.wave_w, again.batch) == \
         (best.tile_w, best.tile_h, best.schedule, best.wave_w, best.batch)
     say("autotune", timings)
+
+
+def test_batched_16views_1m_against_the_oracle():
+    """The 16-view workload (1M Gaussians, uneven orbit views) through the
+    batched plan at its tuned launch shape (8x8 tiles, heavy-first order,
+    128-splat staging batches), graph-replayed: maps of three views on
+    sampled pixels against the oracle, and the VJP of upstream gradients on
+    sampled pixels of those views (zero elsewhere) against the oracle's
+    adjoint over all 1M Gaussians."""
+    import torch
+    import oracle
+    from gpu_common import compare_maps, grad_check, oracle_settings
+    from paper_2406_01467_amd import Settings
+    from paper_2406_01467_amd.batched import BatchedPlan
+    dev = device()
+    scene, views = synth.make_workload("batched_16views_1m")
+    st = Settings(tile_w=8, tile_h=8, sh_degree=3, schedule=1, batch=128)
+    params = to_dev(scene, dev)
+    rng = np.random.default_rng(61)
+    sel = [0, 7, 13]
+    from paper_2406_01467_amd.raster import Rasterizer
+    vc = Rasterizer(views, st, dev).views_c
+    P = sum(v.pixels for v in views)
+    fwd_pix = {vi: np.sort(rng.choice(views[vi].pixels, 4096, replace=False)).astype(np.int64)
+               for vi in sel}
+    bwd_pix = {vi: np.sort(rng.choice(views[vi].pixels, 700, replace=False)).astype(np.int64)
+               for vi in sel}
+    gC = np.zeros(3 * P, np.float32)
+    gD = np.zeros(2 * P, np.float32)
+    gN = np.zeros(3 * P, np.float32)
+    gA = np.zeros(P, np.float32)
+    gouts = []
+    for vi in sel:
+        o, Pv, pl = vc[vi].pix_offset, views[vi].pixels, bwd_pix[vi]
+        g = rng.normal(size=(len(pl), 9)).astype(np.float32)
+        for c in range(3):
+            gC[3 * o + c * Pv + pl] = g[:, c]
+            gN[3 * o + c * Pv + pl] = g[:, 5 + c]
+        for c in range(2):
+            gD[2 * o + c * Pv + pl] = g[:, 3 + c]
+        gA[o + pl] = g[:, 8]
+        gouts.append(g.astype(np.float64))
+    t = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    grads_in = [t(gC), t(gD), t(gN), t(gA)]
+    say("batched 16 views: capture and replay")
+    plan = BatchedPlan(views, st, params, lambda maps: grads_in)
+    plan.step()
+    plan.replay()
+    torch.cuda.synchronize()
+    assert not plan.overflowed()
+    say("batched 16 views: pairs", plan.n_pairs())
+    pair_ids = plan.pair_ids[: plan.n_pairs()].cpu().numpy().astype(np.int64)
+    ranges = plan.ranges.cpu().numpy().astype(np.int64).reshape(-1, 2)
+    s_or = oracle_settings(st)
+    sub_views = [views[vi] for vi in sel]
+    rec, _, flags = oracle.project(s_or, sub_views, scene)
+    for k, vi in enumerate(sel):
+        v, o = views[vi], vc[vi].pix_offset
+        Pv, H, W = v.pixels, v.height, v.width
+        d = {}
+        for name, ch in (("color", 3), ("depth", 2), ("normal", 3), ("alpha", 1),
+                         ("t_final", 1), ("median", 1), ("last", 1)):
+            d[name] = plan.maps[name][ch * o: ch * o + ch * Pv].view(ch, H, W).cpu().numpy()
+        py, px = np.mgrid[0:H, 0:W]
+        tile = vc[vi].tile_offset + (py // 8) * vc[vi].tiles_x + px // 8
+        last = d["last"][0]
+        d["last_id"] = np.where(last >= 0, pair_ids[np.clip(ranges[tile, 0] + last, 0,
+                                                            len(pair_ids) - 1)], -1)
+        out = oracle.render(s_or, v, rec[k], flags[k], fwd_pix[vi])
+        nfrag = compare_maps(d, out, pixels=fwd_pix[vi], label=f"batched view {vi}: ")
+        say(f"batched view {vi} ({W}x{H}): fragile {nfrag}, mean blends {out['count'].mean():.1f}")
+        assert nfrag <= max(2, 0.01 * len(fwd_pix[vi]))
+    got = dict(means=plan.grads[0].cpu().numpy(), scales=plan.grads[1].cpu().numpy(),
+               quats=plan.grads[2].cpu().numpy(), opacities=plan.grads[3].cpu().numpy(),
+               sh=plan.grads[4].cpu().numpy().reshape(scene.sh.shape))
+    pl = [bwd_pix[vi] for vi in sel]
+    ref = oracle.backward(s_or, sub_views, scene, gouts, pixels=pl, rec=rec, flags=flags)
+    scale = oracle.gradient_error_scale(s_or, sub_views, scene, gouts, pixels=pl)
+    grad_check(got, ref, scale, "batched 16 views bwd")

@@ -232,10 +232,10 @@ def test_render_fwd_two_uneven_views_with_background():
     _full_parity(scene, views, _settings(sh_degree=3, bg=(0.25, 0.5, 1.0)), "2 views")
 
 
-def _sampled_parity(name, npix, seed, tile=(16, 16)):
+def _sampled_parity(name, npix, seed, tile=(16, 16), schedule=0):
     dev = device()
     scene, views = _workload(name)
-    s = _settings(sh_degree=scene.sh_degree, tile_w=tile[0], tile_h=tile[1])
+    s = _settings(sh_degree=scene.sh_degree, tile_w=tile[0], tile_h=tile[1], schedule=schedule)
     say("sampled parity", name, "N", scene.n, "pixels", npix)
     rast, maps, gv, _ = gpu_forward(scene, views, s, dev)
     v = views[0]
@@ -255,23 +255,33 @@ def test_render_fwd_800x800_200k_sampled():
 
 
 def test_render_fwd_1600x1064_1m_sampled():
-    _sampled_parity("plain_1600x1064_1m", 300, 22)
+    # the benchmark's workload in its launch configuration (16x16 tiles,
+    # heavy-first order), 16,384 seeded pixels
+    _sampled_parity("plain_1600x1064_1m", 16384, 22, schedule=1)
 
 
 def test_tile_size_invariance():
+    # Every map is bitwise identical across the six tile sizes: each pixel
+    # blends the same splats in the same order with the same FP32 operations
+    # (splat centres are rounded relative to a 32-pixel-aligned origin that
+    # depends on the pixel only).  The image is 100x70 so the last tiles are
+    # ragged for every size; the scene puts splats across tile borders.
     dev = device()
     scene = synth.make_scene_ball(5000, seed=12, centre=(0.0, 0.0, 3.0), radius=1.0, log_scale_mu=-3.0)
-    views = [synth.identity_view(96, 80)]
+    views = [synth.identity_view(100, 70)]
     res = {}
-    for tile in [(8, 8), (16, 16), (32, 16), (16, 32)]:
+    for tile in [(8, 8), (16, 16), (32, 16), (16, 32), (16, 8), (8, 16)]:
         _, _, gv, _ = gpu_forward(scene, views, _settings(tile_w=tile[0], tile_h=tile[1], sh_degree=3), dev)
         res[tile] = gv[0]
     base = res[(16, 16)]
+    assert base["count"].sum() > 100000
     for tile, g in res.items():
-        for k in ("count", "median", "last_id"):
-            assert (g[k] != base[k]).mean() < 1e-3, (tile, k)
-        for k in ("color", "depth", "normal", "alpha"):
-            np.testing.assert_allclose(g[k], base[k], rtol=2e-6, atol=2e-6 * np.abs(base[k]).max())
+        for k in ("count", "median", "last_id", "color", "depth", "normal", "alpha", "t_final"):
+            a, b = np.asarray(g[k]), np.asarray(base[k])
+            nbad = int((a.view(np.uint32) != b.view(np.uint32)).sum()) if a.dtype == np.float32 \
+                else int((a != b).sum())
+            say(f"tile {tile} {k}: {nbad} pixels differ from 16x16")
+            assert nbad == 0, (tile, k, nbad)
 
 
 def test_degenerate_inputs():
@@ -369,8 +379,33 @@ def test_render_bwd_recompute_mode():
 def test_render_bwd_800x800_200k_sampled_pixels():
     scene, views = _workload("plain_800x800_200k")
     rng = np.random.default_rng(34)
-    pix = np.sort(rng.choice(views[0].pixels, 400, replace=False)).astype(np.int64)
+    pix = np.sort(rng.choice(views[0].pixels, 1024, replace=False)).astype(np.int64)
     _bwd_parity(scene, views, _settings(sh_degree=3), 35, "bwd 800x800 sampled", pixels=pix)
+
+
+def test_render_bwd_1600x1064_1m_sampled_pixels():
+    # The benchmark's workload (1M Gaussians, one 1600x1064 view, SH degree
+    # 3) in its launch configuration (16x16 tiles, heavy-first order): the
+    # VJP of 2,048 seeded pixels against the oracle's adjoint, over every
+    # Gaussian.
+    scene, views = _workload("plain_1600x1064_1m")
+    rng = np.random.default_rng(36)
+    pix = np.sort(rng.choice(views[0].pixels, 2048, replace=False)).astype(np.int64)
+    _bwd_parity(scene, views, _settings(sh_degree=3, schedule=1), 37, "bwd 1600x1064 sampled",
+                pixels=pix)
+
+
+def test_alpha_min_setting_fwd_bwd():
+    # a non-default alpha_min (1e-3 instead of 1/255): the support rects,
+    # the cull and the per-pixel skip all follow it; maps and gradients
+    # against the oracle run with the same setting
+    scene = synth.make_scene_ball(6000, seed=16, centre=(0.0, 0.0, 3.0), radius=1.2,
+                                  log_scale_mu=-3.2)
+    scene.opacities[:300] = np.float32(2e-3)  # between 1e-3 and 1/255: kept now
+    views = [synth.identity_view(100, 70)]
+    s = _settings(sh_degree=3, alpha_min=1e-3)
+    _full_parity(scene, views, s, "alpha_min 1e-3")
+    _bwd_parity(scene, views, s, 38, "bwd alpha_min 1e-3")
 
 
 @pytest.mark.parametrize("schedule", [1, 2])
