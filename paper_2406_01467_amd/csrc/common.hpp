@@ -41,27 +41,72 @@ inline BlendParams make_blend_params(const rade_settings& s) {
   return b;
 }
 
-// Splat as staged in LDS for one tile: centre relative to the pixel centre of
-// the tile's 32-pixel-aligned origin, factored quadratic form, opacity, depth,
-// colour, plane, normal.  64 bytes = 4 x 16-byte broadcast reads.
+// Splat as staged in LDS for one tile: 64 bytes = 4 x 16-byte broadcast
+// reads (the forward needs the first two before its per-lane decision).
+// The centre is split into its FP32 offset (ur, vr) from the pixel centre of
+// the tile's 32-pixel-aligned origin and the FP32 remainder (ul, vl) of that
+// rounding.  For an integer pixel offset x, ur - x is exact, so (ur - x) + ul
+// is the pixel's offset to within one rounding whatever the origin.  The
+// remainder enters the two linear forms through the constants of
+// StagedForm (t1 = w0 (ur - x) + w1 (vr - y) + c1) and the depth plane
+// through zc (the plane at the rounded centre), so the loops use it at no
+// extra cost; the remainders themselves are staged (StagedRem) only where a
+// loop needs the offset itself (the backward's footprint and plane terms,
+// the exact depth).  EXACT staging keeps the centre depth z in zc.
 struct alignas(16) StagedSplat {
   float ur, vr, w0, w1;
-  float w2, w3, o, z;
+  float w2, w3, o, zc;
   float r, g, b, p0;
   float p1, n0, n1, n2;
 };
+struct alignas(8) StagedForm {
+  float c1, c2;
+};
+struct alignas(8) StagedRem {
+  float ul, vl;
+};
 
-// alpha of a splat at offset (dx, dy) = (u_c - u, v_c - v).  Returns false
+// The centre of splat record `sp` relative to the pixel centre (ox + 0.5,
+// oy + 0.5), split into FP32 head and remainder: U = ur + ul to within FP64
+// rounding (U - ur is exact in FP64).
+struct CentreSplit {
+  float ur, vr, ul, vl;
+};
+__device__ __forceinline__ CentreSplit split_centre(double uc, double vc, int ox, int oy) {
+  const double U = uc - ((double)ox + 0.5), V = vc - ((double)oy + 0.5);
+  CentreSplit c;
+  c.ur = (float)U;
+  c.vr = (float)V;
+  c.ul = (float)(U - (double)c.ur);
+  c.vl = (float)(V - (double)c.vr);
+  return c;
+}
+
+// The depth plane's constant for offsets measured from the rounded centre:
+// d = z + p . (dx_head + rem) = (z + p . rem) + p . dx_head.  The remainder
+// is below half an FP32 unit of the head, so its product with p is formed in
+// FP32 at full relative accuracy; z + p . rem is rounded once.
+__device__ __forceinline__ float plane_const(float z, float p0, float p1, float ul, float vl) {
+  return z + fmaf(p0, ul, p1 * vl);
+}
+
+// The linear-form constant w . rem for the same split (the same argument).
+__device__ __forceinline__ float form_const(float wa, float wb, float ul, float vl) {
+  return fmaf(wa, ul, wb * vl);
+}
+
+// alpha of a splat at offset (dx, dy) = (u_r - u, v_r - v) from its rounded
+// centre (the remainder enters through the form constants c1, c2).  Returns false
 // when the splat is skipped (outside the cut or below alpha_min).  The
 // forward and backward kernels both call exactly this function, compiled
 // without floating-point contraction, so their decisions match bit for bit.
 // splat_eval computes the pieces and leaves the decision to the caller, which
 // must take it as splat_alpha does: pw <= cut2 and alpha >= alpha_min.
-__device__ __forceinline__ void splat_eval(const StagedSplat& s, float dx, float dy,
-                                           const BlendParams& bp, float& t1, float& t2,
+__device__ __forceinline__ void splat_eval(const StagedSplat& s, const StagedForm& f, float dx,
+                                           float dy, const BlendParams& bp, float& t1, float& t2,
                                            float& pw, float& e, float& alpha, bool& clamped) {
-  t1 = fmaf(s.w0, dx, s.w1 * dy);
-  t2 = fmaf(s.w2, dx, s.w3 * dy);
+  t1 = fmaf(s.w0, dx, fmaf(s.w1, dy, f.c1));
+  t2 = fmaf(s.w2, dx, fmaf(s.w3, dy, f.c2));
   pw = fmaf(t1, t1, t2 * t2);
   // evaluated on every lane (no branch): alpha <= alpha_max < 1 always
   e = __builtin_amdgcn_exp2f(-pw);
@@ -70,11 +115,11 @@ __device__ __forceinline__ void splat_eval(const StagedSplat& s, float dx, float
   alpha = fminf(raw, bp.alpha_max);
 }
 
-__device__ __forceinline__ bool splat_alpha(const StagedSplat& s, float dx, float dy,
-                                            const BlendParams& bp, float& t1, float& t2,
+__device__ __forceinline__ bool splat_alpha(const StagedSplat& s, const StagedForm& f, float dx,
+                                            float dy, const BlendParams& bp, float& t1, float& t2,
                                             float& e, float& alpha, bool& clamped) {
   float pw;
-  splat_eval(s, dx, dy, bp, t1, t2, pw, e, alpha, clamped);
+  splat_eval(s, f, dx, dy, bp, t1, t2, pw, e, alpha, clamped);
   return pw <= bp.cut2 && alpha >= bp.alpha_min;
 }
 

@@ -4,8 +4,9 @@
 // of the tile and each lane one pixel.  The tile's list of splats (depth
 // order) is walked in batches: every thread stages one splat into LDS (its
 // centre made relative to the pixel centre of the tile's 32-pixel-aligned
-// origin in FP64 before rounding to FP32: that origin, and so every FP32
-// operation of a pixel, is the same for every tile size), and tests the
+// origin in FP64 and split into an FP32 head and remainder, so a pixel's
+// offset is exact to one rounding; that origin, and so every FP32 operation
+// of a pixel, is the same for every tile size), and tests the
 // splat's support rect against every wavefront's 8x8 block; a ballot per
 // block turns this into a 64-bit mask per (wavefront, stager wavefront), so
 // each wavefront only evaluates splats that can touch its pixels.  A
@@ -175,19 +176,24 @@ __device__ __forceinline__ bool block_reached(float ur, float vr, float w0, floa
 // Stage splat `idx` of the tile list into LDS slot `slot` and return the
 // bit set of wave blocks its support reaches (support rect first, then the
 // exact ellipse-against-block test).
-template <int TW, int TH, int WW, int BT>
+template <int TW, int TH, int WW, int BT, bool EXACT = false>
 __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats, int64_t vbase,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
                                           int slot, const PixelCtx& c, const BlendParams& bp,
-                                          StagedSplat* ss, uint32_t* sgid) {
+                                          StagedSplat* ss, StagedForm* sf, StagedRem* sr,
+                                          uint32_t* sgid) {
   using TG = TileGeom<TW, TH, WW, BT>;
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
   StagedSplat s;
-  s.ur = (float)(sp.uc - ((double)c.ox + 0.5));
-  s.vr = (float)(sp.vc - ((double)c.oy + 0.5));
+  const CentreSplit cs = split_centre(sp.uc, sp.vc, c.ox, c.oy);
+  s.ur = cs.ur; s.vr = cs.vr;
   s.w0 = sp.w[0]; s.w1 = sp.w[1]; s.w2 = sp.w[2]; s.w3 = sp.w[3];
-  s.o = sp.opacity; s.z = sp.z;
+  sf[slot] = StagedForm{form_const(sp.w[0], sp.w[1], cs.ul, cs.vl),
+                        form_const(sp.w[2], sp.w[3], cs.ul, cs.vl)};
+  if (sr) sr[slot] = StagedRem{cs.ul, cs.vl};
+  s.o = sp.opacity;
+  s.zc = EXACT ? sp.z : plane_const(sp.z, sp.p[0], sp.p[1], cs.ul, cs.vl);
   s.r = sp.rgb[0]; s.g = sp.rgb[1]; s.b = sp.rgb[2];
   s.p0 = sp.p[0]; s.p1 = sp.p[1];
   s.n0 = sp.n[0]; s.n1 = sp.n[1]; s.n2 = sp.n[2];
@@ -211,11 +217,13 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     const float invA = A > 0.0f ? 1.0f / A : 0.0f, invC = C > 0.0f ? 1.0f / C : 0.0f;
     const float lo = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
     const float tau2 = fminf(bp.cut2, lo) * 1.001f + 0.01f;
-    const int sx = c.x0 - c.ox, sy = c.y0 - c.oy;  // tile start relative to the origin
+    // centre relative to the tile's first pixel (x0 - ox is a small integer:
+    // exact), so the block offsets below are compile-time constants
+    const float ut = s.ur - (float)(c.x0 - c.ox), vt = s.vr - (float)(c.y0 - c.oy);
 #pragma unroll
     for (int k = 0; k < TG::NW; ++k) {
-      const int bx = sx + WW * (k % TG::NWX), by = sy + TG::WH * (k / TG::NWX);
-      if (((bits >> k) & 1u) && !block_reached(s.ur, s.vr, s.w0, s.w1, s.w2, s.w3, A, B, C, invA,
+      const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
+      if (((bits >> k) & 1u) && !block_reached(ut, vt, s.w0, s.w1, s.w2, s.w3, A, B, C, invA,
                                                invC, tau2, bx, by, WW, TG::WH))
         bits &= ~(1u << k);
     }
@@ -242,6 +250,8 @@ template <int TW, int TH, bool EXACT, int WW, int BT>
 struct FwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
   StagedSplat ss[TG::BATCH];
+  StagedForm sf[TG::BATCH];
+  StagedRem sr[EXACT ? TG::BATCH : 1];
   uint32_t sgid[TG::BATCH];
   uint64_t masks[TG::NW][TG::NCH];
   // EXACT: the ray-maximum depth terms (g0, g1, H00, H01) and H11
@@ -261,6 +271,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
   StagedSplat* ss = sh.ss;
+  StagedForm* sf = sh.sf;
+  StagedRem* sr = EXACT ? sh.sr : nullptr;
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
   const PixelCtx c = pixel_ctx<TW, TH, WW, BT>(a.views, a.V, a.ranges, tile);
@@ -289,7 +301,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       const uint32_t idx = b0 + (uint32_t)slot;
       uint32_t bits = 0;
       if (idx < c.re) {
-        bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, idx, slot, c, bp, ss, sgid);
+        bits = stage<TW, TH, WW, BT, EXACT>(splats, vbase, pair_ids, idx, slot, c, bp, ss, sf,
+                                            sr, sgid);
         if constexpr (EXACT) {
           const float4* q = a.depth_quad + 2 * (vbase + sgid[slot]);
           sh.xq[slot] = q[0];
@@ -306,10 +319,11 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         m &= ~(1ull << j);
         const int r = cw * 64 + j;
         const StagedSplat s = ss[r];
+        const StagedForm f = sf[r];
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, pw, e, al;
         bool cl;
-        splat_eval(s, dx, dy, bp, t1, t2, pw, e, al, cl);
+        splat_eval(s, f, dx, dy, bp, t1, t2, pw, e, al, cl);
         if constexpr (CNT) evl += __builtin_amdgcn_inverse_ballot_w64(~wdone) ? 1 : 0;
         // the decision of splat_alpha, per lane, as masks
         const uint64_t pass = __builtin_amdgcn_ballot_w64(pw <= bp.cut2) &
@@ -330,15 +344,18 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         const float w = take ? al * T : 0.0f;
         float d;
         if constexpr (EXACT) {
-          // z (1 - g.d) / (1 - 2 g.d + H0 dx^2 + H1 dx dy + H2 dy^2)
+          // z (1 - g.d) / (1 - 2 g.d + H0 dx^2 + H1 dx dy + H2 dy^2), with
+          // the offset from the true centre
           const float4 q = sh.xq[r];
           const float h2 = sh.xh[r];
-          const float gd = fmaf(q.y, dy, q.x * dx);
-          const float quad = fmaf(h2 * dy, dy, dx * fmaf(q.z, dx, q.w * dy));
+          const StagedRem rm = sr[r];
+          const float ex = dx + rm.ul, ey = dy + rm.vl;
+          const float gd = fmaf(q.y, ey, q.x * ex);
+          const float quad = fmaf(h2 * ey, ey, ex * fmaf(q.z, ex, q.w * ey));
           const float den = fmaf(-2.0f, gd, 1.0f) + quad;
-          d = s.z * (1.0f - gd) * __builtin_amdgcn_rcpf(den);
+          d = s.zc * (1.0f - gd) * __builtin_amdgcn_rcpf(den);
         } else {
-          d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
+          d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.zc));
         }
         C0 = fmaf(w, s.r, C0); C1 = fmaf(w, s.g, C1); C2 = fmaf(w, s.b, C2);
         D = fmaf(w, d, D);
@@ -378,10 +395,9 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
     // operations as in the loop (bit-identical to tracking it per blend)
     if (medp >= 0) {
       const rade_splat& sp = splats[vbase + pair_ids[c.rb + medp]];
-      const float ur = (float)(sp.uc - ((double)c.ox + 0.5));
-      const float vr = (float)(sp.vc - ((double)c.oy + 0.5));
-      const float dx = ur - fx, dy = vr - fy;
-      dmed = fmaf(sp.p[1], dy, fmaf(sp.p[0], dx, sp.z));
+      const CentreSplit cs = split_centre(sp.uc, sp.vc, c.ox, c.oy);
+      const float dx = cs.ur - fx, dy = cs.vr - fy;
+      dmed = fmaf(sp.p[1], dy, fmaf(sp.p[0], dx, plane_const(sp.z, sp.p[0], sp.p[1], cs.ul, cs.vl)));
     }
   }
   a.depth[2 * c.poff + P + pix] = medp >= 0 ? dmed : 0.0f;
@@ -473,6 +489,8 @@ template <int TW, int TH, int WW, int BT>
 struct BwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
   StagedSplat ss[TG::BATCH];
+  StagedForm sf[TG::BATCH];
+  StagedRem sr[TG::BATCH];
   uint32_t sgid[TG::BATCH];
   uint64_t masks[TG::NW][TG::NCH];
   int smax;
@@ -495,6 +513,8 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
   const float* __restrict__ d_alpha = a.d_alpha;
   float* __restrict__ gsplat = a.gsplat;
   StagedSplat* ss = sh.ss;
+  StagedForm* sf = sh.sf;
+  StagedRem* sr = sh.sr;
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
   int& smax = sh.smax;
@@ -555,7 +575,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (li < bend)
         bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot, c, bp,
-                                     ss, sgid);
+                                     ss, sf, sr, sgid);
       publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
     __syncthreads();
@@ -576,15 +596,17 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         const float4 q0 = s4[0], q1 = s4[1], q2 = s4[2], q3 = s4[3];
         const StagedSplat s{q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
                             q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+        const StagedForm f = sf[r];
+        const StagedRem rm = sr[r];
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, e, al;
         bool cl;
-        const bool has = splat_alpha(s, dx, dy, bp, t1, t2, e, al, cl) && pos <= lastp;
-        // all four 16-byte reads are issued before the branch below (left to
+        const bool has = splat_alpha(s, f, dx, dy, bp, t1, t2, e, al, cl) && pos <= lastp;
+        // all 16-byte reads are issued before the branch below (left to
         // itself the compiler splits the second half into 4-byte reads inside
         // it, each needing its own address register)
         asm volatile("" ::"v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w), "v"(q3.x), "v"(q3.y),
-                     "v"(q3.z), "v"(q3.w));
+                     "v"(q3.z), "v"(q3.w), "v"(rm.ul), "v"(rm.vl));
         if (!__any(has)) continue;
         // Branch-free adjoint: every lane evaluates, lanes without this
         // splat contribute zeros and keep their state (alpha <= alpha_max,
@@ -592,7 +614,9 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         const float inv = __builtin_amdgcn_rcpf(1.0f - al);
         const float Ti = T * inv;
         const float w = al * Ti;
-        const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.z));
+        const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.zc));
+        // the offset from the true centre (footprint and plane terms below)
+        const float ex = dx + rm.ul, ey = dy + rm.vl;
         // explicit FMAs (the file compiles without contraction so that the
         // alpha decisions above match the forward bit for bit)
         float sf = fmaf(gC0, s.r, gA);
@@ -622,14 +646,14 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         g[0] = gop * fmaf(t1, s.w0, t2 * s.w2);
         g[1] = gop * fmaf(t1, s.w1, t2 * s.w3);
         // conic terms: sums of ga e dx^2, ga e dx dy, ga e dy^2
-        const float gpx = gop * dx;
-        g[2] = gpx * dx;
-        g[3] = gpx * dy;
-        g[4] = (gop * dy) * dy;
+        const float gpx = gop * ex;
+        g[2] = gpx * ex;
+        g[3] = gpx * ey;
+        g[4] = (gop * ey) * ey;
         g[5] = gop;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;
-        g[10] = gd * dx; g[11] = gd * dy;
+        g[10] = gd * ex; g[11] = gd * ey;
         g[12] = wg * gN0; g[13] = wg * gN1; g[14] = wg * gN2;
         g[15] = 0.0f;
         {
