@@ -71,6 +71,8 @@ extern "C" {
 #define RADE_ERR_UNSUPPORTED_DEVICE (-4) /* the current device is not a gfx950 GPU (or there
                                             is none); nothing enqueued */
 #define RADE_ERR_WORKSPACE (-5)          /* workspace smaller than required; nothing enqueued */
+#define RADE_ERR_TOO_LARGE (-6)          /* input larger than the fixed scratch of an
+                                            allocation-free entry point; nothing enqueued */
 
 /* Rasterizer settings.  Quantities the paper leaves open default to the
  * values of the 3D Gaussian Splatting code base the paper builds on (it
@@ -318,6 +320,28 @@ int rade_normal_consistency(const rade_view* views_host, const rade_view* views_
                             float weight, float* loss, float* d_depth, float* d_normal,
                             float* d_alpha, int32_t accumulate, void* workspace,
                             size_t workspace_bytes, void* stream);
+
+/* Allocation-free form of rade_normal_consistency, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments without the workspace,
+ * same kernels, same results bit for bit.  Its scratch (one loss partial per
+ * 32x8 pixel block) is a fixed array of RADE_NC_NOALLOC_MAX_BLOCKS floats
+ * (512 KiB) that the library holds on every GPU it runs on until the process
+ * ends; its device address is looked up once per device, on the first call
+ * made with that device current.  Views with more blocks than that in total
+ * (sum over views of ceil(W/32) * ceil(H/8); about 33M pixels) are rejected
+ * with RADE_ERR_TOO_LARGE before anything is enqueued.  Every call on one
+ * GPU shares that one array, and the kernels write every partial they read,
+ * so nothing needs clearing between calls; but calls that overlap on one GPU
+ * (on different streams, or from threads without ordering) race on it and
+ * must be serialised by the caller.  Calls no hipMalloc, hipFree or other
+ * allocating routine. */
+#define RADE_NC_NOALLOC_MAX_BLOCKS 131072
+int rade_normal_consistency_noalloc(const rade_view* views_host, const rade_view* views_dev,
+                                    int32_t V, const float* depth, const float* normal,
+                                    const float* alpha, float weight, float* loss,
+                                    float* d_depth, float* d_normal, float* d_alpha,
+                                    int32_t accumulate, void* stream);
 
 /* Gradient of an L1 colour loss, the mean absolute difference of each
  * view's three colour planes to a target (the colour term of the training

@@ -24,6 +24,8 @@ RADE_ERR_CAPACITY = -2
 RADE_ERR_HIP = -3
 RADE_ERR_UNSUPPORTED_DEVICE = -4
 RADE_ERR_WORKSPACE = -5
+RADE_ERR_TOO_LARGE = -6
+RADE_NC_NOALLOC_MAX_BLOCKS = 131072
 
 RADE_SCHEDULE_TILE, RADE_SCHEDULE_HEAVY_FIRST, RADE_SCHEDULE_PERSISTENT = 0, 1, 2
 
@@ -140,6 +142,9 @@ def load() -> ctypes.CDLL:
     lib.rade_normal_consistency_workspace.restype = SZ
     lib.rade_normal_consistency.argtypes = [P, P, I32] + [P] * 3 + [ctypes.c_float] + [P] * 4 + \
         [I32, P, SZ, P]
+    lib.rade_normal_consistency_noalloc.argtypes = [P, P, I32] + [P] * 3 + [ctypes.c_float] + \
+        [P] * 4 + [I32, P]
+    lib.rade_normal_consistency_noalloc.restype = ctypes.c_int
     lib.rade_l1_color_grad.argtypes = [P, P, I32, P, P, ctypes.c_float, P, P]
     lib.rade_l1_color_grad.restype = ctypes.c_int
     lib.rade_normal_consistency.restype = ctypes.c_int
@@ -170,7 +175,8 @@ EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "ra
             "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
             "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
             "rade_tsdf_fuse", "rade_marching_cubes_workspace", "rade_marching_cubes",
-            "rade_marching_cubes_table", "rade_l1_color_grad", "rade_device_check"]
+            "rade_marching_cubes_table", "rade_l1_color_grad", "rade_device_check",
+            "rade_normal_consistency_noalloc"]
 
 RADE_KERNEL_PROJECT, RADE_KERNEL_RENDER_FWD, RADE_KERNEL_RENDER_BWD, RADE_KERNEL_PROJECT_BWD = 1, 2, 3, 4
 
@@ -337,6 +343,15 @@ def rade_normal_consistency(views_c, views_dev, depth, normal, alpha, weight: fl
         views_c, _p(views_dev), len(views_c), _p(depth), _p(normal), _p(alpha), float(weight),
         _p(loss), _p(d_depth), _p(d_normal), _p(d_alpha), 1 if accumulate else 0, _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_normal_consistency")
+
+
+def rade_normal_consistency_noalloc(views_c, views_dev, depth, normal, alpha, weight: float, loss,
+                                    d_depth, d_normal, d_alpha, stream=None,
+                                    accumulate: bool = True):
+    return _check(load().rade_normal_consistency_noalloc(
+        views_c, _p(views_dev), len(views_c), _p(depth), _p(normal), _p(alpha), float(weight),
+        _p(loss), _p(d_depth), _p(d_normal), _p(d_alpha), 1 if accumulate else 0,
+        _stream(stream)), "rade_normal_consistency_noalloc")
 
 
 def rade_l1_color_grad(views_c, views_dev, color, target, weight: float, d_color, stream=None):

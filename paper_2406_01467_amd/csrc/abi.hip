@@ -55,6 +55,7 @@ hipError_t launch_normal_consistency(const rade_view* views_host, const rade_vie
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t tiles, uint32_t* order, void* ws,
                              hipStream_t st);
 int64_t normal_consistency_blocks(const rade_view* views_host, int V);
+hipError_t nc_scratch_address(void** out);
 hipError_t launch_filter3d_var(const rade_view* views, int V, int64_t N, const float* means,
                                double near_plane, float scale, float margin, float* var,
                                hipStream_t st);
@@ -186,6 +187,8 @@ const char* rade_strerror(int code) {
     case RADE_ERR_HIP: return "HIP runtime error";
     case RADE_ERR_UNSUPPORTED_DEVICE: return "unsupported device (the library runs on gfx950 GPUs only)";
     case RADE_ERR_WORKSPACE: return "workspace too small";
+    case RADE_ERR_TOO_LARGE:
+      return "input larger than the fixed scratch of an allocation-free entry point";
     default: return "unknown error";
   }
 }
@@ -323,6 +326,30 @@ int rade_normal_consistency(const rade_view* views_host, const rade_view* views_
                                                     normal, alpha,
                                                     weight, loss, d_depth, d_normal, d_alpha,
                                                     accumulate != 0, workspace,
+                                                    (hipStream_t)stream));
+}
+
+int rade_normal_consistency_noalloc(const rade_view* views_host, const rade_view* views_dev,
+                                    int32_t V, const float* depth, const float* normal,
+                                    const float* alpha, float weight, float* loss,
+                                    float* d_depth, float* d_normal, float* d_alpha,
+                                    int32_t accumulate, void* stream) {
+  if (!views_ok(views_host, V) || !views_dev || !depth || !normal || !alpha || !loss ||
+      !d_depth || !d_normal || !d_alpha || !std::isfinite(weight))
+    return RADE_ERR_INVALID_ARG;
+  const int64_t total = prepared_pixels(views_host, V);
+  if (total < 0) return RADE_ERR_INVALID_ARG;  // not prepared
+  if (rade::normal_consistency_blocks(views_host, V) > RADE_NC_NOALLOC_MAX_BLOCKS)
+    return RADE_ERR_TOO_LARGE;
+  if (const int dv = device_status(); dv != RADE_OK) return dv;
+  void* ws = nullptr;
+  if (rade::nc_scratch_address(&ws) != hipSuccess) {
+    (void)hipGetLastError();
+    return RADE_ERR_HIP;
+  }
+  return hip_status(rade::launch_normal_consistency(views_host, views_dev, V, total, depth,
+                                                    normal, alpha, weight, loss, d_depth,
+                                                    d_normal, d_alpha, accumulate != 0, ws,
                                                     (hipStream_t)stream));
 }
 

@@ -10,6 +10,8 @@
 // Eq. 24 writes sum_i w_i (1 - n_i . n~) per pixel; with A = sum_i w_i and
 // N = sum_i w_i n_i that is A - N . n~, exactly, from the blended maps.
 // The gradient flows into A, N and (through n~, not detached) D_med.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace rade {
@@ -270,6 +272,36 @@ int64_t normal_consistency_blocks(const rade_view* views_host, int V) {
 // One loss partial per block; every block holds at least one pixel.
 size_t normal_consistency_workspace(int64_t total_pixels) {
   return (size_t)total_pixels * sizeof(float) + 256;
+}
+
+namespace {
+// Scratch of the allocation-free entry point: one loss partial per block.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): it uses the address looked up below.
+static __device__ __align__(256) float scratch[RADE_NC_NOALLOC_MAX_BLOCKS];
+
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kScratchDevices];  // per device ordinal, looked up once
+}  // namespace
+
+// Device address of `scratch` on the calling thread's current device, looked
+// up on the first call made with that device current.
+hipError_t nc_scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_normal_consistency(const rade_view* views_host, const rade_view* views, int V,

@@ -30,7 +30,7 @@ def _declared():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = _declared()
-    assert len(names) == 23, names
+    assert len(names) == 24, names
     so = ctypes.CDLL(lib.LIB_PATH)
     for n in names:
         assert hasattr(so, n), n
@@ -217,9 +217,10 @@ def _no_gpu() -> bool:
 def test_error_codes_are_distinct():
     lib = _lib()
     codes = [lib.RADE_ERR_INVALID_ARG, lib.RADE_ERR_CAPACITY, lib.RADE_ERR_HIP,
-             lib.RADE_ERR_UNSUPPORTED_DEVICE, lib.RADE_ERR_WORKSPACE]
+             lib.RADE_ERR_UNSUPPORTED_DEVICE, lib.RADE_ERR_WORKSPACE, lib.RADE_ERR_TOO_LARGE]
     assert len(set(codes)) == len(codes) and lib.RADE_OK not in codes
     assert lib.RADE_ERR_UNSUPPORTED_DEVICE == -4 and lib.RADE_ERR_WORKSPACE == -5
+    assert lib.RADE_ERR_TOO_LARGE == -6
     msgs = {lib.strerror(c) for c in codes}
     assert len(msgs) == len(codes) and "gfx950" in lib.strerror(lib.RADE_ERR_UNSUPPORTED_DEVICE)
 
@@ -250,3 +251,34 @@ def test_no_device_is_unsupported_and_nothing_launches():
     assert so.rade_bin_sort(ctypes.byref(s), vc, d, 1, 10, d, d, d, d, None, 100, d, None, d,
                             ws, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
     assert so.rade_filter3d_apply(10, d, d, d, d, d, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
+
+
+def test_noalloc_limit_is_checked_on_the_host():
+    """The allocation-free Eq. 24 entry point rejects views with more 32x8
+    blocks than its fixed scratch holds, before the device check and before
+    anything is enqueued (the dummy pointers are never dereferenced); the
+    header's limit is the binding's."""
+    lib = _lib()
+    import synth
+    so = lib.load()
+    text = open(HEADER).read()
+    m = re.search(r"#define RADE_NC_NOALLOC_MAX_BLOCKS (\d+)", text)
+    assert m and int(m.group(1)) == lib.RADE_NC_NOALLOC_MAX_BLOCKS
+    d = ctypes.c_void_p(256)
+
+    def call(sizes):
+        vc = lib.make_views([synth.identity_view(w, h) for w, h in sizes])
+        lib.rade_views_prepare(lib.Settings(), vc)
+        return so.rade_normal_consistency_noalloc(vc, d, len(sizes), d, d, d,
+                                                  ctypes.c_float(1.0), d, d, d, d, 1, None)
+    # 128 x 512 blocks per 4096 x 4096 view: two fill the scratch exactly
+    assert call([(8192, 8192)]) == lib.RADE_ERR_TOO_LARGE
+    assert call([(4096, 4096), (4096, 4096), (32, 8)]) == lib.RADE_ERR_TOO_LARGE
+    ok = lib.RADE_ERR_UNSUPPORTED_DEVICE if _no_gpu() else None
+    if ok is not None:
+        assert call([(4096, 4096), (4096, 4096)]) == ok
+        assert call([(31, 9)]) == ok
+    vc = lib.make_views([synth.identity_view(32, 8)])
+    lib.rade_views_prepare(lib.Settings(), vc)
+    assert so.rade_normal_consistency_noalloc(vc, d, 1, d, None, d, ctypes.c_float(1.0), d, d, d,
+                                              d, 1, None) == lib.RADE_ERR_INVALID_ARG
