@@ -55,6 +55,10 @@ struct TileGeom {
   static constexpr int BLOCK = 64 * NW;
   static constexpr int BATCH = BATCH_ > 0 ? BATCH_ : BLOCK;
   static constexpr int NCH = BATCH / 64;
+  // One wave per tile: staging also computes which of the wave's pixels a
+  // splat can reach (a 64-bit lane mask), so the loops skip the splats none
+  // of their still-active pixels takes.
+  static constexpr bool LM = NW == 1 && WW == 8;
   static_assert(WW == 8 || WW == 16 || WW == 32, "wave width");
   static_assert(TW % WW == 0 && TH % WH == 0 && BLOCK <= 1024 && BATCH % 64 == 0, "tile");
 };
@@ -181,7 +185,7 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
                                           int slot, const PixelCtx& c, const BlendParams& bp,
                                           StagedSplat* ss, StagedForm* sf, StagedRem* sr,
-                                          uint32_t* sgid) {
+                                          uint32_t* sgid, uint64_t* lmask) {
   using TG = TileGeom<TW, TH, WW, BT>;
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
@@ -228,6 +232,41 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
         bits &= ~(1u << k);
     }
   }
+  if constexpr (TG::LM) {
+    // Lane mask of the one 8x8 wave (lane = 8 y + x): per pixel row of the
+    // support rect, the interval of the ellipse Q(dx, dy) <= tau2 along the
+    // row, A dx^2 + 2 B dx dy + C dy^2 <= tau2, widened by a margin and
+    // rounded outwards (conservative: the loops still test every pixel).
+    uint64_t lm = 0;
+    if (bits) {
+      const int x0 = max(rx0, 0), x1 = min(rx1, 7), y0 = max(ry0, 0), y1 = min(ry1, 7);
+      const float A = fmaf(s.w0, s.w0, s.w2 * s.w2), B = fmaf(s.w0, s.w1, s.w2 * s.w3);
+      const float C = fmaf(s.w1, s.w1, s.w3 * s.w3);
+      const float invA = A > 0.0f ? 1.0f / A : 0.0f;
+      const float lo2 = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
+      const float tau2 = fminf(bp.cut2, lo2) * 1.001f + 0.01f;
+      // the Gram determinant A C - B^2 >= 0, lowered by more than its FP32
+      // rounding (a lower value only widens the intervals)
+      const float det = fmaxf(fmaf(A, C, -(B * B)) - 4e-7f * (A * C), 0.0f);
+      const float ut = s.ur - (float)(c.x0 - c.ox), vt = s.vr - (float)(c.y0 - c.oy);
+      for (int y = y0; y <= y1; ++y) {
+        const float dy = vt - (float)y;
+        const float disc = fmaf(-det, dy * dy, A * tau2);
+        if (disc < 0.0f) continue;
+        int xl = x0, xh = x1;
+        if (A > 0.0f) {
+          // pixels x = ut - dx with dx in -B dy / A -+ sqrt(disc) / A
+          const float xc = fmaf(B * dy, invA, ut), half = sqrtf(disc) * invA;
+          const float m = 2e-3f + 1e-5f * (fabsf(xc) + half);
+          xl = max(xl, (int)ceilf(fmaxf(xc - half - m, -1.0f)));
+          xh = min(xh, (int)floorf(fminf(xc + half + m, 8.0f)));
+        }
+        if (xl <= xh) lm |= ((2ull << xh) - (1ull << xl)) << (8 * y);
+      }
+    }
+    lmask[slot] = lm;
+    if (!lm) bits = 0;
+  }
   return bits;
 }
 
@@ -253,6 +292,7 @@ struct FwdShared {
   StagedForm sf[TG::BATCH];
   StagedRem sr[EXACT ? TG::BATCH : 1];
   uint32_t sgid[TG::BATCH];
+  uint64_t lmask[TG::LM ? TG::BATCH : 1];
   uint64_t masks[TG::NW][TG::NCH];
   // EXACT: the ray-maximum depth terms (g0, g1, H00, H01) and H11
   float4 xq[EXACT ? TG::BATCH : 1];
@@ -302,7 +342,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (idx < c.re) {
         bits = stage<TW, TH, WW, BT, EXACT>(splats, vbase, pair_ids, idx, slot, c, bp, ss, sf,
-                                            sr, sgid);
+                                            sr, sgid, sh.lmask);
         if constexpr (EXACT) {
           const float4* q = a.depth_quad + 2 * (vbase + sgid[slot]);
           sh.xq[slot] = q[0];
@@ -314,6 +354,11 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
     __syncthreads();
     for (int cw = 0; cw < TG::NCH && wdone != ~0ull; ++cw) {
       uint64_t m = uniform_u64(masks[wave][cw]);
+      if constexpr (TG::LM) {
+        // drop the chunk's splats whose lane mask holds no pixel still
+        // blending (lane l tests staged splat cw * 64 + l)
+        m &= __builtin_amdgcn_ballot_w64((sh.lmask[cw * 64 + (threadIdx.x & 63)] & ~wdone) != 0);
+      }
       while (m && wdone != ~0ull) {
         const int j = __builtin_ctzll(m);
         m &= ~(1ull << j);
@@ -492,6 +537,7 @@ struct BwdShared {
   StagedForm sf[TG::BATCH];
   StagedRem sr[TG::BATCH];
   uint32_t sgid[TG::BATCH];
+  uint64_t lmask[TG::LM ? TG::BATCH : 1];
   uint64_t masks[TG::NW][TG::NCH];
   int smax;
 };
@@ -575,7 +621,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (li < bend)
         bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot, c, bp,
-                                     ss, sf, sr, sgid);
+                                     ss, sf, sr, sgid, sh.lmask);
       publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
     __syncthreads();
@@ -584,6 +630,13 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
       if (lim < 0) continue;  // nothing at or below our last blend
       uint64_t m = uniform_u64(masks[wave][cw]);
       if (lim < 63) m &= (2ull << lim) - 1;  // positions up to wlast
+      if constexpr (TG::LM) {
+        // drop the chunk's splats whose lane mask holds no pixel that blends
+        // at the chunk's first position or later (lane l tests staged splat
+        // cw * 64 + l)
+        const uint64_t live = __builtin_amdgcn_ballot_w64(bstart + cw * 64 <= lastp);
+        m &= __builtin_amdgcn_ballot_w64((sh.lmask[cw * 64 + lane] & live) != 0);
+      }
       // the chunk's Gaussian ids, one per lane; a splat's id is read from
       // its lane
       const int cgid = (int)sgid[cw * 64 + lane];

@@ -284,6 +284,60 @@ def test_tile_size_invariance():
             assert nbad == 0, (tile, k, nbad)
 
 
+def _needle_scene(n, seed):
+    # strongly anisotropic Gaussians (one long axis, two thin ones) at random
+    # orientations: their support boxes are far larger than the pixels they
+    # reach, which is what the 8x8 tiles' per-row lane masks cut away
+    scene = synth.make_scene_ball(n, seed=seed, centre=(0.0, 0.0, 3.0), radius=1.0,
+                                  log_scale_mu=-4.0, log_scale_sd=0.3)
+    rng = np.random.default_rng(seed + 100)
+    long_axis = rng.integers(0, 3, n)
+    scene.scales[np.arange(n), long_axis] *= np.float32(15.0)
+    return scene
+
+
+def test_lane_masks_keep_every_blend_of_needle_splats():
+    # 8x8 tiles (one wave per tile, lane masks from per-row ellipse
+    # intervals) against 16x16 tiles (no lane masks): bitwise equal maps and
+    # saved state, gradients equal up to the order of the FP32 atomics; and
+    # the 8x8 maps and gradients against the oracle
+    import torch
+    dev = device()
+    from paper_2406_01467_amd.raster import Rasterizer
+    scene = _needle_scene(6000, 41)
+    views = [synth.identity_view(100, 70)]
+    params = to_dev(scene, dev)
+    outs = {}
+    for tile in (16, 8):
+        s = _settings(sh_degree=3, tile_w=tile, tile_h=tile, schedule=1)
+        rast = Rasterizer(views, s, dev)
+        maps = rast.forward(*params, want_count=True)
+        rng = np.random.default_rng(4)
+        P = rast.total_pixels
+        g = [torch.from_numpy(rng.normal(size=k * P).astype(np.float32)).to(dev) for k in (3, 2, 3, 1)]
+        grads = rast.backward(maps.state, *params, *g)
+        torch.cuda.synchronize()
+        outs[tile] = (maps, [x.cpu().numpy() for x in grads])
+    m0, g0 = outs[16]
+    m1, g1 = outs[8]
+    assert int(m0.count.sum()) > 50000
+    for k in ("color", "depth", "normal", "alpha", "count"):
+        assert torch.equal(getattr(m0, k), getattr(m1, k)), k
+    for k in ("t_final", "median"):
+        assert torch.equal(getattr(m0.state, k), getattr(m1.state, k)), k
+    for a, b in zip(g0, g1):
+        say(f"  8x8 vs 16x16 gradient difference, normwise: "
+            f"{np.linalg.norm(a - b) / np.linalg.norm(a):.3g}")
+    # the gradients of both tile sizes against the oracle's adjoint (their
+    # atomics sum each Gaussian's pixels in different groups, and the long
+    # splats' gradients cancel heavily, so they are compared with the oracle
+    # rather than with each other)
+    s8 = _settings(sh_degree=3, tile_w=8, tile_h=8, schedule=1)
+    _full_parity(scene, views, s8, "needles 8x8")
+    _bwd_parity(scene, views, s8, 42, "bwd needles 8x8")
+    _bwd_parity(scene, views, _settings(sh_degree=3, schedule=1), 42, "bwd needles 16x16")
+
+
 def test_degenerate_inputs():
     # no Gaussian, all culled (behind camera, NaN, tiny opacity), zero quaternion
     import torch
