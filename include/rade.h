@@ -265,7 +265,13 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
 /* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
  * recompute the splats (splats == NULL in rade_render_bwd).  The workspace
  * must be 16-byte aligned (device allocations are); RADE_ERR_INVALID_ARG
- * otherwise. */
+ * otherwise.  Layout, each region starting at a multiple of 256 bytes from
+ * the workspace start: the per-(view, Gaussian) gradient records (V*N*64
+ * bytes), then, with recompute, the recomputed splat records (V*N rade_splat)
+ * and tile counts (V*N int32) exactly as rade_project writes them.  A caller
+ * may therefore let its forward pass project into those two regions: the
+ * recomputing backward overwrites them with the same values, and no second
+ * copy of the records is needed. */
 size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute);
 
 /* Backward pass: gradients of the Gaussian parameters from the upstream

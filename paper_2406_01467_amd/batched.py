@@ -58,9 +58,12 @@ class BatchedPlan:
         self.distortion = distortion
         self.graph = None
         if capacity is None:
-            # one eager binning pass sizes the pair buffers (with slack)
+            # one eager binning pass sizes the pair buffers (with slack); the
+            # rasterizer's buffers for it are released after
             splats, tt = self.rast.project(*self.params)
             _, _, M = self.rast.bin_sort(self.N, splats, tt)
+            del splats, tt
+            self.rast.release_pairs()
             capacity = int(M * 1.15) + 4096
         self._alloc(capacity)
 
@@ -69,14 +72,39 @@ class BatchedPlan:
         dev, V, N, r = self.device, self.V, self.N, self.rast
         VN = max(1, V * N)
         self.capacity = int(capacity)
-        self.splats = torch.empty(VN * _lib.SPLAT_BYTES, dtype=torch.uint8, device=dev)
-        self.tt = torch.empty(VN, dtype=torch.int32, device=dev)
         self.pair_ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=dev)
         self.ranges = torch.empty(2 * max(1, r.total_tiles), dtype=torch.int32, device=dev)
         self.n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.bin_ws = torch.empty(max(1, _lib.rade_bin_sort_workspace(V, N, self.capacity,
-                                                                      r.total_tiles)),
-                                  dtype=torch.uint8, device=dev)
+        # One arena holds the binning workspace and the backward's workspace.
+        # The binning workspace is scratch of rade_bin_sort only, and the
+        # backward's gradient records (its first V x N x 64 bytes) are
+        # written after its start and read by its end: stream order keeps the
+        # two apart, so they share memory.  With recompute, the backward
+        # recomputes the splat records and tile counts into its workspace
+        # after the gradient records (rade.h gives the layout); the forward
+        # projects into that same region, so no second copy of the V x N
+        # records exists, and the region lies after the binning workspace,
+        # which reads the records while it runs.
+        a256 = lambda b: (b + 255) & ~255  # noqa: E731
+        bin_bytes = a256(max(1, _lib.rade_bin_sort_workspace(V, N, self.capacity,
+                                                             r.total_tiles)))
+        bwd_bytes = a256(max(1, _lib.rade_render_bwd_workspace(self.settings, V, N,
+                                                               self.recompute)))
+        g_bytes = a256(V * N * 16 * 4)
+        if self.recompute and V * N > 0:
+            head = max(bin_bytes, g_bytes)
+            self.arena = torch.empty(head - g_bytes + bwd_bytes, dtype=torch.uint8, device=dev)
+            self.bwd_ws = self.arena[head - g_bytes:]
+            s_bytes = V * N * _lib.SPLAT_BYTES
+            self.splats = self.arena[head: head + s_bytes]
+            t0 = head + a256(s_bytes)
+            self.tt = self.arena[t0: t0 + 4 * V * N].view(torch.int32)
+        else:
+            self.arena = torch.empty(max(bin_bytes, bwd_bytes), dtype=torch.uint8, device=dev)
+            self.bwd_ws = self.arena[:bwd_bytes]
+            self.splats = torch.empty(VN * _lib.SPLAT_BYTES, dtype=torch.uint8, device=dev)
+            self.tt = torch.empty(VN, dtype=torch.int32, device=dev)
+        self.bin_ws = self.arena[:bin_bytes]
         self.order = torch.empty(r.total_tiles + 1, dtype=torch.int32, device=dev)
         self.order_ws = torch.empty(max(1, _lib.rade_tile_order_workspace(r.total_tiles)),
                                     dtype=torch.uint8, device=dev)
@@ -87,8 +115,6 @@ class BatchedPlan:
                          last=i(), median=i())
         if self.distortion:
             self.maps["distortion"] = f(1)
-        self.bwd_ws = torch.empty(max(1, _lib.rade_render_bwd_workspace(
-            self.settings, V, N, self.recompute)), dtype=torch.uint8, device=dev)
         m, s, q, o, sh = self.params
         self.grads = [torch.zeros_like(m), torch.zeros_like(s), torch.zeros((N, 4), device=dev),
                       torch.zeros_like(o), torch.zeros_like(sh)]

@@ -115,6 +115,13 @@ class Rasterizer:
     def exact_depth(self) -> bool:
         return self.settings.depth_mode == _lib.RADE_DEPTH_EXACT
 
+    def release_pairs(self):
+        """Free the pair buffers and binning workspace (reallocated on the
+        next bin_sort)."""
+        self._pairs = None
+        self._bin_ws = None
+        self._n = -1
+
     def bin_sort(self, N: int, splats, tt, want_keys: bool = False, stream=None):
         if self._pairs is None or self._n != N:
             self._alloc_pairs(N, max(self.capacity, 16 * max(N, 1) * self.V // 4 + 1024))

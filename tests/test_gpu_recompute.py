@@ -49,15 +49,33 @@ def test_recompute_at_full_scale_matches_stored_splats():
         return ups["c"], ups["d"], ups["n"], ups["a"]
 
     out = {}
+    peak = {}
     for recompute in (False, True):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
         plan = BatchedPlan(views, s, params, fixed, recompute=recompute)
+        torch.cuda.synchronize()
+        # the steady state of a training loop: the plan's buffers and the
+        # peak of a step (the construction's one-off sizing pass excluded)
+        torch.cuda.reset_peak_memory_stats()
         n = plan.step()
         torch.cuda.synchronize()
+        peak[recompute] = torch.cuda.max_memory_allocated() - base
         assert not plan.overflowed()
-        say("  recompute", recompute, "pairs", plan.n_pairs(), "replays", n)
+        say("  recompute", recompute, "pairs", plan.n_pairs(), "replays", n,
+            f"peak memory {peak[recompute] / 2**30:.2f} GiB")
         out[recompute] = ({k: v.clone() for k, v in plan.maps.items()},
                           [g.clone() for g in plan.grads], plan.rast)
         del plan
+    # recompute mode keeps no second copy of the V x N splat records (80 B)
+    # and tile counts (4 B): the forward writes them into the region the
+    # backward recomputes them in, so it needs no more memory than stored
+    # mode (it needed V x N x 84 B more when the plan kept both); in both
+    # modes the binning workspace and the gradient records share memory
+    VN = len(views) * scene.n
+    say(f"  step peak: stored {peak[False] / 2**30:.2f} GiB, recompute {peak[True] / 2**30:.2f} "
+        f"GiB (splat records and counts {VN * 84 / 2**30:.2f} GiB)")
+    assert peak[True] <= peak[False] + 0.02 * VN * 84
     (m0, g0, rast), (m1, g1, _) = out[False], out[True]
     for k in m0:
         assert torch.equal(m0[k], m1[k]), k
