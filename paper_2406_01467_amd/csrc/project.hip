@@ -481,6 +481,44 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
   }
 }
 
+// Colour part of the projection backward for one view: the gradient of the
+// view's SH row, row[3k + c] = g_c Y_k(u) (0 for a clamped channel, the
+// forward's decision from the same FP64 colour), and the viewing
+// direction's share of the mean gradient, added to gmu.  mu: the mean, C:
+// the camera centre, (gr, gg, gb): the colour gradient of the record.
+template <int K>
+__device__ __forceinline__ void sh_view_bwd(int deg, const double* mu, const double* C,
+                                            const float (&coef)[3 * K], float gr, float gg,
+                                            float gbl, float (&row)[3 * K], double* gmu) {
+  double u[3], raw[3];
+  const double idn = view_dir(mu, C, u);
+  sh_colour<K>(deg, u, coef, raw);
+  {
+    // the gradient arithmetic may use fused multiply-adds (the colour whose
+    // clamp decisions must match the forward is computed without, above)
+#pragma clang fp contract(fast)
+    const double g0 = raw[0] < 0.0 ? 0.0 : (double)gr;
+    const double g1 = raw[1] < 0.0 ? 0.0 : (double)gg;
+    const double g2 = raw[2] < 0.0 ? 0.0 : (double)gbl;
+    double Y[16], cw[16];
+    sh_basis(deg, u[0], u[1], u[2], Y);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cw[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double c0 = coef[3 * k + 0], c1 = coef[3 * k + 1], c2 = coef[3 * k + 2];
+      cw[k] = g0 * c0 + g1 * c1 + g2 * c2;
+      row[3 * k + 0] = (float)(g0 * Y[k]);
+      row[3 * k + 1] = (float)(g1 * Y[k]);
+      row[3 * k + 2] = (float)(g2 * Y[k]);
+    }
+    double gu[3];
+    sh_grad(deg, u[0], u[1], u[2], cw, gu);
+    const double ud = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
+    for (int i = 0; i < 3; ++i) gmu[i] += (gu[i] - u[i] * ud) * idn;
+  }
+}
+
 // Gradient record of one (view, Gaussian) from the render backward, with
 // g_o = dL/d opacity per pixel (zero where alpha is clamped):
 //   0, 1   sums of g_o (t1 w0 + t2 w2), g_o (t1 w1 + t2 w3): the centre
@@ -490,32 +528,32 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
 //   5      do;  6-8 drgb;  9 dz;  10, 11 dp;  12-14 dn;  15 pad.
 constexpr int kGradStride = 16;
 
-template <int KMAX, bool VEC>
-__global__ void __launch_bounds__(256)
-k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
-              const float* __restrict__ means, const float* __restrict__ scales,
-              const float* __restrict__ quats, const float* __restrict__ opac,
-              const float* __restrict__ sh, const float* __restrict__ gsplat,
-              float* __restrict__ d_means, float* __restrict__ d_scales,
-              float* __restrict__ d_quats, float* __restrict__ d_opac,
-              float* __restrict__ d_sh) {
+// SH: also the colour part, view by view (d_sh accumulated in place), in
+// one kernel (k_project_bwd); else k_project_bwd_sh follows
+// (k_project_bwd_geo).  One lane holds the geometry
+// and the SH row at once (one wave per SIMD): the fused form suits one view,
+// the split one many (the geometry kernel then needs no SH row, and the
+// colour kernel keeps its row's gradient in registers).
+template <int KMAX, bool VEC, bool SH>
+__device__ __forceinline__ void project_bwd_body(
+    const rade_settings& st, const rade_view* __restrict__ views, int V, int64_t N,
+    const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ quats, const float* __restrict__ opac,
+    const float* __restrict__ sh, const float* __restrict__ gsplat,
+    float* __restrict__ d_means, float* __restrict__ d_scales, float* __restrict__ d_quats,
+    float* __restrict__ d_opac, float* __restrict__ d_sh) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
-  const int deg = st.sh_degree;
   constexpr int K = KMAX;
   const float* __restrict__ coef_g = sh + 3 * K * g;
-  float* __restrict__ gcoef = d_sh + 3 * K * g;
   // the first view's gradient record is loaded together with the
-  // parameters and the SH row, so its latency is not paid after theirs
+  // parameters, so its latency is not paid after theirs.  (A Gaussian whose
+  // SH row is not finite is culled by the forward in every view: its
+  // records are zero, so every view is skipped and its gradients are zero.)
   const float4* gr0 = reinterpret_cast<const float4*>(gsplat + g * kGradStride);
   const float4 g0a = gr0[0], g0b = gr0[1], g0c = gr0[2], g0d = gr0[3];
   Params P;
   bool ok = load_params(g, means, scales, quats, opac, st.alpha_min, P);
-  {
-    float coef[3 * K];
-    load_row<K, VEC>(coef_g, coef);
-    ok = ok && row_finite<K>(coef);
-  }
   bool sh_written = false;
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gqn[4] = {0, 0, 0, 0}, go = 0.0;
   for (int vi = 0; ok && vi < V; ++vi) {
@@ -678,38 +716,14 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     // x = R mu + t
     for (int i = 0; i < 3; ++i)
       gmu[i] += v.R[i] * gx[0] + v.R[3 + i] * gx[1] + v.R[6 + i] * gx[2];
-
-    // --- colour -> SH coefficients (accumulated in place in d_sh) and the
-    // viewing direction
-    {
-      float coef[3 * K], gc_row[3 * K];
+    if constexpr (SH) {
+      float coef[3 * K], row[3 * K];
       load_row<K, VEC>(coef_g, coef);
-      double u[3], raw[3];
-      const double idn = view_dir(P.mu, v.C, u);
-      sh_colour<K>(deg, u, coef, raw);
-      // clamped channels pass no gradient (same decision as the forward)
-      const double g0 = raw[0] < 0.0 ? 0.0 : (double)gb.z;
-      const double g1 = raw[1] < 0.0 ? 0.0 : (double)gb.w;
-      const double g2 = raw[2] < 0.0 ? 0.0 : (double)gc.x;
-      double Y[16], cw[16];
-      sh_basis(deg, u[0], u[1], u[2], Y);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) cw[k] = 0.0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double c0 = coef[3 * k + 0], c1 = coef[3 * k + 1], c2 = coef[3 * k + 2];
-        cw[k] = g0 * c0 + g1 * c1 + g2 * c2;
-        gc_row[3 * k + 0] = (float)(g0 * Y[k]);
-        gc_row[3 * k + 1] = (float)(g1 * Y[k]);
-        gc_row[3 * k + 2] = (float)(g2 * Y[k]);
-      }
-      store_row<K, VEC>(gcoef, gc_row, sh_written);
+      sh_view_bwd<K>(st.sh_degree, P.mu, v.C, coef, gb.z, gb.w, gc.x, row, gmu);
+      store_row<K, VEC>(d_sh + 3 * K * g, row, sh_written);
       sh_written = true;
-      double gu[3];
-      sh_grad(deg, u[0], u[1], u[2], cw, gu);
-      const double ud = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
-      for (int i = 0; i < 3; ++i) gmu[i] += (gu[i] - u[i] * ud) * idn;
     }
+
     }
   }
   // unit quaternion -> raw quaternion
@@ -726,12 +740,87 @@ k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int6
     d_scales[3 * g + i] = ok ? (float)gs[i] : 0.0f;
   }
   d_opac[g] = ok ? (float)go : 0.0f;
-  if (!sh_written) {
+  if (SH && !sh_written) {
     float zero[3 * K];
 #pragma unroll
     for (int i = 0; i < 3 * K; ++i) zero[i] = 0.0f;
-    store_row<K, VEC>(gcoef, zero, false);
+    store_row<K, VEC>(d_sh + 3 * K * g, zero, false);
   }
+}
+
+template <int KMAX, bool VEC>
+__global__ void __launch_bounds__(256)
+k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
+              const float* __restrict__ means, const float* __restrict__ scales,
+              const float* __restrict__ quats, const float* __restrict__ opac,
+              const float* __restrict__ sh, const float* __restrict__ gsplat,
+              float* __restrict__ d_means, float* __restrict__ d_scales,
+              float* __restrict__ d_quats, float* __restrict__ d_opac,
+              float* __restrict__ d_sh) {
+  project_bwd_body<KMAX, VEC, true>(st, views, V, N, means, scales, quats, opac, sh, gsplat,
+                                    d_means, d_scales, d_quats, d_opac, d_sh);
+}
+
+// The geometry alone at two waves per SIMD: its registers are held to 256
+// (a few values spill to scratch memory; measured faster on 16 views than
+// one wave per SIMD without spills).
+template <int KMAX, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_project_bwd_geo(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
+                  const float* __restrict__ means, const float* __restrict__ scales,
+                  const float* __restrict__ quats, const float* __restrict__ opac,
+                  const float* __restrict__ gsplat, float* __restrict__ d_means,
+                  float* __restrict__ d_scales, float* __restrict__ d_quats,
+                  float* __restrict__ d_opac) {
+  project_bwd_body<KMAX, VEC, false>(st, views, V, N, means, scales, quats, opac, nullptr,
+                                     gsplat, d_means, d_scales, d_quats, d_opac, nullptr);
+}
+
+// The colour part of the projection backward, after k_project_bwd_geo: the SH
+// coefficient gradients (one row per Gaussian, summed over the views in
+// registers and stored once) and the viewing direction's share of the mean
+// gradient, added to what k_project_bwd wrote.  A view contributes when its
+// colour gradient is not zero; such a record comes from blended pixels, so
+// the splat exists in that view and the geometry the fused form would check
+// succeeds.  The clamp decisions are the forward's (same FP64 colour).
+template <int KMAX, bool VEC>
+__global__ void __launch_bounds__(256)
+k_project_bwd_sh(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
+                 const float* __restrict__ means, const float* __restrict__ scales,
+                 const float* __restrict__ quats, const float* __restrict__ opac,
+                 const float* __restrict__ sh, const float* __restrict__ gsplat,
+                 float* __restrict__ d_means, float* __restrict__ d_sh) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int deg = st.sh_degree;
+  constexpr int K = KMAX;
+  Params P;
+  bool ok = load_params(g, means, scales, quats, opac, st.alpha_min, P);
+  float coef[3 * K], acc[3 * K];
+  load_row<K, VEC>(sh + 3 * K * g, coef);
+  ok = ok && row_finite<K>(coef);
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) acc[i] = 0.0f;
+  double gmu[3] = {0, 0, 0};
+  for (int vi = 0; ok && vi < V; ++vi) {
+    const float4* gr = reinterpret_cast<const float4*>(gsplat + ((int64_t)vi * N + g) * kGradStride);
+    const float4 gb = gr[1], gc = gr[2];
+    if (gb.z == 0.f && gb.w == 0.f && gc.x == 0.f) continue;
+    double C[3];
+    {
+      const rade_view& rv = views[vi];
+      for (int i = 0; i < 3; ++i)
+        C[i] = -((double)rv.R[i] * (double)rv.t[0] + (double)rv.R[3 + i] * (double)rv.t[1] +
+                 (double)rv.R[6 + i] * (double)rv.t[2]);
+    }
+    float row[3 * K];
+    sh_view_bwd<K>(deg, P.mu, C, coef, gb.z, gb.w, gc.x, row, gmu);
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) acc[i] += row[i];
+  }
+  store_row<K, VEC>(d_sh + 3 * K * g, acc, false);
+  if (ok)
+    for (int i = 0; i < 3; ++i) d_means[3 * g + i] += (float)gmu[i];
 }
 
 }  // namespace
@@ -774,9 +863,20 @@ hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, i
   const dim3 grid((unsigned)((N + 255) / 256));
   EventScope timing(RADE_KERNEL_PROJECT_BWD, stream);
   const bool vec = ((reinterpret_cast<uintptr_t>(sh) | reinterpret_cast<uintptr_t>(d_sh)) & 15) == 0;
-#define RADE_PROJECT_BWD(K, V4)                                                             \
-  hipLaunchKernelGGL((k_project_bwd<K, V4>), grid, block, 0, stream, st, views, V, N, means, \
-                     scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats, d_opac, d_sh)
+#define RADE_PROJECT_BWD(K, V4)                                                               \
+  do {                                                                                        \
+    if (V == 1) {                                                                             \
+      hipLaunchKernelGGL((k_project_bwd<K, V4>), grid, block, 0, stream, st, views, V, N,      \
+                         means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats,   \
+                         d_opac, d_sh);                                                        \
+    } else {                                                                                  \
+      hipLaunchKernelGGL((k_project_bwd_geo<K, V4>), grid, block, 0, stream, st, views, V, N,  \
+                         means, scales, quats, opac, gsplat, d_means, d_scales, d_quats,       \
+                         d_opac);                                                              \
+      hipLaunchKernelGGL((k_project_bwd_sh<K, V4>), grid, block, 0, stream, st, views, V, N,  \
+                         means, scales, quats, opac, sh, gsplat, d_means, d_sh);             \
+    }                                                                                         \
+  } while (0)
   switch (st.sh_degree) {
     case 0: RADE_PROJECT_BWD(1, false); break;
     case 1: if (vec) RADE_PROJECT_BWD(4, true); else RADE_PROJECT_BWD(4, false); break;
