@@ -118,7 +118,10 @@ struct BwdArgs {
   float* gsplat;
 };
 
-template <int TW, int TH, int WW, int BT>
+// Q: an 8x8 tile held by one wave as four 16-lane groups, one per 4x4
+// quadrant: lane = 16 q + 4 y + x, quadrant q = 2 (y / 4) + x / 4 (one DPP
+// row of 16 lanes per quadrant).
+template <int TW, int TH, int WW, int BT, bool Q = false>
 __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
                                               const uint32_t* ranges, int64_t tile) {
   using TG = TileGeom<TW, TH, WW, BT>;
@@ -133,8 +136,14 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
   c.ox = c.x0 & ~(kOriginAlign - 1);
   c.oy = c.y0 & ~(kOriginAlign - 1);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  c.lxi = WW * (wave % TG::NWX) + (lane & (WW - 1));
-  c.lyi = TG::WH * (wave / TG::NWX) + (lane >> TG::LW);
+  if constexpr (Q) {
+    const int q = lane >> 4, i = lane & 15;
+    c.lxi = 4 * (q & 1) + (i & 3);
+    c.lyi = 4 * (q >> 1) + (i >> 2);
+  } else {
+    c.lxi = WW * (wave % TG::NWX) + (lane & (WW - 1));
+    c.lyi = TG::WH * (wave / TG::NWX) + (lane >> TG::LW);
+  }
   c.px = c.x0 + c.lxi;
   c.py = c.y0 + c.lyi;
   c.inside = c.px < vw.width && c.py < vw.height;
@@ -180,7 +189,7 @@ __device__ __forceinline__ bool block_reached(float ur, float vr, float w0, floa
 // Stage splat `idx` of the tile list into LDS slot `slot` and return the
 // bit set of wave blocks its support reaches (support rect first, then the
 // exact ellipse-against-block test).
-template <int TW, int TH, int WW, int BT, bool EXACT = false>
+template <int TW, int TH, int WW, int BT, bool EXACT = false, bool QL = false>
 __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats, int64_t vbase,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
                                           int slot, const PixelCtx& c, const BlendParams& bp,
@@ -233,7 +242,8 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     }
   }
   if constexpr (TG::LM) {
-    // Lane mask of the one 8x8 wave (lane = 8 y + x): per pixel row of the
+    // Lane mask of the one 8x8 wave (lane = 8 y + x, or with QL the
+    // quadrant layout of pixel_ctx<..., true>): per pixel row of the
     // support rect, the interval of the ellipse Q(dx, dy) <= tau2 along the
     // row, A dx^2 + 2 B dx dy + C dy^2 <= tau2, widened by a margin and
     // rounded outwards (conservative: the loops still test every pixel).
@@ -261,7 +271,16 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
           xl = max(xl, (int)ceilf(fmaxf(xc - half - m, -1.0f)));
           xh = min(xh, (int)floorf(fminf(xc + half + m, 8.0f)));
         }
-        if (xl <= xh) lm |= ((2ull << xh) - (1ull << xl)) << (8 * y);
+        if (xl <= xh) {
+          if constexpr (QL) {
+            // quadrant 2 (y / 4) and 2 (y / 4) + 1, row 4 (y % 4) in each
+            const int base = 32 * (y >> 2) + 4 * (y & 3);
+            if (xl <= 3) lm |= ((2ull << min(xh, 3)) - (1ull << xl)) << base;
+            if (xh >= 4) lm |= ((2ull << (xh - 4)) - (1ull << (max(xl, 4) - 4))) << (base + 16);
+          } else {
+            lm |= ((2ull << xh) - (1ull << xl)) << (8 * y);
+          }
+        }
       }
     }
     lmask[slot] = lm;
@@ -298,6 +317,21 @@ struct FwdShared {
   float4 xq[EXACT ? TG::BATCH : 1];
   float xh[EXACT ? TG::BATCH : 1];
 };
+
+// The 16-bit quadrant slices (quadrant layout of pixel_ctx<..., true>) of
+// the staged splats' lane masks that hold active lanes, as four chunk masks
+// (bit l: staged splat chunk * 64 + l), each lane keeping its own
+// quadrant's.  lm: the mask of the splat this lane staged-reads (slot
+// chunk * 64 + lane); act: the lanes still working.
+__device__ __forceinline__ uint64_t quadrant_chunk_mask(uint64_t lm, uint64_t act, uint64_t m) {
+  const uint64_t x = lm & act;
+  const uint64_t q0 = __builtin_amdgcn_ballot_w64((x & 0xFFFFull) != 0);
+  const uint64_t q1 = __builtin_amdgcn_ballot_w64((x & 0xFFFF0000ull) != 0);
+  const uint64_t q2 = __builtin_amdgcn_ballot_w64((x & 0xFFFF00000000ull) != 0);
+  const uint64_t q3 = __builtin_amdgcn_ballot_w64((x & 0xFFFF000000000000ull) != 0);
+  const int q = (threadIdx.x & 63) >> 4;
+  return m & (q == 0 ? q0 : q == 1 ? q1 : q == 2 ? q2 : q3);
+}
 
 // Forward blend of one tile (all threads of the workgroup take part).  DIST:
 // also the distortion map; CNT: also the blend-count and evaluation-count
@@ -530,6 +564,28 @@ __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
   return y;
 }
 
+// Sum 16 per-lane values over each 16-lane DPP row of the wave by
+// transpose-reduction (one level more than the last three of wave_sum16):
+// partners lane ^ 8 (row_ror:8), ^ 7 (row_half_mirror), ^ 1 and ^ 2
+// (quad_perm), each level keeping half of the values (by the lane bit the
+// partner differs in) and adding the partner's copy of them; the partner
+// offsets reach all 16 lanes of the row once.  On return lane i of a row
+// holds the row's total of value 8 b3 + 4 b2 + 2 b0 + b1 (b_k: bit k of i).
+__device__ __forceinline__ float row_sum16(const float (&v)[16]) {
+  const int l = (int)threadIdx.x;
+  const bool b3 = (l & 8) != 0, b2 = (l & 4) != 0, b1 = (l & 2) != 0, b0 = (l & 1) != 0;
+  float u[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) u[k] = (b3 ? v[k + 8] : v[k]) + dpp<0x128>(b3 ? v[k] : v[k + 8]);
+  float w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = (b2 ? u[k + 4] : u[k]) + dpp<0x141>(b2 ? u[k] : u[k + 4]);
+  float x[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) x[k] = (b0 ? w[k + 2] : w[k]) + dpp<0xB1>(b0 ? w[k] : w[k + 2]);
+  return (b1 ? x[1] : x[0]) + dpp<0x4E>(b1 ? x[0] : x[1]);
+}
+
 template <int TW, int TH, int WW, int BT>
 struct BwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
@@ -542,11 +598,170 @@ struct BwdShared {
   int smax;
 };
 
+// Backward pass of one 8x8 tile by one wave as four 16-lane groups, one per
+// 4x4 quadrant (pixel_ctx<..., true>): each group walks, from the back, the
+// staged splats whose lane mask reaches its pixels that blend at or after
+// them, so one step of the wave can take a different splat in every
+// quadrant (splats that reach few pixels leave most of a 64-lane step idle
+// otherwise), and each group's 15 sums come out of one 16-lane reduction.
+// Per pixel the splats, their order and the operations are those of
+// bwd_tile.  (The forward keeps one splat per step: its per-splat work is
+// small enough that the per-lane bookkeeping of four streams costs more
+// than it saves.)
+template <int BT>
+__device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
+                                           BwdShared<8, 8, 8, BT>& sh) {
+  using TG = TileGeom<8, 8, 8, BT>;
+  const BlendParams& bp = a.bp;
+  const rade_splat* __restrict__ splats = a.splats;
+  const uint32_t* __restrict__ pair_ids = a.pair_ids;
+  float* __restrict__ gsplat = a.gsplat;
+  StagedSplat* ss = sh.ss;
+  StagedForm* sf = sh.sf;
+  StagedRem* sr = sh.sr;
+  uint32_t* sgid = sh.sgid;
+  const PixelCtx c = pixel_ctx<8, 8, 8, BT, true>(a.views, a.V, a.ranges, tile);
+  const int lane = threadIdx.x & 63;
+  const int64_t vbase = (int64_t)c.v * a.N;
+  // the lane's pixel centre relative to the origin's (exact in FP32)
+  const float fx = (float)(c.px - c.ox), fy = (float)(c.py - c.oy);
+
+  float T = 0.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gM = 0.f;
+  float gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gA = 0.f;
+  int lastp = -1, med = -1;
+  if (c.inside) {
+    const int64_t P = c.P, pix = c.pix;
+    T = a.t_final[c.poff + pix];
+    lastp = a.last[c.poff + pix];
+    med = a.median[c.poff + pix];
+    if (a.d_color) {
+      gC0 = a.d_color[3 * c.poff + pix];
+      gC1 = a.d_color[3 * c.poff + P + pix];
+      gC2 = a.d_color[3 * c.poff + 2 * P + pix];
+    }
+    if (a.d_depth) { gD = a.d_depth[2 * c.poff + pix]; gM = a.d_depth[2 * c.poff + P + pix]; }
+    if (a.d_normal) {
+      gN0 = a.d_normal[3 * c.poff + pix];
+      gN1 = a.d_normal[3 * c.poff + P + pix];
+      gN2 = a.d_normal[3 * c.poff + 2 * P + pix];
+    }
+    if (a.d_alpha) gA = a.d_alpha[c.poff + pix];
+  }
+  float Racc = T * (gC0 * bp.bg[0] + gC1 * bp.bg[1] + gC2 * bp.bg[2]);
+
+  // the furthest last blend of the wave and of the lane's quadrant
+  int wlast = lastp;
+#pragma unroll
+  for (int d = 8; d >= 1; d >>= 1) wlast = max(wlast, __shfl_xor(wlast, d, 64));
+  const int qlast = wlast;
+  wlast = max(wlast, __shfl_xor(wlast, 16, 64));
+  wlast = max(wlast, __shfl_xor(wlast, 32, 64));
+  wlast = __builtin_amdgcn_readfirstlane(wlast);
+  // records to visit: up to the furthest last blend of the tile (clamped to
+  // the list length in case the saved state does not match the lists)
+  const int nrec = min(wlast + 1, (int)(c.re - c.rb));
+  // the sums a lane carries to the splat's record (row_sum16's order)
+  const int vi = 8 * ((lane >> 3) & 1) + 4 * ((lane >> 2) & 1) + 2 * (lane & 1) + ((lane >> 1) & 1);
+
+  for (int bend = nrec; bend > 0; bend -= TG::BATCH) {
+    const int bstart = bend > TG::BATCH ? bend - TG::BATCH : 0;
+#pragma unroll
+    for (int k = 0; k < (TG::BATCH + TG::BLOCK - 1) / TG::BLOCK; ++k) {
+      const int slot = (int)threadIdx.x + k * TG::BLOCK;
+      if (TG::BATCH % TG::BLOCK != 0 && slot >= TG::BATCH) break;  // wave-uniform
+      const int li = bstart + slot;
+      uint32_t bits = 0;
+      if (li < bend)
+        bits = stage<8, 8, 8, BT, false, true>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot,
+                                               c, bp, ss, sf, sr, sgid, sh.lmask);
+      publish_masks<8, 8, 8, BT>(bits, slot >> 6, sh.masks);
+    }
+    __syncthreads();
+    for (int cw = TG::NCH - 1; cw >= 0; --cw) {
+      const int lo = bstart + cw * 64;  // the chunk's first position
+      if (wlast < lo) continue;         // nothing at or below a last blend
+      // the chunk's splats that reach a pixel of the quadrant blending at
+      // the chunk's first position or later, at positions up to the
+      // quadrant's furthest last blend
+      uint64_t mg = quadrant_chunk_mask(sh.lmask[cw * 64 + lane],
+                                        __builtin_amdgcn_ballot_w64(lo <= lastp),
+                                        uniform_u64(sh.masks[0][cw]));
+      const int ql = qlast - lo;
+      mg = ql < 0 ? 0ull : ql < 63 ? mg & ((2ull << ql) - 1) : mg;
+      for (;;) {
+        const bool work = mg != 0;
+        if (!__any(work)) break;
+        int j = 0;
+        if (work) {
+          j = 63 - __builtin_clzll(mg);
+          mg &= ~(1ull << j);
+        }
+        const int r = cw * 64 + j;
+        const int pos = lo + j;
+        const float4* s4 = reinterpret_cast<const float4*>(ss + r);
+        const float4 q0 = s4[0], q1 = s4[1], q2 = s4[2], q3 = s4[3];
+        const StagedSplat s{q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+        const StagedForm f = sf[r];
+        const StagedRem rm = sr[r];
+        const int gid = (int)sgid[r];
+        const float dx = s.ur - fx, dy = s.vr - fy;
+        float t1, t2, e, al;
+        bool cl;
+        const bool has =
+            work && splat_alpha(s, f, dx, dy, bp, t1, t2, e, al, cl) && pos <= lastp;
+        if (!__any(has)) continue;
+        // the operations of bwd_tile's branch-free adjoint (lanes of a
+        // quadrant without a splat this step read slot cw * 64, a staged
+        // one, and contribute zeros to their own row only)
+        const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+        const float Ti = T * inv;
+        const float w = al * Ti;
+        const float d = fmaf(s.p1, dy, fmaf(s.p0, dx, s.zc));
+        const float ex = dx + rm.ul, ey = dy + rm.vl;
+        float sfm = fmaf(gC0, s.r, gA);
+        sfm = fmaf(gC1, s.g, sfm);
+        sfm = fmaf(gC2, s.b, sfm);
+        sfm = fmaf(gD, d, sfm);
+        sfm = fmaf(gN0, s.n0, sfm);
+        sfm = fmaf(gN1, s.n1, sfm);
+        sfm = fmaf(gN2, s.n2, sfm);
+        const float ga = fmaf(Ti, sfm, -(Racc * inv));
+        T = has ? Ti : T;
+        Racc = has ? fmaf(w, sfm, Racc) : Racc;
+        const float wg = has ? w : 0.0f;
+        const float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
+        const float gop = (has && !cl) ? ga * e : 0.0f;
+        float g[16];
+        g[0] = gop * fmaf(t1, s.w0, t2 * s.w2);
+        g[1] = gop * fmaf(t1, s.w1, t2 * s.w3);
+        const float gpx = gop * ex;
+        g[2] = gpx * ex;
+        g[3] = gpx * ey;
+        g[4] = (gop * ey) * ey;
+        g[5] = gop;
+        g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
+        g[9] = gd;
+        g[10] = gd * ex; g[11] = gd * ey;
+        g[12] = wg * gN0; g[13] = wg * gN1; g[14] = wg * gN2;
+        g[15] = 0.0f;
+        const float tot = row_sum16(g);
+        if (work && vi < 15 && tot != 0.0f) atomicAdd(gsplat + (vbase + gid) * 16 + vi, tot);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Backward pass of one tile (all threads of the workgroup take part).
 template <int TW, int TH, bool DIST, int WW, int BT>
 __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
                                          BwdShared<TW, TH, WW, BT>& sh) {
   using TG = TileGeom<TW, TH, WW, BT>;
+  if constexpr (TG::LM && !DIST) {
+    bwd_tile_q<BT>(a, tile, sh);
+    return;
+  }
   const BlendParams& bp = a.bp;
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
