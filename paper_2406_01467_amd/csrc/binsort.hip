@@ -61,10 +61,12 @@ struct VisibleOut {
   }
 };
 
-// Tiles touched by the j-th depth-sorted splat (its record's count).
+// Tiles touched by the j-th depth-sorted splat (its record's count, which
+// the depth sort's last pass also writes to an array of its own, so the
+// scans read 4 bytes per splat rather than the 16-byte records).
 struct SortedCount {
-  const uint4* recs;
-  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)recs[j].w; }
+  const uint32_t* cnt;
+  __device__ uint64_t operator()(int64_t j) const { return (uint64_t)cnt[j]; }
 };
 // Total pair count: stored as 64 bits, as the count the tile sort processes
 // (0 when it exceeds the capacity, so nothing is written) and as the
@@ -229,14 +231,16 @@ struct RankShared {
 // into each other).  The block is then sorted in LDS and each digit's run
 // written contiguously at its region start plus the row-scanned count of
 // the blocks before this one.  GATHER: each item also carries the record
-// gsrc[value] (values index gsrc), written to gout in the sorted order.
+// gsrc[value] (values index gsrc), written to gout in the sorted order, and
+// its last word to cout.
 template <bool GATHER>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int64_t n_max, int shift, int64_t nblocks,
                 const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot,
-                const uint4* __restrict__ gsrc, uint4* __restrict__ gout) {
+                const uint4* __restrict__ gsrc, uint4* __restrict__ gout,
+                uint32_t* __restrict__ cout) {
   __shared__ RankShared sh;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t base = blk * kTile;
@@ -309,7 +313,11 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
       const uint32_t dst = sh.dbase[d] + ((uint32_t)i - sh.lstart[d]);
       kout[dst] = k;
       vout[dst] = v;
-      if constexpr (GATHER) gout[dst] = gsrc[v];
+      if constexpr (GATHER) {
+        const uint4 rec = gsrc[v];
+        gout[dst] = rec;
+        cout[dst] = rec.w;
+      }
     }
   }
 }
@@ -447,6 +455,10 @@ __device__ __forceinline__ void range_edge(uint32_t* __restrict__ ranges, int64_
   }
 }
 
+// Keys per thread of k_ranges (four 16-byte loads; consecutive threads take
+// consecutive runs, so a thread's previous key is its left neighbour's last).
+constexpr int kRangeKeys = 16;
+
 __global__ void __launch_bounds__(kThreads)
 k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32, int64_t tiles,
          uint32_t* __restrict__ ranges) {
@@ -459,19 +471,28 @@ k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32, i
     }
     return;
   }
-  const int64_t i0 = 4 * g;
-  if (i0 > m) return;
-  uint32_t k[4];
-  if (i0 + 4 <= m) {  // tkeys is 16-byte aligned
-    const uint4 q = *reinterpret_cast<const uint4*>(tkeys + i0);
-    k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+  const int64_t i0 = (int64_t)kRangeKeys * g;
+  uint32_t k[kRangeKeys];
+  if (i0 + kRangeKeys <= m) {  // tkeys is 16-byte aligned
+#pragma unroll
+    for (int q = 0; q < kRangeKeys / 4; ++q) {
+      const uint4 v = *reinterpret_cast<const uint4*>(tkeys + i0 + 4 * q);
+      k[4 * q] = v.x; k[4 * q + 1] = v.y; k[4 * q + 2] = v.z; k[4 * q + 3] = v.w;
+    }
   } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) k[r] = i0 + r < m ? tkeys[i0 + r] : 0u;
+    for (int r = 0; r < kRangeKeys; ++r) k[r] = i0 + r < m ? tkeys[i0 + r] : 0u;
   }
-  int64_t prev = i0 > 0 ? (int64_t)tkeys[i0 - 1] : -1;
+  // the previous key: the left lane's last one (whole waves take part in
+  // the shuffle; lane 0 of a wave reads it)
+  const uint32_t left = (uint32_t)__shfl_up((int)k[kRangeKeys - 1], 1, 64);
+  if (i0 > m) return;
+  int64_t prev;
+  if (i0 == 0) prev = -1;
+  else if ((threadIdx.x & 63) != 0) prev = (int64_t)left;
+  else prev = (int64_t)tkeys[i0 - 1];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < kRangeKeys; ++r) {
     const int64_t i = i0 + r;
     if (i > m) break;
     const int64_t cur = i < m ? (int64_t)k[r] : tiles;
@@ -522,11 +543,12 @@ inline SortSpace sort_space(char* w, int64_t n_max) {
 // number of passes is even, else in (k1, v1).  Returns the number of passes.
 // first_counted: the first pass's per-block counts are already in sp.hist.
 // gsrc: the last pass also writes the record gsrc[value] of every item (the
-// values index gsrc), in the sorted order, to gout.
+// values index gsrc), in the sorted order, to gout, and its last word to
+// cout.
 int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
                const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
                bool first_counted = false, const uint4* gsrc = nullptr,
-               uint4* gout = nullptr) {
+               uint4* gout = nullptr, uint32_t* cout = nullptr) {
   const int64_t nb = sort_blocks(n_max);
   const int passes = bits > kRadixBits ? (bits + kRadixBits - 1) / kRadixBits : 1;
   for (int p = 0; p < passes; ++p) {
@@ -542,17 +564,19 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n
     if (gsrc && p == passes - 1)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi,
                          ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
-                         (const uint32_t*)sp.dtot, gsrc, gout);
+                         (const uint32_t*)sp.dtot, gsrc, gout, cout);
     else
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki,
                          vi, ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
-                         (const uint32_t*)sp.dtot, (const uint4*)nullptr, (uint4*)nullptr);
+                         (const uint32_t*)sp.dtot, (const uint4*)nullptr, (uint4*)nullptr,
+                         (uint32_t*)nullptr);
   }
   return passes;
 }
 
 struct Layout {
-  size_t starts, dkeys0, dvals0, dkeys1, dvals1, crec, drec, offs, tkeys0, tkeys1, pids1, sort, sums, scal;
+  size_t starts, dkeys0, dvals0, dkeys1, dvals1, crec, drec, dcnt, offs, tkeys0, tkeys1, pids1,
+      sort, sums, scal;
   size_t total;
 };
 
@@ -574,6 +598,7 @@ Layout layout(int64_t VN, int64_t capacity) {
   L.dvals1 = take(sizeof(uint32_t) * VN);
   L.crec = take(sizeof(uint4) * VN);
   L.drec = take(sizeof(uint4) * VN);
+  L.dcnt = take(sizeof(uint32_t) * VN);
   L.offs = take(sizeof(uint64_t) * VN);
   L.tkeys0 = take(sizeof(uint32_t) * capacity);
   L.tkeys1 = take(sizeof(uint32_t) * capacity);
@@ -714,6 +739,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* dv1 = (uint32_t*)(w + L.dvals1);
   uint4* crec = (uint4*)(w + L.crec);
   uint4* drec = (uint4*)(w + L.drec);
+  uint32_t* dcnt = (uint32_t*)(w + L.dcnt);
   uint64_t* offs = (uint64_t*)(w + L.offs);
   uint32_t* tk0 = (uint32_t*)(w + L.tkeys0);
   uint32_t* tk1 = (uint32_t*)(w + L.tkeys1);
@@ -737,10 +763,11 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, n_vis, 1, 0u);
   }
   // 2. depth sort
-  radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st, false, crec, drec);
+  radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st, false, crec, drec,
+             dcnt);
   // 3. pair offsets in depth order (and the pair counts)
   if (VN > 0) {
-    scan_to<uint64_t>(SortedCount{drec}, VN, n_vis,
+    scan_to<uint64_t>(SortedCount{dcnt}, VN, n_vis,
                       OffsetsOut{offs, starts, (capacity + kEmitPairs - 1) / kEmitPairs},
                       (uint64_t*)sums, PairsTotal{m64, m32, capacity, n_pairs_dev}, st);
   } else {
@@ -783,8 +810,8 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;
   // 6. tile ranges
   if (capacity > 0)
-    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(capacity + 1, 4 * kThreads)), dim3(kThreads), 0,
-                       st, sk, m32, total_tiles, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(capacity + 1, kRangeKeys * kThreads)),
+                       dim3(kThreads), 0, st, sk, m32, total_tiles, ranges);
   else
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * total_tiles, kThreads)), dim3(kThreads), 0,
                        st, ranges, 2 * total_tiles, 0u);
