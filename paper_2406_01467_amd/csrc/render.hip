@@ -220,45 +220,40 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
     if (rx0 <= bx + WW - 1 && rx1 >= bx && ry0 <= by + TG::WH - 1 && ry1 >= by) bits |= 1u << k;
   }
+  uint64_t lm = 0;
   if (bits) {
-    // drop the blocks the ellipse misses (also when the rect touches a
-    // single block: one test per staged pair is far cheaper than a wave
-    // iteration over a splat that reaches none of its pixels).
     // Support: power <= cut and opacity 2^-power >= alpha_min.
     const float A = fmaf(s.w0, s.w0, s.w2 * s.w2), B = fmaf(s.w0, s.w1, s.w2 * s.w3);
     const float C = fmaf(s.w1, s.w1, s.w3 * s.w3);
-    const float invA = A > 0.0f ? 1.0f / A : 0.0f, invC = C > 0.0f ? 1.0f / C : 0.0f;
+    const float invA = A > 0.0f ? 1.0f / A : 0.0f;
     const float lo = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
     const float tau2 = fminf(bp.cut2, lo) * 1.001f + 0.01f;
     // centre relative to the tile's first pixel (x0 - ox is a small integer:
     // exact), so the block offsets below are compile-time constants
     const float ut = s.ur - (float)(c.x0 - c.ox), vt = s.vr - (float)(c.y0 - c.oy);
+    if constexpr (!TG::LM) {
+      // drop the blocks the ellipse misses (also when the rect touches a
+      // single block: one test per staged pair is far cheaper than a wave
+      // iteration over a splat that reaches none of its pixels)
+      const float invC = C > 0.0f ? 1.0f / C : 0.0f;
 #pragma unroll
-    for (int k = 0; k < TG::NW; ++k) {
-      const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
-      if (((bits >> k) & 1u) && !block_reached(ut, vt, s.w0, s.w1, s.w2, s.w3, A, B, C, invA,
-                                               invC, tau2, bx, by, WW, TG::WH))
-        bits &= ~(1u << k);
-    }
-  }
-  if constexpr (TG::LM) {
-    // Lane mask of the one 8x8 wave (lane = 8 y + x, or with QL the
-    // quadrant layout of pixel_ctx<..., true>): per pixel row of the
-    // support rect, the interval of the ellipse Q(dx, dy) <= tau2 along the
-    // row, A dx^2 + 2 B dx dy + C dy^2 <= tau2, widened by a margin and
-    // rounded outwards (conservative: the loops still test every pixel).
-    uint64_t lm = 0;
-    if (bits) {
+      for (int k = 0; k < TG::NW; ++k) {
+        const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
+        if (((bits >> k) & 1u) && !block_reached(ut, vt, s.w0, s.w1, s.w2, s.w3, A, B, C, invA,
+                                                 invC, tau2, bx, by, WW, TG::WH))
+          bits &= ~(1u << k);
+      }
+    } else {
+      // Lane mask of the one 8x8 wave (lane = 8 y + x, or with QL the
+      // quadrant layout of pixel_ctx<..., true>), which also stands for the
+      // block test: per pixel row of the support rect, the interval of the
+      // ellipse A dx^2 + 2 B dx dy + C dy^2 <= tau2 along the row, widened
+      // by a margin and rounded outwards (conservative: the loops still test
+      // every pixel).
       const int x0 = max(rx0, 0), x1 = min(rx1, 7), y0 = max(ry0, 0), y1 = min(ry1, 7);
-      const float A = fmaf(s.w0, s.w0, s.w2 * s.w2), B = fmaf(s.w0, s.w1, s.w2 * s.w3);
-      const float C = fmaf(s.w1, s.w1, s.w3 * s.w3);
-      const float invA = A > 0.0f ? 1.0f / A : 0.0f;
-      const float lo2 = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
-      const float tau2 = fminf(bp.cut2, lo2) * 1.001f + 0.01f;
       // the Gram determinant A C - B^2 >= 0, lowered by more than its FP32
       // rounding (a lower value only widens the intervals)
       const float det = fmaxf(fmaf(A, C, -(B * B)) - 4e-7f * (A * C), 0.0f);
-      const float ut = s.ur - (float)(c.x0 - c.ox), vt = s.vr - (float)(c.y0 - c.oy);
       for (int y = y0; y <= y1; ++y) {
         const float dy = vt - (float)y;
         const float disc = fmaf(-det, dy * dy, A * tau2);
@@ -283,6 +278,8 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
         }
       }
     }
+  }
+  if constexpr (TG::LM) {
     lmask[slot] = lm;
     if (!lm) bits = 0;
   }
