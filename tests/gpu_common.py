@@ -45,7 +45,9 @@ def gpu_forward(scene, views, settings, dev, keep=True):
     from paper_2406_01467_amd.raster import Rasterizer
     rast = Rasterizer(views, settings, dev)
     params = to_dev(scene, dev)
-    maps = rast.forward(*params, want_count=True, keep_splats=keep)
+    # the counting pass exists for the default wave shape and batch only
+    count = settings.batch == 0 and settings.wave_w == 0
+    maps = rast.forward(*params, want_count=count, keep_splats=keep)
     torch.cuda.synchronize()
     per_view = []
     pair_ids = maps.state.pair_ids.cpu().numpy().astype(np.int64)

@@ -335,6 +335,9 @@ def test_lane_masks_keep_every_blend_of_needle_splats():
     s8 = _settings(sh_degree=3, tile_w=8, tile_h=8, schedule=1)
     _full_parity(scene, views, s8, "needles 8x8")
     _bwd_parity(scene, views, s8, 42, "bwd needles 8x8")
+    # four 64-splat chunks per staging round in the quadrant backward
+    _bwd_parity(scene, views, _settings(sh_degree=3, tile_w=8, tile_h=8, schedule=1, batch=256),
+                43, "bwd needles 8x8 batch 256")
     _bwd_parity(scene, views, _settings(sh_degree=3, schedule=1), 42, "bwd needles 16x16")
 
 

@@ -77,7 +77,9 @@ def test_gradients_agree_across_shapes():
     P = views[0].pixels
     ups = [rng.normal(size=k * P).astype(np.float32) for k in (3, 2, 3, 1)]
     ref = None
-    for tile in [(16, 16), (32, 16)]:
+    # 8x8 tiles take the quadrant-group backward (one, two or four 64-splat
+    # chunks per staging round)
+    for tile in [(16, 16), (32, 16), (8, 8)]:
         for ww, bt in _shapes(*tile):
             rast = Rasterizer(views, _settings(sh_degree=3, tile_w=tile[0], tile_h=tile[1],
                                                wave_w=ww, batch=bt), dev)
