@@ -564,8 +564,8 @@ __device__ __forceinline__ void project_bwd_body(
     }
     // the power gradient is -o g_o: the per-Gaussian factor of the
     // footprint terms
-    const double mo = -(double)P.o, mok = mo * (2.0 / kLog2eD);
-    const double guc = ga.x * mok, gvc = ga.y * mok, gA = ga.z * mo, gB = ga.w * mo;
+    const double mo = -(double)P.o;
+    const double gA = ga.z * mo, gB = ga.w * mo;
     const double gC = gb.x * mo, gO = gb.y;
     const double gZd = gc.y, gp0 = gc.z, gp1 = gc.w;
     const double gn0 = gd.x, gn1 = gd.y, gn2 = gd.z;
@@ -589,6 +589,11 @@ __device__ __forceinline__ void project_bwd_body(
     // plane depth z + p . (u_c - u) moves with the centre by p, so that share
     // is p times the summed depth gradient
     const double zt = Z / tc;
+    // the centre's share through the footprint: the first moments of the
+    // offset times the conic (the inverse of the dilated footprint D)
+    const double idt = 1.0 / G.detD;
+    const double qa = G.D11 * idt, qb = -G.B01 * idt, qc = G.D00 * idt;
+    const double guc = mo * (qa * ga.x + qb * ga.y), gvc = mo * (qb * ga.x + qc * ga.y);
     const double gu = guc + zt * G.q0 * gZd, gv = gvc + zt * G.q1 * gZd;
     double gx[3];
     gx[0] = gu * v.fx * iz;

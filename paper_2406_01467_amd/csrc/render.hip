@@ -730,12 +730,11 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
         const float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         const float gop = (has && !cl) ? ga * e : 0.0f;
         float g[16];
-        g[0] = gop * fmaf(t1, s.w0, t2 * s.w2);
-        g[1] = gop * fmaf(t1, s.w1, t2 * s.w3);
-        const float gpx = gop * ex;
+        const float gpx = gop * ex, gpy = gop * ey;
+        g[0] = gpx; g[1] = gpy;
         g[2] = gpx * ex;
         g[3] = gpx * ey;
-        g[4] = (gop * ey) * ey;
+        g[4] = gpy * ey;
         g[5] = gop;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;
@@ -899,22 +898,22 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         if constexpr (DIST) gd = fmaf(kdist * wg, d - mdist, gd);
         // opacity gradient ga e.  Where alpha is not clamped, alpha = o e, so
-        // the power gradient is -ga alpha = -o (ga e): the footprint terms
-        // below are sums of products with ga e, and the projection backward
-        // applies the per-Gaussian factor -o (times 2 / log2(e) for the
-        // centre, since d power / d(dx, dy) = (t1 w0 + t2 w2, t1 w1 + t2 w3)
-        // 2 / log2(e)).
+        // the gradient of the power p = (dx, dy) Q (dx, dy)^T / 2 (Q the
+        // conic) is -ga alpha = -o (ga e): the footprint terms below are
+        // sums of ga e times the moments 1, dx, dy, dx^2, dx dy, dy^2 of the
+        // offset, and the projection backward applies the per-Gaussian
+        // factor -o and, for the centre, the conic (d p / d(dx, dy) =
+        // Q (dx, dy)^T).
         const float gop = (has && !cl) ? ga * e : 0.0f;
         float g[16];
-        // centre gradient through the footprint; the depth plane's share,
-        // p times the summed g[9], is added by the projection backward
-        g[0] = gop * fmaf(t1, s.w0, t2 * s.w2);
-        g[1] = gop * fmaf(t1, s.w1, t2 * s.w3);
-        // conic terms: sums of ga e dx^2, ga e dx dy, ga e dy^2
-        const float gpx = gop * ex;
+        // first moments (centre gradient through the footprint; the depth
+        // plane's share, p times the summed g[9], is added by the
+        // projection backward) and second moments (conic terms)
+        const float gpx = gop * ex, gpy = gop * ey;
+        g[0] = gpx; g[1] = gpy;
         g[2] = gpx * ex;
         g[3] = gpx * ey;
-        g[4] = (gop * ey) * ey;
+        g[4] = gpy * ey;
         g[5] = gop;
         g[6] = wg * gC0; g[7] = wg * gC1; g[8] = wg * gC2;
         g[9] = gd;
