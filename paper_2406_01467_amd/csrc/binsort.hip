@@ -28,6 +28,10 @@ constexpr int kItems = kScanItems;              // items per thread
 constexpr int kTile = kScanTile;                // items per block (2048)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+// Widest digit of a pass: 9 bits where that saves a pass (17 or 18 key bits,
+// e.g. the tile keys of many views of small tiles, sort in two 9-bit passes
+// instead of three 8-bit ones).
+constexpr int kMaxRadix = 512;
 
 constexpr int kEmitPairs = kTile;                // pairs per emission block (one radix block)
 
@@ -100,18 +104,20 @@ struct OffsetsOut {
 };
 
 // ---------------------------------------------------------------------------
-// LSD radix sort, 8-bit digits, stable.  Each pass counts the digits of
-// every block of kTile consecutive items (k_radix_hist, counts stored
-// digit-major: hist[d * nblocks + block]), scans each digit's row of counts
-// (k_radix_colscan) and scatters (k_radix_scatter).
+// LSD radix sort, RB-bit digits (8, or 9 where that saves a pass), stable.
+// Each pass counts the digits of every block of kTile consecutive items
+// (k_radix_hist, counts stored digit-major: hist[d * nblocks + block]), scans
+// each digit's row of counts (k_radix_colscan) and scatters
+// (k_radix_scatter).
 //
 // Workgroups are dealt to the XCDs round-robin, so the sort kernels remap
 // the workgroup index to a block index such that each XCD takes one
 // contiguous run of blocks: the counts of neighbouring blocks (which share
 // cache lines of the digit-major rows) then meet in one L2 instead of up to
 // eight.
+template <int RB = kRadixBits>
 __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
-  return (k >> shift) & (kRadix - 1);
+  return (k >> shift) & ((1u << RB) - 1u);
 }
 
 constexpr int kXcds = 8;
@@ -128,7 +134,8 @@ __device__ __forceinline__ int64_t xcd_block(int64_t wg, int64_t grid) {
 // per wave, round after round, and combined across waves in wave order are
 // stable.  All loads of a thread are issued before any ranking.
 constexpr int kWaves = kThreads / 64;
-static_assert(kRadix == kThreads, "one digit per thread in the block-wide steps");
+static_assert(kRadix == kThreads && kMaxRadix == 2 * kThreads,
+              "one or two digits per thread in the block-wide steps");
 
 __device__ __forceinline__ int64_t item_index(int64_t base, int r) {
   return base + (int64_t)(threadIdx.x >> 6) * (64 * kItems) + (int64_t)r * 64 +
@@ -139,11 +146,12 @@ __device__ __forceinline__ int64_t item_index(int64_t base, int r) {
 // digit bit, each lane keeping the lanes that agree with its own bit.  With
 // s = 0 or ~0 from the lane's bit, the lanes that agree are ~(m ^ s); the
 // halves are kept apart so the selection stays a few 32-bit logic ops.
+template <int RB = kRadixBits>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   const uint64_t v = __ballot(valid);
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
-  for (int b = 0; b < kRadixBits; ++b) {
+  for (int b = 0; b < RB; ++b) {
     const uint32_t s = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
     const uint64_t m = __builtin_amdgcn_ballot_w64(s != 0u);
     lo &= ~((uint32_t)m ^ s);
@@ -159,10 +167,12 @@ __device__ __forceinline__ uint64_t lanes_below() {
 
 // Per-block digit counts (LDS atomics; lanes that hit one counter are
 // serialised by the LDS, not by vector instructions).
+template <int RB>
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
              int64_t n_max, int shift, int64_t nblocks, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRadix];
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t h[R];
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t base = blk * kTile;
   // the loads are bounded by the buffer size, so they need not wait for
@@ -174,17 +184,19 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
     key[r] = i < n_max ? keys[i] : 0u;
   }
   const int64_t n = *n_dev;
-  h[threadIdx.x] = 0;
+#pragma unroll
+  for (int d = threadIdx.x; d < R; d += kThreads) h[d] = 0;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r)
-    if (item_index(base, r) < n) atomicAdd(&h[digit_of(key[r], shift)], 1u);
+    if (item_index(base, r) < n) atomicAdd(&h[digit_of<RB>(key[r], shift)], 1u);
   __syncthreads();
-  if (threadIdx.x < kRadix) hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
+#pragma unroll
+  for (int d = threadIdx.x; d < R; d += kThreads) hist[(int64_t)d * nblocks + blk] = h[d];
 }
 
 // Exclusive scan of one digit's row of per-block counts (one workgroup per
-// digit) and the digit's total.  Together with the scan of the 256 totals
+// digit) and the digit's total.  Together with the scan of the digit totals
 // in the scatter's prologue this replaces a global scan of the whole count
 // matrix.
 __global__ void __launch_bounds__(kThreads)
@@ -213,10 +225,11 @@ k_radix_colscan(uint32_t* __restrict__ hist, int64_t nblocks, uint32_t* __restri
 }
 
 // Shared memory of one sorting workgroup.
+template <int R>
 struct RankShared {
-  uint32_t wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave digit starts
-  uint32_t lstart[kRadix];        // first local position of each digit
-  uint32_t dbase[kRadix];         // global position of each digit's run
+  uint32_t wcnt[kWaves][R];  // per-wave digit counts, then per-wave digit starts
+  uint32_t lstart[R];        // first local position of each digit
+  uint32_t dbase[R];         // global position of each digit's run
   uint32_t skey[kTile];
   uint32_t sval[kTile];
   uint64_t lw[kWaves];
@@ -232,8 +245,9 @@ struct RankShared {
 // written contiguously at its region start plus the row-scanned count of
 // the blocks before this one.  GATHER: each item also carries the record
 // gsrc[value] (values index gsrc), written to gout in the sorted order, and
-// its last word to cout.
-template <bool GATHER>
+// its last word to cout.  Thread t takes digits DPT t .. DPT t + DPT - 1 in
+// the block-wide steps (DPT = 2 for 9-bit digits).
+template <bool GATHER, int RB>
 __global__ void __launch_bounds__(kThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -241,7 +255,8 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
                 const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ dtot,
                 const uint4* __restrict__ gsrc, uint4* __restrict__ gout,
                 uint32_t* __restrict__ cout) {
-  __shared__ RankShared sh;
+  constexpr int R = 1 << RB, DPT = R / kThreads;
+  __shared__ RankShared<R> sh;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t base = blk * kTile;
   const int lane = threadIdx.x & 63;
@@ -256,19 +271,24 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     key[r] = inb ? kin[i] : 0u;
     val[r] = inb ? vin[i] : 0u;
   }
-  const uint32_t dtot_d = dtot[threadIdx.x];
-  const uint32_t goff_d = offsets[(int64_t)threadIdx.x * nblocks + blk];
+  uint32_t dtot_d[DPT], goff_d[DPT];
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int d = DPT * (int)threadIdx.x + k;
+    dtot_d[k] = dtot[d];
+    goff_d[k] = offsets[(int64_t)d * nblocks + blk];
+  }
   const int64_t n = *n_dev;
   if (base >= n) return;  // uniform per block
   uint32_t* wc = sh.wcnt[wave];
 #pragma unroll
-  for (int k = 0; k < kRadix / 64; ++k) wc[k * 64 + lane] = 0;
+  for (int k = 0; k < R / 64; ++k) wc[k * 64 + lane] = 0;
   const uint64_t lt = lanes_below();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const bool valid = item_index(base, r) < n;
-    const uint32_t d = digit_of(key[r], shift);
-    const uint64_t peers = digit_peers(d, valid);
+    const uint32_t d = digit_of<RB>(key[r], shift);
+    const uint64_t peers = digit_peers<RB>(d, valid);
     // LDS operations of one wave complete in issue order; the leader's
     // store depends on the value every lane read
     const uint32_t pre = wc[d];
@@ -277,25 +297,35 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
   }
   __syncthreads();
   {
-    const int d = threadIdx.x;
-    uint32_t c = 0;
+    uint64_t dc[DPT], sum = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t x = sh.wcnt[w][d];
-      sh.wcnt[w][d] = c;
-      c += x;
+    for (int k = 0; k < DPT; ++k) {
+      const int d = DPT * (int)threadIdx.x + k;
+      uint32_t c = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t x = sh.wcnt[w][d];
+        sh.wcnt[w][d] = c;
+        c += x;
+      }
+      dc[k] = ((uint64_t)dtot_d[k] << 32) | c;
+      sum += dc[k];
     }
     uint64_t tot;
-    const uint64_t ex =
-        block_exclusive_scan<uint64_t>(((uint64_t)dtot_d << 32) | c, sh.lw, tot);
-    sh.lstart[d] = (uint32_t)ex;
-    sh.dbase[d] = (uint32_t)(ex >> 32) + goff_d;
+    uint64_t ex = block_exclusive_scan<uint64_t>(sum, sh.lw, tot);
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      const int d = DPT * (int)threadIdx.x + k;
+      sh.lstart[d] = (uint32_t)ex;
+      sh.dbase[d] = (uint32_t)(ex >> 32) + goff_d[k];
+      ex += dc[k];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     if (item_index(base, r) < n) {
-      const uint32_t d = digit_of(key[r], shift);
+      const uint32_t d = digit_of<RB>(key[r], shift);
       const uint32_t p = pos[r] + sh.lstart[d] + sh.wcnt[wave][d];
       sh.skey[p] = key[r];
       sh.sval[p] = val[r];
@@ -309,7 +339,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     if (i < nb) {
       const uint32_t k = sh.skey[i];
       const uint32_t v = sh.sval[i];
-      const uint32_t d = digit_of(k, shift);
+      const uint32_t d = digit_of<RB>(k, shift);
       const uint32_t dst = sh.dbase[d] + ((uint32_t)i - sh.lstart[d]);
       kout[dst] = k;
       vout[dst] = v;
@@ -330,28 +360,30 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 // kEmitPairs consecutive pairs, hence at most kEmitPairs consecutive splats
 // (each has >= 1 pair), starting with starts[b]: their offsets and ids are
 // staged in LDS.  Writes are coalesced and the work is balanced whatever the
-// splat sizes.  The block also counts the low 8 bits of its tile keys, the
+// splat sizes.  The block also counts the low RB bits of its tile keys, the
 // per-block digit counts of the tile sort's first pass.
 constexpr int kEmitThreads = 512;
 constexpr int kEmitPerThread = kEmitPairs / kEmitThreads;  // 4 consecutive pairs
 static_assert(kEmitPerThread == 4, "emit stores four pairs as one 16-byte word");
 
+template <int RB>
 __global__ void __launch_bounds__(kEmitThreads)
 k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
        const uint32_t* __restrict__ starts, const uint32_t* __restrict__ n_dev,
        const uint64_t* __restrict__ m_dev, int64_t capacity,
        const rade_view* __restrict__ views, FastDiv div_n, uint32_t* __restrict__ tkeys,
        uint32_t* __restrict__ pids, int vec_stores, int64_t nblocks, uint32_t* __restrict__ hist) {
+  constexpr int R = 1 << RB;
   __shared__ uint64_t win[kEmitPairs + 1];
-  __shared__ uint32_t h[kRadix];
+  __shared__ uint32_t h[R];
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint64_t M = *m_dev;
   const int64_t nvis = *n_dev;
   const int64_t j0 = starts[blk];
   const uint64_t P0 = (uint64_t)blk * kEmitPairs;
-  if (threadIdx.x < kRadix) h[threadIdx.x] = 0u;
+  for (int d = threadIdx.x; d < R; d += kEmitThreads) h[d] = 0u;
   if (P0 >= M || M > (uint64_t)capacity) {  // uniform per block
-    if (threadIdx.x < kRadix) hist[(int64_t)threadIdx.x * nblocks + blk] = 0u;
+    for (int d = threadIdx.x; d < R; d += kEmitThreads) hist[(int64_t)d * nblocks + blk] = 0u;
     return;
   }
   for (int w = threadIdx.x; w <= kEmitPairs; w += kEmitThreads) {
@@ -408,7 +440,7 @@ k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
       const uint32_t ty = min(ty0 + row, ty1);
       tk[r] = toff + ty * tiles_x + tx0 + col;
       pg[r] = g;
-      atomicAdd(&h[tk[r] & (kRadix - 1)], 1u);
+      atomicAdd(&h[tk[r] & (R - 1)], 1u);
     }
     if (vec_stores && pb + kEmitPerThread <= M) {
       *reinterpret_cast<uint4*>(tkeys + pb) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
@@ -423,7 +455,7 @@ k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
     }
   }
   __syncthreads();
-  if (threadIdx.x < kRadix) hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < R; d += kEmitThreads) hist[(int64_t)d * nblocks + blk] = h[d];
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -518,7 +550,7 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Work space of one radix sort of at most n_max items: the digit-major
-// per-block counts and the 256 digit totals.
+// per-block counts and the digit totals (room for 9-bit digits).
 struct SortSpace {
   uint32_t* hist;
   uint32_t* dtot;
@@ -527,51 +559,70 @@ struct SortSpace {
 inline int64_t sort_blocks(int64_t n_max) { return n_max > 0 ? (n_max + kTile - 1) / kTile : 1; }
 
 inline size_t sort_space_bytes(int64_t n_max) {
-  return align_up(sizeof(uint32_t) * sort_blocks(n_max) * kRadix) +
-         align_up(sizeof(uint32_t) * kRadix);
+  return align_up(sizeof(uint32_t) * sort_blocks(n_max) * kMaxRadix) +
+         align_up(sizeof(uint32_t) * kMaxRadix);
 }
 
 inline SortSpace sort_space(char* w, int64_t n_max) {
   SortSpace sp;
   sp.hist = (uint32_t*)w;
-  sp.dtot = (uint32_t*)(w + align_up(sizeof(uint32_t) * sort_blocks(n_max) * kRadix));
+  sp.dtot = (uint32_t*)(w + align_up(sizeof(uint32_t) * sort_blocks(n_max) * kMaxRadix));
   return sp;
 }
 
+// Digit width of a sort by `bits` key bits: 9 where that takes fewer passes
+// than 8 (17-18 or 25-27 bits), else 8.
+inline int digit_bits(int bits) {
+  return (bits + 8) / 9 < (bits + 7) / 8 ? 9 : kRadixBits;
+}
+
 // Sorts (keys, vals) of *n_dev items (at most n_max < 2^32) by the low
-// `bits` bits of the keys; on return the sorted data are in (k0, v0) when the
-// number of passes is even, else in (k1, v1).  Returns the number of passes.
-// first_counted: the first pass's per-block counts are already in sp.hist.
+// `bits` bits of the keys, in passes of digit_bits(bits) bits; on return the
+// sorted data are in (k0, v0) when the number of passes is even, else in
+// (k1, v1).  Returns the number of passes.  first_counted: the first pass's
+// per-block counts (of digits that wide) are already in sp.hist.
 // gsrc: the last pass also writes the record gsrc[value] of every item (the
 // values index gsrc), in the sorted order, to gout, and its last word to
 // cout.
-int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
-               const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
-               bool first_counted = false, const uint4* gsrc = nullptr,
-               uint4* gout = nullptr, uint32_t* cout = nullptr) {
+template <int RB>
+int radix_sort_rb(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
+                  const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
+                  bool first_counted, const uint4* gsrc, uint4* gout, uint32_t* cout) {
   const int64_t nb = sort_blocks(n_max);
-  const int passes = bits > kRadixBits ? (bits + kRadixBits - 1) / kRadixBits : 1;
+  const int passes = bits > RB ? (bits + RB - 1) / RB : 1;
   for (int p = 0; p < passes; ++p) {
-    const int shift = p * kRadixBits;
+    const int shift = p * RB;
     uint32_t* ki = (p & 1) ? k1 : k0;
     uint32_t* vi = (p & 1) ? v1 : v0;
     uint32_t* ko = (p & 1) ? k0 : k1;
     uint32_t* vo = (p & 1) ? v0 : v1;
     if (p > 0 || !first_counted)
-      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev,
+      hipLaunchKernelGGL(k_radix_hist<RB>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n_dev,
                          n_max, shift, nb, sp.hist);
-    hipLaunchKernelGGL(k_radix_colscan, dim3(kRadix), dim3(kThreads), 0, st, sp.hist, nb, sp.dtot);
+    hipLaunchKernelGGL(k_radix_colscan, dim3(1u << RB), dim3(kThreads), 0, st, sp.hist, nb,
+                       sp.dtot);
     if (gsrc && p == passes - 1)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi,
-                         ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
+      hipLaunchKernelGGL((k_radix_scatter<true, RB>), dim3((unsigned)nb), dim3(kThreads), 0, st,
+                         ki, vi, ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
                          (const uint32_t*)sp.dtot, gsrc, gout, cout);
     else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki,
-                         vi, ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
+      hipLaunchKernelGGL((k_radix_scatter<false, RB>), dim3((unsigned)nb), dim3(kThreads), 0, st,
+                         ki, vi, ko, vo, n_dev, n_max, shift, nb, (const uint32_t*)sp.hist,
                          (const uint32_t*)sp.dtot, (const uint4*)nullptr, (uint4*)nullptr,
                          (uint32_t*)nullptr);
   }
   return passes;
+}
+
+int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
+               const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
+               bool first_counted = false, const uint4* gsrc = nullptr,
+               uint4* gout = nullptr, uint32_t* cout = nullptr) {
+  if (digit_bits(bits) == 9)
+    return radix_sort_rb<9>(k0, v0, k1, v1, n_max, n_dev, bits, sp, st, first_counted, gsrc,
+                            gout, cout);
+  return radix_sort_rb<kRadixBits>(k0, v0, k1, v1, n_max, n_dev, bits, sp, st, first_counted,
+                                   gsrc, gout, cout);
 }
 
 struct Layout {
@@ -790,7 +841,8 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   // 4. emit pairs; the tile sort's passes alternate buffers, so emit into
   // the buffer that makes the last pass land in pair_ids.
   const int tbits = total_tiles > 1 ? ceil_log2(total_tiles) : 1;
-  const int tpasses = (tbits + kRadixBits - 1) / kRadixBits;
+  const int trb = digit_bits(tbits);
+  const int tpasses = tbits > trb ? (tbits + trb - 1) / trb : 1;
   uint32_t* ek = tk0;
   uint32_t* ev = (tpasses & 1) ? pid1 : pair_ids;
   uint32_t* ok_ = tk1;
@@ -799,12 +851,18 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   const SortSpace tsp = sort_space(sortw, capacity);
   const bool emitted = VN > 0 && capacity > 0;
   static_assert(kEmitPairs == kTile, "emission blocks are the tile sort's blocks");
-  if (emitted)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)sort_blocks(capacity)), dim3(kEmitThreads), 0, st,
-                       (const uint4*)drec, offs, starts, n_vis, m64, capacity, views_dev,
-                       FastDiv((uint32_t)(N > 0 ? N : 1)), ek, ev,
-                       (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0, sort_blocks(capacity),
-                       tsp.hist);
+  if (emitted) {
+    const int vec = (((uintptr_t)ek | (uintptr_t)ev) & 15) == 0 ? 1 : 0;
+    const FastDiv divn((uint32_t)(N > 0 ? N : 1));
+    if (trb == 9)
+      hipLaunchKernelGGL(k_emit<9>, dim3((unsigned)sort_blocks(capacity)), dim3(kEmitThreads), 0,
+                         st, (const uint4*)drec, offs, starts, n_vis, m64, capacity, views_dev,
+                         divn, ek, ev, vec, sort_blocks(capacity), tsp.hist);
+    else
+      hipLaunchKernelGGL(k_emit<kRadixBits>, dim3((unsigned)sort_blocks(capacity)),
+                         dim3(kEmitThreads), 0, st, (const uint4*)drec, offs, starts, n_vis, m64,
+                         capacity, views_dev, divn, ek, ev, vec, sort_blocks(capacity), tsp.hist);
+  }
   // 5. stable sort by tile
   radix_sort(ek, ev, ok_, ov, capacity, m32, tbits, tsp, st, emitted);
   uint32_t* sk = (tpasses & 1) ? ok_ : ek;

@@ -139,6 +139,50 @@ def test_bin_sort_bit_exact_on_shared_input(tile):
     assert (ids[M:].cpu().numpy() == -7).all()  # nothing written past M
 
 
+@pytest.mark.parametrize("sizes", [[(2400, 1800)], [(2400, 1800), (2304, 1900)]])
+def test_bin_sort_nine_bit_tile_digits(sizes):
+    # 67,500 and 135,900 tiles of 8x8 pixels: 17- and 18-bit tile keys,
+    # sorted in two 9-bit passes (the emission counts 9-bit digits)
+    import torch
+    from paper_2406_01467_amd import _lib
+    dev = device()
+    tile = (8, 8)
+    scene = synth.make_scene_clusters(30000, seed=9, width=sizes[0][0], height=sizes[0][1])
+    views = [synth.identity_view(*sizes[0])]
+    if len(sizes) > 1:
+        views.append(synth.make_views_orbit(scene.means.mean(0), 12.0, 1, seed=10,
+                                            sizes=[sizes[1]])[0])
+    s = _settings(tile_w=tile[0], tile_h=tile[1], sh_degree=3)
+    rec, rect, flags = oracle.project(oracle_settings(s), views, scene)
+    z = rec[..., oracle.R["z"]].astype(np.float32)
+    ids_ref, keys_ref, ranges_ref = oracle.bin_pairs(views, rect, z, tile)
+    sp = _pack_splats(rect, z)
+    vis = rect[..., 0] <= rect[..., 1]
+    tt = np.where(vis, (rect[..., 1] // tile[0] - rect[..., 0] // tile[0] + 1) *
+                  (rect[..., 3] // tile[1] - rect[..., 2] // tile[1] + 1), 0).astype(np.int32)
+    vc = _lib.make_views(views)
+    P, T = _lib.rade_views_prepare(s, vc)
+    assert T > 65536
+    say("bin 9-bit", sizes, T, len(ids_ref))
+    vdev = _lib.views_to_device(vc, dev)
+    V = len(views)
+    sp_d = torch.from_numpy(sp.view(np.uint8).reshape(-1).copy()).to(dev)
+    tt_d = torch.from_numpy(tt.reshape(-1)).to(dev)
+    cap = len(ids_ref) + 5
+    ids = torch.full((cap,), -7, dtype=torch.int32, device=dev)
+    keys = torch.zeros(cap, dtype=torch.int64, device=dev)
+    ranges = torch.empty(2 * T, dtype=torch.int32, device=dev)
+    ndev = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(_lib.rade_bin_sort_workspace(V, scene.n, cap, T), dtype=torch.uint8, device=dev)
+    code, M = _lib.rade_bin_sort(s, vc, vdev, V, scene.n, sp_d, tt_d, ids, ranges, keys, cap, ndev, ws)
+    torch.cuda.synchronize()
+    assert code == 0 and M == len(ids_ref) and int(ndev.item()) == M
+    assert np.array_equal(ids[:M].cpu().numpy().view(np.uint32), ids_ref)
+    assert np.array_equal(keys[:M].cpu().numpy().view(np.uint64), keys_ref)
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges_ref)
+    assert (ids[M:].cpu().numpy() == -7).all()
+
+
 @pytest.mark.parametrize("name,n,tile", [("plain_64x64_1k", None, (16, 16)),
                                          ("plain_800x800_200k", 20000, (16, 16)),
                                          ("plain_800x800_200k", 20000, (8, 8)),
