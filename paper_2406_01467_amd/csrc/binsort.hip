@@ -504,6 +504,10 @@ k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32, i
     return;
   }
   const int64_t i0 = (int64_t)kRangeKeys * g;
+  // the key before a wave's first run, loaded with the runs (not after the
+  // shuffle below, which would add a second memory latency to every wave)
+  const bool first_lane = (threadIdx.x & 63) == 0;
+  const uint32_t before = first_lane && i0 > 0 && i0 <= m ? tkeys[i0 - 1] : 0u;
   uint32_t k[kRangeKeys];
   if (i0 + kRangeKeys <= m) {  // tkeys is 16-byte aligned
 #pragma unroll
@@ -521,8 +525,8 @@ k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32, i
   if (i0 > m) return;
   int64_t prev;
   if (i0 == 0) prev = -1;
-  else if ((threadIdx.x & 63) != 0) prev = (int64_t)left;
-  else prev = (int64_t)tkeys[i0 - 1];
+  else if (!first_lane) prev = (int64_t)left;
+  else prev = (int64_t)before;
 #pragma unroll
   for (int r = 0; r < kRangeKeys; ++r) {
     const int64_t i = i0 + r;

@@ -522,6 +522,34 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
+// Pair sums of one transpose-reduction level whose partner lanes lie in the
+// other 4-lane bank group of a DPP row: lanes of the banks that hold bit b
+// of the lane index clear get a + a(partner), the others b + b(partner).
+// Two DPP adds, each writing only its banks (bank_mask), replace the
+// select-select-add of the general form.  ror8: partner lane ^ 8 (b = 3,
+// banks 0-1 against 2-3); mirror: partner lane ^ 7 within 8 lanes (b = 2,
+// banks 0, 2 against 1, 3).  The leading s_nop gives the two wait states a
+// DPP read of a vector register needs after the instruction that wrote it.
+__device__ __forceinline__ float ror8_pair_sum(float a, float b) {
+  float z;
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %0, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xc"
+      : "=&v"(z)
+      : "v"(a), "v"(b));
+  return z;
+}
+
+__device__ __forceinline__ float mirror_pair_sum(float a, float b) {
+  float z;
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+      "v_add_f32_dpp %0, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xa"
+      : "=&v"(z)
+      : "v"(a), "v"(b));
+  return z;
+}
+
 // Sum 16 per-lane values over the wavefront by transpose-reduction: every
 // level pairs each lane with a partner across one more lane direction, keeps
 // half of its values and adds the partner's copy of them, so the number of
@@ -552,10 +580,9 @@ __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
                                                     __float_as_uint(u[k + 4]), false, false);
     w[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  const bool b3 = (threadIdx.x & 8) != 0, b2 = (threadIdx.x & 4) != 0;
-  const float x0 = (b3 ? w[2] : w[0]) + dpp<0x128>(b3 ? w[0] : w[2]);
-  const float x1 = (b3 ? w[3] : w[1]) + dpp<0x128>(b3 ? w[1] : w[3]);
-  float y = (b2 ? x1 : x0) + dpp<0x141>(b2 ? x0 : x1);
+  const float x0 = ror8_pair_sum(w[0], w[2]);
+  const float x1 = ror8_pair_sum(w[1], w[3]);
+  float y = mirror_pair_sum(x0, x1);
   y += dpp<0xB1>(y);
   y += dpp<0x4E>(y);
   return y;
@@ -570,13 +597,13 @@ __device__ __forceinline__ float wave_sum16(const float (&v)[16]) {
 // holds the row's total of value 8 b3 + 4 b2 + 2 b0 + b1 (b_k: bit k of i).
 __device__ __forceinline__ float row_sum16(const float (&v)[16]) {
   const int l = (int)threadIdx.x;
-  const bool b3 = (l & 8) != 0, b2 = (l & 4) != 0, b1 = (l & 2) != 0, b0 = (l & 1) != 0;
+  const bool b1 = (l & 2) != 0, b0 = (l & 1) != 0;
   float u[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) u[k] = (b3 ? v[k + 8] : v[k]) + dpp<0x128>(b3 ? v[k] : v[k + 8]);
+  for (int k = 0; k < 8; ++k) u[k] = ror8_pair_sum(v[k], v[k + 8]);
   float w[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = (b2 ? u[k + 4] : u[k]) + dpp<0x141>(b2 ? u[k] : u[k + 4]);
+  for (int k = 0; k < 4; ++k) w[k] = mirror_pair_sum(u[k], u[k + 4]);
   float x[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) x[k] = (b0 ? w[k + 2] : w[k]) + dpp<0xB1>(b0 ? w[k] : w[k + 2]);
