@@ -29,6 +29,7 @@ struct BlendParams {
   float alpha_max;
   float t_min;
   float bg[3];
+  float log2_alpha_min;  // for the support bound of the staging masks
 };
 
 inline BlendParams make_blend_params(const rade_settings& s) {
@@ -38,6 +39,7 @@ inline BlendParams make_blend_params(const rade_settings& s) {
   b.alpha_max = (float)s.alpha_max;
   b.t_min = (float)s.t_min;
   for (int i = 0; i < 3; ++i) b.bg[i] = (float)s.bg[i];
+  b.log2_alpha_min = (float)log2(s.alpha_min);
   return b;
 }
 

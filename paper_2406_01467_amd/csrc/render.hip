@@ -222,11 +222,18 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
   }
   uint64_t lm = 0;
   if (bits) {
-    // Support: power <= cut and opacity 2^-power >= alpha_min.
+    // Support: power <= cut and opacity 2^-power >= alpha_min.  The bound
+    // and the tests below carry margins far above the error of the
+    // hardware reciprocal, square root and logarithm (about one unit in
+    // the last place), so those stand in for the correctly rounded forms.
     const float A = fmaf(s.w0, s.w0, s.w2 * s.w2), B = fmaf(s.w0, s.w1, s.w2 * s.w3);
     const float C = fmaf(s.w1, s.w1, s.w3 * s.w3);
-    const float invA = A > 0.0f ? 1.0f / A : 0.0f;
-    const float lo = s.o > 0.0f ? log2f(s.o / bp.alpha_min) : -1.0f;
+    const float invA = A > 0.0f ? __builtin_amdgcn_rcpf(A) : 0.0f;
+    float lo = -1.0f;
+    if (s.o >= 1.17549435e-38f && bp.alpha_min >= 1.17549435e-38f)
+      lo = __builtin_amdgcn_logf(s.o) - bp.log2_alpha_min;  // no denormal operands
+    else if (s.o > 0.0f)
+      lo = log2f(s.o / bp.alpha_min);
     const float tau2 = fminf(bp.cut2, lo) * 1.001f + 0.01f;
     // centre relative to the tile's first pixel (x0 - ox is a small integer:
     // exact), so the block offsets below are compile-time constants
@@ -235,7 +242,7 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
       // drop the blocks the ellipse misses (also when the rect touches a
       // single block: one test per staged pair is far cheaper than a wave
       // iteration over a splat that reaches none of its pixels)
-      const float invC = C > 0.0f ? 1.0f / C : 0.0f;
+      const float invC = C > 0.0f ? __builtin_amdgcn_rcpf(C) : 0.0f;
 #pragma unroll
       for (int k = 0; k < TG::NW; ++k) {
         const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
@@ -261,7 +268,7 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
         int xl = x0, xh = x1;
         if (A > 0.0f) {
           // pixels x = ut - dx with dx in -B dy / A -+ sqrt(disc) / A
-          const float xc = fmaf(B * dy, invA, ut), half = sqrtf(disc) * invA;
+          const float xc = fmaf(B * dy, invA, ut), half = __builtin_amdgcn_sqrtf(disc) * invA;
           const float m = 2e-3f + 1e-5f * (fabsf(xc) + half);
           xl = max(xl, (int)ceilf(fmaxf(xc - half - m, -1.0f)));
           xh = min(xh, (int)floorf(fminf(xc + half + m, 8.0f)));
