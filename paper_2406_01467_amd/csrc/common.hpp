@@ -152,4 +152,18 @@ struct EventScope {
   }
 };
 
+// Workgroups of `block` threads that fit on the current device at once for a
+// kernel; `cached` is the caller's per-kernel cache (0 until first computed).
+template <typename K>
+unsigned resident_blocks(K kernel, int block, unsigned cap, unsigned& cached) {
+  if (cached == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    cached = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
+  }
+  return cached < cap ? cached : cap;
+}
+
 }  // namespace rade

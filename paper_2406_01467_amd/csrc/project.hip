@@ -299,29 +299,50 @@ __device__ bool geometry(const ViewD& v, const Params& P, const rade_settings& s
   return true;
 }
 
-// Loads Gaussian g; false when it is culled (a parameter not finite, a zero
-// quaternion, or opacity <= alpha_min, which leaves no pixel with alpha >=
-// alpha_min).
-__device__ __forceinline__ bool load_params(int64_t g, const float* means, const float* scales,
-                                            const float* quats, const float* opac,
-                                            double alpha_min, Params& P) {
-  const float m0 = means[3 * g], m1 = means[3 * g + 1], m2 = means[3 * g + 2];
-  const float s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
-  const float4 q = *reinterpret_cast<const float4*>(quats + 4 * g);
-  const float o = opac[g];
-  bool ok = finitef(m0) && finitef(m1) && finitef(m2) && finitef(s0) && finitef(s1) &&
-            finitef(s2) && finitef(q.x) && finitef(q.y) && finitef(q.z) && finitef(q.w) &&
-            finitef(o);
-  P.mu[0] = m0; P.mu[1] = m1; P.mu[2] = m2;
-  P.s[0] = s0; P.s[1] = s1; P.s[2] = s2;
-  P.o = o;
+// The stored inputs of one Gaussian (loaded ahead of their use by the
+// pipelined kernel).
+struct RawGauss {
+  float m0, m1, m2, s0, s1, s2, o;
+  float4 q;
+};
+
+__device__ __forceinline__ RawGauss load_raw(int64_t g, const float* __restrict__ means,
+                                             const float* __restrict__ scales,
+                                             const float* __restrict__ quats,
+                                             const float* __restrict__ opac) {
+  RawGauss r;
+  r.m0 = means[3 * g]; r.m1 = means[3 * g + 1]; r.m2 = means[3 * g + 2];
+  r.s0 = scales[3 * g]; r.s1 = scales[3 * g + 1]; r.s2 = scales[3 * g + 2];
+  r.q = *reinterpret_cast<const float4*>(quats + 4 * g);
+  r.o = opac[g];
+  return r;
+}
+
+// The parameters of a loaded Gaussian; false when it is culled (a parameter
+// not finite, a zero quaternion, or opacity <= alpha_min, which leaves no
+// pixel with alpha >= alpha_min).
+__device__ __forceinline__ bool params_of(const RawGauss& r, double alpha_min, Params& P) {
+  const float4 q = r.q;
+  bool ok = finitef(r.m0) && finitef(r.m1) && finitef(r.m2) && finitef(r.s0) &&
+            finitef(r.s1) && finitef(r.s2) && finitef(q.x) && finitef(q.y) && finitef(q.z) &&
+            finitef(q.w) && finitef(r.o);
+  P.mu[0] = r.m0; P.mu[1] = r.m1; P.mu[2] = r.m2;
+  P.s[0] = r.s0; P.s[1] = r.s1; P.s[2] = r.s2;
+  P.o = r.o;
   const double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
   const double qq = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  ok = ok && qq > 0.0 && ((double)o > alpha_min);
+  ok = ok && qq > 0.0 && ((double)r.o > alpha_min);
   P.qinv = ok ? 1.0 / qq : 0.0;
   P.qn[0] = qw * P.qinv; P.qn[1] = qx * P.qinv; P.qn[2] = qy * P.qinv; P.qn[3] = qz * P.qinv;
   quat_to_mat(P.qn, P.Rg);
   return ok;
+}
+
+// Loads Gaussian g (params_of's culling).
+__device__ __forceinline__ bool load_params(int64_t g, const float* means, const float* scales,
+                                            const float* quats, const float* opac,
+                                            double alpha_min, Params& P) {
+  return params_of(load_raw(g, means, scales, quats, opac), alpha_min, P);
 }
 
 __device__ __forceinline__ void store_invisible(rade_splat* out) {
@@ -521,39 +542,46 @@ __device__ __forceinline__ void sh_view_bwd(int deg, const double* mu, const dou
 
 // Gradient record of one (view, Gaussian) from the render backward, with
 // g_o = dL/d opacity per pixel (zero where alpha is clamped):
-//   0, 1   sums of g_o (t1 w0 + t2 w2), g_o (t1 w1 + t2 w3): the centre
-//          gradient through the footprint is -o 2 / log2(e) times these
+//   0, 1   sums of g_o dx, g_o dy (first moments of the pixel offset from
+//          the centre): the centre gradient through the footprint is -o Q
+//          times these, Q the conic
 //   2-4    sums of g_o dx^2, g_o dx dy, g_o dy^2: the gradient of the conic
 //          (power a dx^2 / 2 + b dx dy + c dy^2 / 2) is -o (s2 / 2, s3, s4 / 2)
 //   5      do;  6-8 drgb;  9 dz;  10, 11 dp;  12-14 dn;  15 pad.
 constexpr int kGradStride = 16;
 
-// SH: also the colour part, view by view (d_sh accumulated in place), in
-// one kernel (k_project_bwd); else k_project_bwd_sh follows
-// (k_project_bwd_geo).  One lane holds the geometry
-// and the SH row at once (one wave per SIMD): the fused form suits one view,
-// the split one many (the geometry kernel then needs no SH row, and the
-// colour kernel keeps its row's gradient in registers).
-template <int KMAX, bool VEC, bool SH>
-__device__ __forceinline__ void project_bwd_body(
-    const rade_settings& st, const rade_view* __restrict__ views, int V, int64_t N,
-    const float* __restrict__ means, const float* __restrict__ scales,
-    const float* __restrict__ quats, const float* __restrict__ opac,
-    const float* __restrict__ sh, const float* __restrict__ gsplat,
-    float* __restrict__ d_means, float* __restrict__ d_scales, float* __restrict__ d_quats,
-    float* __restrict__ d_opac, float* __restrict__ d_sh) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  constexpr int K = KMAX;
-  const float* __restrict__ coef_g = sh + 3 * K * g;
-  // the first view's gradient record is loaded together with the
-  // parameters, so its latency is not paid after theirs.  (A Gaussian whose
-  // SH row is not finite is culled by the forward in every view: its
-  // records are zero, so every view is skipped and its gradients are zero.)
+// The projection backward comes in two forms.  One view: geometry and colour
+// in one kernel (k_project_bwd_pipe), one lane holding both and the SH row
+// (one wave per SIMD).  Many views: the geometry (k_project_bwd_geo, no SH
+// row, two waves per SIMD) and then the colour (k_project_bwd_sh, which
+// keeps its row's gradient in registers over the views).
+//
+// The first view's gradient record of Gaussian g.
+struct Rec0 {
+  float4 a, b, c, d;
+};
+
+__device__ __forceinline__ Rec0 load_rec0(const float* __restrict__ gsplat, int64_t g) {
   const float4* gr0 = reinterpret_cast<const float4*>(gsplat + g * kGradStride);
-  const float4 g0a = gr0[0], g0b = gr0[1], g0c = gr0[2], g0d = gr0[3];
+  return Rec0{gr0[0], gr0[1], gr0[2], gr0[3]};
+}
+
+// Projection backward of Gaussian g from its loaded parameters and first
+// record.  (A Gaussian whose SH row is not finite is culled by the forward
+// in every view: its records are zero, so every view is skipped and its
+// gradients are zero.)
+template <int KMAX, bool VEC, bool SH, bool PRE = false>
+__device__ __forceinline__ void project_bwd_gauss(
+    const rade_settings& st, const rade_view* __restrict__ views, int V, int64_t N, int64_t g,
+    const RawGauss& raw, const Rec0& r0, const float* __restrict__ sh,
+    const float (&pre_coef)[3 * KMAX],
+    const float* __restrict__ gsplat, float* __restrict__ d_means, float* __restrict__ d_scales,
+    float* __restrict__ d_quats, float* __restrict__ d_opac, float* __restrict__ d_sh) {
+  constexpr int K = KMAX;
+  const float* __restrict__ coef_g = SH ? sh + 3 * K * g : nullptr;
+  const float4 g0a = r0.a, g0b = r0.b, g0c = r0.c, g0d = r0.d;
   Params P;
-  bool ok = load_params(g, means, scales, quats, opac, st.alpha_min, P);
+  bool ok = params_of(raw, st.alpha_min, P);
   bool sh_written = false;
   double gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gqn[4] = {0, 0, 0, 0}, go = 0.0;
   for (int vi = 0; ok && vi < V; ++vi) {
@@ -723,7 +751,12 @@ __device__ __forceinline__ void project_bwd_body(
       gmu[i] += v.R[i] * gx[0] + v.R[3 + i] * gx[1] + v.R[6 + i] * gx[2];
     if constexpr (SH) {
       float coef[3 * K], row[3 * K];
-      load_row<K, VEC>(coef_g, coef);
+      if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < 3 * K; ++i) coef[i] = pre_coef[i];
+      } else {
+        load_row<K, VEC>(coef_g, coef);
+      }
       sh_view_bwd<K>(st.sh_degree, P.mu, v.C, coef, gb.z, gb.w, gc.x, row, gmu);
       store_row<K, VEC>(d_sh + 3 * K * g, row, sh_written);
       sh_written = true;
@@ -753,17 +786,70 @@ __device__ __forceinline__ void project_bwd_body(
   }
 }
 
+// One lane per Gaussian; the first view's gradient record is loaded together
+// with the parameters, so its latency is not paid after theirs.
+template <int KMAX, bool VEC, bool SH>
+__device__ __forceinline__ void project_bwd_body(
+    const rade_settings& st, const rade_view* __restrict__ views, int V, int64_t N,
+    const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ quats, const float* __restrict__ opac,
+    const float* __restrict__ sh, const float* __restrict__ gsplat,
+    float* __restrict__ d_means, float* __restrict__ d_scales, float* __restrict__ d_quats,
+    float* __restrict__ d_opac, float* __restrict__ d_sh) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const Rec0 r0 = load_rec0(gsplat, g);
+  const RawGauss raw = load_raw(g, means, scales, quats, opac);
+  float unused[3 * KMAX];
+  project_bwd_gauss<KMAX, VEC, SH>(st, views, V, N, g, raw, r0, sh, unused, gsplat, d_means,
+                                   d_scales, d_quats, d_opac, d_sh);
+}
+
+// One view, software-pipelined over a grid that fits the device at once
+// (its registers allow one wave per SIMD, so no other wave hides the load
+// latency): lane l takes the Gaussians l, l + S, l + 2 S, ... (S lanes in
+// the grid) and issues the loads of its next Gaussian's parameters and
+// record before the arithmetic of the current one.
 template <int KMAX, bool VEC>
 __global__ void __launch_bounds__(256)
-k_project_bwd(rade_settings st, const rade_view* __restrict__ views, int V, int64_t N,
-              const float* __restrict__ means, const float* __restrict__ scales,
-              const float* __restrict__ quats, const float* __restrict__ opac,
-              const float* __restrict__ sh, const float* __restrict__ gsplat,
-              float* __restrict__ d_means, float* __restrict__ d_scales,
-              float* __restrict__ d_quats, float* __restrict__ d_opac,
-              float* __restrict__ d_sh) {
-  project_bwd_body<KMAX, VEC, true>(st, views, V, N, means, scales, quats, opac, sh, gsplat,
-                                    d_means, d_scales, d_quats, d_opac, d_sh);
+k_project_bwd_pipe(rade_settings st, const rade_view* __restrict__ views, int64_t N,
+                   const float* __restrict__ means, const float* __restrict__ scales,
+                   const float* __restrict__ quats, const float* __restrict__ opac,
+                   const float* __restrict__ sh, const float* __restrict__ gsplat,
+                   float* __restrict__ d_means, float* __restrict__ d_scales,
+                   float* __restrict__ d_quats, float* __restrict__ d_opac,
+                   float* __restrict__ d_sh) {
+  const int64_t S = (int64_t)gridDim.x * blockDim.x;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  constexpr int K = KMAX;
+  Rec0 ra = load_rec0(gsplat, g), rb = ra;
+  RawGauss pa = load_raw(g, means, scales, quats, opac), pb = pa;
+  float ca[3 * K], cb[3 * K];
+  load_row<K, VEC>(sh + 3 * K * g, ca);
+  for (;;) {
+    // two Gaussians per trip, so the prefetch buffers alternate without copies
+    int64_t gn = g + S;
+    if (gn < N) {
+      rb = load_rec0(gsplat, gn);
+      pb = load_raw(gn, means, scales, quats, opac);
+      load_row<K, VEC>(sh + 3 * K * gn, cb);
+    }
+    project_bwd_gauss<KMAX, VEC, true, true>(st, views, 1, N, g, pa, ra, sh, ca, gsplat, d_means,
+                                       d_scales, d_quats, d_opac, d_sh);
+    if (gn >= N) break;
+    g = gn;
+    gn = g + S;
+    if (gn < N) {
+      ra = load_rec0(gsplat, gn);
+      pa = load_raw(gn, means, scales, quats, opac);
+      load_row<K, VEC>(sh + 3 * K * gn, ca);
+    }
+    project_bwd_gauss<KMAX, VEC, true, true>(st, views, 1, N, g, pb, rb, sh, cb, gsplat, d_means,
+                                       d_scales, d_quats, d_opac, d_sh);
+    if (gn >= N) break;
+    g = gn;
+  }
 }
 
 // The geometry alone at two waves per SIMD: its registers are held to 256
@@ -784,7 +870,7 @@ k_project_bwd_geo(rade_settings st, const rade_view* __restrict__ views, int V, 
 // The colour part of the projection backward, after k_project_bwd_geo: the SH
 // coefficient gradients (one row per Gaussian, summed over the views in
 // registers and stored once) and the viewing direction's share of the mean
-// gradient, added to what k_project_bwd wrote.  A view contributes when its
+// gradient, added to what k_project_bwd_geo wrote.  A view contributes when its
 // colour gradient is not zero; such a record comes from blended pixels, so
 // the splat exists in that view and the geometry the fused form would check
 // succeeds.  The clamp decisions are the forward's (same FP64 colour).
@@ -871,9 +957,11 @@ hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, i
 #define RADE_PROJECT_BWD(K, V4)                                                               \
   do {                                                                                        \
     if (V == 1) {                                                                             \
-      hipLaunchKernelGGL((k_project_bwd<K, V4>), grid, block, 0, stream, st, views, V, N,      \
-                         means, scales, quats, opac, sh, gsplat, d_means, d_scales, d_quats,   \
-                         d_opac, d_sh);                                                        \
+      static unsigned cached = 0;                                                             \
+      const unsigned gp = resident_blocks(k_project_bwd_pipe<K, V4>, 256, grid.x, cached);    \
+      hipLaunchKernelGGL((k_project_bwd_pipe<K, V4>), dim3(gp), block, 0, stream, st, views,  \
+                         N, means, scales, quats, opac, sh, gsplat, d_means, d_scales,         \
+                         d_quats, d_opac, d_sh);                                               \
     } else {                                                                                  \
       hipLaunchKernelGGL((k_project_bwd_geo<K, V4>), grid, block, 0, stream, st, views, V, N,  \
                          means, scales, quats, opac, gsplat, d_means, d_scales, d_quats,       \

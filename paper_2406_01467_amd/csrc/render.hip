@@ -1000,20 +1000,6 @@ __global__ void __launch_bounds__(kZeroThreads) k_zero(float4* __restrict__ a, i
 
 __global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
 
-// Workgroups that fit on the device at once for a kernel; `cached` is the
-// caller's per-kernel cache (0 until first computed).
-template <typename K>
-unsigned resident_blocks(K kernel, int block, unsigned cap, unsigned& cached) {
-  if (cached == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
-    cached = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
-  }
-  return cached < cap ? cached : cap;
-}
-
 template <int TW, int TH, bool DIST, bool CNT, bool EXACT, int WW = 8, int BT = 0>
 void launch_fwd_d(const FwdArgs& a, int schedule, hipStream_t st) {
   constexpr int B = TileGeom<TW, TH, WW, BT>::BLOCK;
