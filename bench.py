@@ -108,13 +108,13 @@ def kernel_bytes(kernel: str, n: int, views: int, pairs: int, pixels: int) -> in
 MEASURED = [
     {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
      "schedule": 1, "wave_w": 0, "batch": 0,
-     "sources_sha1": "c53bee3dc44a6b92026e24c201b67b5dbea418ae",
-     "fetch_bytes": 374479321, "write_bytes": 154785088, "valu_issue": 0.87,
+     "sources_sha1": "1d02c24950d1ad4cbac087bbb0f70ed9676efa33",
+     "fetch_bytes": 374565304, "write_bytes": 154785088, "valu_issue": 0.84,
      "profile": "profiles/kernels_1600x1064_1m_pmc.md"},
     {"kernel": "render_bwd", "workload": "batched_16views_1m", "tile": "8x8",
      "schedule": 1, "wave_w": 0, "batch": 0,
-     "sources_sha1": "c53bee3dc44a6b92026e24c201b67b5dbea418ae",
-     "fetch_bytes": 8411367761, "write_bytes": 2768289856, "valu_issue": 1.12,
+     "sources_sha1": "1d02c24950d1ad4cbac087bbb0f70ed9676efa33",
+     "fetch_bytes": 8410815712, "write_bytes": 2768274272, "valu_issue": 0.98,
      "profile": "profiles/kernels_batched_16views_1m_pmc.md"},
 ]
 
