@@ -43,8 +43,10 @@ inline BlendParams make_blend_params(const rade_settings& s) {
   return b;
 }
 
-// Splat as staged in LDS for one tile: 64 bytes = 4 x 16-byte broadcast
-// reads (the forward needs the first two before its per-lane decision).
+// Splat as staged in LDS for one tile: 64 bytes, held as four 16-byte
+// quarters in arrays of their own (StagedArrays), so that one address
+// register reaches every field of a slot through constant offsets (the
+// forward needs the first two quarters before its per-lane decision).
 // The centre is split into its FP32 offset (ur, vr) from the pixel centre of
 // the tile's 32-pixel-aligned origin and the FP32 remainder (ul, vl) of that
 // rounding.  For an integer pixel offset x, ur - x is exact, so (ur - x) + ul
@@ -66,6 +68,30 @@ struct alignas(8) StagedForm {
 };
 struct alignas(8) StagedRem {
   float ul, vl;
+};
+
+// LDS arrays of B staged splats: quarter k of slot r at q[k * B + r] (k < 4),
+// the form constants and the remainder (c1, c2, ul, vl) at q[4 * B + r].
+template <int B>
+struct StagedArrays {
+  float4 q[5 * B];
+
+  __device__ __forceinline__ void put(int r, const StagedSplat& s, const StagedForm& f,
+                                      const StagedRem& rm) {
+    q[r] = make_float4(s.ur, s.vr, s.w0, s.w1);
+    q[B + r] = make_float4(s.w2, s.w3, s.o, s.zc);
+    q[2 * B + r] = make_float4(s.r, s.g, s.b, s.p0);
+    q[3 * B + r] = make_float4(s.p1, s.n0, s.n1, s.n2);
+    q[4 * B + r] = make_float4(f.c1, f.c2, rm.ul, rm.vl);
+  }
+  __device__ __forceinline__ void get(int r, StagedSplat& s, StagedForm& f,
+                                      StagedRem& rm) const {
+    const float4 a = q[r], b = q[B + r], c = q[2 * B + r], d = q[3 * B + r], e = q[4 * B + r];
+    s = StagedSplat{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
+                    c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+    f = StagedForm{e.x, e.y};
+    rm = StagedRem{e.z, e.w};
+  }
 };
 
 // The centre of splat record `sp` relative to the pixel centre (ox + 0.5,

@@ -193,7 +193,7 @@ template <int TW, int TH, int WW, int BT, bool EXACT = false, bool QL = false>
 __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats, int64_t vbase,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
                                           int slot, const PixelCtx& c, const BlendParams& bp,
-                                          StagedSplat* ss, StagedForm* sf, StagedRem* sr,
+                                          StagedArrays<TileGeom<TW, TH, WW, BT>::BATCH>& st,
                                           uint32_t* sgid, uint64_t* lmask) {
   using TG = TileGeom<TW, TH, WW, BT>;
   const uint32_t g = pair_ids[idx];
@@ -202,15 +202,14 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
   const CentreSplit cs = split_centre(sp.uc, sp.vc, c.ox, c.oy);
   s.ur = cs.ur; s.vr = cs.vr;
   s.w0 = sp.w[0]; s.w1 = sp.w[1]; s.w2 = sp.w[2]; s.w3 = sp.w[3];
-  sf[slot] = StagedForm{form_const(sp.w[0], sp.w[1], cs.ul, cs.vl),
-                        form_const(sp.w[2], sp.w[3], cs.ul, cs.vl)};
-  if (sr) sr[slot] = StagedRem{cs.ul, cs.vl};
+  const StagedForm sform{form_const(sp.w[0], sp.w[1], cs.ul, cs.vl),
+                         form_const(sp.w[2], sp.w[3], cs.ul, cs.vl)};
   s.o = sp.opacity;
   s.zc = EXACT ? sp.z : plane_const(sp.z, sp.p[0], sp.p[1], cs.ul, cs.vl);
   s.r = sp.rgb[0]; s.g = sp.rgb[1]; s.b = sp.rgb[2];
   s.p0 = sp.p[0]; s.p1 = sp.p[1];
   s.n0 = sp.n[0]; s.n1 = sp.n[1]; s.n2 = sp.n[2];
-  ss[slot] = s;
+  st.put(slot, s, sform, StagedRem{cs.ul, cs.vl});
   sgid[slot] = g;
   const int rx0 = sp.rect[0] - c.x0, rx1 = sp.rect[1] - c.x0;
   const int ry0 = sp.rect[2] - c.y0, ry1 = sp.rect[3] - c.y0;
@@ -311,9 +310,7 @@ __device__ __forceinline__ void publish_masks(
 template <int TW, int TH, bool EXACT, int WW, int BT>
 struct FwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
-  StagedSplat ss[TG::BATCH];
-  StagedForm sf[TG::BATCH];
-  StagedRem sr[EXACT ? TG::BATCH : 1];
+  StagedArrays<TG::BATCH> st;
   uint32_t sgid[TG::BATCH];
   uint64_t lmask[TG::LM ? TG::BATCH : 1];
   uint64_t masks[TG::NW][TG::NCH];
@@ -348,9 +345,6 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
   const BlendParams& bp = a.bp;
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
-  StagedSplat* ss = sh.ss;
-  StagedForm* sf = sh.sf;
-  StagedRem* sr = EXACT ? sh.sr : nullptr;
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
   const PixelCtx c = pixel_ctx<TW, TH, WW, BT>(a.views, a.V, a.ranges, tile);
@@ -379,8 +373,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       const uint32_t idx = b0 + (uint32_t)slot;
       uint32_t bits = 0;
       if (idx < c.re) {
-        bits = stage<TW, TH, WW, BT, EXACT>(splats, vbase, pair_ids, idx, slot, c, bp, ss, sf,
-                                            sr, sgid, sh.lmask);
+        bits = stage<TW, TH, WW, BT, EXACT>(splats, vbase, pair_ids, idx, slot, c, bp, sh.st,
+                                            sgid, sh.lmask);
         if constexpr (EXACT) {
           const float4* q = a.depth_quad + 2 * (vbase + sgid[slot]);
           sh.xq[slot] = q[0];
@@ -401,8 +395,10 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
         const int j = __builtin_ctzll(m);
         m &= ~(1ull << j);
         const int r = cw * 64 + j;
-        const StagedSplat s = ss[r];
-        const StagedForm f = sf[r];
+        StagedSplat s;
+        StagedForm f;
+        StagedRem rm;
+        sh.st.get(r, s, f, rm);
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, pw, e, al;
         bool cl;
@@ -431,7 +427,6 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
           // the offset from the true centre
           const float4 q = sh.xq[r];
           const float h2 = sh.xh[r];
-          const StagedRem rm = sr[r];
           const float ex = dx + rm.ul, ey = dy + rm.vl;
           const float gd = fmaf(q.y, ey, q.x * ex);
           const float quad = fmaf(h2 * ey, ey, ex * fmaf(q.z, ex, q.w * ey));
@@ -620,9 +615,7 @@ __device__ __forceinline__ float row_sum16(const float (&v)[16]) {
 template <int TW, int TH, int WW, int BT>
 struct BwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
-  StagedSplat ss[TG::BATCH];
-  StagedForm sf[TG::BATCH];
-  StagedRem sr[TG::BATCH];
+  StagedArrays<TG::BATCH> st;
   uint32_t sgid[TG::BATCH];
   uint64_t lmask[TG::LM ? TG::BATCH : 1];
   uint64_t masks[TG::NW][TG::NCH];
@@ -647,9 +640,6 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
   float* __restrict__ gsplat = a.gsplat;
-  StagedSplat* ss = sh.ss;
-  StagedForm* sf = sh.sf;
-  StagedRem* sr = sh.sr;
   uint32_t* sgid = sh.sgid;
   const PixelCtx c = pixel_ctx<8, 8, 8, BT, true>(a.views, a.V, a.ranges, tile);
   const int lane = threadIdx.x & 63;
@@ -704,7 +694,7 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (li < bend)
         bits = stage<8, 8, 8, BT, false, true>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot,
-                                               c, bp, ss, sf, sr, sgid, sh.lmask);
+                                               c, bp, sh.st, sgid, sh.lmask);
       publish_masks<8, 8, 8, BT>(bits, slot >> 6, sh.masks);
     }
     __syncthreads();
@@ -729,12 +719,10 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
         }
         const int r = cw * 64 + j;
         const int pos = lo + j;
-        const float4* s4 = reinterpret_cast<const float4*>(ss + r);
-        const float4 q0 = s4[0], q1 = s4[1], q2 = s4[2], q3 = s4[3];
-        const StagedSplat s{q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
-        const StagedForm f = sf[r];
-        const StagedRem rm = sr[r];
+        StagedSplat s;
+        StagedForm f;
+        StagedRem rm;
+        sh.st.get(r, s, f, rm);
         const int gid = (int)sgid[r];
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, e, al;
@@ -803,9 +791,6 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
   const float* __restrict__ d_normal = a.d_normal;
   const float* __restrict__ d_alpha = a.d_alpha;
   float* __restrict__ gsplat = a.gsplat;
-  StagedSplat* ss = sh.ss;
-  StagedForm* sf = sh.sf;
-  StagedRem* sr = sh.sr;
   uint32_t* sgid = sh.sgid;
   auto masks = sh.masks;
   int& smax = sh.smax;
@@ -866,7 +851,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (li < bend)
         bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot, c, bp,
-                                     ss, sf, sr, sgid, sh.lmask);
+                                     sh.st, sgid, sh.lmask);
       publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
     __syncthreads();
@@ -890,12 +875,10 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         m &= ~(1ull << j);
         const int r = cw * 64 + j;
         const int pos = bstart + r;
-        const float4* s4 = reinterpret_cast<const float4*>(ss + r);
-        const float4 q0 = s4[0], q1 = s4[1], q2 = s4[2], q3 = s4[3];
-        const StagedSplat s{q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
-        const StagedForm f = sf[r];
-        const StagedRem rm = sr[r];
+        StagedSplat s;
+        StagedForm f;
+        StagedRem rm;
+        sh.st.get(r, s, f, rm);
         const float dx = s.ur - fx, dy = s.vr - fy;
         float t1, t2, e, al;
         bool cl;
@@ -903,8 +886,8 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         // all 16-byte reads are issued before the branch below (left to
         // itself the compiler splits the second half into 4-byte reads inside
         // it, each needing its own address register)
-        asm volatile("" ::"v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w), "v"(q3.x), "v"(q3.y),
-                     "v"(q3.z), "v"(q3.w), "v"(rm.ul), "v"(rm.vl));
+        asm volatile("" ::"v"(s.r), "v"(s.g), "v"(s.b), "v"(s.p0), "v"(s.p1), "v"(s.n0),
+                     "v"(s.n1), "v"(s.n2), "v"(rm.ul), "v"(rm.vl));
         if (!__any(has)) continue;
         // Branch-free adjoint: every lane evaluates, lanes without this
         // splat contribute zeros and keep their state (alpha <= alpha_max,
