@@ -747,8 +747,8 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
         sfm = fmaf(gN2, s.n2, sfm);
         const float ga = fmaf(Ti, sfm, -(Racc * inv));
         T = has ? Ti : T;
-        Racc = has ? fmaf(w, sfm, Racc) : Racc;
         const float wg = has ? w : 0.0f;
+        Racc = fmaf(wg, sfm, Racc);  // + 0 x (finite) where the lane has no blend
         const float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         const float gop = (has && !cl) ? ga * e : 0.0f;
         float g[16];
@@ -909,9 +909,11 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         sf = fmaf(gN2, s.n2, sf);
         const float ga = fmaf(Ti, sf, -(Racc * inv));
         T = has ? Ti : T;
-        Racc = has ? fmaf(w, sf, Racc) : Racc;
         const int gid = __builtin_amdgcn_readlane(cgid, j);
         const float wg = has ? w : 0.0f;
+        // lanes without the blend add 0 x sf (sf is finite: a sum of finite
+        // products), which leaves Racc unchanged
+        Racc = fmaf(wg, sf, Racc);
         float gd = fmaf(wg, gD, (has && gid == med) ? gM : 0.0f);
         if constexpr (DIST) gd = fmaf(kdist * wg, d - mdist, gd);
         // opacity gradient ga e.  Where alpha is not clamped, alpha = o e, so
