@@ -140,7 +140,9 @@ __device__ __forceinline__ void splat_eval(const StagedSplat& s, const StagedFor
   e = __builtin_amdgcn_exp2f(-pw);
   const float raw = s.o * e;
   clamped = raw > bp.alpha_max;
-  alpha = fminf(raw, bp.alpha_max);
+  // min(raw, alpha_max) for raw >= 0 (o > 0, e >= 0), as one median: fminf
+  // would re-canonicalise the kernel argument on every call
+  alpha = __builtin_amdgcn_fmed3f(raw, 0.0f, bp.alpha_max);
 }
 
 __device__ __forceinline__ bool splat_alpha(const StagedSplat& s, const StagedForm& f, float dx,
