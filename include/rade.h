@@ -159,7 +159,12 @@ int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
 
 /* Projection (Sec. 3.1 Eq. 1-2; Sec. 3.2 Eq. 4, 13-17; Sec. 3.3 Eq. 21-22).
  * For every Gaussian g and view v writes splats[v*N + g] and
- * tiles_touched[v*N + g] = number of tiles its rect covers (0 if culled).
+ * tiles_touched[v*N + g] = number of tiles its rect covers (0 if culled),
+ * and, when bin_records is not NULL, the 16-byte binning record
+ * bin_records[4*(v*N + g) .. +3] = {bits of the float32 depth z (as in the
+ * splat), tx0 | ty0 << 16, tx1 | ty1 << 16, tiles_touched}: the first and
+ * last tile column and row the rect covers (all four words 0 if culled).
+ * rade_bin_sort reads these 16 bytes instead of the 80-byte splat.
  *   views_dev : V rade_view structs in device memory (after views_prepare)
  *   means N*3, scales N*3, quats N*4, opacities N, sh N*K*3 (see above)
  * A Gaussian is culled when a parameter is not finite, its camera z <=
@@ -180,7 +185,8 @@ int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
 int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
                  const float* means, const float* scales, const float* quats,
                  const float* opacities, const float* sh, rade_splat* splats,
-                 int32_t* tiles_touched, float* depth_quad, void* stream);
+                 int32_t* tiles_touched, uint32_t* bin_records, float* depth_quad,
+                 void* stream);
 
 /* Workspace bytes for rade_bin_sort with V views, N Gaussians, `capacity`
  * pairs and `total_tiles` tiles. */
@@ -191,7 +197,8 @@ size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t t
  * covers and orders the pairs by (global tile, float32 depth, Gaussian id);
  * equivalently a stable sort by the 64-bit key (tile << 32 | bits(z)).
  *   views_host/views_dev : the same V prepared views, host and device copies
- *   splats, tiles_touched: rade_project's outputs
+ *   tiles_touched, bin_records: rade_project's outputs (same settings and
+ *                           views; bin_records is required)
  *   pair_ids   [capacity] : Gaussian id of each sorted pair
  *   tile_ranges[2*total_tiles]: [begin, end) into pair_ids per global tile
  *   keys       [capacity] : optional (may be NULL), the sorted 64-bit keys
@@ -203,8 +210,9 @@ size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t t
  * range is empty ([0, 0)); *n_pairs_dev still holds M so the caller can
  * retry with capacity >= M.  capacity must be < 2^32. */
 int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
-                  const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
-                  const int32_t* tiles_touched, uint32_t* pair_ids, uint32_t* tile_ranges,
+                  const rade_view* views_dev, int32_t V, int64_t N,
+                  const int32_t* tiles_touched, const uint32_t* bin_records,
+                  uint32_t* pair_ids, uint32_t* tile_ranges,
                   uint64_t* keys, int64_t capacity, int64_t* n_pairs_dev,
                   int64_t* n_pairs_host, void* workspace, size_t workspace_bytes, void* stream);
 
@@ -465,7 +473,7 @@ const char* rade_strerror(int code);
  * present).  The entry points above make the same check themselves. */
 int rade_device_check(void);
 
-/* ABI version of this header: 5. */
+/* ABI version of this header: 6. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

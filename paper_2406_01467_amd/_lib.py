@@ -104,7 +104,7 @@ class Settings:
 
 
 _lib = None
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 def load() -> ctypes.CDLL:
@@ -117,7 +117,7 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     lib.rade_views_prepare.argtypes = [P, P, I32, P, P]
-    lib.rade_project.argtypes = [P, P, I32, I64] + [P] * 8 + [P]
+    lib.rade_project.argtypes = [P, P, I32, I64] + [P] * 9 + [P]
     lib.rade_bin_sort_workspace.argtypes = [I32, I64, I64, I64]
     lib.rade_bin_sort_workspace.restype = SZ
     lib.rade_bin_sort.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I64, P, P, P, SZ, P]
@@ -251,11 +251,12 @@ def views_to_device(views_c: ctypes.Array, device):
 
 
 def rade_project(settings: Settings, views_dev, V: int, N: int, means, scales, quats, opacities,
-                 sh, splats, tiles_touched, stream=None, depth_quad=None):
+                 sh, splats, tiles_touched, stream=None, depth_quad=None, bin_records=None):
     s = settings.c()
     return _check(load().rade_project(ctypes.byref(s), _p(views_dev), V, N, _p(means), _p(scales),
                                       _p(quats), _p(opacities), _p(sh), _p(splats),
-                                      _p(tiles_touched), _p(depth_quad), _stream(stream)),
+                                      _p(tiles_touched), _p(bin_records), _p(depth_quad),
+                                      _stream(stream)),
                   "rade_project")
 
 
@@ -263,15 +264,16 @@ def rade_bin_sort_workspace(V: int, N: int, capacity: int, total_tiles: int) -> 
     return int(load().rade_bin_sort_workspace(V, N, capacity, total_tiles))
 
 
-def rade_bin_sort(settings: Settings, views_c, views_dev, V: int, N: int, splats, tiles_touched,
-                  pair_ids, tile_ranges, keys, capacity: int, n_pairs_dev, workspace,
+def rade_bin_sort(settings: Settings, views_c, views_dev, V: int, N: int, tiles_touched,
+                  bin_records, pair_ids, tile_ranges, keys, capacity: int, n_pairs_dev, workspace,
                   stream=None, sync_count: bool = True):
     """Returns (status, M) where M is the pair count when sync_count, else None.
     Raises on any error except RADE_ERR_CAPACITY (returned as status)."""
     s = settings.c()
     host = ctypes.c_int64(-1)
-    code = load().rade_bin_sort(ctypes.byref(s), views_c, _p(views_dev), V, N, _p(splats),
-                                _p(tiles_touched), _p(pair_ids), _p(tile_ranges), _p(keys),
+    code = load().rade_bin_sort(ctypes.byref(s), views_c, _p(views_dev), V, N,
+                                _p(tiles_touched), _p(bin_records), _p(pair_ids),
+                                _p(tile_ranges), _p(keys),
                                 capacity, _p(n_pairs_dev),
                                 ctypes.byref(host) if sync_count else None, _p(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream))

@@ -60,9 +60,9 @@ class BatchedPlan:
         if capacity is None:
             # one eager binning pass sizes the pair buffers (with slack); the
             # rasterizer's buffers for it are released after
-            splats, tt = self.rast.project(*self.params)
-            _, _, M = self.rast.bin_sort(self.N, splats, tt)
-            del splats, tt
+            splats, tt, brec = self.rast.project(*self.params)
+            _, _, M = self.rast.bin_sort(self.N, tt, brec)
+            del splats, tt, brec
             self.rast.release_pairs()
             capacity = int(M * 1.15) + 4096
         self._alloc(capacity)
@@ -84,24 +84,32 @@ class BatchedPlan:
         # after the gradient records (rade.h gives the layout); the forward
         # projects into that same region, so no second copy of the V x N
         # records exists, and the region lies after the binning workspace,
-        # which reads the records while it runs.
+        # which reads the records while it runs.  The 16-byte binning records
+        # are read by rade_bin_sort while its workspace is in use: they lie
+        # beyond it (after the backward's regions with recompute, else
+        # between the binning workspace and the arena's end).
         a256 = lambda b: (b + 255) & ~255  # noqa: E731
         bin_bytes = a256(max(1, _lib.rade_bin_sort_workspace(V, N, self.capacity,
                                                              r.total_tiles)))
         bwd_bytes = a256(max(1, _lib.rade_render_bwd_workspace(self.settings, V, N,
                                                                self.recompute)))
         g_bytes = a256(V * N * 16 * 4)
+        brec_bytes = a256(16 * VN)
         if self.recompute and V * N > 0:
             head = max(bin_bytes, g_bytes)
-            self.arena = torch.empty(head - g_bytes + bwd_bytes, dtype=torch.uint8, device=dev)
-            self.bwd_ws = self.arena[head - g_bytes:]
+            end = head - g_bytes + bwd_bytes
+            self.arena = torch.empty(end + brec_bytes, dtype=torch.uint8, device=dev)
+            self.bwd_ws = self.arena[head - g_bytes: end]
+            self.brec = self.arena[end: end + 16 * VN].view(torch.int32)
             s_bytes = V * N * _lib.SPLAT_BYTES
             self.splats = self.arena[head: head + s_bytes]
             t0 = head + a256(s_bytes)
             self.tt = self.arena[t0: t0 + 4 * V * N].view(torch.int32)
         else:
-            self.arena = torch.empty(max(bin_bytes, bwd_bytes), dtype=torch.uint8, device=dev)
+            self.arena = torch.empty(max(bin_bytes + brec_bytes, bwd_bytes), dtype=torch.uint8,
+                                     device=dev)
             self.bwd_ws = self.arena[:bwd_bytes]
+            self.brec = self.arena[bin_bytes: bin_bytes + 16 * VN].view(torch.int32)
             self.splats = torch.empty(VN * _lib.SPLAT_BYTES, dtype=torch.uint8, device=dev)
             self.tt = torch.empty(VN, dtype=torch.int32, device=dev)
         self.bin_ws = self.arena[:bin_bytes]
@@ -125,8 +133,9 @@ class BatchedPlan:
         """Enqueue one fwd+bwd on the current stream (no host sync)."""
         st, r, V, N = self.settings, self.rast, self.V, self.N
         m, s, q, o, sh = self.params
-        _lib.rade_project(st, r.views_dev, V, N, m, s, q, o, sh, self.splats, self.tt)
-        _lib.rade_bin_sort(st, r.views_c, r.views_dev, V, N, self.splats, self.tt, self.pair_ids,
+        _lib.rade_project(st, r.views_dev, V, N, m, s, q, o, sh, self.splats, self.tt,
+                          bin_records=self.brec)
+        _lib.rade_bin_sort(st, r.views_c, r.views_dev, V, N, self.tt, self.brec, self.pair_ids,
                            self.ranges, None, self.capacity, self.n_dev, self.bin_ws,
                            sync_count=False)
         order = None

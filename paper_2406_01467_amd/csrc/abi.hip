@@ -12,7 +12,8 @@ namespace rade {
 hipError_t launch_project(const rade_settings& st, const rade_view* views, int V, int64_t N,
                           const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, rade_splat* splats,
-                          int32_t* tiles_touched, float* depth_quad, hipStream_t stream);
+                          int32_t* tiles_touched, uint32_t* bin_records, float* depth_quad,
+                          hipStream_t stream);
 hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, int V, int64_t N,
                               const float* means, const float* scales, const float* quats,
                               const float* opac, const float* sh, const float* gsplat,
@@ -21,7 +22,7 @@ hipError_t launch_project_bwd(const rade_settings& st, const rade_view* views, i
 size_t bin_sort_workspace(int64_t VN, int64_t capacity);
 hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
                            const rade_view* views_dev, int V, int64_t N,
-                           const rade_splat* splats, const int32_t* tt, uint32_t* pair_ids,
+                           const int32_t* tt, const uint32_t* bin_records, uint32_t* pair_ids,
                            uint32_t* ranges, uint64_t* keys, int64_t capacity,
                            int64_t* n_pairs_dev, int64_t* n_pairs_host, void* ws,
                            hipStream_t st, int* capacity_exceeded);
@@ -166,7 +167,7 @@ KernelEvents& kernel_events(int kernel) {
 
 extern "C" {
 
-int rade_abi_version(void) { return 5; }
+int rade_abi_version(void) { return 6; }
 
 int rade_device_check(void) { return device_status(); }
 
@@ -214,18 +215,20 @@ int rade_views_prepare(const rade_settings* s, rade_view* views, int32_t V,
 int rade_project(const rade_settings* s, const rade_view* views_dev, int32_t V, int64_t N,
                  const float* means, const float* scales, const float* quats,
                  const float* opacities, const float* sh, rade_splat* splats,
-                 int32_t* tiles_touched, float* depth_quad, void* stream) {
+                 int32_t* tiles_touched, uint32_t* bin_records, float* depth_quad,
+                 void* stream) {
   if (!settings_ok(s) || !views_dev || !counts_ok(V, N)) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !splats || !tiles_touched))
     return RADE_ERR_INVALID_ARG;
-  if ((reinterpret_cast<uintptr_t>(quats) & 15) != 0) return RADE_ERR_INVALID_ARG;
+  if (((reinterpret_cast<uintptr_t>(quats) | reinterpret_cast<uintptr_t>(bin_records)) & 15) != 0)
+    return RADE_ERR_INVALID_ARG;
   const bool exact = s->depth_mode == RADE_DEPTH_EXACT;
   if (exact && N > 0 && (!depth_quad || (reinterpret_cast<uintptr_t>(depth_quad) & 15) != 0))
     return RADE_ERR_INVALID_ARG;
   if (const int dv = device_status(); dv != RADE_OK) return dv;
   return hip_status(rade::launch_project(*s, views_dev, V, N, means, scales, quats, opacities,
-                                         sh, splats, tiles_touched, exact ? depth_quad : nullptr,
-                                         (hipStream_t)stream));
+                                         sh, splats, tiles_touched, bin_records,
+                                         exact ? depth_quad : nullptr, (hipStream_t)stream));
 }
 
 size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t total_tiles) {
@@ -235,8 +238,9 @@ size_t rade_bin_sort_workspace(int32_t V, int64_t N, int64_t capacity, int64_t t
 }
 
 int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
-                  const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
-                  const int32_t* tiles_touched, uint32_t* pair_ids, uint32_t* tile_ranges,
+                  const rade_view* views_dev, int32_t V, int64_t N,
+                  const int32_t* tiles_touched, const uint32_t* bin_records,
+                  uint32_t* pair_ids, uint32_t* tile_ranges,
                   uint64_t* keys, int64_t capacity, int64_t* n_pairs_dev,
                   int64_t* n_pairs_host, void* workspace, size_t workspace_bytes,
                   void* stream) {
@@ -244,7 +248,8 @@ int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
     return RADE_ERR_INVALID_ARG;
   if (capacity < 0 || capacity >= ((int64_t)1 << 32)) return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !n_pairs_dev || (capacity > 0 && !pair_ids)) return RADE_ERR_INVALID_ARG;
-  if (N > 0 && (!splats || !tiles_touched)) return RADE_ERR_INVALID_ARG;
+  if (N > 0 && (!tiles_touched || !bin_records)) return RADE_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(bin_records) & 15) != 0) return RADE_ERR_INVALID_ARG;
   for (int i = 0; i < V; ++i)
     if (views_host[i].tiles_x != (views_host[i].width + s->tile_w - 1) / s->tile_w ||
         views_host[i].tiles_y != (views_host[i].height + s->tile_h - 1) / s->tile_h)
@@ -253,8 +258,8 @@ int rade_bin_sort(const rade_settings* s, const rade_view* views_host,
     return RADE_ERR_WORKSPACE;
   if (const int dv = device_status(); dv != RADE_OK) return dv;
   int exceeded = 0;
-  const hipError_t e = rade::launch_bin_sort(*s, views_host, views_dev, V, N, splats,
-                                             tiles_touched, pair_ids, tile_ranges, keys, capacity,
+  const hipError_t e = rade::launch_bin_sort(*s, views_host, views_dev, V, N, tiles_touched,
+                                             bin_records, pair_ids, tile_ranges, keys, capacity,
                                              n_pairs_dev, n_pairs_host, workspace,
                                              (hipStream_t)stream, &exceeded);
   if (e != hipSuccess) return RADE_ERR_HIP;
@@ -432,7 +437,7 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
     int32_t* tt = reinterpret_cast<int32_t*>(
         w + g_bytes + (((VN * sizeof(rade_splat)) + 255) & ~size_t(255)));
     const hipError_t e = rade::launch_project(*s, views_dev, V, N, means, scales, quats,
-                                              opacities, sh, rs, tt, nullptr, st);
+                                              opacities, sh, rs, tt, nullptr, nullptr, st);
     if (e != hipSuccess) return RADE_ERR_HIP;
     splats = rs;
   }

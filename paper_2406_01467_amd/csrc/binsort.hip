@@ -36,32 +36,22 @@ constexpr int kMaxRadix = 512;
 constexpr int kEmitPairs = kTile;                // pairs per emission block (one radix block)
 
 // Compaction of the visible splats (tiles touched > 0), read in index order:
-// the depth sort's keys (bits of the float32 view depth) and values (the
-// compaction position p), and a 16-byte record per visible splat: its index
-// and tile rect (tx0 | ty0 << 16, tx1 | ty1 << 16; a visible splat's pixel
-// rect lies inside its view, so the tile bounds are shifts of it, tile sizes
-// being powers of two) and its tile count.  The depth sort's last pass
-// gathers the records into depth order, so the pair emission reads them in
-// order instead of gathering 80-byte splat records.
+// the depth sort's keys (bits of the float32 view depth, from the splat's
+// 16-byte binning record) and values (the splat's index).  The depth sort's
+// last pass gathers the binning records into depth order (the index in
+// place of the depth word), so the pair emission reads them in order
+// instead of gathering records by index.
 struct Visible {
   const int32_t* tt;
   __device__ uint32_t operator()(int64_t i) const { return tt[i] > 0 ? 1u : 0u; }
 };
 struct VisibleOut {
-  const rade_splat* splats;
-  int log2_tw, log2_th;
+  const uint4* brecs;
   uint32_t* keys;
   uint32_t* vals;
-  uint4* recs;
   __device__ void operator()(int64_t i, uint32_t p, uint32_t) const {
-    const rade_splat& sp = splats[i];
-    keys[p] = __float_as_uint(sp.z);  // z > near > 0: bits order like values
-    vals[p] = p;
-    const uint32_t tx0 = (uint32_t)sp.rect[0] >> log2_tw, tx1 = (uint32_t)sp.rect[1] >> log2_tw;
-    const uint32_t ty0 = (uint32_t)sp.rect[2] >> log2_th, ty1 = (uint32_t)sp.rect[3] >> log2_th;
-    // the tile count, as the projection counts it from the same rect
-    recs[p] = make_uint4((uint32_t)i, tx0 | (ty0 << 16), tx1 | (ty1 << 16),
-                         (tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    keys[p] = brecs[i].x;  // z > near > 0: bits order like values
+    vals[p] = (uint32_t)i;
   }
 };
 
@@ -345,7 +335,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
       vout[dst] = v;
       if constexpr (GATHER) {
         const uint4 rec = gsrc[v];
-        gout[dst] = rec;
+        gout[dst] = make_uint4(v, rec.y, rec.z, rec.w);
         cout[dst] = rec.w;
       }
     }
@@ -539,14 +529,14 @@ k_ranges(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ m32, i
 
 __global__ void __launch_bounds__(kThreads)
 k_keys(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ pids,
-       const uint32_t* __restrict__ m32, const rade_splat* __restrict__ splats,
+       const uint32_t* __restrict__ m32, const uint4* __restrict__ brecs,
        const rade_view* __restrict__ views, int V, int64_t N, uint64_t* __restrict__ keys) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= (int64_t)*m32) return;
   const uint32_t t = tkeys[i];
   const int v = view_of_tile(views, V, t);
-  const float z = splats[(int64_t)v * N + pids[i]].z;
-  keys[i] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(z);
+  const uint32_t zbits = brecs[(int64_t)v * N + pids[i]].x;  // bits of the float32 depth
+  keys[i] = ((uint64_t)t << 32) | (uint64_t)zbits;
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -586,8 +576,8 @@ inline int digit_bits(int bits) {
 // (k1, v1).  Returns the number of passes.  first_counted: the first pass's
 // per-block counts (of digits that wide) are already in sp.hist.
 // gsrc: the last pass also writes the record gsrc[value] of every item (the
-// values index gsrc), in the sorted order, to gout, and its last word to
-// cout.
+// values index gsrc), in the sorted order and with the value in place of
+// its first word, to gout, and its last word to cout.
 template <int RB>
 int radix_sort_rb(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_max,
                   const uint32_t* n_dev, int bits, const SortSpace& sp, hipStream_t st,
@@ -630,7 +620,7 @@ int radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n
 }
 
 struct Layout {
-  size_t starts, dkeys0, dvals0, dkeys1, dvals1, crec, drec, dcnt, offs, tkeys0, tkeys1, pids1,
+  size_t starts, dkeys0, dvals0, dkeys1, dvals1, drec, dcnt, offs, tkeys0, tkeys1, pids1,
       sort, sums, scal;
   size_t total;
 };
@@ -651,7 +641,6 @@ Layout layout(int64_t VN, int64_t capacity) {
   L.dvals0 = take(sizeof(uint32_t) * VN);
   L.dkeys1 = take(sizeof(uint32_t) * VN);
   L.dvals1 = take(sizeof(uint32_t) * VN);
-  L.crec = take(sizeof(uint4) * VN);
   L.drec = take(sizeof(uint4) * VN);
   L.dcnt = take(sizeof(uint32_t) * VN);
   L.offs = take(sizeof(uint64_t) * VN);
@@ -779,7 +768,7 @@ size_t bin_sort_workspace(int64_t VN, int64_t capacity) { return layout(VN, capa
 
 hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
                            const rade_view* views_dev, int V, int64_t N,
-                           const rade_splat* splats, const int32_t* tt, uint32_t* pair_ids,
+                           const int32_t* tt, const uint32_t* bin_records, uint32_t* pair_ids,
                            uint32_t* ranges, uint64_t* keys, int64_t capacity,
                            int64_t* n_pairs_dev, int64_t* n_pairs_host, void* ws,
                            hipStream_t st, int* capacity_exceeded) {
@@ -792,7 +781,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   uint32_t* dv0 = (uint32_t*)(w + L.dvals0);
   uint32_t* dk1 = (uint32_t*)(w + L.dkeys1);
   uint32_t* dv1 = (uint32_t*)(w + L.dvals1);
-  uint4* crec = (uint4*)(w + L.crec);
+  const uint4* brecs = reinterpret_cast<const uint4*>(bin_records);
   uint4* drec = (uint4*)(w + L.drec);
   uint32_t* dcnt = (uint32_t*)(w + L.dcnt);
   uint64_t* offs = (uint64_t*)(w + L.offs);
@@ -812,13 +801,13 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   // 1. visible splats -> compact (depth key, index) list
   if (VN > 0) {
     scan_emit<uint32_t>(Visible{tt}, VN, (uint32_t*)sums, n_vis,
-                        VisibleOut{splats, ceil_log2(s.tile_w), ceil_log2(s.tile_h), dk0, dv0, crec},
+                        VisibleOut{brecs, dk0, dv0},
                         st);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, n_vis, 1, 0u);
   }
   // 2. depth sort
-  radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st, false, crec, drec,
+  radix_sort(dk0, dv0, dk1, dv1, VN, n_vis, 32, sort_space(sortw, VN), st, false, brecs, drec,
              dcnt);
   // 3. pair offsets in depth order (and the pair counts)
   if (VN > 0) {
@@ -880,7 +869,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
   // 7. optional 64-bit keys
   if (keys && capacity > 0)
     hipLaunchKernelGGL(k_keys, dim3(blocks_for(capacity, kThreads)), dim3(kThreads), 0, st, sk,
-                       pair_ids, m32, splats, views_dev, V, N, keys);
+                       pair_ids, m32, brecs, views_dev, V, N, keys);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "rade.h"
@@ -19,6 +20,12 @@ constexpr int kOriginAlign = 32;
 constexpr double kLog2eD = 1.4426950408889634;
 
 static_assert(sizeof(rade_splat) == 80, "splat record must be 80 bytes");
+// the projection stores the record as five 16-byte words
+static_assert(offsetof(rade_splat, w) == 16 && offsetof(rade_splat, opacity) == 32 &&
+                  offsetof(rade_splat, rgb) == 36 && offsetof(rade_splat, z) == 48 &&
+                  offsetof(rade_splat, p) == 52 && offsetof(rade_splat, n) == 60 &&
+                  offsetof(rade_splat, rect) == 72,
+              "splat record layout");
 static_assert(sizeof(rade_view) == 96, "view record must be 96 bytes");
 
 // Render thresholds in the precision the blend loop uses.  Shared by the

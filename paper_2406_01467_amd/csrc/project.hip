@@ -391,7 +391,8 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
           const float* __restrict__ means, const float* __restrict__ scales,
           const float* __restrict__ quats, const float* __restrict__ opac,
           const float* __restrict__ sh, rade_splat* __restrict__ splats,
-          int32_t* __restrict__ tiles_touched, float4* __restrict__ depth_quad) {
+          int32_t* __restrict__ tiles_touched, uint4* __restrict__ bin_records,
+          float4* __restrict__ depth_quad) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   const int deg = st.sh_degree;
@@ -423,6 +424,7 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
     if (!vis) {
       store_invisible(splats + o);
       tiles_touched[o] = 0;
+      if (bin_records) bin_records[o] = make_uint4(0u, 0u, 0u, 0u);
       if constexpr (EXACT) {
         depth_quad[2 * o] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         depth_quad[2 * o + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -430,9 +432,44 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
       continue;
     }
     if constexpr (EXACT) exact_depth_record(v, P, G, depth_quad + 2 * o);
-    rade_splat out;
-    out.uc = v.fx * G.X / G.Z + v.cx;
-    out.vc = v.fy * G.Y / G.Z + v.cy;
+    // The record is stored in its five 16-byte words as soon as each is
+    // complete (fewer values live at once than with one store at the end).
+    float4* rec = reinterpret_cast<float4*>(splats + o);
+    const double uc = v.fx * G.X / G.Z + v.cx;
+    const double vc = v.fy * G.Y / G.Z + v.cy;
+    reinterpret_cast<double2*>(splats + o)[0] = make_double2(uc, vc);
+    // support rect: alpha = o e^-power >= alpha_min inside power <= tau
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    {
+      const double tau = fmin(st.power_cut, log((double)P.o / st.alpha_min));
+      const double rx = sqrt(2.0 * tau * G.D00) * (1.0 + 1e-6) + 1e-3;
+      const double ry = sqrt(2.0 * tau * G.D11) * (1.0 + 1e-6) + 1e-3;
+      const double xlo = (uc - rx) - 0.5, xhi = (uc + rx) - 0.5;
+      const double ylo = (vc - ry) - 0.5, yhi = (vc + ry) - 0.5;
+      if (isfinite(xlo) && isfinite(xhi) && isfinite(ylo) && isfinite(yhi) && xhi >= 0.0 &&
+          yhi >= 0.0 && xlo <= v.W - 1.0 && ylo <= v.H - 1.0) {
+        x0 = max(0, (int)ceil(fmax(xlo, -1.0)));
+        x1 = min(v.W - 1, (int)floor(fmin(xhi, (double)v.W)));
+        y0 = max(0, (int)ceil(fmax(ylo, -1.0)));
+        y1 = min(v.H - 1, (int)floor(fmin(yhi, (double)v.H)));
+      }
+    }
+    // tile sizes are powers of two
+    const int lw = __builtin_ctz((unsigned)st.tile_w), lh = __builtin_ctz((unsigned)st.tile_h);
+    int32_t nt = 0;
+    if (x0 <= x1 && y0 <= y1) {
+      nt = ((x1 >> lw) - (x0 >> lw) + 1) * ((y1 >> lh) - (y0 >> lh) + 1);
+    } else {
+      x0 = 0; x1 = -1; y0 = 0; y1 = -1;
+    }
+    tiles_touched[o] = nt;
+    const float z = (float)G.Z;
+    if (bin_records)
+      bin_records[o] = nt > 0 ? make_uint4(__float_as_uint(z),
+                                           (uint32_t)(x0 >> lw) | ((uint32_t)(y0 >> lh) << 16),
+                                           (uint32_t)(x1 >> lw) | ((uint32_t)(y1 >> lh) << 16),
+                                           (uint32_t)nt)
+                              : make_uint4(0u, 0u, 0u, 0u);
     // Eigen-factored quadratic form of the dilated footprint.
     {
       const double m = 0.5 * (G.D00 + G.D11);
@@ -453,52 +490,26 @@ k_project(rade_settings st, const rade_view* __restrict__ views, int V, int64_t 
       ex *= en; ey *= en;
       const double k1 = sqrt(kLog2eD / (2.0 * l1));
       const double k2 = sqrt(kLog2eD / (2.0 * l2));
-      out.w[0] = (float)(ex * k1); out.w[1] = (float)(ey * k1);
-      out.w[2] = (float)(-ey * k2); out.w[3] = (float)(ex * k2);
+      rec[1] = make_float4((float)(ex * k1), (float)(ey * k1), (float)(-ey * k2),
+                           (float)(ex * k2));
     }
-    out.opacity = P.o;
-    out.z = (float)G.Z;
-    const double zt = G.Z / G.tc;
-    out.p[0] = (float)(zt * G.q0);
-    out.p[1] = (float)(zt * G.q1);
-    const double inl = 1.0 / G.nlen;
-    out.n[0] = (float)(G.nr[0] * inl);
-    out.n[1] = (float)(G.nr[1] * inl);
-    out.n[2] = (float)(G.nr[2] * inl);
+    {
+      const double zt = G.Z / G.tc;
+      const double inl = 1.0 / G.nlen;
+      rec[3] = make_float4(z, (float)(zt * G.q0), (float)(zt * G.q1), (float)(G.nr[0] * inl));
+      // normal (y, z) and the rect x0, x1, y0, y1 as 16-bit integers
+      const uint32_t rx01 = (uint32_t)(uint16_t)x0 | ((uint32_t)(uint16_t)x1 << 16);
+      const uint32_t ry01 = (uint32_t)(uint16_t)y0 | ((uint32_t)(uint16_t)y1 << 16);
+      rec[4] = make_float4((float)(G.nr[1] * inl), (float)(G.nr[2] * inl), __uint_as_float(rx01),
+                           __uint_as_float(ry01));
+    }
     {
       double u[3], raw[3];
       view_dir(P.mu, v.C, u);
       sh_colour<K>(deg, u, coef, raw);
-      out.rgb[0] = (float)fmax(raw[0], 0.0);
-      out.rgb[1] = (float)fmax(raw[1], 0.0);
-      out.rgb[2] = (float)fmax(raw[2], 0.0);
+      rec[2] = make_float4(P.o, (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0),
+                           (float)fmax(raw[2], 0.0));
     }
-    // support rect: alpha = o e^-power >= alpha_min inside power <= tau
-    const double tau = fmin(st.power_cut, log((double)P.o / st.alpha_min));
-    const double rx = sqrt(2.0 * tau * G.D00) * (1.0 + 1e-6) + 1e-3;
-    const double ry = sqrt(2.0 * tau * G.D11) * (1.0 + 1e-6) + 1e-3;
-    const double xlo = (out.uc - rx) - 0.5, xhi = (out.uc + rx) - 0.5;
-    const double ylo = (out.vc - ry) - 0.5, yhi = (out.vc + ry) - 0.5;
-    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
-    if (isfinite(xlo) && isfinite(xhi) && isfinite(ylo) && isfinite(yhi) && xhi >= 0.0 &&
-        yhi >= 0.0 && xlo <= v.W - 1.0 && ylo <= v.H - 1.0) {
-      x0 = max(0, (int)ceil(fmax(xlo, -1.0)));
-      x1 = min(v.W - 1, (int)floor(fmin(xhi, (double)v.W)));
-      y0 = max(0, (int)ceil(fmax(ylo, -1.0)));
-      y1 = min(v.H - 1, (int)floor(fmin(yhi, (double)v.H)));
-    }
-    int32_t nt = 0;
-    if (x0 <= x1 && y0 <= y1) {
-      const int tx0 = x0 / st.tile_w, tx1 = x1 / st.tile_w;
-      const int ty0 = y0 / st.tile_h, ty1 = y1 / st.tile_h;
-      nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    } else {
-      x0 = 0; x1 = -1; y0 = 0; y1 = -1;
-    }
-    out.rect[0] = (int16_t)x0; out.rect[1] = (int16_t)x1;
-    out.rect[2] = (int16_t)y0; out.rect[3] = (int16_t)y1;
-    splats[o] = out;
-    tiles_touched[o] = nt;
   }
 }
 
@@ -919,8 +930,10 @@ k_project_bwd_sh(rade_settings st, const rade_view* __restrict__ views, int V, i
 hipError_t launch_project(const rade_settings& st, const rade_view* views, int V, int64_t N,
                           const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, rade_splat* splats,
-                          int32_t* tiles_touched, float* depth_quad, hipStream_t stream) {
+                          int32_t* tiles_touched, uint32_t* bin_records, float* depth_quad,
+                          hipStream_t stream) {
   if (N == 0) return hipSuccess;
+  uint4* br = reinterpret_cast<uint4*>(bin_records);
   const dim3 block(256);
   const dim3 grid((unsigned)((N + 255) / 256));
   EventScope timing(RADE_KERNEL_PROJECT, stream);
@@ -928,7 +941,7 @@ hipError_t launch_project(const rade_settings& st, const rade_view* views, int V
   float4* dq = reinterpret_cast<float4*>(depth_quad);
 #define RADE_PROJECT_E(K, V4, E)                                                             \
   hipLaunchKernelGGL((k_project<K, V4, E>), grid, block, 0, stream, st, views, V, N, means,  \
-                     scales, quats, opac, sh, splats, tiles_touched, dq)
+                     scales, quats, opac, sh, splats, tiles_touched, br, dq)
 #define RADE_PROJECT(K, V4)                                                                 \
   do {                                                                                      \
     if (dq) RADE_PROJECT_E(K, V4, true); else RADE_PROJECT_E(K, V4, false);                 \

@@ -101,15 +101,17 @@ class Rasterizer:
 
     # -- forward -------------------------------------------------------------
     def project(self, means, scales, quats, opacities, sh, stream=None, depth_quad=None):
-        """depth_quad: (V*N*8,) float32 buffer for the exact-depth records
-        (required in RADE_DEPTH_EXACT mode)."""
+        """Returns (splats, tiles_touched, bin_records).  depth_quad: (V*N*8,)
+        float32 buffer for the exact-depth records (required in
+        RADE_DEPTH_EXACT mode)."""
         N = means.shape[0]
         VN = self.V * N
         splats = torch.empty(max(1, VN) * _lib.SPLAT_BYTES, dtype=torch.uint8, device=self.device)
         tt = torch.empty(max(1, VN), dtype=torch.int32, device=self.device)
+        brec = torch.empty(4 * max(1, VN), dtype=torch.int32, device=self.device)
         _lib.rade_project(self.settings, self.views_dev, self.V, N, means, scales,
-                          _aligned16(quats), opacities, sh, splats, tt, stream, depth_quad)
-        return splats, tt
+                          _aligned16(quats), opacities, sh, splats, tt, stream, depth_quad, brec)
+        return splats, tt, brec
 
     @property
     def exact_depth(self) -> bool:
@@ -122,7 +124,7 @@ class Rasterizer:
         self._bin_ws = None
         self._n = -1
 
-    def bin_sort(self, N: int, splats, tt, want_keys: bool = False, stream=None):
+    def bin_sort(self, N: int, tt, brec, want_keys: bool = False, stream=None):
         if self._pairs is None or self._n != N:
             self._alloc_pairs(N, max(self.capacity, 16 * max(N, 1) * self.V // 4 + 1024))
         ranges = torch.empty(2 * max(1, self.total_tiles), dtype=torch.int32, device=self.device)
@@ -131,7 +133,7 @@ class Rasterizer:
             keys = (torch.empty(max(1, self.capacity), dtype=torch.int64, device=self.device)
                     if want_keys else None)
             code, M = _lib.rade_bin_sort(self.settings, self.views_c, self.views_dev, self.V, N,
-                                         splats, tt, self._pairs, ranges, keys, self.capacity,
+                                         tt, brec, self._pairs, ranges, keys, self.capacity,
                                          n_dev, self._bin_ws, stream, sync_count=True)
             if code == _lib.RADE_OK:
                 break
@@ -147,8 +149,8 @@ class Rasterizer:
         N = means.shape[0]
         quad = (torch.empty(max(1, self.V * N) * 8, dtype=torch.float32, device=self.device)
                 if self.exact_depth else None)
-        splats, tt = self.project(means, scales, quats, opacities, sh, stream, depth_quad=quad)
-        pair_ids, ranges, M = self.bin_sort(N, splats, tt, stream=stream)
+        splats, tt, brec = self.project(means, scales, quats, opacities, sh, stream, depth_quad=quad)
+        pair_ids, ranges, M = self.bin_sort(N, tt, brec, stream=stream)
         order = self.tile_order(ranges, stream)
         color, depth, normal, alpha, tf, last, med, cnt = self._new_maps(want_count)
         dist = (torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)

@@ -92,7 +92,7 @@ def test_invalid_settings_rejected_without_launch(bad):
     # an invalid setting or a zero view count never reach HIP
     so = lib.load()
     s = lib.Settings(**bad).c()
-    assert so.rade_project(ctypes.byref(s), None, 1, 10, *([None] * 8), None) == \
+    assert so.rade_project(ctypes.byref(s), None, 1, 10, *([None] * 9), None) == \
         lib.RADE_ERR_INVALID_ARG
 
 
@@ -102,26 +102,28 @@ def test_null_pointers_rejected():
     s = lib.Settings().c()
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     assert so.rade_project(ctypes.byref(s), dummy, 1, 10, None, dummy, dummy, dummy, dummy,
-                           dummy, dummy, None, None) == lib.RADE_ERR_INVALID_ARG
-    assert so.rade_project(ctypes.byref(s), dummy, 0, 10, *([dummy] * 8), None) == \
+                           dummy, dummy, None, None, None) == lib.RADE_ERR_INVALID_ARG
+    assert so.rade_project(ctypes.byref(s), dummy, 0, 10, *([dummy] * 9), None) == \
         lib.RADE_ERR_INVALID_ARG
-    # misaligned quaternion array
+    # misaligned quaternion array, misaligned binning records
     assert so.rade_project(ctypes.byref(s), dummy, 1, 10, dummy, dummy, ctypes.c_void_p(20),
-                           dummy, dummy, dummy, dummy, None, None) == lib.RADE_ERR_INVALID_ARG
+                           dummy, dummy, dummy, dummy, None, None, None) == lib.RADE_ERR_INVALID_ARG
+    assert so.rade_project(ctypes.byref(s), dummy, 1, 10, *([dummy] * 7), ctypes.c_void_p(24),
+                           None, None) == lib.RADE_ERR_INVALID_ARG
     # exact depth: the depth_quad records are required and 16-byte aligned;
     # the backward rejects the mode; unknown modes and a nonzero reserved
     # field are rejected
     se = lib.Settings(depth_mode=lib.RADE_DEPTH_EXACT).c()
-    assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), None, None) == \
+    assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), None, None, None) == \
         lib.RADE_ERR_INVALID_ARG
-    assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), ctypes.c_void_p(24),
-                           None) == lib.RADE_ERR_INVALID_ARG
+    assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), None,
+                           ctypes.c_void_p(24), None) == lib.RADE_ERR_INVALID_ARG
     bad = lib.Settings(depth_mode=2).c()
-    assert so.rade_project(ctypes.byref(bad), dummy, 1, 10, *([dummy] * 8), None) == \
+    assert so.rade_project(ctypes.byref(bad), dummy, 1, 10, *([dummy] * 9), None) == \
         lib.RADE_ERR_INVALID_ARG
     res = lib.Settings().c()
     res.reserved = 1
-    assert so.rade_project(ctypes.byref(res), dummy, 1, 10, *([dummy] * 8), None) == \
+    assert so.rade_project(ctypes.byref(res), dummy, 1, 10, *([dummy] * 9), None) == \
         lib.RADE_ERR_INVALID_ARG
     import synth
     vc = lib.make_views([synth.identity_view(32, 32)])
@@ -135,6 +137,11 @@ def test_null_pointers_rejected():
     code = so.rade_bin_sort(ctypes.byref(s2), vc, dummy, 1, 10, dummy, dummy, dummy, dummy, None,
                             100, dummy, None, dummy, 1 << 30, None)
     assert code == lib.RADE_ERR_INVALID_ARG
+    # the binning records are required and 16-byte aligned
+    for brec in (None, ctypes.c_void_p(24)):
+        code = so.rade_bin_sort(ctypes.byref(s), vc, dummy, 1, 10, dummy, brec, dummy, dummy,
+                                None, 100, dummy, None, dummy, 1 << 30, None)
+        assert code == lib.RADE_ERR_INVALID_ARG
     assert lib.strerror(lib.RADE_ERR_CAPACITY).startswith("output capacity")
 
 
@@ -239,9 +246,9 @@ def test_no_device_is_unsupported_and_nothing_launches():
     assert lib.rade_device_check() == lib.RADE_ERR_UNSUPPORTED_DEVICE  # cached answer
     s = lib.Settings().c()
     d = ctypes.c_void_p(256)
-    assert so.rade_project(ctypes.byref(s), d, 1, 10, *([d] * 7), None, None) == \
+    assert so.rade_project(ctypes.byref(s), d, 1, 10, *([d] * 7), None, None, None) == \
         lib.RADE_ERR_UNSUPPORTED_DEVICE
-    assert so.rade_project(ctypes.byref(s), d, 0, 10, *([d] * 7), None, None) == \
+    assert so.rade_project(ctypes.byref(s), d, 0, 10, *([d] * 7), None, None, None) == \
         lib.RADE_ERR_INVALID_ARG
     vc = lib.make_views([synth.identity_view(32, 32)])
     lib.rade_views_prepare(lib.Settings(), vc)

@@ -87,8 +87,8 @@ def test_tile_order_is_heavy_first_permutation(large):
         st = Settings(sh_degree=3, schedule=1, tile_w=8, tile_h=8)
     rast = Rasterizer(views, st, dev)
     assert (rast.total_tiles > 16384) == large
-    splats, tt = rast.project(*to_dev(scene, dev))
-    _, ranges, M = rast.bin_sort(scene.n, splats, tt)
+    splats, tt, brec = rast.project(*to_dev(scene, dev))
+    _, ranges, M = rast.bin_sort(scene.n, tt, brec)
     order = rast.tile_order(ranges)
     torch.cuda.synchronize()
     o = order.cpu().numpy()[:-1].astype(np.int64)

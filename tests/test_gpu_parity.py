@@ -36,10 +36,11 @@ def _gpu_splats(scene, views, s, dev):
     from paper_2406_01467_amd.raster import Rasterizer
     from paper_2406_01467_amd import _lib
     rast = Rasterizer(views, s, dev)
-    splats, tt = rast.project(*to_dev(scene, dev))
+    splats, tt, brec = rast.project(*to_dev(scene, dev))
     torch.cuda.synchronize()
     sp = splats.cpu().numpy().view(_lib.SPLAT_DTYPE).reshape(len(views), scene.n)
-    return sp, tt.cpu().numpy().reshape(len(views), scene.n), rast
+    br = brec.cpu().numpy().view(np.uint32).reshape(len(views), scene.n, 4)
+    return sp, tt.cpu().numpy().reshape(len(views), scene.n), rast, br
 
 
 @pytest.mark.parametrize("name,n", [("plain_64x64_1k", None), ("plain_800x800_200k", 20000),
@@ -49,7 +50,7 @@ def test_project_parity(name, n):
     scene, views = _workload(name, n)
     s = _settings(sh_degree=scene.sh_degree)
     say("project parity", name, scene.n)
-    sp, tt, _ = _gpu_splats(scene, views, s, dev)
+    sp, tt, _, br = _gpu_splats(scene, views, s, dev)
     rec, rect, flags = oracle.project(oracle_settings(s), views, scene)
     R = oracle.R
     vis = (flags & oracle.F_VISIBLE) != 0
@@ -60,6 +61,9 @@ def test_project_parity(name, n):
     tx = (rect[..., 1] // 16 - rect[..., 0] // 16 + 1) * (rect[..., 3] // 16 - rect[..., 2] // 16 + 1)
     np.testing.assert_array_equal(tt[vis], tx[vis])
     assert (tt[~vis] == 0).all()
+    # the binning records: depth bits, first and last tile column and row,
+    # tile count; zero for culled splats
+    np.testing.assert_array_equal(br, _pack_bin_records(rect, sp["z"], (16, 16)))
     g, o = sp[vis], rec[vis]
 
     def rel(got, ref, what, tol=1e-5):
@@ -91,12 +95,21 @@ def test_project_parity(name, n):
 # ---------------------------------------------------------------------------
 # binning / sorting
 
-def _pack_splats(rect, z):
-    from paper_2406_01467_amd import _lib
-    sp = np.zeros(rect.shape[:2], _lib.SPLAT_DTYPE)
-    sp["rect"] = rect.astype(np.int16)
-    sp["z"] = z
-    return sp
+def _pack_bin_records(rect, z, tile):
+    """rade_project's 16-byte binning records for pixel rects (x0, x1, y0,
+    y1; empty when x0 > x1) and float32 depths: (bits of z, tx0 | ty0 << 16,
+    tx1 | ty1 << 16, tile count), zero for an empty rect."""
+    rect = np.asarray(rect, np.int64)
+    vis = rect[..., 0] <= rect[..., 1]
+    tx0, tx1 = rect[..., 0] // tile[0], rect[..., 1] // tile[0]
+    ty0, ty1 = rect[..., 2] // tile[1], rect[..., 3] // tile[1]
+    out = np.zeros(rect.shape[:-1] + (4,), np.uint32)
+    out[..., 0] = np.ascontiguousarray(z, np.float32).view(np.uint32)
+    out[..., 1] = tx0 | (ty0 << 16)
+    out[..., 2] = tx1 | (ty1 << 16)
+    out[..., 3] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
+    out[~vis] = 0
+    return out
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32), (32, 16)])
@@ -115,14 +128,14 @@ def test_bin_sort_bit_exact_on_shared_input(tile):
     z[0, :300] = z[0, 300]  # ties resolved by id
     ids_ref, keys_ref, ranges_ref = oracle.bin_pairs(views, rect, z, tile)
     say("bin exact", tile, len(ids_ref))
-    sp = _pack_splats(rect, z)
+    br = _pack_bin_records(rect, z, tile)
     vis = rect[..., 0] <= rect[..., 1]
     tt = np.where(vis, (rect[..., 1] // tile[0] - rect[..., 0] // tile[0] + 1) *
                   (rect[..., 3] // tile[1] - rect[..., 2] // tile[1] + 1), 0).astype(np.int32)
     vc = _lib.make_views(views)
     P, T = _lib.rade_views_prepare(s, vc)
     vdev = _lib.views_to_device(vc, dev)
-    sp_d = torch.from_numpy(sp.view(np.uint8).reshape(-1).copy()).to(dev)
+    br_d = torch.from_numpy(br.view(np.int32).reshape(-1).copy()).to(dev)
     tt_d = torch.from_numpy(tt.reshape(-1)).to(dev)
     cap = len(ids_ref) + 37
     ids = torch.full((cap,), -7, dtype=torch.int32, device=dev)
@@ -130,7 +143,7 @@ def test_bin_sort_bit_exact_on_shared_input(tile):
     ranges = torch.empty(2 * T, dtype=torch.int32, device=dev)
     ndev = torch.empty(1, dtype=torch.int64, device=dev)
     ws = torch.empty(_lib.rade_bin_sort_workspace(2, scene.n, cap, T), dtype=torch.uint8, device=dev)
-    code, M = _lib.rade_bin_sort(s, vc, vdev, 2, scene.n, sp_d, tt_d, ids, ranges, keys, cap, ndev, ws)
+    code, M = _lib.rade_bin_sort(s, vc, vdev, 2, scene.n, tt_d, br_d, ids, ranges, keys, cap, ndev, ws)
     torch.cuda.synchronize()
     assert code == 0 and M == len(ids_ref) and int(ndev.item()) == M
     assert np.array_equal(ids[:M].cpu().numpy().view(np.uint32), ids_ref)
@@ -156,7 +169,7 @@ def test_bin_sort_nine_bit_tile_digits(sizes):
     rec, rect, flags = oracle.project(oracle_settings(s), views, scene)
     z = rec[..., oracle.R["z"]].astype(np.float32)
     ids_ref, keys_ref, ranges_ref = oracle.bin_pairs(views, rect, z, tile)
-    sp = _pack_splats(rect, z)
+    br = _pack_bin_records(rect, z, tile)
     vis = rect[..., 0] <= rect[..., 1]
     tt = np.where(vis, (rect[..., 1] // tile[0] - rect[..., 0] // tile[0] + 1) *
                   (rect[..., 3] // tile[1] - rect[..., 2] // tile[1] + 1), 0).astype(np.int32)
@@ -166,7 +179,7 @@ def test_bin_sort_nine_bit_tile_digits(sizes):
     say("bin 9-bit", sizes, T, len(ids_ref))
     vdev = _lib.views_to_device(vc, dev)
     V = len(views)
-    sp_d = torch.from_numpy(sp.view(np.uint8).reshape(-1).copy()).to(dev)
+    br_d = torch.from_numpy(br.view(np.int32).reshape(-1).copy()).to(dev)
     tt_d = torch.from_numpy(tt.reshape(-1)).to(dev)
     cap = len(ids_ref) + 5
     ids = torch.full((cap,), -7, dtype=torch.int32, device=dev)
@@ -174,7 +187,7 @@ def test_bin_sort_nine_bit_tile_digits(sizes):
     ranges = torch.empty(2 * T, dtype=torch.int32, device=dev)
     ndev = torch.empty(1, dtype=torch.int64, device=dev)
     ws = torch.empty(_lib.rade_bin_sort_workspace(V, scene.n, cap, T), dtype=torch.uint8, device=dev)
-    code, M = _lib.rade_bin_sort(s, vc, vdev, V, scene.n, sp_d, tt_d, ids, ranges, keys, cap, ndev, ws)
+    code, M = _lib.rade_bin_sort(s, vc, vdev, V, scene.n, tt_d, br_d, ids, ranges, keys, cap, ndev, ws)
     torch.cuda.synchronize()
     assert code == 0 and M == len(ids_ref) and int(ndev.item()) == M
     assert np.array_equal(ids[:M].cpu().numpy().view(np.uint32), ids_ref)
@@ -192,12 +205,12 @@ def test_bin_sort_end_to_end(name, n, tile):
     dev = device()
     scene, views = _workload(name, n)
     s = _settings(sh_degree=scene.sh_degree, tile_w=tile[0], tile_h=tile[1])
-    sp, tt, rast = _gpu_splats(scene, views, s, dev)
+    sp, tt, rast, _ = _gpu_splats(scene, views, s, dev)
     rec, rect, flags = oracle.project(oracle_settings(s), views, scene)
     ids_ref, keys_ref, ranges_ref = oracle.bin_pairs(views, rect, rec[..., oracle.R["z"]].astype(np.float32), tile)
     params = to_dev(scene, dev)
-    splats, ttd = rast.project(*params)
-    pair_ids, ranges, M, keys = rast.bin_sort(scene.n, splats, ttd, want_keys=True)
+    splats, ttd, brec = rast.project(*params)
+    pair_ids, ranges, M, keys = rast.bin_sort(scene.n, ttd, brec, want_keys=True)
     torch.cuda.synchronize()
     say("bin e2e", name, tile, M)
     assert M == len(ids_ref)
@@ -214,25 +227,25 @@ def test_capacity_overflow_reports_and_retries():
     s = _settings()
     from paper_2406_01467_amd.raster import Rasterizer
     rast = Rasterizer(views, s, dev)
-    splats, tt = rast.project(*to_dev(scene, dev))
+    splats, tt, brec = rast.project(*to_dev(scene, dev))
     cap = 10
     ids = torch.full((cap,), -3, dtype=torch.int32, device=dev)
     ranges = torch.full((2 * rast.total_tiles,), 5, dtype=torch.int32, device=dev)
     ndev = torch.empty(1, dtype=torch.int64, device=dev)
     ws = torch.empty(_lib.rade_bin_sort_workspace(1, scene.n, cap, rast.total_tiles), dtype=torch.uint8, device=dev)
-    code, M = _lib.rade_bin_sort(s, rast.views_c, rast.views_dev, 1, scene.n, splats, tt, ids, ranges, None, cap, ndev, ws)
+    code, M = _lib.rade_bin_sort(s, rast.views_c, rast.views_dev, 1, scene.n, tt, brec, ids, ranges, None, cap, ndev, ws)
     torch.cuda.synchronize()
     assert code == _lib.RADE_ERR_CAPACITY and M > cap and int(ndev.item()) == M
     assert (ranges.cpu().numpy() == 0).all() and (ids.cpu().numpy() == -3).all()
     # asynchronous form (no host count): flag in n_pairs, empty ranges
     ranges.fill_(5)
-    code, _ = _lib.rade_bin_sort(s, rast.views_c, rast.views_dev, 1, scene.n, splats, tt, ids, ranges, None, cap, ndev, ws, sync_count=False)
+    code, _ = _lib.rade_bin_sort(s, rast.views_c, rast.views_dev, 1, scene.n, tt, brec, ids, ranges, None, cap, ndev, ws, sync_count=False)
     torch.cuda.synchronize()
     assert code == 0 and int(ndev.item()) == M and (ranges.cpu().numpy() == 0).all()
     # retry with enough capacity succeeds
     ids2 = torch.empty(M, dtype=torch.int32, device=dev)
     ws2 = torch.empty(_lib.rade_bin_sort_workspace(1, scene.n, M, rast.total_tiles), dtype=torch.uint8, device=dev)
-    code, M2 = _lib.rade_bin_sort(s, rast.views_c, rast.views_dev, 1, scene.n, splats, tt, ids2, ranges, None, M, ndev, ws2)
+    code, M2 = _lib.rade_bin_sort(s, rast.views_c, rast.views_dev, 1, scene.n, tt, brec, ids2, ranges, None, M, ndev, ws2)
     assert code == 0 and M2 == M
 
 
