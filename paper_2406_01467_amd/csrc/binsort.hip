@@ -376,7 +376,13 @@ k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
     for (int d = threadIdx.x; d < R; d += kEmitThreads) hist[(int64_t)d * nblocks + blk] = 0u;
     return;
   }
-  for (int w = threadIdx.x; w <= kEmitPairs; w += kEmitThreads) {
+  // The block's pairs belong to the splats j0 .. j1, j1 the splat of the next
+  // block's first pair (starts[blk + 1], written when that pair exists); the
+  // window holds their offsets and the one after (at most kEmitPairs + 1
+  // entries: every splat has at least one pair).
+  const int64_t j1 = P0 + kEmitPairs >= M ? nvis - 1 : (int64_t)starts[blk + 1];
+  const int nwin = (int)min((int64_t)kEmitPairs, j1 - j0 + 1);
+  for (int w = threadIdx.x; w <= nwin; w += kEmitThreads) {
     const int64_t j = j0 + w;
     const bool in = j < nvis;
     win[w] = in ? offs[j] : M;
@@ -388,7 +394,7 @@ k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
   const uint64_t pb = P0 + (uint64_t)kEmitPerThread * threadIdx.x;
   uint32_t tk[kEmitPerThread], pg[kEmitPerThread];
   if (pb < M) {
-    int lo = 0, hi = kEmitPairs;
+    int lo = 0, hi = nwin;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (win[mid] <= pb) lo = mid; else hi = mid - 1;
@@ -401,7 +407,7 @@ k_emit(const uint4* __restrict__ drecs, const uint64_t* __restrict__ offs,
       tk[r] = 0u;
       pg[r] = 0u;
       if (p >= M) continue;
-      while (lo < kEmitPairs && win[lo + 1] <= p) ++lo;
+      while (lo < nwin && win[lo + 1] <= p) ++lo;
       if (lo != cur) {
         cur = lo;
         // the splat's record in depth order (index, tile rect); V*N < 2^32
