@@ -103,7 +103,7 @@ def kernel_bytes(kernel: str, n: int, views: int, pairs: int, pixels: int) -> in
 # issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x duration x 2.4 GHz)).
 # Valid only for the kernel sources they were measured on (SHA-1 of
 # render.hip + common.hpp) and for the workload in the launch configuration
-# they were measured in (tile, schedule, wave shape, batch); reported as null
+# they were measured in (tile, schedule, wave shape, batch, lane masks); reported as null
 # otherwise.
 MEASURED = [
     {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
@@ -120,9 +120,10 @@ MEASURED = [
 
 
 # Launch settings of the 16-view batch, as the autotuner chose them over tile
-# size x schedule, then wave shape x staging batch (`--tile auto` with
-# `--workload batched_16views_1m`); fixed here so the timed run does no tuning.
-BATCHED_TUNED = {"tile": "8x8", "schedule": 1, "batch": 0, "wave_w": 0}
+# size x schedule x lane masks, then wave shape x staging batch (`--tile auto`
+# with `--workload batched_16views_1m`); fixed here so the timed run does no
+# tuning.
+BATCHED_TUNED = {"tile": "16x16", "schedule": 1, "batch": 0, "wave_w": 0, "lane_masks": 1}
 
 
 def _render_sources_sha1() -> str:
@@ -142,7 +143,8 @@ def measured(kernel: str, workload: str, settings, distortion: bool = False):
     for t in MEASURED:
         if (t["kernel"] == kernel and t["workload"] == workload and t["tile"] == tile
                 and t["schedule"] == settings.schedule and t["wave_w"] == settings.wave_w
-                and t["batch"] == settings.batch and t["sources_sha1"] == sha):
+                and t["batch"] == settings.batch
+                and t.get("lane_masks", 0) == settings.lane_masks and t["sources_sha1"] == sha):
             return t
     return None
 
@@ -157,6 +159,8 @@ def parse():
     ap.add_argument("--schedule", type=int, default=1,
                     help="0: one workgroup per tile, 1: heavy first (default, the autotuner's choice "
                          "for the default workload), 2: persistent")
+    ap.add_argument("--lane-masks", type=int, default=0,
+                    help="1: lane masks on every 8x8 wave of larger tiles (rade_settings.lane_masks)")
     ap.add_argument("--cpu-pixels", type=int, default=4096,
                     help="pixels of the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--eager-steps", type=int, default=5,
@@ -182,6 +186,7 @@ def parse():
     ap.add_argument("--batched-schedule", type=int, default=BATCHED_TUNED["schedule"])
     ap.add_argument("--batched-batch", type=int, default=BATCHED_TUNED["batch"])
     ap.add_argument("--batched-wave", type=int, default=BATCHED_TUNED["wave_w"])
+    ap.add_argument("--batched-lane-masks", type=int, default=BATCHED_TUNED["lane_masks"])
     return ap.parse_args()
 
 
@@ -337,7 +342,8 @@ def count_pass(views, settings, params, dev):
 
     from paper_2406_01467_amd.raster import Rasterizer
     with torch.no_grad():
-        counter = Rasterizer(views, dataclasses.replace(settings, wave_w=0, batch=0), dev)
+        counter = Rasterizer(views, dataclasses.replace(settings, wave_w=0, batch=0, lane_masks=0),
+                             dev)
         maps = counter.forward(*params, want_count=True, want_evals=True)
         torch.cuda.synchronize()
         blends = int(maps.count.sum().item())
@@ -470,7 +476,8 @@ def batched_leg(args, params, scene_n: int, sh_degree: int, dev) -> dict:
         raise RuntimeError("the many-view leg renders the headline workload's scene")
     tw, th = (int(x) for x in args.batched_tile.split("x"))
     st = Settings(tile_w=tw, tile_h=th, sh_degree=sh_degree, schedule=args.batched_schedule,
-                  batch=args.batched_batch, wave_w=args.batched_wave)
+                  batch=args.batched_batch, wave_w=args.batched_wave,
+                  lane_masks=args.batched_lane_masks)
     V = len(views)
     target = torch.from_numpy(synth.random_targets(views, seed=7)["color"]).to(dev)
     rast = Rasterizer(views, st, dev)
@@ -488,6 +495,7 @@ def batched_leg(args, params, scene_n: int, sh_degree: int, dev) -> dict:
             "sizes": [[v.width, v.height] for v in views], "pixels": rast.total_pixels,
             "tile": args.batched_tile, "schedule": st.schedule,
             "batch": st.batch or tw * th, "wave": f"{st.wave_w or 8}x{64 // (st.wave_w or 8)}",
+            "lane_masks": st.lane_masks,
             "mode": "all views in one launch per kernel, whole fwd+bwd step replayed as one "
                     "HIP graph",
             "ms_per_step": ms, "ms_per_view": ms / V,
@@ -518,7 +526,8 @@ def main():
     dev = torch.device("cuda:0")
     scene, views = synth.make_workload(args.workload)
     tw, th = (16, 16) if args.tile == "auto" else (int(x) for x in args.tile.split("x"))
-    settings = Settings(tile_w=tw, tile_h=th, sh_degree=scene.sh_degree, schedule=args.schedule)
+    settings = Settings(tile_w=tw, tile_h=th, sh_degree=scene.sh_degree, schedule=args.schedule,
+                        lane_masks=args.lane_masks)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     params = [t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacities),
               t(scene.sh.reshape(scene.n, -1))]
@@ -604,6 +613,7 @@ def main():
                    "tile": f"{settings.tile_w}x{settings.tile_h}",
                    "wave": f"{settings.wave_w or 8}x{64 // (settings.wave_w or 8)}",
                    "batch": settings.batch or settings.tile_w * settings.tile_h,
+                   "lane_masks": settings.lane_masks,
                    "schedule": settings.schedule,
                    "loss": "L1 colour + 5 x normal consistency (Eq. 24, median depth)" +
                            (" + 100 x depth distortion (Eq. 23)" if args.distortion else ""),

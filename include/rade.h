@@ -106,7 +106,14 @@ typedef struct rade_settings {
                               render calls return RADE_ERR_INVALID_ARG.  Maps do not
                               depend on either field; gradients only up to the order of
                               FP32 additions. */
-  int32_t reserved;        /* must be 0 */
+  int32_t lane_masks;      /* 0 or 1.  Tiles of one 8x8 wave always stage, per splat, the
+                              64-bit mask of the wave's pixels its ellipse can reach (the
+                              loops skip splats that reach no pixel still working) and walk
+                              the backward as four 4x4 quadrant groups per wave; 1 does
+                              the same on every wave of larger tiles of 8x8 waves (with
+                              batch 0; the plain forward and backward only, as above).
+                              Maps do not depend on it; gradients only up to the order of
+                              FP32 additions. */
 } rade_settings;
 
 /* Per-pixel depth of a splat.  AFFINE: the plane d = z + p . (u_c - u,
@@ -473,7 +480,7 @@ const char* rade_strerror(int code);
  * present).  The entry points above make the same check themselves. */
 int rade_device_check(void);
 
-/* ABI version of this header: 6. */
+/* ABI version of this header: 7. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

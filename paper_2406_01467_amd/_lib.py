@@ -54,7 +54,7 @@ class CSettings(ctypes.Structure):
                 ("fov_clamp", ctypes.c_double), ("degenerate", ctypes.c_double),
                 ("bg", ctypes.c_double * 3), ("depth_mode", ctypes.c_int32),
                 ("wave_w", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lane_masks", ctypes.c_int32)]
 
 
 class CView(ctypes.Structure):
@@ -89,6 +89,7 @@ class Settings:
     depth_mode: int = 0        # RADE_DEPTH_AFFINE (Eq. 4) or RADE_DEPTH_EXACT (Eq. 7, forward only)
     wave_w: int = 0            # pixels per wave row: 8 (8x8), 16 (16x4), 32 (32x2); 0 = 8
     batch: int = 0             # splats staged per round: 64..512; 0 = tile_w * tile_h
+    lane_masks: int = 0        # 1: per-wave lane masks on tiles of several 8x8 waves
 
     def c(self) -> CSettings:
         s = CSettings()
@@ -99,12 +100,13 @@ class Settings:
         s.power_cut, s.fov_clamp, s.degenerate = self.power_cut, self.fov_clamp, self.degenerate
         for i in range(3):
             s.bg[i] = float(self.bg[i])
-        s.depth_mode, s.wave_w, s.batch, s.reserved = self.depth_mode, self.wave_w, self.batch, 0
+        s.depth_mode, s.wave_w, s.batch = self.depth_mode, self.wave_w, self.batch
+        s.lane_masks = self.lane_masks
         return s
 
 
 _lib = None
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 
 def load() -> ctypes.CDLL:

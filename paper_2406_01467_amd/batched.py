@@ -229,13 +229,14 @@ def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, gr
              reps: int = 3, use_cache: bool = True, log: Optional[Callable] = None,
              distortion: bool = False) -> tuple:
     """Time the graph-replayed fwd+bwd over the candidates and return (best
-    Settings, {candidate: ms}).  Two stages: every (tile, schedule), then,
-    for the best of those, every wave shape the tile holds x staging batch
-    (these exist for the plain path only, so not with the distortion term).
-    Results are cached in a JSON file keyed by device name and workload
-    signature."""
+    Settings, {candidate: ms}).  Two stages: every (tile, schedule), with and
+    without lane masks on tiles of several 8x8 waves, then, for the best
+    plain shape of those, every wave shape the tile holds x staging batch
+    (the tuned shapes exist for the plain path only, so not with the
+    distortion term).  Results are cached in a JSON file keyed by device
+    name and workload signature."""
     sig = signature(views, params[0].shape[0], base.sh_degree) + ("|dist" if distortion else "")
-    sig += "|shape"
+    sig += "|shape|lm"
     path = _cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -248,7 +249,8 @@ def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, gr
         c = cache[sig]
         return Settings(**{**base.__dict__, "tile_w": c["tile_w"], "tile_h": c["tile_h"],
                            "schedule": c["schedule"], "wave_w": c.get("wave_w", 0),
-                           "batch": c.get("batch", 0)}), c.get("timings", {})
+                           "batch": c.get("batch", 0),
+                           "lane_masks": c.get("lane_masks", 0)}), c.get("timings", {})
     timings = {}
 
     def timed(st: Settings, key: str) -> float:
@@ -267,15 +269,23 @@ def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, gr
         return ms
 
     best = None
+    best_plain = None
     for tw, th in tiles:
         for sch in schedules:
             st = Settings(**{**base.__dict__, "tile_w": tw, "tile_h": th, "schedule": sch,
-                             "wave_w": 0, "batch": 0})
+                             "wave_w": 0, "batch": 0, "lane_masks": 0})
             ms = timed(st, f"{tw}x{th}/{sch}")
             if best is None or ms < best[0]:
                 best = (ms, st)
+            if best_plain is None or ms < best_plain[0]:
+                best_plain = (ms, st)
+            if not distortion and tw * th > 64:
+                st = Settings(**{**st.__dict__, "lane_masks": 1})
+                ms = timed(st, f"{tw}x{th}/{sch}/lm")
+                if ms < best[0]:
+                    best = (ms, st)
     if not distortion:
-        b = best[1]
+        b = best_plain[1]
         for ww in wave_widths:
             if not _shape_fits(b.tile_w, b.tile_h, ww):
                 continue
@@ -289,7 +299,7 @@ def autotune(views: Sequence, params: Sequence[torch.Tensor], base: Settings, gr
     if use_cache:
         cache[sig] = dict(tile_w=best[1].tile_w, tile_h=best[1].tile_h,
                           schedule=best[1].schedule, wave_w=best[1].wave_w,
-                          batch=best[1].batch, timings=timings)
+                          batch=best[1].batch, lane_masks=best[1].lane_masks, timings=timings)
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path, "w") as f:

@@ -28,7 +28,7 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
                            hipStream_t st, int* capacity_exceeded);
 bool tile_supported(int tw, int th);
 bool wave_shape_supported(int tw, int th, int wave_w);
-bool render_shape_is_default(int tw, int th, int wave_w, int batch);
+bool render_shape_is_default(int tw, int th, int wave_w, int batch, int lane_masks);
 hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, float* color,
@@ -103,7 +103,7 @@ bool settings_ok(const rade_settings* s) {
   if (s->depth_mode != RADE_DEPTH_AFFINE && s->depth_mode != RADE_DEPTH_EXACT) return false;
   if (!rade::wave_shape_supported(s->tile_w, s->tile_h, s->wave_w)) return false;
   if (s->batch != 0 && s->batch != 64 && s->batch != 128 && s->batch != 256) return false;
-  if (s->reserved != 0) return false;
+  if (s->lane_masks != 0 && s->lane_masks != 1) return false;
   return true;
 }
 
@@ -167,7 +167,7 @@ KernelEvents& kernel_events(int kernel) {
 
 extern "C" {
 
-int rade_abi_version(void) { return 6; }
+int rade_abi_version(void) { return 7; }
 
 int rade_device_check(void) { return device_status(); }
 
@@ -373,7 +373,7 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
   if (exact && N > 0 && (!depth_quad || (reinterpret_cast<uintptr_t>(depth_quad) & 15) != 0))
     return RADE_ERR_INVALID_ARG;
   // tuned wave shapes / batches exist for the plain forward only
-  if (!rade::render_shape_is_default(s->tile_w, s->tile_h, s->wave_w, s->batch) &&
+  if (!rade::render_shape_is_default(s->tile_w, s->tile_h, s->wave_w, s->batch, s->lane_masks) &&
       (exact || distortion || count || evals))
     return RADE_ERR_INVALID_ARG;
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
@@ -412,7 +412,7 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   if (!tile_ranges || !t_final || !last || !median) return RADE_ERR_INVALID_ARG;
   if (s->depth_mode != RADE_DEPTH_AFFINE) return RADE_ERR_INVALID_ARG;  // forward-only variant
   if (d_distortion && (!depth || !alpha)) return RADE_ERR_INVALID_ARG;
-  if (d_distortion && !rade::render_shape_is_default(s->tile_w, s->tile_h, s->wave_w, s->batch))
+  if (d_distortion && !rade::render_shape_is_default(s->tile_w, s->tile_h, s->wave_w, s->batch, s->lane_masks))
     return RADE_ERR_INVALID_ARG;  // tuned shapes exist for the plain backward only
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && (!means || !scales || !quats || !opacities || !sh || !d_means || !d_scales ||

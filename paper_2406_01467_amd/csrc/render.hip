@@ -42,9 +42,13 @@
 namespace rade {
 namespace {
 
+// Staging batch parameter of a tile of 8x8 waves with lane masks on every
+// wave (one splat staged per thread).
+constexpr int kLaneMaskBatch = -1;
+
 // Tile of TW x TH pixels, wavefronts of WW x WH = 64 pixels (row-major in
-// the tile), BATCH splats staged per round (0: one per thread), in NCH
-// chunks of 64.
+// the tile), BATCH splats staged per round (0 or kLaneMaskBatch: one per
+// thread), in NCH chunks of 64.
 template <int TW, int TH, int WW = 8, int BATCH_ = 0>
 struct TileGeom {
   static constexpr int WH = 64 / WW;
@@ -55,10 +59,11 @@ struct TileGeom {
   static constexpr int BLOCK = 64 * NW;
   static constexpr int BATCH = BATCH_ > 0 ? BATCH_ : BLOCK;
   static constexpr int NCH = BATCH / 64;
-  // One wave per tile: staging also computes which of the wave's pixels a
-  // splat can reach (a 64-bit lane mask), so the loops skip the splats none
-  // of their still-active pixels takes.
-  static constexpr bool LM = NW == 1 && WW == 8;
+  // One wave per tile, or 8x8 waves with kLaneMaskBatch: staging also
+  // computes which of each wave's pixels a splat can reach (a 64-bit lane
+  // mask per wave), so the loops skip the splats none of their still-active
+  // pixels takes.
+  static constexpr bool LM = WW == 8 && (NW == 1 || BATCH_ == kLaneMaskBatch);
   static_assert(WW == 8 || WW == 16 || WW == 32, "wave width");
   static_assert(TW % WW == 0 && TH % WH == 0 && BLOCK <= 1024 && BATCH % 64 == 0, "tile");
 };
@@ -137,9 +142,10 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const rade_view* views, int V,
   c.oy = c.y0 & ~(kOriginAlign - 1);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if constexpr (Q) {
+    // 8x8 waves, each as four 4x4 quadrants
     const int q = lane >> 4, i = lane & 15;
-    c.lxi = 4 * (q & 1) + (i & 3);
-    c.lyi = 4 * (q >> 1) + (i >> 2);
+    c.lxi = 8 * (wave % TG::NWX) + 4 * (q & 1) + (i & 3);
+    c.lyi = 8 * (wave / TG::NWX) + 4 * (q >> 1) + (i >> 2);
   } else {
     c.lxi = WW * (wave % TG::NWX) + (lane & (WW - 1));
     c.lyi = TG::WH * (wave / TG::NWX) + (lane >> TG::LW);
@@ -195,6 +201,7 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
                                           int slot, const PixelCtx& c, const BlendParams& bp,
                                           StagedArrays<TileGeom<TW, TH, WW, BT>::BATCH>& st,
                                           uint32_t* sgid, uint64_t* lmask) {
+  // lmask (LM tiles): the lane mask of wave k at lmask[k * BATCH + slot]
   using TG = TileGeom<TW, TH, WW, BT>;
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
@@ -219,7 +226,7 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     const int bx = WW * (k % TG::NWX), by = TG::WH * (k / TG::NWX);
     if (rx0 <= bx + WW - 1 && rx1 >= bx && ry0 <= by + TG::WH - 1 && ry1 >= by) bits |= 1u << k;
   }
-  uint64_t lm = 0;
+  uint64_t lm[TG::LM ? TG::NW : 1] = {};
   if (bits) {
     // Support: power <= cut and opacity 2^-power >= alpha_min.  The bound
     // and the tests below carry margins far above the error of the
@@ -250,44 +257,58 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
           bits &= ~(1u << k);
       }
     } else {
-      // Lane mask of the one 8x8 wave (lane = 8 y + x, or with QL the
-      // quadrant layout of pixel_ctx<..., true>), which also stands for the
+      // Lane masks of the 8x8 waves (lane = 8 y + x, or with QL the
+      // quadrant layout of pixel_ctx<..., true>), which also stand for the
       // block test: per pixel row of the support rect, the interval of the
       // ellipse A dx^2 + 2 B dx dy + C dy^2 <= tau2 along the row, widened
       // by a margin and rounded outwards (conservative: the loops still test
-      // every pixel).
-      const int x0 = max(rx0, 0), x1 = min(rx1, 7), y0 = max(ry0, 0), y1 = min(ry1, 7);
+      // every pixel), split over the waves the row crosses.
+      const int x0 = max(rx0, 0), x1 = min(rx1, TW - 1), y0 = max(ry0, 0), y1 = min(ry1, TH - 1);
       // the Gram determinant A C - B^2 >= 0, lowered by more than its FP32
       // rounding (a lower value only widens the intervals)
       const float det = fmaxf(fmaf(A, C, -(B * B)) - 4e-7f * (A * C), 0.0f);
-      for (int y = y0; y <= y1; ++y) {
-        const float dy = vt - (float)y;
-        const float disc = fmaf(-det, dy * dy, A * tau2);
-        if (disc < 0.0f) continue;
-        int xl = x0, xh = x1;
-        if (A > 0.0f) {
-          // pixels x = ut - dx with dx in -B dy / A -+ sqrt(disc) / A
-          const float xc = fmaf(B * dy, invA, ut), half = __builtin_amdgcn_sqrtf(disc) * invA;
-          const float m = 2e-3f + 1e-5f * (fabsf(xc) + half);
-          xl = max(xl, (int)ceilf(fmaxf(xc - half - m, -1.0f)));
-          xh = min(xh, (int)floorf(fminf(xc + half + m, 8.0f)));
-        }
-        if (xl <= xh) {
-          if constexpr (QL) {
-            // quadrant 2 (y / 4) and 2 (y / 4) + 1, row 4 (y % 4) in each
-            const int base = 32 * (y >> 2) + 4 * (y & 3);
-            if (xl <= 3) lm |= ((2ull << min(xh, 3)) - (1ull << xl)) << base;
-            if (xh >= 4) lm |= ((2ull << (xh - 4)) - (1ull << (max(xl, 4) - 4))) << (base + 16);
-          } else {
-            lm |= ((2ull << xh) - (1ull << xl)) << (8 * y);
+#pragma unroll
+      for (int by = 0; by < TG::NWY; ++by) {  // the waves' rows of 8 pixel rows
+        for (int y = max(y0, 8 * by); y <= min(y1, 8 * by + 7); ++y) {
+          const float dy = vt - (float)y;
+          const float disc = fmaf(-det, dy * dy, A * tau2);
+          if (disc < 0.0f) continue;
+          int xl = x0, xh = x1;
+          if (A > 0.0f) {
+            // pixels x = ut - dx with dx in -B dy / A -+ sqrt(disc) / A
+            const float xc = fmaf(B * dy, invA, ut), half = __builtin_amdgcn_sqrtf(disc) * invA;
+            const float m = 2e-3f + 1e-5f * (fabsf(xc) + half);
+            xl = max(xl, (int)ceilf(fmaxf(xc - half - m, -1.0f)));
+            xh = min(xh, (int)floorf(fminf(xc + half + m, (float)TW)));
+          }
+          const int yy = y - 8 * by;
+#pragma unroll
+          for (int bx = 0; bx < TG::NWX; ++bx) {
+            const int l = max(xl - 8 * bx, 0), h = min(xh - 8 * bx, 7);
+            if (l > h) continue;
+            uint64_t bm;
+            if constexpr (QL) {
+              // quadrant 2 (yy / 4) and 2 (yy / 4) + 1, row 4 (yy % 4) in each
+              const int base = 32 * (yy >> 2) + 4 * (yy & 3);
+              bm = 0;
+              if (l <= 3) bm |= ((2ull << min(h, 3)) - (1ull << l)) << base;
+              if (h >= 4) bm |= ((2ull << (h - 4)) - (1ull << (max(l, 4) - 4))) << (base + 16);
+            } else {
+              bm = ((2ull << h) - (1ull << l)) << (8 * yy);
+            }
+            lm[by * TG::NWX + bx] |= bm;
           }
         }
       }
     }
   }
   if constexpr (TG::LM) {
-    lmask[slot] = lm;
-    if (!lm) bits = 0;
+    bits = 0;
+#pragma unroll
+    for (int k = 0; k < TG::NW; ++k) {
+      lmask[k * TG::BATCH + slot] = lm[k];
+      if (lm[k]) bits |= 1u << k;
+    }
   }
   return bits;
 }
@@ -312,7 +333,7 @@ struct FwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
   StagedArrays<TG::BATCH> st;
   uint32_t sgid[TG::BATCH];
-  uint64_t lmask[TG::LM ? TG::BATCH : 1];
+  uint64_t lmask[TG::LM ? TG::NW * TG::BATCH : 1];
   uint64_t masks[TG::NW][TG::NCH];
   // EXACT: the ray-maximum depth terms (g0, g1, H00, H01) and H11
   float4 xq[EXACT ? TG::BATCH : 1];
@@ -389,7 +410,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       if constexpr (TG::LM) {
         // drop the chunk's splats whose lane mask holds no pixel still
         // blending (lane l tests staged splat cw * 64 + l)
-        m &= __builtin_amdgcn_ballot_w64((sh.lmask[cw * 64 + (threadIdx.x & 63)] & ~wdone) != 0);
+        m &= __builtin_amdgcn_ballot_w64(
+            (sh.lmask[wave * TG::BATCH + cw * 64 + (threadIdx.x & 63)] & ~wdone) != 0);
       }
       while (m && wdone != ~0ull) {
         const int j = __builtin_ctzll(m);
@@ -617,7 +639,7 @@ struct BwdShared {
   using TG = TileGeom<TW, TH, WW, BT>;
   StagedArrays<TG::BATCH> st;
   uint32_t sgid[TG::BATCH];
-  uint64_t lmask[TG::LM ? TG::BATCH : 1];
+  uint64_t lmask[TG::LM ? TG::NW * TG::BATCH : 1];
   uint64_t masks[TG::NW][TG::NCH];
   int smax;
 };
@@ -632,17 +654,17 @@ struct BwdShared {
 // bwd_tile.  (The forward keeps one splat per step: its per-splat work is
 // small enough that the per-lane bookkeeping of four streams costs more
 // than it saves.)
-template <int BT>
+template <int TW, int TH, int BT>
 __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
-                                           BwdShared<8, 8, 8, BT>& sh) {
-  using TG = TileGeom<8, 8, 8, BT>;
+                                           BwdShared<TW, TH, 8, BT>& sh) {
+  using TG = TileGeom<TW, TH, 8, BT>;
   const BlendParams& bp = a.bp;
   const rade_splat* __restrict__ splats = a.splats;
   const uint32_t* __restrict__ pair_ids = a.pair_ids;
   float* __restrict__ gsplat = a.gsplat;
   uint32_t* sgid = sh.sgid;
-  const PixelCtx c = pixel_ctx<8, 8, 8, BT, true>(a.views, a.V, a.ranges, tile);
-  const int lane = threadIdx.x & 63;
+  const PixelCtx c = pixel_ctx<TW, TH, 8, BT, true>(a.views, a.V, a.ranges, tile);
+  const int wave = wave_index(), lane = threadIdx.x & 63;
   const int64_t vbase = (int64_t)c.v * a.N;
   // the lane's pixel centre relative to the origin's (exact in FP32)
   const float fx = (float)(c.px - c.ox), fy = (float)(c.py - c.oy);
@@ -680,7 +702,15 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
   wlast = __builtin_amdgcn_readfirstlane(wlast);
   // records to visit: up to the furthest last blend of the tile (clamped to
   // the list length in case the saved state does not match the lists)
-  const int nrec = min(wlast + 1, (int)(c.re - c.rb));
+  int tlast = wlast;
+  if constexpr (TG::NW > 1) {
+    if (threadIdx.x == 0) sh.smax = -1;
+    __syncthreads();
+    if (lane == 0) atomicMax(&sh.smax, wlast);
+    __syncthreads();
+    tlast = sh.smax;
+  }
+  const int nrec = min(tlast + 1, (int)(c.re - c.rb));
   // the sums a lane carries to the splat's record (row_sum16's order)
   const int vi = 8 * ((lane >> 3) & 1) + 4 * ((lane >> 2) & 1) + 2 * (lane & 1) + ((lane >> 1) & 1);
 
@@ -693,9 +723,9 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
       const int li = bstart + slot;
       uint32_t bits = 0;
       if (li < bend)
-        bits = stage<8, 8, 8, BT, false, true>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot,
-                                               c, bp, sh.st, sgid, sh.lmask);
-      publish_masks<8, 8, 8, BT>(bits, slot >> 6, sh.masks);
+        bits = stage<TW, TH, 8, BT, false, true>(splats, vbase, pair_ids, c.rb + (uint32_t)li,
+                                                 slot, c, bp, sh.st, sgid, sh.lmask);
+      publish_masks<TW, TH, 8, BT>(bits, slot >> 6, sh.masks);
     }
     __syncthreads();
     for (int cw = TG::NCH - 1; cw >= 0; --cw) {
@@ -704,9 +734,9 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
       // the chunk's splats that reach a pixel of the quadrant blending at
       // the chunk's first position or later, at positions up to the
       // quadrant's furthest last blend
-      uint64_t mg = quadrant_chunk_mask(sh.lmask[cw * 64 + lane],
+      uint64_t mg = quadrant_chunk_mask(sh.lmask[wave * TG::BATCH + cw * 64 + lane],
                                         __builtin_amdgcn_ballot_w64(lo <= lastp),
-                                        uniform_u64(sh.masks[0][cw]));
+                                        uniform_u64(sh.masks[wave][cw]));
       const int ql = qlast - lo;
       mg = ql < 0 ? 0ull : ql < 63 ? mg & ((2ull << ql) - 1) : mg;
       for (;;) {
@@ -777,7 +807,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
                                          BwdShared<TW, TH, WW, BT>& sh) {
   using TG = TileGeom<TW, TH, WW, BT>;
   if constexpr (TG::LM && !DIST) {
-    bwd_tile_q<BT>(a, tile, sh);
+    bwd_tile_q<TW, TH, BT>(a, tile, sh);
     return;
   }
   const BlendParams& bp = a.bp;
@@ -865,7 +895,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
         // at the chunk's first position or later (lane l tests staged splat
         // cw * 64 + l)
         const uint64_t live = __builtin_amdgcn_ballot_w64(bstart + cw * 64 <= lastp);
-        m &= __builtin_amdgcn_ballot_w64((sh.lmask[cw * 64 + lane] & live) != 0);
+        m &= __builtin_amdgcn_ballot_w64((sh.lmask[wave * TG::BATCH + cw * 64 + lane] & live) != 0);
       }
       // the chunk's Gaussian ids, one per lane; a splat's id is read from
       // its lane
@@ -1034,6 +1064,11 @@ void launch_bwd_d(const BwdArgs& a, int schedule, hipStream_t st) {
 // distortion, blend count or exact depth); the caller checks this.
 constexpr bool shape_fits(int tw, int th, int ww) { return tw % ww == 0 && th % (64 / ww) == 0; }
 
+// Tiles of several 8x8 waves with lane masks on each (lane_masks = 1).
+inline bool lane_mask_shape(int tw, int th, int wave_w, int batch, int lane_masks) {
+  return lane_masks == 1 && (wave_w == 0 || wave_w == 8) && batch == 0 && tw * th > 64;
+}
+
 inline bool default_shape(int tw, int th, int wave_w, int batch) {
   return (wave_w == 0 || wave_w == 8) && (batch == 0 || batch == tw * th);
 }
@@ -1067,8 +1102,15 @@ bool launch_bwd_shape_b(const BwdArgs& a, int schedule, int batch, hipStream_t s
 }
 
 template <int TW, int TH>
-hipError_t launch_fwd_t(const FwdArgs& a, int schedule, int wave_w, int batch, hipStream_t st) {
+hipError_t launch_fwd_t(const FwdArgs& a, int schedule, int wave_w, int batch, int lane_masks,
+                        hipStream_t st) {
   EventScope timing(RADE_KERNEL_RENDER_FWD, st);
+  if (lane_mask_shape(TW, TH, wave_w, batch, lane_masks)) {
+    if (a.depth_quad || a.distortion || a.count || a.evals) return hipErrorInvalidValue;
+    if constexpr (TW * TH > 64)
+      launch_fwd_d<TW, TH, false, false, false, 8, kLaneMaskBatch>(a, schedule, st);
+    return hipSuccess;
+  }
   if (default_shape(TW, TH, wave_w, batch)) {
     if (a.depth_quad) launch_fwd_e<TW, TH, true>(a, schedule, st);
     else launch_fwd_e<TW, TH, false>(a, schedule, st);
@@ -1083,8 +1125,14 @@ hipError_t launch_fwd_t(const FwdArgs& a, int schedule, int wave_w, int batch, h
 }
 
 template <int TW, int TH>
-hipError_t launch_bwd_t(const BwdArgs& a, int schedule, int wave_w, int batch, hipStream_t st) {
+hipError_t launch_bwd_t(const BwdArgs& a, int schedule, int wave_w, int batch, int lane_masks,
+                        hipStream_t st) {
   EventScope timing(RADE_KERNEL_RENDER_BWD, st);
+  if (lane_mask_shape(TW, TH, wave_w, batch, lane_masks)) {
+    if (a.d_distortion) return hipErrorInvalidValue;
+    if constexpr (TW * TH > 64) launch_bwd_d<TW, TH, false, 8, kLaneMaskBatch>(a, schedule, st);
+    return hipSuccess;
+  }
   if (default_shape(TW, TH, wave_w, batch)) {
     if (a.d_distortion) launch_bwd_d<TW, TH, true>(a, schedule, st);
     else launch_bwd_d<TW, TH, false>(a, schedule, st);
@@ -1107,8 +1155,9 @@ bool wave_shape_supported(int tw, int th, int wave_w) {
   return shape_fits(tw, th, ww);
 }
 
-bool render_shape_is_default(int tw, int th, int wave_w, int batch) {
-  return default_shape(tw, th, wave_w, batch);
+bool render_shape_is_default(int tw, int th, int wave_w, int batch, int lane_masks) {
+  return default_shape(tw, th, wave_w, batch) &&
+         !lane_mask_shape(tw, th, wave_w, batch, lane_masks);
 }
 
 bool tile_supported(int tw, int th) {
@@ -1142,7 +1191,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
   a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
   a.last = last; a.median = med; a.count = cnt; a.evals = evals; a.distortion = distortion;
   a.depth_quad = reinterpret_cast<const float4*>(depth_quad);
-  RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, s.wave_w, s.batch, st))
+  RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, s.wave_w, s.batch, s.lane_masks, st))
   return hipGetLastError();
 }
 
@@ -1170,7 +1219,7 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
   a.d_color = dc; a.d_depth = dd; a.d_normal = dn; a.d_alpha = da;
   a.d_distortion = ddist; a.fwd_depth = fwd_depth; a.fwd_alpha = fwd_alpha;
   a.gsplat = gsplat;
-  RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, s.wave_w, s.batch, st))
+  RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, s.wave_w, s.batch, s.lane_masks, st))
   return hipGetLastError();
 }
 

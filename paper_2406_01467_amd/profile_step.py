@@ -32,6 +32,8 @@ def main(argv=None):
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--batch", type=int, default=0, help="splats staged per round (0: default)")
     ap.add_argument("--wave", type=int, default=0, help="pixels per wave row (0: 8x8 waves)")
+    ap.add_argument("--lane-masks", type=int, default=0,
+                    help="1: per-lane splat masks on every 8x8 wave of larger tiles")
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
     args = ap.parse_args(argv)
 
@@ -56,7 +58,7 @@ def main(argv=None):
     scene, views = synth.make_workload(args.workload)
     tw, th = (int(x) for x in args.tile.split("x"))
     st = Settings(tile_w=tw, tile_h=th, sh_degree=scene.sh_degree, schedule=args.schedule,
-                  batch=args.batch, wave_w=args.wave)
+                  batch=args.batch, wave_w=args.wave, lane_masks=args.lane_masks)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     params = [t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacities),
               t(scene.sh.reshape(scene.n, -1))]

@@ -46,7 +46,7 @@ def gpu_forward(scene, views, settings, dev, keep=True):
     rast = Rasterizer(views, settings, dev)
     params = to_dev(scene, dev)
     # the counting pass exists for the default wave shape and batch only
-    count = settings.batch == 0 and settings.wave_w == 0
+    count = settings.batch == 0 and settings.wave_w == 0 and settings.lane_masks == 0
     maps = rast.forward(*params, want_count=count, keep_splats=keep)
     torch.cuda.synchronize()
     per_view = []

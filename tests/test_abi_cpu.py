@@ -111,8 +111,8 @@ def test_null_pointers_rejected():
     assert so.rade_project(ctypes.byref(s), dummy, 1, 10, *([dummy] * 7), ctypes.c_void_p(24),
                            None, None) == lib.RADE_ERR_INVALID_ARG
     # exact depth: the depth_quad records are required and 16-byte aligned;
-    # the backward rejects the mode; unknown modes and a nonzero reserved
-    # field are rejected
+    # the backward rejects the mode; unknown modes and lane_masks values
+    # other than 0 and 1 are rejected
     se = lib.Settings(depth_mode=lib.RADE_DEPTH_EXACT).c()
     assert so.rade_project(ctypes.byref(se), dummy, 1, 10, *([dummy] * 7), None, None, None) == \
         lib.RADE_ERR_INVALID_ARG
@@ -122,7 +122,7 @@ def test_null_pointers_rejected():
     assert so.rade_project(ctypes.byref(bad), dummy, 1, 10, *([dummy] * 9), None) == \
         lib.RADE_ERR_INVALID_ARG
     res = lib.Settings().c()
-    res.reserved = 1
+    res.lane_masks = 2
     assert so.rade_project(ctypes.byref(res), dummy, 1, 10, *([dummy] * 9), None) == \
         lib.RADE_ERR_INVALID_ARG
     import synth

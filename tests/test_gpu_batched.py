@@ -115,27 +115,31 @@ def test_autotuner_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     g = _fixed_grads(P, dev)
     best, timings = autotune(views, params, Settings(sh_degree=3), lambda m: g,
                              tiles=[(8, 8), (16, 16)], schedules=[0, 2], reps=2)
-    # stage 1: every (tile, schedule); stage 2: wave shapes x batches of the best
+    # stage 1: every (tile, schedule), and with lane masks on the tiles of
+    # several 8x8 waves; stage 2: wave shapes x batches of the best plain one
     stage1 = {k: v for k, v in timings.items() if "/w" not in k}
-    assert len(stage1) == 4
-    b1 = min(stage1, key=stage1.get)
+    assert sorted(stage1) == ["16x16/0", "16x16/0/lm", "16x16/2", "16x16/2/lm", "8x8/0", "8x8/2"]
+    b1 = min((k for k in stage1 if not k.endswith("/lm")), key=stage1.get)
     stage2 = [k for k in timings if "/w" in k]
     assert stage2 and all(k.startswith(b1 + "/w") for k in stage2)
     key = f"{best.tile_w}x{best.tile_h}/{best.schedule}"
     if best.wave_w or best.batch:
         key += f"/w{best.wave_w}/b{best.batch}"
+    if best.lane_masks:
+        key += "/lm"
     assert key in timings and timings[key] == min(timings.values())
     again, t2 = autotune(views, params, Settings(sh_degree=3), lambda m: g,
                          tiles=[(8, 8), (16, 16)], schedules=[0, 2], reps=2)
-    assert (again.tile_w, again.tile_h, again.schedule, again.wave_w, again.batch) == \
-        (best.tile_w, best.tile_h, best.schedule, best.wave_w, best.batch)
+    assert (again.tile_w, again.tile_h, again.schedule, again.wave_w, again.batch,
+            again.lane_masks) == \
+        (best.tile_w, best.tile_h, best.schedule, best.wave_w, best.batch, best.lane_masks)
     say("autotune", timings)
 
 
 def test_batched_16views_1m_against_the_oracle():
     """The 16-view workload (1M Gaussians, uneven orbit views) through the
-    batched plan at its tuned launch shape (8x8 tiles, heavy-first order,
-    128-splat staging batches), graph-replayed: maps of three views on
+    batched plan at its tuned launch shape (16x16 tiles with lane masks on
+    their four 8x8 waves, heavy-first order), graph-replayed: maps of three views on
     sampled pixels against the oracle, and the VJP of upstream gradients on
     sampled pixels of those views (zero elsewhere) against the oracle's
     adjoint over all 1M Gaussians."""
@@ -146,7 +150,7 @@ def test_batched_16views_1m_against_the_oracle():
     from paper_2406_01467_amd.batched import BatchedPlan
     dev = device()
     scene, views = synth.make_workload("batched_16views_1m")
-    st = Settings(tile_w=8, tile_h=8, sh_degree=3, schedule=1, batch=128)
+    st = Settings(tile_w=16, tile_h=16, sh_degree=3, schedule=1, lane_masks=1)
     params = to_dev(scene, dev)
     rng = np.random.default_rng(61)
     sel = [0, 7, 13]
@@ -194,7 +198,7 @@ def test_batched_16views_1m_against_the_oracle():
                          ("t_final", 1), ("median", 1), ("last", 1)):
             d[name] = plan.maps[name][ch * o: ch * o + ch * Pv].view(ch, H, W).cpu().numpy()
         py, px = np.mgrid[0:H, 0:W]
-        tile = vc[vi].tile_offset + (py // 8) * vc[vi].tiles_x + px // 8
+        tile = vc[vi].tile_offset + (py // st.tile_h) * vc[vi].tiles_x + px // st.tile_w
         last = d["last"][0]
         d["last_id"] = np.where(last >= 0, pair_ids[np.clip(ranges[tile, 0] + last, 0,
                                                             len(pair_ids) - 1)], -1)

@@ -22,12 +22,16 @@ def _settings(**kw):
 
 
 def _shapes(tw, th):
+    """(wave width, staging batch, lane masks) of every shape the tile holds;
+    lane masks on tiles of several 8x8 waves with one splat per thread."""
     out = []
     for ww in (8, 16, 32):
         if tw % ww or th % (64 // ww):
             continue
         for bt in (0, 64, 128, 256):
-            out.append((ww, bt))
+            out.append((ww, bt, 0))
+    if tw * th > 64:
+        out.append((8, 0, 1))
     return out
 
 
@@ -45,9 +49,9 @@ def test_maps_are_identical_across_shapes(tile):
     scene, views = _scene()
     params = to_dev(scene, dev)
     ref = None
-    for ww, bt in _shapes(*tile):
+    for ww, bt, lm in _shapes(*tile):
         rast = Rasterizer(views, _settings(sh_degree=3, tile_w=tile[0], tile_h=tile[1],
-                                           wave_w=ww, batch=bt), dev)
+                                           wave_w=ww, batch=bt, lane_masks=lm), dev)
         maps = rast.forward(*params)
         torch.cuda.synchronize()
         got = {k: getattr(maps, k) if hasattr(maps, k) else getattr(maps.state, k) for k in KEYS}
@@ -56,7 +60,8 @@ def test_maps_are_identical_across_shapes(tile):
             ref = got
             continue
         for k in KEYS:
-            assert np.array_equal(got[k].view(np.uint32), ref[k].view(np.uint32)), (tile, ww, bt, k)
+            assert np.array_equal(got[k].view(np.uint32), ref[k].view(np.uint32)), \
+                (tile, ww, bt, lm, k)
     say(f"  tile {tile}: {len(_shapes(*tile))} shapes, identical maps")
 
 
@@ -77,12 +82,12 @@ def test_gradients_agree_across_shapes():
     P = views[0].pixels
     ups = [rng.normal(size=k * P).astype(np.float32) for k in (3, 2, 3, 1)]
     ref = None
-    # 8x8 tiles take the quadrant-group backward (one, two or four 64-splat
-    # chunks per staging round)
+    # 8x8 tiles and lane-mask shapes take the quadrant-group backward (one,
+    # two or four 64-splat chunks per staging round)
     for tile in [(16, 16), (32, 16), (8, 8)]:
-        for ww, bt in _shapes(*tile):
+        for ww, bt, lm in _shapes(*tile):
             rast = Rasterizer(views, _settings(sh_degree=3, tile_w=tile[0], tile_h=tile[1],
-                                               wave_w=ww, batch=bt), dev)
+                                               wave_w=ww, batch=bt, lane_masks=lm), dev)
             g = _grads(rast, rast.forward(*params), params, ups, dev)
             if ref is None:
                 ref = g
@@ -91,7 +96,7 @@ def test_gradients_agree_across_shapes():
                 rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
                 # FP32 atomics add the per-wave partial sums in another grouping:
                 # the bar of the recompute-vs-stored comparison
-                assert rel <= 1e-5, (tile, ww, bt, name, rel)
+                assert rel <= 1e-5, (tile, ww, bt, lm, name, rel)
 
 
 def test_tuned_shape_matches_the_oracle():
