@@ -281,20 +281,23 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
             xl = max(xl, (int)ceilf(fmaxf(xc - half - m, -1.0f)));
             xh = min(xh, (int)floorf(fminf(xc + half + m, (float)TW)));
           }
+          if (xl > xh) continue;
           const int yy = y - 8 * by;
+          // pixels xl..xh of the tile row (TW <= 32; the unsigned shifts
+          // wrap to the right mask also for xh = 31)
+          const uint32_t row = (2u << xh) - (1u << xl);
 #pragma unroll
           for (int bx = 0; bx < TG::NWX; ++bx) {
-            const int l = max(xl - 8 * bx, 0), h = min(xh - 8 * bx, 7);
-            if (l > h) continue;
+            const uint32_t r8 = (row >> (8 * bx)) & 0xFFu;  // the wave's 8 pixels
             uint64_t bm;
             if constexpr (QL) {
-              // quadrant 2 (yy / 4) and 2 (yy / 4) + 1, row 4 (yy % 4) in each
-              const int base = 32 * (yy >> 2) + 4 * (yy & 3);
-              bm = 0;
-              if (l <= 3) bm |= ((2ull << min(h, 3)) - (1ull << l)) << base;
-              if (h >= 4) bm |= ((2ull << (h - 4)) - (1ull << (max(l, 4) - 4))) << (base + 16);
+              // x 0-3 to bits 0-3 (quadrant 2 (yy / 4)), x 4-7 to bits
+              // 16-19 (quadrant 2 (yy / 4) + 1): r8 + r8 << 12 does not
+              // overlap itself; then row yy % 4 of the two quadrants
+              const uint32_t q = (r8 * 0x1001u) & 0x000F000Fu;
+              bm = (uint64_t)q << (32 * (yy >> 2) + 4 * (yy & 3));
             } else {
-              bm = ((2ull << h) - (1ull << l)) << (8 * yy);
+              bm = (uint64_t)r8 << (8 * yy);
             }
             lm[by * TG::NWX + bx] |= bm;
           }
@@ -728,27 +731,48 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
       publish_masks<TW, TH, 8, BT>(bits, slot >> 6, sh.masks);
     }
     __syncthreads();
-    for (int cw = TG::NCH - 1; cw >= 0; --cw) {
+    // per chunk, the splats that reach a pixel of the lane's quadrant
+    // blending at the chunk's first position or later, at positions up to
+    // the quadrant's furthest last blend
+    uint64_t qm[TG::NCH];
+#pragma unroll
+    for (int cw = 0; cw < TG::NCH; ++cw) {
       const int lo = bstart + cw * 64;  // the chunk's first position
-      if (wlast < lo) continue;         // nothing at or below a last blend
-      // the chunk's splats that reach a pixel of the quadrant blending at
-      // the chunk's first position or later, at positions up to the
-      // quadrant's furthest last blend
+      qm[cw] = 0;
+      if (wlast < lo) continue;  // nothing at or below a last blend (uniform)
       uint64_t mg = quadrant_chunk_mask(sh.lmask[wave * TG::BATCH + cw * 64 + lane],
                                         __builtin_amdgcn_ballot_w64(lo <= lastp),
                                         uniform_u64(sh.masks[wave][cw]));
       const int ql = qlast - lo;
-      mg = ql < 0 ? 0ull : ql < 63 ? mg & ((2ull << ql) - 1) : mg;
-      for (;;) {
-        const bool work = mg != 0;
-        if (!__any(work)) break;
+      qm[cw] = ql < 0 ? 0ull : ql < 63 ? mg & ((2ull << ql) - 1) : mg;
+    }
+    // Each quadrant walks the batch's chunks from the back on its own (a
+    // wave step ends when every quadrant has run out of splats in the whole
+    // batch, not in each chunk): cw, the quadrant's current chunk, mg, what
+    // is left of it.
+    int cw = TG::NCH - 1;
+    uint64_t mg = qm[TG::NCH - 1];
+    for (;;) {
+      if (TG::NCH > 1 && mg == 0) {
+        // the next chunk down that holds splats of the quadrant, if any
+        int nc = -1;
+        uint64_t nm = 0;
+#pragma unroll
+        for (int k = 0; k < TG::NCH - 1; ++k)
+          if (k < cw && qm[k] != 0) { nc = k; nm = qm[k]; }
+        cw = nc;
+        mg = nm;
+      }
+      const bool work = mg != 0;
+      if (!__any(work)) break;
+      {
         int j = 0;
         if (work) {
           j = 63 - __builtin_clzll(mg);
           mg &= ~(1ull << j);
         }
-        const int r = cw * 64 + j;
-        const int pos = lo + j;
+        const int r = (work ? cw * 64 : 0) + j;
+        const int pos = bstart + r;
         StagedSplat s;
         StagedForm f;
         StagedRem rm;
@@ -761,8 +785,8 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
             work && splat_alpha(s, f, dx, dy, bp, t1, t2, e, al, cl) && pos <= lastp;
         if (!__any(has)) continue;
         // the operations of bwd_tile's branch-free adjoint (lanes of a
-        // quadrant without a splat this step read slot cw * 64, a staged
-        // one, and contribute zeros to their own row only)
+        // quadrant without a splat this step read slot 0, a staged one, and
+        // contribute zeros to their own row only)
         const float inv = __builtin_amdgcn_rcpf(1.0f - al);
         const float Ti = T * inv;
         const float w = al * Ti;
