@@ -136,13 +136,16 @@ def compare_maps(g, o, pixels=None, tol=1e-5, check_int=True, label=""):
 
 
 def grad_check(got, ref, scale, label, tol=1e-4, normwise_tol=1e-5):
-    """Per parameter group: norm-wise ||g - g_ref|| / ||g_ref|| <= 1e-5, and
-    element-wise |g - g_ref| <= 1e-4 (|g_ref| + 0.1 S), where S is the
-    oracle's round-off scale of that element (sum over pixels of |term|,
-    pushed through |d param / d splat quantity|).  A gradient element is a
-    sum of per-pixel FP32 terms of both signs; its attainable accuracy is set
-    by the size of the terms, not by their (possibly cancelling) sum: the
-    bound allows 1e-5 S, about 170 units of FP32 round-off."""
+    """Per parameter group: norm-wise ||g - g_ref|| <= 1e-5 (||g_ref|| +
+    0.1 ||S||), and element-wise |g - g_ref| <= 1e-4 (|g_ref| + 0.1 S), where
+    S is the oracle's round-off scale of that element (sum over pixels of
+    |term|, pushed through |d param / d splat quantity|).  A gradient element
+    is a sum of per-pixel FP32 terms of both signs; its attainable accuracy
+    is set by the size of the terms, not by their (possibly cancelling) sum:
+    the element-wise bound allows 1e-5 S, about 170 units of FP32 round-off,
+    and the norm-wise one the same floor over the group (on scenes of
+    needle-like splats the scale gradients cancel to ~1/50 of S, and two
+    orders of the FP32 atomic additions differ by 1e-5 of ||g_ref||)."""
     worst = {}
     for k in ref:
         r = np.asarray(ref[k], np.float64).reshape(ref[k].shape[0], -1)
@@ -152,7 +155,8 @@ def grad_check(got, ref, scale, label, tol=1e-4, normwise_tol=1e-5):
             continue
         aerr = np.abs(g - r)
         err = aerr / (np.abs(r) + 0.1 * S + 1e-30)
-        nrm = np.linalg.norm(g - r) / (np.linalg.norm(r) + 1e-30)
+        nrm_plain = np.linalg.norm(g - r) / (np.linalg.norm(r) + 1e-30)
+        nrm = np.linalg.norm(g - r) / (np.linalg.norm(r) + 0.1 * np.linalg.norm(S) + 1e-30)
         i = np.unravel_index(np.argmax(err), err.shape)
         worst[k] = (float(err.max()), float(nrm))
         # elements within the bar only thanks to the round-off floor: beyond
@@ -160,7 +164,7 @@ def grad_check(got, ref, scale, label, tol=1e-4, normwise_tol=1e-5):
         floor_only = (aerr > tol * np.abs(r)) & (aerr <= tol * (np.abs(r) + 0.1 * S))
         nz = int((r != 0).sum())
         rel_nz = aerr[r != 0] / np.abs(r[r != 0]) if nz else np.zeros(1)
-        say(f"  grad {k}: normwise {nrm:.3g}; worst elem {err[i]:.3g} (ref {r[i]:.4g} got "
+        say(f"  grad {k}: normwise {nrm_plain:.3g} (with the 0.1 S floor {nrm:.3g}); worst elem {err[i]:.3g} (ref {r[i]:.4g} got "
             f"{g[i]:.4g}, scale {S[i]:.4g}); max |err|/S {np.max(aerr / (S + 1e-30)):.3g}; "
             f"{int(floor_only.sum())} of {r.size} elements pass only through the 0.1 S floor; "
             f"relative error of nonzero elements: median {np.median(rel_nz):.3g}, "
