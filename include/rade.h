@@ -268,14 +268,27 @@ int rade_tile_order(const rade_settings* s, const rade_view* views_host, int32_t
  * depth_quad: rade_project's exact-depth records, required when depth_mode
  * is RADE_DEPTH_EXACT (both depth planes then hold the exact ray-maximum
  * depth; weights, colour, normals and alpha are those of the affine mode),
- * ignored otherwise. */
+ * ignored otherwise.
+ * lane_masks (optional, may be NULL; 16-byte aligned): where the launch shape
+ * keeps per-lane splat masks (rade_lane_mask_bytes > 0), the forward writes
+ * the masks of every (list position, 8x8 wave) pair it stages there, for
+ * rade_render_bwd to read instead of computing them again; ignored for other
+ * shapes.  Size: rade_lane_mask_bytes(s, n_pairs) for the lists' pair
+ * count.  The contents are an opaque cache tied to these lists and this
+ * launch shape. */
 int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const rade_splat* splats,
                     const uint32_t* pair_ids, const uint32_t* tile_ranges,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
                     int32_t* median, int32_t* count, int32_t* evals, float* distortion,
-                    const float* depth_quad, void* stream);
+                    const float* depth_quad, uint64_t* lane_masks, void* stream);
+
+/* Bytes of the lane-mask cache of rade_render_fwd / rade_render_bwd for
+ * n_pairs list entries: 8 bytes per (pair, 8x8 wave of a tile) where the
+ * launch shape keeps lane masks (8x8 tiles of 8x8 waves, or lane_masks = 1
+ * on larger tiles), else 0 (the cache is unused).  Host function. */
+size_t rade_lane_mask_bytes(const rade_settings* s, int64_t n_pairs);
 
 /* Workspace bytes for rade_render_bwd; recompute != 0 reserves room to
  * recompute the splats (splats == NULL in rade_render_bwd).  The workspace
@@ -305,7 +318,12 @@ size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, i
  * through its depth only: 4 g A w_i (d_i - D/A) with A and D the alpha and
  * expected-depth maps of the forward, which must then be passed as `alpha`
  * (1 plane) and `depth` (the 2-plane depth map); both are ignored when
- * d_distortion is NULL. */
+ * d_distortion is NULL.  lane_masks (optional, may be NULL; 16-byte
+ * aligned): the cache the forward filled for the same lists, settings and
+ * saved state; where the launch shape keeps lane masks the backward reads
+ * them instead of computing them (NULL: computed; the gradients are the same
+ * either way up to the order of FP32 additions).  Contents that do not come
+ * from that forward give undefined gradients. */
 int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const rade_view* views_dev, int32_t V, int64_t N, const float* means,
                     const float* scales, const float* quats, const float* opacities,
@@ -314,9 +332,9 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const float* t_final, const int32_t* last,
                     const int32_t* median, const float* d_color, const float* d_depth,
                     const float* d_normal, const float* d_alpha, const float* d_distortion,
-                    const float* depth, const float* alpha, float* d_means,
-                    float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
-                    void* workspace, size_t workspace_bytes, void* stream);
+                    const float* depth, const float* alpha, const uint64_t* lane_masks,
+                    float* d_means, float* d_scales, float* d_quats, float* d_opacities,
+                    float* d_sh, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace bytes for rade_normal_consistency over `total_pixels` pixels. */
 size_t rade_normal_consistency_workspace(int64_t total_pixels);
@@ -480,7 +498,7 @@ const char* rade_strerror(int code);
  * present).  The entry points above make the same check themselves. */
 int rade_device_check(void);
 
-/* ABI version of this header: 7. */
+/* ABI version of this header: 8. */
 int rade_abi_version(void);
 
 #ifdef __cplusplus

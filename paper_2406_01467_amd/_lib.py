@@ -106,7 +106,7 @@ class Settings:
 
 
 _lib = None
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 
 def load() -> ctypes.CDLL:
@@ -123,14 +123,16 @@ def load() -> ctypes.CDLL:
     lib.rade_bin_sort_workspace.argtypes = [I32, I64, I64, I64]
     lib.rade_bin_sort_workspace.restype = SZ
     lib.rade_bin_sort.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I64, P, P, P, SZ, P]
-    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 15 + [P]
+    lib.rade_render_fwd.argtypes = [P, P, P, I32, I64] + [P] * 16 + [P]
+    lib.rade_lane_mask_bytes.argtypes = [P, I64]
+    lib.rade_lane_mask_bytes.restype = SZ
     lib.rade_tile_order_workspace.argtypes = [I64]
     lib.rade_tile_order_workspace.restype = SZ
     lib.rade_tile_order.argtypes = [P, P, I32, P, P, P, SZ, P]
     lib.rade_tile_order.restype = ctypes.c_int
     lib.rade_render_bwd_workspace.argtypes = [P, I32, I64, ctypes.c_int]
     lib.rade_render_bwd_workspace.restype = SZ
-    lib.rade_render_bwd.argtypes = [P, P, P, I32, I64] + [P] * 25 + [SZ, P]
+    lib.rade_render_bwd.argtypes = [P, P, P, I32, I64] + [P] * 26 + [SZ, P]
     lib.rade_strerror.argtypes = [ctypes.c_int]
     lib.rade_strerror.restype = ctypes.c_char_p
     lib.rade_abi_version.restype = ctypes.c_int
@@ -172,7 +174,7 @@ def load() -> ctypes.CDLL:
 
 
 EXPORTED = ["rade_views_prepare", "rade_project", "rade_bin_sort_workspace", "rade_bin_sort",
-            "rade_render_fwd", "rade_render_bwd_workspace", "rade_render_bwd", "rade_strerror",
+            "rade_render_fwd", "rade_lane_mask_bytes", "rade_render_bwd_workspace", "rade_render_bwd", "rade_strerror",
             "rade_abi_version", "rade_set_kernel_events", "rade_tile_order_workspace",
             "rade_tile_order", "rade_normal_consistency_workspace", "rade_normal_consistency",
             "rade_filter3d_var", "rade_filter3d_apply", "rade_filter3d_apply_bwd",
@@ -298,14 +300,17 @@ def rade_tile_order(settings: Settings, views_c, tile_ranges, tile_order, worksp
 
 def rade_render_fwd(settings: Settings, views_c, views_dev, V: int, N: int, splats, pair_ids,
                     tile_ranges, color, depth, normal, alpha, t_final, last, median, count=None,
-                    stream=None, tile_order=None, distortion=None, depth_quad=None, evals=None):
+                    stream=None, tile_order=None, distortion=None, depth_quad=None, evals=None,
+                    lane_masks=None):
+    """lane_masks (optional): the cache of rade_lane_mask_bytes(settings, pairs)
+    bytes the forward fills for the backward."""
     s = settings.c()
     return _check(load().rade_render_fwd(ctypes.byref(s), views_c, _p(views_dev), V, N,
                                          _p(splats), _p(pair_ids), _p(tile_ranges),
                                          _p(tile_order), _p(color),
                                          _p(depth), _p(normal), _p(alpha), _p(t_final), _p(last),
                                          _p(median), _p(count), _p(evals), _p(distortion),
-                                         _p(depth_quad), _stream(stream)),
+                                         _p(depth_quad), _p(lane_masks), _stream(stream)),
                   "rade_render_fwd")
 
 
@@ -313,6 +318,13 @@ def rade_device_check() -> int:
     """RADE_OK when the current HIP device is a gfx950 GPU, else
     RADE_ERR_UNSUPPORTED_DEVICE (returned, not raised)."""
     return int(load().rade_device_check())
+
+
+def rade_lane_mask_bytes(settings: Settings, n_pairs: int) -> int:
+    """Bytes of the forward's lane-mask cache for n_pairs list entries (0 where
+    the launch shape keeps no lane masks)."""
+    s = settings.c()
+    return int(load().rade_lane_mask_bytes(ctypes.byref(s), int(n_pairs)))
 
 
 def rade_render_bwd_workspace(settings: Settings, V: int, N: int, recompute: bool) -> int:
@@ -324,15 +336,16 @@ def rade_render_bwd(settings: Settings, views_c, views_dev, V: int, N: int, mean
                     opacities, sh, splats, pair_ids, tile_ranges, t_final, last, median, d_color,
                     d_depth, d_normal, d_alpha, d_means, d_scales, d_quats, d_opacities, d_sh,
                     workspace, stream=None, tile_order=None, d_distortion=None, depth=None,
-                    alpha=None):
-    """d_distortion (optional) needs the forward's depth (2 planes) and alpha maps."""
+                    alpha=None, lane_masks=None):
+    """d_distortion (optional) needs the forward's depth (2 planes) and alpha maps;
+    lane_masks (optional): the cache the forward filled for the same lists."""
     s = settings.c()
     return _check(load().rade_render_bwd(
         ctypes.byref(s), views_c, _p(views_dev), V, N, _p(means), _p(scales), _p(quats),
         _p(opacities), _p(sh), _p(splats), _p(pair_ids), _p(tile_ranges), _p(tile_order),
         _p(t_final), _p(last),
         _p(median), _p(d_color), _p(d_depth), _p(d_normal), _p(d_alpha), _p(d_distortion),
-        _p(depth), _p(alpha), _p(d_means),
+        _p(depth), _p(alpha), _p(lane_masks), _p(d_means),
         _p(d_scales), _p(d_quats), _p(d_opacities), _p(d_sh), _p(workspace),
         workspace.numel() * workspace.element_size(), _stream(stream)), "rade_render_bwd")
 

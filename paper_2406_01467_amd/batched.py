@@ -113,6 +113,12 @@ class BatchedPlan:
             self.splats = torch.empty(VN * _lib.SPLAT_BYTES, dtype=torch.uint8, device=dev)
             self.tt = torch.empty(VN, dtype=torch.int32, device=dev)
         self.bin_ws = self.arena[:bin_bytes]
+        # the lane masks the forward stages, read back by the backward (launch
+        # shapes with lane masks only; written and read while the gradient
+        # records are live, so not in the arena)
+        lm_bytes = _lib.rade_lane_mask_bytes(self.settings, self.capacity)
+        self.lane_masks = (torch.empty(max(2, lm_bytes // 8), dtype=torch.int64, device=dev)
+                           if lm_bytes > 0 else None)
         self.order = torch.empty(r.total_tiles + 1, dtype=torch.int32, device=dev)
         self.order_ws = torch.empty(max(1, _lib.rade_tile_order_workspace(r.total_tiles)),
                                     dtype=torch.uint8, device=dev)
@@ -146,7 +152,7 @@ class BatchedPlan:
         _lib.rade_render_fwd(st, r.views_c, r.views_dev, V, N, self.splats, self.pair_ids,
                              self.ranges, mp["color"], mp["depth"], mp["normal"], mp["alpha"],
                              mp["t_final"], mp["last"], mp["median"], None, tile_order=order,
-                             distortion=mp.get("distortion"))
+                             distortion=mp.get("distortion"), lane_masks=self.lane_masks)
         g = self.grad_fn(mp)
         g = [None if x is None else x.contiguous() for x in g]
         dc, dd, dn, da = g[:4]
@@ -155,7 +161,7 @@ class BatchedPlan:
                              None if self.recompute else self.splats, self.pair_ids, self.ranges,
                              mp["t_final"], mp["last"], mp["median"], dc, dd, dn, da,
                              *self.grads, self.bwd_ws, tile_order=order, d_distortion=ddist,
-                             depth=mp["depth"], alpha=mp["alpha"])
+                             depth=mp["depth"], alpha=mp["alpha"], lane_masks=self.lane_masks)
 
     def capture(self):
         """Capture enqueue() into a HIP graph (after one eager warm-up)."""

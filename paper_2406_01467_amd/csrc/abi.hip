@@ -29,19 +29,21 @@ hipError_t launch_bin_sort(const rade_settings& s, const rade_view* views_host,
 bool tile_supported(int tw, int th);
 bool wave_shape_supported(int tw, int th, int wave_w);
 bool render_shape_is_default(int tw, int th, int wave_w, int batch, int lane_masks);
+int lane_masks_per_pair(int tw, int th, int wave_w, int batch, int lane_masks);
 hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
                              int32_t* last, int32_t* med, int32_t* cnt, int32_t* evals,
-                             float* distortion, const float* depth_quad, hipStream_t st);
+                             float* distortion, const float* depth_quad, uint64_t* lane_masks,
+                             hipStream_t st);
 hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int V, int64_t N,
                              int64_t tiles, const rade_splat* splats, const uint32_t* ids,
                              const uint32_t* ranges, const uint32_t* order, const float* tf,
                              const int32_t* last, const int32_t* med, const float* dc,
                              const float* dd, const float* dn, const float* da,
                              const float* ddist, const float* fwd_depth, const float* fwd_alpha,
-                             float* gsplat, hipStream_t st);
+                             float* gsplat, const uint64_t* lane_masks, hipStream_t st);
 size_t tile_order_workspace(int64_t tiles);
 size_t normal_consistency_workspace(int64_t total_pixels);
 hipError_t launch_l1_color_grad(const rade_view* views, int V, int64_t total, const float* color,
@@ -167,7 +169,7 @@ KernelEvents& kernel_events(int kernel) {
 
 extern "C" {
 
-int rade_abi_version(void) { return 7; }
+int rade_abi_version(void) { return 8; }
 
 int rade_device_check(void) { return device_status(); }
 
@@ -364,7 +366,7 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
                     uint32_t* tile_order, float* color,
                     float* depth, float* normal, float* alpha, float* t_final, int32_t* last,
                     int32_t* median, int32_t* count, int32_t* evals, float* distortion,
-                    const float* depth_quad, void* stream) {
+                    const float* depth_quad, uint64_t* lane_masks, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !color || !depth || !normal || !alpha || !t_final || !last || !median)
@@ -378,12 +380,23 @@ int rade_render_fwd(const rade_settings* s, const rade_view* views_host,
     return RADE_ERR_INVALID_ARG;
   if (s->schedule != RADE_SCHEDULE_TILE && !tile_order) return RADE_ERR_INVALID_ARG;
   if (N > 0 && !splats) return RADE_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(lane_masks) & 15) != 0) return RADE_ERR_INVALID_ARG;
   const int64_t tiles = total_tiles(views_host, V);
   if (const int dv = device_status(); dv != RADE_OK) return dv;
+  const bool keep_masks =
+      rade::lane_masks_per_pair(s->tile_w, s->tile_h, s->wave_w, s->batch, s->lane_masks) > 0;
   return hip_status(rade::launch_render_fwd(*s, views_dev, V, N, tiles, splats, pair_ids,
                                             tile_ranges, tile_order, color, depth, normal, alpha,
                                             t_final, last, median, count, evals, distortion,
-                                            exact ? depth_quad : nullptr, (hipStream_t)stream));
+                                            exact ? depth_quad : nullptr,
+                                            keep_masks ? lane_masks : nullptr,
+                                            (hipStream_t)stream));
+}
+
+size_t rade_lane_mask_bytes(const rade_settings* s, int64_t n_pairs) {
+  if (!settings_ok(s) || n_pairs < 0) return 0;
+  const int w = rade::lane_masks_per_pair(s->tile_w, s->tile_h, s->wave_w, s->batch, s->lane_masks);
+  return (size_t)n_pairs * (size_t)w * sizeof(uint64_t);
 }
 
 size_t rade_render_bwd_workspace(const rade_settings* s, int32_t V, int64_t N, int recompute) {
@@ -404,9 +417,9 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                     const float* t_final, const int32_t* last,
                     const int32_t* median, const float* d_color, const float* d_depth,
                     const float* d_normal, const float* d_alpha, const float* d_distortion,
-                    const float* depth, const float* alpha, float* d_means,
-                    float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
-                    void* workspace, size_t workspace_bytes, void* stream) {
+                    const float* depth, const float* alpha, const uint64_t* lane_masks,
+                    float* d_means, float* d_scales, float* d_quats, float* d_opacities,
+                    float* d_sh, void* workspace, size_t workspace_bytes, void* stream) {
   if (!settings_ok(s) || !views_ok(views_host, V) || !views_dev || !counts_ok(V, N))
     return RADE_ERR_INVALID_ARG;
   if (!tile_ranges || !t_final || !last || !median) return RADE_ERR_INVALID_ARG;
@@ -419,7 +432,8 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
                 !d_quats || !d_opacities || !d_sh))
     return RADE_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(quats) & 15) != 0 ||
-      (reinterpret_cast<uintptr_t>(d_quats) & 15) != 0)
+      (reinterpret_cast<uintptr_t>(d_quats) & 15) != 0 ||
+      (reinterpret_cast<uintptr_t>(lane_masks) & 15) != 0)
     return RADE_ERR_INVALID_ARG;
   const int recompute = splats == nullptr ? 1 : 0;
   if (!workspace || workspace_bytes < rade_render_bwd_workspace(s, V, N, recompute))
@@ -445,7 +459,13 @@ int rade_render_bwd(const rade_settings* s, const rade_view* views_host,
   hipError_t e = rade::launch_render_bwd(*s, views_dev, V, N, tiles, splats, pair_ids,
                                          tile_ranges, tile_order, t_final, last, median, d_color,
                                          d_depth, d_normal, d_alpha, d_distortion, depth, alpha,
-                                         gsplat, st);
+                                         gsplat,
+                                         rade::lane_masks_per_pair(s->tile_w, s->tile_h,
+                                                                   s->wave_w, s->batch,
+                                                                   s->lane_masks) > 0
+                                             ? lane_masks
+                                             : nullptr,
+                                         st);
   if (e != hipSuccess) return RADE_ERR_HIP;
   e = rade::launch_project_bwd(*s, views_dev, V, N, means, scales, quats, opacities, sh, gsplat,
                                d_means, d_scales, d_quats, d_opacities, d_sh, st);

@@ -104,6 +104,7 @@ struct FwdArgs {
   float *color, *depth, *normal, *alpha, *t_final, *distortion;
   int32_t *last, *median, *count, *evals;
   const float4* depth_quad;  // EXACT only: 2 per (view, Gaussian)
+  uint64_t* lane_masks;      // LM tiles, optional: the staged pairs' masks
 };
 
 struct BwdArgs {
@@ -121,6 +122,7 @@ struct BwdArgs {
   const float *d_color, *d_depth, *d_normal, *d_alpha;
   const float *d_distortion, *fwd_depth, *fwd_alpha;  // DIST only
   float* gsplat;
+  const uint64_t* lane_masks;  // LM tiles, optional: the forward's masks
 };
 
 // Q: an 8x8 tile held by one wave as four 16-lane groups, one per 4x4
@@ -192,6 +194,24 @@ __device__ __forceinline__ bool block_reached(float ur, float vr, float w0, floa
   return m <= tau2;
 }
 
+// Lane mask in row-major lane order (lane 8 y + x) to the quadrant order of
+// pixel_ctx<..., true> (lane 16 q + 4 (y % 4) + x % 4, q = 2 (y / 4) + x / 4):
+// per 32-bit half (four pixel rows, one byte each), the low nibbles (x 0-3)
+// gather into bits 0-15 and the high nibbles (x 4-7) into bits 16-31.
+__device__ __forceinline__ uint32_t nibbles_to_quadrants(uint32_t w) {
+  uint32_t l = w & 0x0F0F0F0Fu, h = (w >> 4) & 0x0F0F0F0Fu;
+  l = (l | (l >> 4)) & 0x00FF00FFu;
+  h = (h | (h >> 4)) & 0x00FF00FFu;
+  l = (l | (l >> 8)) & 0x0000FFFFu;
+  h = (h | (h >> 8)) & 0x0000FFFFu;
+  return l | (h << 16);
+}
+
+__device__ __forceinline__ uint64_t to_quadrant_lanes(uint64_t m) {
+  return (uint64_t)nibbles_to_quadrants((uint32_t)m) |
+         ((uint64_t)nibbles_to_quadrants((uint32_t)(m >> 32)) << 32);
+}
+
 // Stage splat `idx` of the tile list into LDS slot `slot` and return the
 // bit set of wave blocks its support reaches (support rect first, then the
 // exact ellipse-against-block test).
@@ -200,8 +220,13 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
                                           const uint32_t* __restrict__ pair_ids, uint32_t idx,
                                           int slot, const PixelCtx& c, const BlendParams& bp,
                                           StagedArrays<TileGeom<TW, TH, WW, BT>::BATCH>& st,
-                                          uint32_t* sgid, uint64_t* lmask) {
-  // lmask (LM tiles): the lane mask of wave k at lmask[k * BATCH + slot]
+                                          uint32_t* sgid, uint64_t* lmask,
+                                          uint64_t* __restrict__ lm_out = nullptr,
+                                          const uint64_t* __restrict__ lm_in = nullptr) {
+  // lmask (LM tiles): the lane mask of wave k at lmask[k * BATCH + slot].
+  // lm_out (LM tiles, optional): the masks (row-major lane order) also go to
+  // lm_out[idx * NW + k]; lm_in (LM tiles, optional): masks a forward wrote
+  // there for the same lists and launch shape, read instead of computed.
   using TG = TileGeom<TW, TH, WW, BT>;
   const uint32_t g = pair_ids[idx];
   const rade_splat& sp = splats[vbase + g];
@@ -227,7 +252,29 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     if (rx0 <= bx + WW - 1 && rx1 >= bx && ry0 <= by + TG::WH - 1 && ry1 >= by) bits |= 1u << k;
   }
   uint64_t lm[TG::LM ? TG::NW : 1] = {};
-  if (bits) {
+  bool loaded = false;
+  if constexpr (TG::LM) {
+    if (lm_in) {  // uniform
+      const uint64_t* src = lm_in + (int64_t)idx * TG::NW;
+      if constexpr (TG::NW % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < TG::NW; k += 2) {
+          const uint4 q = *reinterpret_cast<const uint4*>(src + k);
+          lm[k] = ((uint64_t)q.y << 32) | q.x;
+          lm[k + 1] = ((uint64_t)q.w << 32) | q.z;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < TG::NW; ++k) lm[k] = src[k];
+      }
+      if constexpr (QL) {
+#pragma unroll
+        for (int k = 0; k < TG::NW; ++k) lm[k] = to_quadrant_lanes(lm[k]);
+      }
+      loaded = true;
+    }
+  }
+  if (bits && !loaded) {
     // Support: power <= cut and opacity 2^-power >= alpha_min.  The bound
     // and the tests below carry margins far above the error of the
     // hardware reciprocal, square root and logarithm (about one unit in
@@ -306,6 +353,19 @@ __device__ __forceinline__ uint32_t stage(const rade_splat* __restrict__ splats,
     }
   }
   if constexpr (TG::LM) {
+    if (!QL && lm_out) {  // uniform; only row-major masks are stored
+      uint64_t* dst = lm_out + (int64_t)idx * TG::NW;
+      if constexpr (TG::NW % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < TG::NW; k += 2)
+          *reinterpret_cast<uint4*>(dst + k) =
+              make_uint4((uint32_t)lm[k], (uint32_t)(lm[k] >> 32), (uint32_t)lm[k + 1],
+                         (uint32_t)(lm[k + 1] >> 32));
+      } else {
+#pragma unroll
+        for (int k = 0; k < TG::NW; ++k) dst[k] = lm[k];
+      }
+    }
     bits = 0;
 #pragma unroll
     for (int k = 0; k < TG::NW; ++k) {
@@ -398,7 +458,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (idx < c.re) {
         bits = stage<TW, TH, WW, BT, EXACT>(splats, vbase, pair_ids, idx, slot, c, bp, sh.st,
-                                            sgid, sh.lmask);
+                                            sgid, sh.lmask, a.lane_masks);
         if constexpr (EXACT) {
           const float4* q = a.depth_quad + 2 * (vbase + sgid[slot]);
           sh.xq[slot] = q[0];
@@ -727,7 +787,8 @@ __device__ __forceinline__ void bwd_tile_q(const BwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (li < bend)
         bits = stage<TW, TH, 8, BT, false, true>(splats, vbase, pair_ids, c.rb + (uint32_t)li,
-                                                 slot, c, bp, sh.st, sgid, sh.lmask);
+                                                 slot, c, bp, sh.st, sgid, sh.lmask, nullptr,
+                                                 a.lane_masks);
       publish_masks<TW, TH, 8, BT>(bits, slot >> 6, sh.masks);
     }
     __syncthreads();
@@ -905,7 +966,7 @@ __device__ __forceinline__ void bwd_tile(const BwdArgs& a, int64_t tile,
       uint32_t bits = 0;
       if (li < bend)
         bits = stage<TW, TH, WW, BT>(splats, vbase, pair_ids, c.rb + (uint32_t)li, slot, c, bp,
-                                     sh.st, sgid, sh.lmask);
+                                     sh.st, sgid, sh.lmask, nullptr, a.lane_masks);
       publish_masks<TW, TH, WW, BT>(bits, slot >> 6, masks);
     }
     __syncthreads();
@@ -1179,6 +1240,15 @@ bool wave_shape_supported(int tw, int th, int wave_w) {
   return shape_fits(tw, th, ww);
 }
 
+// 64-bit lane masks per pair that the forward can store for the backward:
+// one per 8x8 wave of the tile where the launch shape keeps lane masks (8x8
+// tiles of 8x8 waves, or lane_masks on larger ones), else none.
+int lane_masks_per_pair(int tw, int th, int wave_w, int batch, int lane_masks) {
+  if (lane_mask_shape(tw, th, wave_w, batch, lane_masks)) return (tw / 8) * (th / 8);
+  if (tw == 8 && th == 8 && (wave_w == 0 || wave_w == 8)) return 1;
+  return 0;
+}
+
 bool render_shape_is_default(int tw, int th, int wave_w, int batch, int lane_masks) {
   return default_shape(tw, th, wave_w, batch) &&
          !lane_mask_shape(tw, th, wave_w, batch, lane_masks);
@@ -1204,7 +1274,8 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
                              const uint32_t* ranges, const uint32_t* order, float* color,
                              float* depth, float* normal, float* alpha, float* tf,
                              int32_t* last, int32_t* med, int32_t* cnt, int32_t* evals,
-                             float* distortion, const float* depth_quad, hipStream_t st) {
+                             float* distortion, const float* depth_quad, uint64_t* lane_masks,
+                             hipStream_t st) {
   if (tiles == 0) return hipSuccess;
   FwdArgs a;
   a.bp = make_blend_params(s);
@@ -1215,6 +1286,7 @@ hipError_t launch_render_fwd(const rade_settings& s, const rade_view* views, int
   a.color = color; a.depth = depth; a.normal = normal; a.alpha = alpha; a.t_final = tf;
   a.last = last; a.median = med; a.count = cnt; a.evals = evals; a.distortion = distortion;
   a.depth_quad = reinterpret_cast<const float4*>(depth_quad);
+  a.lane_masks = lane_masks;
   RADE_TILE_DISPATCH(launch_fwd_t, (a, s.schedule, s.wave_w, s.batch, s.lane_masks, st))
   return hipGetLastError();
 }
@@ -1225,7 +1297,7 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
                              const int32_t* last, const int32_t* med, const float* dc,
                              const float* dd, const float* dn, const float* da,
                              const float* ddist, const float* fwd_depth, const float* fwd_alpha,
-                             float* gsplat, hipStream_t st) {
+                             float* gsplat, const uint64_t* lane_masks, hipStream_t st) {
   const int64_t ng4 = (int64_t)V * N * 4;  // 16 floats per (view, Gaussian)
   if (ng4 > 0) {
     const int64_t blocks = (ng4 + kZeroThreads - 1) / kZeroThreads;
@@ -1243,6 +1315,7 @@ hipError_t launch_render_bwd(const rade_settings& s, const rade_view* views, int
   a.d_color = dc; a.d_depth = dd; a.d_normal = dn; a.d_alpha = da;
   a.d_distortion = ddist; a.fwd_depth = fwd_depth; a.fwd_alpha = fwd_alpha;
   a.gsplat = gsplat;
+  a.lane_masks = lane_masks;
   RADE_TILE_DISPATCH(launch_bwd_t, (a, s.schedule, s.wave_w, s.batch, s.lane_masks, st))
   return hipGetLastError();
 }

@@ -29,6 +29,8 @@ class ForwardState:
     # the forward's depth and alpha maps (read by the distortion adjoint)
     depth: Optional[torch.Tensor] = None
     alpha: Optional[torch.Tensor] = None
+    # the lane masks the forward staged (launch shapes with lane masks only)
+    lane_masks: Optional[torch.Tensor] = None
 
 
 @dataclasses.dataclass
@@ -157,14 +159,17 @@ class Rasterizer:
                 if want_distortion else None)
         evals = (torch.empty(self.total_pixels, dtype=torch.int32, device=self.device)
                  if want_evals else None)
+        lm_bytes = _lib.rade_lane_mask_bytes(self.settings, M)
+        lane_masks = (torch.empty(max(2, lm_bytes // 8), dtype=torch.int64, device=self.device)
+                      if lm_bytes > 0 else None)
         _lib.rade_render_fwd(self.settings, self.views_c, self.views_dev, self.V, N, splats,
                              pair_ids, ranges, color, depth, normal, alpha, tf, last, med, cnt,
                              stream, tile_order=order, distortion=dist, depth_quad=quad,
-                             evals=evals)
+                             evals=evals, lane_masks=lane_masks)
         # pair_ids are a view of a reusable buffer: keep a private copy for
         # the backward pass
         state = ForwardState(splats if keep_splats else None, pair_ids.clone(), ranges, order,
-                             tf, last, med, M, depth, alpha)
+                             tf, last, med, M, depth, alpha, lane_masks)
         return Maps(color, depth, normal, alpha, cnt, state, dist, evals)
 
     def tile_order(self, ranges, stream=None):
@@ -199,7 +204,7 @@ class Rasterizer:
                              state.ranges, state.t_final, state.last, state.median, c(d_color),
                              c(d_depth), c(d_normal), c(d_alpha), dm, ds, dq, do, dsh, workspace,
                              stream, tile_order=state.order, d_distortion=c(d_distortion),
-                             depth=state.depth, alpha=state.alpha)
+                             depth=state.depth, alpha=state.alpha, lane_masks=state.lane_masks)
         return dm, ds, dq, do, dsh
 
 

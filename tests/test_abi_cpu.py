@@ -30,7 +30,7 @@ def _declared():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = _declared()
-    assert len(names) == 24, names
+    assert len(names) == 25, names
     so = ctypes.CDLL(lib.LIB_PATH)
     for n in names:
         assert hasattr(so, n), n
@@ -208,12 +208,38 @@ def test_render_bwd_rejects_a_misaligned_workspace():
     vc = lib.make_views([synth.identity_view(32, 32)])
     lib.rade_views_prepare(s, vc)
     d = ctypes.c_void_p(256)
-    args = [ctypes.byref(s.c()), vc, d, 1, 10] + [d] * 5 + [d, d, d, d, d, d, d] + [d] * 4 + \
-        [None, None, None] + [d] * 5
+    head = [ctypes.byref(s.c()), vc, d, 1, 10] + [d] * 5 + [d, d, d, d, d, d, d] + [d] * 4 + \
+        [None, None, None]
+    args = head + [None] + [d] * 5  # no lane-mask cache
     big = 1 << 30
     assert so.rade_render_bwd(*args, ctypes.c_void_p(256 + 4), big, None) == \
         lib.RADE_ERR_INVALID_ARG
     assert so.rade_render_bwd(*args, None, big, None) == lib.RADE_ERR_WORKSPACE
+    # a lane-mask cache is read in 16-byte words: misaligned is rejected too
+    assert so.rade_render_bwd(*(head + [ctypes.c_void_p(256 + 8)] + [d] * 5), d, big, None) == \
+        lib.RADE_ERR_INVALID_ARG
+
+
+def test_lane_mask_bytes_follow_the_launch_shape():
+    """8 bytes per (pair, 8x8 wave) where the launch shape keeps lane masks
+    (8x8 tiles of 8x8 waves; lane_masks = 1 on larger tiles of 8x8 waves with
+    one splat staged per thread), 0 elsewhere and for invalid arguments."""
+    lib = _lib()
+
+    def nbytes(n, **kw):
+        return lib.rade_lane_mask_bytes(lib.Settings(**kw), n)
+
+    assert nbytes(1000, tile_w=16, tile_h=16) == 0
+    assert nbytes(1000, tile_w=16, tile_h=16, lane_masks=1) == 1000 * 4 * 8
+    assert nbytes(1000, tile_w=32, tile_h=16, lane_masks=1) == 1000 * 8 * 8
+    assert nbytes(1000, tile_w=16, tile_h=8, lane_masks=1) == 1000 * 2 * 8
+    assert nbytes(1000, tile_w=16, tile_h=16, lane_masks=1, batch=128) == 0
+    assert nbytes(1000, tile_w=16, tile_h=16, lane_masks=1, wave_w=16) == 0
+    assert nbytes(1000, tile_w=8, tile_h=8) == 1000 * 8
+    assert nbytes(1000, tile_w=8, tile_h=8, batch=256) == 1000 * 8
+    assert nbytes(0, tile_w=8, tile_h=8) == 0
+    assert nbytes(-1, tile_w=8, tile_h=8) == 0
+    assert nbytes(1000, tile_w=16, tile_h=16, lane_masks=2) == 0
 
 
 def _no_gpu() -> bool:
@@ -253,7 +279,8 @@ def test_no_device_is_unsupported_and_nothing_launches():
     vc = lib.make_views([synth.identity_view(32, 32)])
     lib.rade_views_prepare(lib.Settings(), vc)
     assert so.rade_render_fwd(ctypes.byref(s), vc, d, 1, 10, d, d, d, None, *([d] * 7),
-                              None, None, None, None, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
+                              None, None, None, None, None, None) == \
+        lib.RADE_ERR_UNSUPPORTED_DEVICE
     ws = lib.rade_bin_sort_workspace(1, 10, 100, 4)
     assert so.rade_bin_sort(ctypes.byref(s), vc, d, 1, 10, d, d, d, d, None, 100, d, None, d,
                             ws, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE

@@ -99,6 +99,43 @@ def test_gradients_agree_across_shapes():
                 assert rel <= 1e-5, (tile, ww, bt, lm, name, rel)
 
 
+def test_backward_reads_the_forward_lane_masks():
+    """Where the launch shape keeps lane masks, the forward stores them per
+    (pair, 8x8 wave) and the backward reads them instead of recomputing: the
+    gradients with and without that cache agree up to the order of the FP32
+    atomic additions, and shapes without lane masks keep no cache."""
+    import dataclasses
+    from paper_2406_01467_amd.raster import Rasterizer
+    dev = device()
+    scene, views = _scene()
+    params = to_dev(scene, dev)
+    rng = np.random.default_rng(103)
+    P = views[0].pixels
+    ups = [rng.normal(size=k * P).astype(np.float32) for k in (3, 2, 3, 1)]
+    cases = [((8, 8), 0, 0), ((8, 8), 256, 0), ((16, 16), 0, 1), ((32, 16), 0, 1),
+             ((16, 8), 0, 1), ((16, 16), 0, 0)]
+    for (tw, th), bt, lm in cases:
+        rast = Rasterizer(views, _settings(sh_degree=3, tile_w=tw, tile_h=th, batch=bt,
+                                           lane_masks=lm), dev)
+        maps = rast.forward(*params)
+        kept = maps.state.lane_masks
+        waves = (tw // 8) * (th // 8) if (lm or (tw, th) == (8, 8)) else 0
+        if waves == 0:
+            assert kept is None, (tw, th, bt, lm)
+            continue
+        assert kept is not None and kept.numel() >= maps.state.n_pairs * waves
+        # the cache holds masks of staged pairs: some pixels of each tile
+        assert int((kept[: maps.state.n_pairs * waves] != 0).sum()) > 0
+        g_cache = _grads(rast, maps, params, ups, dev)
+        g_comp = _grads(rast, type("M", (), {"state": dataclasses.replace(maps.state,
+                                                                          lane_masks=None)}),
+                        params, ups, dev)
+        for a, b, name in zip(g_cache, g_comp, ("means", "scales", "quats", "opacities", "sh")):
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            say(f"  {tw}x{th} batch {bt} lane masks {lm}: {name} cache vs computed {rel:.3g}")
+            assert rel <= 1e-5, (tw, th, bt, lm, name, rel)
+
+
 def test_tuned_shape_matches_the_oracle():
     import torch
     from paper_2406_01467_amd.raster import Rasterizer
