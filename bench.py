@@ -108,13 +108,13 @@ def kernel_bytes(kernel: str, n: int, views: int, pairs: int, pixels: int) -> in
 MEASURED = [
     {"kernel": "render_bwd", "workload": "plain_1600x1064_1m", "tile": "16x16",
      "schedule": 1, "wave_w": 0, "batch": 0, "lane_masks": 0,
-     "sources_sha1": "836440a46d839f14b3974bddd06e4b5c784a115b",
-     "fetch_bytes": 374617806, "write_bytes": 154785088, "valu_issue": 0.85,
+     "sources_sha1": "208baf9f505f40f3b6b7fac587f2e696860e6b1a",
+     "fetch_bytes": 374456425, "write_bytes": 154785088, "valu_issue": 0.84,
      "profile": "profiles/kernels_1600x1064_1m_pmc.md"},
     {"kernel": "render_bwd", "workload": "batched_16views_1m", "tile": "16x16",
      "schedule": 1, "wave_w": 0, "batch": 0, "lane_masks": 1,
-     "sources_sha1": "836440a46d839f14b3974bddd06e4b5c784a115b",
-     "fetch_bytes": 5566466923, "write_bytes": 2709135936, "valu_issue": 0.95,
+     "sources_sha1": "208baf9f505f40f3b6b7fac587f2e696860e6b1a",
+     "fetch_bytes": 6220774192, "write_bytes": 2709135936, "valu_issue": 0.85,
      "profile": "profiles/kernels_batched_16views_1m_pmc.md"},
 ]
 
