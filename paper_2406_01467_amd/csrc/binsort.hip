@@ -156,7 +156,11 @@ __device__ __forceinline__ uint64_t lanes_below() {
 }
 
 // Per-block digit counts (LDS atomics; lanes that hit one counter are
-// serialised by the LDS, not by vector instructions).
+// serialised by the LDS, not by vector instructions).  The top digit of
+// 32-bit keys (the sign and exponent byte of the float depths) takes few
+// values: there the lanes of one digit are matched by ballots (digit_peers)
+// and their lowest lane adds their number, one LDS atomic per distinct digit
+// of a wave (elsewhere the ballots cost more than the contention they save).
 template <int RB>
 __global__ void __launch_bounds__(kThreads)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
@@ -177,9 +181,20 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
 #pragma unroll
   for (int d = threadIdx.x; d < R; d += kThreads) h[d] = 0;
   __syncthreads();
+  if (shift + RB >= 32) {  // uniform
+    const uint64_t lt = lanes_below();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r)
-    if (item_index(base, r) < n) atomicAdd(&h[digit_of<RB>(key[r], shift)], 1u);
+    for (int r = 0; r < kItems; ++r) {
+      const bool valid = item_index(base, r) < n;
+      const uint32_t d = digit_of<RB>(key[r], shift);
+      const uint64_t peers = digit_peers<RB>(d, valid);
+      if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+      if (item_index(base, r) < n) atomicAdd(&h[digit_of<RB>(key[r], shift)], 1u);
+  }
   __syncthreads();
 #pragma unroll
   for (int d = threadIdx.x; d < R; d += kThreads) hist[(int64_t)d * nblocks + blk] = h[d];
