@@ -22,21 +22,27 @@ def _fixed_grads(P, dev, seed=5):
     return [torch.from_numpy(rng.normal(size=k * P).astype(np.float32)).to(dev) for k in (3, 2, 3, 1)]
 
 
-@pytest.mark.parametrize("schedule,tile", [(0, (16, 16)), (1, (8, 8)), (2, (16, 16)), (2, (32, 16))])
-def test_graph_replay_equals_plain_path(schedule, tile):
+@pytest.mark.parametrize("schedule,tile,lm", [(0, (16, 16), 0), (1, (8, 8), 0), (2, (16, 16), 0),
+                                              (2, (32, 16), 0), (1, (16, 16), 1)])
+def test_graph_replay_equals_plain_path(schedule, tile, lm):
+    """Replays of the captured step equal the plain path's maps bit for bit
+    and its gradients to FP32 atomic order; with lane masks (lm) both paths
+    also pass the forward's mask cache to the backward."""
     import torch
     from paper_2406_01467_amd import Settings
     from paper_2406_01467_amd.batched import BatchedPlan
     from paper_2406_01467_amd.raster import Rasterizer
     dev = device()
     scene, views = _scene_views()
-    st = Settings(tile_w=tile[0], tile_h=tile[1], sh_degree=3, schedule=schedule)
+    st = Settings(tile_w=tile[0], tile_h=tile[1], sh_degree=3, schedule=schedule, lane_masks=lm)
     params = to_dev(scene, dev)
-    rast = Rasterizer(views, Settings(tile_w=tile[0], tile_h=tile[1], sh_degree=3), dev)
+    rast = Rasterizer(views, Settings(tile_w=tile[0], tile_h=tile[1], sh_degree=3, lane_masks=lm),
+                      dev)
     g = _fixed_grads(rast.total_pixels, dev)
     ref = rast.forward(*params, want_count=False)
     ref_grads = [x.clone() for x in rast.backward(ref.state, *params, *g)]
     plan = BatchedPlan(views, st, params, lambda maps: g)
+    assert (plan.lane_masks is not None) == (lm == 1 or tile == (8, 8))
     plan.capture()
     for rep in range(3):
         plan.replay()
@@ -53,7 +59,11 @@ def test_graph_replay_equals_plain_path(schedule, tile):
     say("graph replay ok", schedule, tile, "pairs", plan.n_pairs())
 
 
-def test_capacity_overflow_grows_and_recaptures():
+@pytest.mark.parametrize("lm", [0, 1])
+def test_capacity_overflow_grows_and_recaptures(lm):
+    """A plan sized for 100 pairs overflows, grows (with lane masks, also the
+    forward's mask cache) and re-captures: the second replay equals the
+    plain path."""
     import torch
     from paper_2406_01467_amd import Settings
     from paper_2406_01467_amd.batched import BatchedPlan
@@ -61,15 +71,21 @@ def test_capacity_overflow_grows_and_recaptures():
     dev = device()
     scene, views = _scene_views(8000, seed=31)
     params = to_dev(scene, dev)
-    st = Settings(sh_degree=3, schedule=2)
-    rast = Rasterizer(views, Settings(sh_degree=3), dev)
+    st = Settings(sh_degree=3, schedule=2, lane_masks=lm)
+    rast = Rasterizer(views, Settings(sh_degree=3, lane_masks=lm), dev)
     g = _fixed_grads(rast.total_pixels, dev)
     ref = rast.forward(*params)
+    ref_grads = [x.clone() for x in rast.backward(ref.state, *params, *g)]
     plan = BatchedPlan(views, st, params, lambda maps: g, capacity=100)
     n = plan.step()
     torch.cuda.synchronize()
     assert n == 2 and plan.capacity >= plan.n_pairs() and plan.n_pairs() == ref.state.n_pairs
     assert torch.equal(plan.maps["color"], ref.color)
+    if lm:
+        assert plan.lane_masks is not None
+        assert plan.lane_masks.numel() * 8 >= plan.capacity * 4 * 8
+    for a, b in zip(plan.grads, ref_grads):
+        assert torch.linalg.norm(a - b) <= 1e-6 * torch.linalg.norm(b)
 
 
 @pytest.mark.parametrize("large", [False, True])
