@@ -23,7 +23,8 @@ def _fixed_grads(P, dev, seed=5):
 
 
 @pytest.mark.parametrize("schedule,tile,lm", [(0, (16, 16), 0), (1, (8, 8), 0), (2, (16, 16), 0),
-                                              (2, (32, 16), 0), (1, (16, 16), 1)])
+                                              (2, (32, 16), 0), (1, (16, 16), 1), (2, (16, 16), 1),
+                                              (0, (32, 16), 1)])
 def test_graph_replay_equals_plain_path(schedule, tile, lm):
     """Replays of the captured step equal the plain path's maps bit for bit
     and its gradients to FP32 atomic order; with lane masks (lm) both paths
