@@ -220,6 +220,24 @@ def test_render_bwd_rejects_a_misaligned_workspace():
         lib.RADE_ERR_INVALID_ARG
 
 
+def test_render_fwd_rejects_a_misaligned_lane_mask_cache():
+    """The forward writes the lane-mask cache in 16-byte words: a pointer that
+    is not 16-byte aligned is rejected before the device check (the dummy
+    device pointers are never dereferenced); NULL means no cache."""
+    lib = _lib()
+    import synth
+    so = lib.load()
+    s = lib.Settings()
+    vc = lib.make_views([synth.identity_view(32, 32)])
+    lib.rade_views_prepare(s, vc)
+    d = ctypes.c_void_p(256)
+    head = [ctypes.byref(s.c()), vc, d, 1, 10, d, d, d, None] + [d] * 7 + [None] * 4
+    assert so.rade_render_fwd(*head, ctypes.c_void_p(256 + 8), None) == lib.RADE_ERR_INVALID_ARG
+    if _no_gpu():
+        assert so.rade_render_fwd(*head, None, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
+        assert so.rade_render_fwd(*head, d, None) == lib.RADE_ERR_UNSUPPORTED_DEVICE
+
+
 def test_lane_mask_bytes_follow_the_launch_shape():
     """8 bytes per (pair, 8x8 wave) where the launch shape keeps lane masks
     (8x8 tiles of 8x8 waves; lane_masks = 1 on larger tiles of 8x8 waves with
